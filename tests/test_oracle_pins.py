@@ -1,0 +1,389 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these tests retypes an oracle formula: each one checks the oracle
+against a closed form, an invariant, a special case that reduces to a textbook
+or library routine, exact rational arithmetic, or brute force on tiny inputs.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import gen
+import oracle
+from oracle import solver as oa
+
+
+def _tiny(n=15, k=8, active=0.2, seed=0):
+    w = gen.c1_workload(n=n, k=k, seeds=(seed,), active=active)
+    return w, w.op.S(), w.instances[0]
+
+
+def _restricted(S, Z, mask):
+    I, g2l, nI = oracle.compact(mask)
+    S_II, d_I = oracle.restrict(S, I)
+    return I, g2l, nI, S_II, d_I
+
+
+# ---------------------------------------------------------------------------
+# compaction and restriction
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_compaction_properties(seed):
+    rng = np.random.default_rng(seed)
+    mask = (rng.uniform(size=1000) < 0.3).astype(np.uint8)
+    I, g2l, nI = oracle.compact(mask)
+    assert nI == int((mask == 0).sum())
+    assert np.all(np.diff(I) > 0)                       # strictly ascending
+    assert np.all(mask[I] == 0)
+    assert np.all(g2l[I] == np.arange(nI))
+    assert np.all(g2l[mask == 1] == -1)
+
+
+def test_compaction_edge_cases():
+    for mask in [np.zeros(7, np.uint8), np.ones(7, np.uint8), np.zeros(0, np.uint8)]:
+        I, g2l, nI = oracle.compact(mask)
+        assert nI == int((mask == 0).sum()) and len(I) == nI
+
+
+def test_restriction_equals_scatter_matvec_gather():
+    w, S, inst = _tiny()
+    I, _, nI, S_II, d_I = _restricted(S, w.Z, inst.mask)
+    x = np.random.default_rng(1).standard_normal(nI)
+    full = np.zeros(S.shape[0])
+    full[I] = x
+    np.testing.assert_allclose(S_II @ x, (S @ full)[I], rtol=0, atol=1e-15 * abs(S).max() * 13)
+    np.testing.assert_array_equal(d_I, S.diagonal()[I])
+    assert abs(S_II - S_II.T).max() == 0.0
+
+
+def test_cauchy_interlacing():
+    """lambda_j(S) <= mu_j(S_II) <= lambda_{j+N-n_I}(S)  (Sec. spectral coherence)."""
+    w, S, inst = _tiny(n=11, active=0.3)
+    I, _, nI, S_II, _ = _restricted(S, w.Z, inst.mask)
+    lam = np.linalg.eigvalsh(S.toarray())
+    mu = np.linalg.eigvalsh(S_II.toarray())
+    N = S.shape[0]
+    tol = 1e-12 * lam[-1]
+    assert np.all(lam[:nI] <= mu + tol)
+    assert np.all(mu <= lam[N - nI:] + tol)
+
+
+def test_min_eigenvalue_bounded_by_shift():
+    """lambda_min(S) >= c for S = a B + c I with B PSD (paper: lambda_min(M) >= 1)."""
+    for w in (gen.c1_workload(n=9, k=0), ):
+        S = w.op.S().toarray()
+        assert np.linalg.eigvalsh(S)[0] >= w.op.shift * (1 - 1e-10)
+    op, _ = gen.c2_operator(n=9)
+    assert np.linalg.eigvalsh(op.S().toarray())[0] >= op.shift * (1 - 1e-8)
+
+
+# ---------------------------------------------------------------------------
+# restricted basis (QR) and coarse space
+# ---------------------------------------------------------------------------
+def test_restricted_basis_orthonormal_same_span():
+    w, S, inst = _tiny(n=15, k=10)
+    I, *_ = _restricted(S, w.Z, inst.mask)
+    Q, kept = oracle.restricted_basis(w.Z, I)
+    assert Q.shape[1] == 10 and list(kept) == list(range(10))
+    np.testing.assert_allclose(Q.T @ Q, np.eye(10), atol=1e-13)
+    ZI = w.Z[I, :]
+    # same span: the orthogonal projector onto span(Z_I) fixes Q
+    Pz = ZI @ np.linalg.solve(ZI.T @ ZI, ZI.T)
+    np.testing.assert_allclose(Pz @ Q, Q, atol=1e-12)
+
+
+def test_restricted_basis_drops_dependent_and_zero_columns():
+    w, S, inst = _tiny(n=15, k=6)
+    I, *_ = _restricted(S, w.Z, inst.mask)
+    Z = np.column_stack([w.Z[:, :3], w.Z[:, 1], np.zeros(w.Z.shape[0]), w.Z[:, 3:]])
+    Q, kept = oracle.restricted_basis(Z, I)
+    assert list(kept) == [0, 1, 2, 5, 6, 7]
+    assert Q.shape[1] == 6
+    np.testing.assert_allclose(Q.T @ Q, np.eye(6), atol=1e-13)
+
+
+def test_projector_is_M_orthogonal():
+    """P^2 = P and M P = P^T M  (eq. proj; P is an M_II-orthogonal projector)."""
+    w, S, inst = _tiny(n=11, k=6)
+    I, _, nI, S_II, _ = _restricted(S, w.Z, inst.mask)
+    Zo, _ = oracle.restricted_basis(w.Z, I)
+    cs, fb = oracle.coarse_setup(S_II, Zo)
+    assert not fb
+    P = np.column_stack([oa.apply_projector(cs, e) for e in np.eye(nI)])
+    M = S_II.toarray()
+    scale = np.abs(M).max()
+    np.testing.assert_allclose(P @ P, P, atol=1e-10)
+    np.testing.assert_allclose(M @ P, P.T @ M, atol=1e-10 * scale)
+    np.testing.assert_allclose(P @ Zo, 0.0, atol=1e-10)
+
+
+def test_condition_number_of_exact_eigenbasis():
+    """With Z = eigenvectors of M_II, E = diag(lambda): cond = lambda_max/lambda_min."""
+    w, S, inst = _tiny(n=9, k=0)
+    mask = np.zeros(S.shape[0], np.uint8)
+    lam, V = np.linalg.eigh(S.toarray())
+    cs, fb = oracle.coarse_setup(S, V[:, :5])
+    assert not fb
+    np.testing.assert_allclose(cs.E, np.diag(lam[:5]), atol=1e-12 * lam[4])
+    assert abs(cs.cond / (lam[4] / lam[0]) - 1) < 1e-10
+    cs, fb = oracle.coarse_setup(S, V[:, :5], tau_cond=0.5 * lam[4] / lam[0])
+    assert fb
+
+
+# ---------------------------------------------------------------------------
+# A-DEF2 loop
+# ---------------------------------------------------------------------------
+def test_k0_is_textbook_jacobi_pcg_scipy():
+    w, S, inst = _tiny(n=31, k=0)
+    I, _, nI, S_II, d_I = _restricted(S, w.Z, inst.mask)
+    b = inst.b[I]
+    res = oracle.jacobi_pcg(S_II, b, 1e-8)
+    count = [0]
+    xs, info = spla.cg(S_II, b, rtol=1e-8, atol=0.0, maxiter=100000,
+                       M=sp.diags(1.0 / d_I), callback=lambda xk: count.__setitem__(0, count[0] + 1))
+    assert info == 0
+    assert abs(res.iters - count[0]) <= 1
+    assert oracle.rel_err(res.x, xs) < 1e-6
+    assert np.linalg.norm(b - S_II @ res.x) <= 1.01e-8 * np.linalg.norm(b) * 10
+
+
+def test_finite_termination_unpreconditioned():
+    """No preconditioner, b a combination of m eigenvectors of M_II outside
+    span(Z): CG terminates after exactly m steps (Krylov space of dim m)."""
+    w, S, inst = _tiny(n=9, k=0)
+    M = S.toarray()
+    lam, V = np.linalg.eigh(M)
+    Z = V[:, :3]
+    cs, _ = oracle.coarse_setup(S, Z)
+    m = 4
+    b = V[:, [3, 6, 10, 20]] @ np.array([1.0, 2.0, -1.0, 0.5])
+    res = oracle.adef2(S, b, cs, 1e-10, d_inv=np.ones(S.shape[0]))
+    assert res.iters == m
+    x_exact = V[:, [3, 6, 10, 20]] @ (np.array([1.0, 2.0, -1.0, 0.5]) / lam[[3, 6, 10, 20]])
+    assert oracle.rel_err(res.x, x_exact) < 1e-9
+
+
+def test_rhs_in_coarse_space_needs_no_iteration():
+    w, S, inst = _tiny(n=15, k=8)
+    I, _, nI, S_II, _ = _restricted(S, w.Z, inst.mask)
+    Zo, _ = oracle.restricted_basis(w.Z, I)
+    cs, _ = oracle.coarse_setup(S_II, Zo)
+    c = np.arange(1, 9, dtype=float)
+    b = S_II @ (Zo @ c)
+    res = oracle.adef2(S_II, b, cs, 1e-10)
+    assert res.iters == 0
+    assert oracle.rel_err(res.x, Zo @ c) < 1e-12
+
+
+def test_full_rank_coarse_space_is_exact():
+    """k = n_I: the coarse correction alone solves the system (0 iterations)."""
+    N = 25
+    w, S, inst = _tiny(n=5, k=0)
+    mask = np.zeros(N, np.uint8)
+    mask[[0, 7, 12, 18, 24]] = 1
+    I, _, nI, S_II, _ = _restricted(S, None, mask)
+    Z = np.random.default_rng(3).standard_normal((N, nI))
+    Zo, kept = oracle.restricted_basis(Z, I)
+    assert len(kept) == nI
+    cs, _ = oracle.coarse_setup(S_II, Zo)
+    b = np.random.default_rng(4).standard_normal(nI)
+    res = oracle.adef2(S_II, b, cs, 1e-12)
+    assert res.iters == 0
+    assert oracle.rel_err(res.x, np.linalg.solve(S_II.toarray(), b)) < 1e-10
+
+
+def _run_recorded(n=15, k=8, tol=1e-12, seed=0, maxit=1500):
+    w, S, inst = _tiny(n=n, k=k, seed=seed)
+    I, _, nI, S_II, _ = _restricted(S, w.Z, inst.mask)
+    Zo, _ = oracle.restricted_basis(w.Z, I)
+    cs, _ = oracle.coarse_setup(S_II, Zo)
+    b = inst.b[I]
+    res = oracle.adef2(S_II, b, cs, tol, maxit=maxit, record=True)
+    xs = oracle.exact_solution(S_II, b)
+    return S_II, b, Zo, res, xs
+
+
+def _invariant_violations(S_II, b, Zo, res, xs):
+    """Which A-DEF2 pins fail for a recorded run (used by the mutation test)."""
+    bad = []
+    bn = np.linalg.norm(b)
+    # recurrence residual equals the true residual (unprojected, App. stopping)
+    for x, r in res.history:
+        if np.linalg.norm(r - (b - S_II @ x)) > 1e-9 * bn:
+            bad.append("residual_drift")
+            break
+    # Z^T r_k = 0 relative to ||b||
+    if max(np.linalg.norm(Zo.T @ r) for _, r in res.history) > 1e-11 * bn:
+        bad.append("ZTr")
+    # energy norm of the error is non-increasing
+    en = [float(np.sqrt(max((x - xs) @ (S_II @ (x - xs)), 0.0))) for x, _ in res.history]
+    if any(en[i + 1] > en[i] * (1 + 1e-8) + 1e-14 * en[0] for i in range(len(en) - 1)):
+        bad.append("energy")
+    if not res.converged or oracle.rel_err(res.x, xs) > 1e-8:
+        bad.append("accuracy")
+    return bad
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_adef2_invariants(seed):
+    S_II, b, Zo, res, xs = _run_recorded(seed=seed)
+    assert res.converged and res.iters > 5
+    assert _invariant_violations(S_II, b, Zo, res, xs) == []
+
+
+def test_deflation_reduces_iterations_c1():
+    w = gen.c1_workload(n=63, k=16)
+    S = w.op.S()
+    inst = w.instances[0]
+    rd = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-8)
+    rp = oracle.solve_instance(S, w.Z[:, :0], inst.mask, inst.b, 1e-8)
+    assert rd.status == 0 and rp.status == 0
+    assert rd.iters < rp.iters
+    assert rd.relres_true < 1.5e-8 and rp.relres_true < 1.5e-8
+
+
+def test_fallback_is_plain_pcg():
+    w = gen.c1_workload(n=31, k=8)
+    S = w.op.S()
+    inst = w.instances[0]
+    rf = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-8, tau_cond=1.0)
+    rp = oracle.solve_instance(S, w.Z[:, :0], inst.mask, inst.b, 1e-8)
+    assert rf.status == oracle.STATUS_FALLBACK and rf.k_eff == 0
+    assert rf.iters == rp.iters
+    np.testing.assert_array_equal(rf.x, rp.x)
+
+
+def test_maxit_status():
+    w = gen.c1_workload(n=31, k=8)
+    inst = w.instances[0]
+    r = oracle.solve_instance(w.op.S(), w.Z, inst.mask, inst.b, 1e-12, maxit=3)
+    assert r.status == oracle.STATUS_MAXIT and r.iters == 3
+
+
+def test_two_dimensional_symmetric_closed_form():
+    """The paper's 2d_sym case (golden fixture): y_d = a sin(pi x) sin(pi y) is an
+    eigenvector of M = alpha L^2 + I, so y* = y_d / lambda_11 and deflation with
+    the sine modes needs no iteration; lambda_11 -> 1 + 4 pi^4 alpha as h -> 0."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "2d_sym.txt")
+    vals = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            key, *rest = line.split()
+            vals[key] = rest
+    alpha = float(vals["alpha"][0])
+    lam_cont = 1 + 4 * math.pi ** 4 * alpha
+    prev = None
+    for n in (15, 31, 63):
+        h = 1.0 / (n + 1)
+        L = gen.laplacian_2d(n) / (h * h)
+        M = sp.csr_matrix(alpha * (L @ L) + sp.identity(n * n))
+        Z, pairs, _ = gen.sine_modes_2d(n, 3)
+        assert pairs[0] == (1, 1)
+        mu1 = 4 / h ** 2 * math.sin(math.pi / (2 * (n + 1))) ** 2
+        lam11 = alpha * (2 * mu1) ** 2 + 1
+        for a in map(float, vals["a_values"]):
+            yd = a * Z[:, 0] * (n + 1) / 2.0          # a sin(pi x) sin(pi y) on the nodes
+            cs, fb = oracle.coarse_setup(M, Z)
+            # the exact x = y_d / lambda_11 leaves a rounding residual ~ u ||M|| ||x||
+            res = oracle.adef2(M, yd, cs, 1e-8)
+            assert res.iters == 0
+            assert oracle.rel_err(res.x, yd / lam11) < 1e-11
+            # unpreconditioned CG: an eigenvector rhs converges in one step
+            res0 = oracle.jacobi_pcg(M, yd, 1e-8, d_inv=np.ones(n * n))
+            assert res0.iters == 1
+        err = abs(lam11 - lam_cont)
+        if prev is not None:
+            assert err < prev / 3.5                   # O(h^2) convergence to the printed value
+        prev = err
+    assert prev / lam_cont < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# exact solution machinery
+# ---------------------------------------------------------------------------
+def test_two_sum_two_prod_exact():
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal(200) * 10.0 ** rng.integers(-8, 8, 200)
+    b = rng.standard_normal(200) * 10.0 ** rng.integers(-8, 8, 200)
+    s, e = oa.two_sum(a, b)
+    p, f = oa.two_prod(a, b)
+    for i in range(200):
+        assert Fraction(s[i]) + Fraction(e[i]) == Fraction(a[i]) + Fraction(b[i])
+        assert Fraction(p[i]) + Fraction(f[i]) == Fraction(a[i]) * Fraction(b[i])
+
+
+def test_dd_residual_against_exact_rationals():
+    rng = np.random.default_rng(1)
+    A = sp.random(12, 12, density=0.5, random_state=2, format="csr") + sp.identity(12)
+    x = rng.standard_normal(12)
+    b = A @ x + 1e-12 * rng.standard_normal(12)
+    r = oracle.dd_residual(A, x, b)
+    Ad = A.toarray()
+    for i in range(12):
+        exact = Fraction(b[i]) - sum(Fraction(Ad[i, j]) * Fraction(x[j]) for j in range(12))
+        assert abs(Fraction(r[i]) - exact) <= abs(exact) * Fraction(2.3e-16) + Fraction(1e-300)
+
+
+def _fraction_solve(A, b):
+    n = len(b)
+    M = [[Fraction(A[i, j]) for j in range(n)] + [Fraction(b[i])] for i in range(n)]
+    for c in range(n):
+        piv = M[c][c]
+        for r_ in range(c + 1, n):
+            f = M[r_][c] / piv
+            for j in range(c, n + 1):
+                M[r_][j] -= f * M[c][j]
+    x = [Fraction(0)] * n
+    for i in reversed(range(n)):
+        x[i] = (M[i][n] - sum(M[i][j] * x[j] for j in range(i + 1, n))) / M[i][i]
+    return x
+
+
+@pytest.mark.parametrize("dense_limit", [4000, 2])
+def test_exact_solution_matches_rational_solve(dense_limit):
+    """An ill-conditioned SPD system (cond ~ 1e9) solved to ~1 ulp forward error."""
+    w = gen.c1_workload(n=3, k=0)
+    A = w.op.S()
+    Q, _ = np.linalg.qr(np.random.default_rng(5).standard_normal((9, 9)))
+    Ad = (Q * np.logspace(0, 9, 9)) @ Q.T
+    Ad = 0.5 * (Ad + Ad.T)
+    A = sp.csr_matrix(Ad)
+    b = np.random.default_rng(6).standard_normal(9)
+    x = oracle.exact_solution(A, b, dense_limit=dense_limit)
+    xe = np.array([float(v) for v in _fraction_solve(Ad, b)])
+    assert np.linalg.norm(x - xe) <= 4e-16 * np.linalg.norm(xe)
+
+
+# ---------------------------------------------------------------------------
+# mutation check: plausible oracle mistakes are caught by the pins above
+# ---------------------------------------------------------------------------
+def _mut_no_projection(cs, v):          # Alg. 1 exactly as printed: p built from K r
+    return v
+
+
+def _mut_sign(cs, v):
+    return v if cs.k == 0 else v + cs.Z @ cs.solve(cs.W.T @ v)
+
+
+def _mut_transposed_operand(cs, v):     # Z^T v where W^T v belongs
+    return v if cs.k == 0 else v - cs.Z @ cs.solve(cs.Z.T @ v)
+
+
+@pytest.mark.parametrize("mutant", [_mut_no_projection, _mut_sign, _mut_transposed_operand])
+def test_planted_mistakes_are_detected(monkeypatch, mutant):
+    monkeypatch.setattr(oa, "apply_projector", mutant)
+    S_II, b, Zo, res, xs = _run_recorded(tol=1e-12)
+    assert _invariant_violations(S_II, b, Zo, res, xs) != []
+
+
+def test_planted_coarse_correction_mistake_is_detected(monkeypatch):
+    monkeypatch.setattr(oa, "coarse_coefficients", lambda cs, r: np.zeros(0) if cs.k == 0
+                        else -cs.solve(cs.Z.T @ r))
+    S_II, b, Zo, res, xs = _run_recorded(tol=1e-12)
+    assert _invariant_violations(S_II, b, Zo, res, xs) != []
