@@ -1,0 +1,190 @@
+/*
+ * adef2.h - C ABI of the MI355X (gfx950) restricted-system A-DEF2 solver.
+ *
+ * Solves the restricted SPD system of a state-constrained optimal control
+ * problem (paper: "Online Spectral Deflation for State Constrained Optimal
+ * Control Problems", arXiv 2606.17971, Sec. 2 "Reduced inactive set system",
+ * eq. (reduced)):
+ *
+ *      S_II x_I = b_I,      I = { i : active_mask[i] == 0 },
+ *
+ * with A-DEF2 deflated, Jacobi-preconditioned conjugate gradients (Alg. 1,
+ * projected search directions; App. "CG stopping criterion"), using reference
+ * modes Z computed once on the full domain and restricted to I online
+ * (Sec. "Core idea: reference eigenmode basis", Alg. 3 "Online workflow").
+ *
+ * Conventions
+ *   - Pointers documented as "device" point to device memory of the GPU that
+ *     was current when the context was created; "host" pointers to host
+ *     memory.  The caller owns every pointer it passes; the library copies
+ *     what it keeps and owns its internal buffers.
+ *   - All device work is ordered on the context's HIP stream.  Calls that fill
+ *     host outputs synchronise that stream before returning.
+ *   - Return codes: 0 = OK; < 0 = error (context unchanged, message in
+ *     adef2_last_error); > 0 = warning with a valid, flagged result.
+ *   - Vectors are in global order (length n).  Entries on the active set are
+ *     ignored on input and returned as 0.
+ *   - Operators must be banded/stencil matrices: at most ADEF2_MAX_DIAGS
+ *     distinct diagonals (column - row offsets).  Others give ADEF2_E_UNSUPPORTED.
+ *   - Not thread-safe per context; distinct contexts are independent.
+ */
+#ifndef ADEF2_H
+#define ADEF2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ADEF2_MAX_DIAGS 64   /* distinct diagonals of S                  */
+#define ADEF2_MAX_K     64   /* deflation rank (shared + per-instance)   */
+
+enum adef2_status {
+  ADEF2_OK = 0,
+  ADEF2_E_ARG = -1,         /* invalid argument (sizes, NaN, null pointer)  */
+  ADEF2_E_STATE = -2,       /* call order: restrict before set_reference,
+                               solve before restrict                         */
+  ADEF2_E_HIP = -3,         /* HIP runtime error                             */
+  ADEF2_E_NOMEM = -4,       /* device allocation failed                      */
+  ADEF2_E_NOT_SPD = -5,     /* non-positive diagonal or breakdown (p.Sp<=0)  */
+  ADEF2_E_UNSUPPORTED = -6, /* operator has more than ADEF2_MAX_DIAGS diags  */
+  ADEF2_W_FALLBACK = 1,     /* cond(E) > tau_cond or Cholesky of E failed:
+                               solved as plain Jacobi-PCG (Alg. 3, Remark
+                               tau_cond)                                     */
+  ADEF2_W_MAXIT = 2         /* not converged within maxit; x = last iterate  */
+};
+
+enum adef2_precision {
+  ADEF2_FP64 = 0,           /* all vectors, S, Z and W in FP64 (the paper's
+                               setting, App. "GPU implementation")           */
+  ADEF2_FP32_REFINE = 1     /* inner A-DEF2 sweeps with FP32 S, Z, W and
+                               vectors (FP64 accumulation of dot products);
+                               FP64 outer residual b - S x and FP64 x; the
+                               k x k coarse algebra stays FP64               */
+};
+
+enum adef2_precond {
+  ADEF2_JACOBI = 0,         /* K = diag(S_II)^{-1} (Sec. A-DEF2; App. stopping) */
+  ADEF2_NONE = 1            /* identity (test option)                        */
+};
+
+typedef struct {
+  double tau_cond;      /* solve-time fallback threshold on cond(E); 1e10
+                           (Remark tau_cond)                                 */
+  double drop_rel;      /* restricted-basis column dropped when its part
+                           orthogonal to earlier columns is <= drop_rel times
+                           its own norm; 1e-6                                 */
+  int32_t maxit;        /* iteration cap (total over refinement sweeps);
+                           100000 (App. "CG stopping criterion")             */
+  int32_t precision;    /* enum adef2_precision                              */
+  int32_t precond;      /* enum adef2_precond                                */
+  double inner_rtol;    /* FP32 sweep stops when ||r32|| <= inner_rtol times
+                           the FP64 residual it started from; 1e-4          */
+  int32_t max_sweeps;   /* FP32_REFINE: cap on refinement sweeps; 30         */
+  int32_t check_every;  /* iterations between host polls of convergence; 32 */
+  int32_t rows_per_thread; /* 0 = autotuned; else 1, 2 or 4                  */
+  int32_t profile;      /* 1 = time kernels with HIP events (adef2_get_stats) */
+} adef2_opts;
+
+typedef struct adef2_ctx adef2_ctx;
+
+/* Fill *opts with the defaults listed above. */
+void adef2_default_opts(adef2_opts *opts);
+
+/* Create a context on the current device.  opts may be NULL (defaults).
+ * hip_stream: a hipStream_t (NULL = the default stream). */
+int adef2_create(adef2_ctx **ctx, const adef2_opts *opts, void *hip_stream);
+int adef2_destroy(adef2_ctx *ctx);
+/* Replace the options (does not touch reference data or restrictions). */
+int adef2_set_opts(adef2_ctx *ctx, const adef2_opts *opts);
+
+/* Reference operator and modes (Sec. "Core idea", App. "Matrix assembly").
+ *   n        : number of unknowns N.
+ *   row_ptr  : device int64[n+1]; col_idx: device int32[nnz]; vals: device
+ *              f64[nnz]: S in CSR, symmetric positive definite, sorted columns.
+ *   k        : number of reference modes (0 <= k <= ADEF2_MAX_K).
+ *   Z        : device f64[n*k], column-major (Z[j*n + i]); may be NULL if k = 0.
+ * S is converted on the device to a diagonal format (FP64 + FP32 copies); Z is
+ * copied (FP64 + FP32).  Invalidates any restriction. */
+int adef2_set_reference(adef2_ctx *ctx, int64_t n, const int64_t *row_ptr,
+                        const int32_t *col_idx, const double *vals, int64_t nnz,
+                        int32_t k, const double *Z);
+
+/* Operator family S = a * S_ref + c * I applied to later restrict/solve calls
+ * (a > 0, a + c*... must keep S SPD).  Default a = 1, c = 0. */
+int adef2_set_operator_scale(adef2_ctx *ctx, double a, double c);
+
+/* Inactive-set compaction (eq. reduced; App. "Matrix assembly and active set
+ * restriction").  mask: device uint8[n] (1 = active, 0 = inactive).
+ * Outputs (device): I int32[n] (first *n_inactive entries = inactive indices,
+ * ascending), g2l int32[n] (position in I, or -1 where active).
+ * n_inactive: host out.  Exact integer result. */
+int adef2_compact(adef2_ctx *ctx, const uint8_t *mask, int64_t n, int32_t *I,
+                  int32_t *g2l, int64_t *n_inactive);
+
+/* Restrict to the inactive set of mask (device uint8[n]) and build the coarse
+ * space: restricted modes Z_I, their orthonormalisation (CholQR with column
+ * dropping, folded into the k x k coarse matrix), W = S_II Z_I,
+ * E = Z^T S_II Z (orthonormal basis), cond(E) and its Cholesky factor
+ * (Sec. A-DEF2; Alg. 3 restrict .. form E, fallback test).
+ * n_inactive, k_eff, cond_E: host outs (may be NULL).  k_eff = 0 means the
+ * fallback (plain Jacobi-PCG) will be used; cond_E is +inf when Cholesky of E
+ * failed.  Returns ADEF2_W_FALLBACK in that case. */
+int adef2_restrict(adef2_ctx *ctx, const uint8_t *active_mask, int64_t *n_inactive,
+                   int32_t *k_eff, double *cond_E);
+
+/* Solve S_II x_I = b_I for the current restriction.
+ *   b  : device f64[n] (b on the active set ignored).
+ *   x0 : device f64[n] warm start, or NULL for x0 = 0 (Remark warm start).
+ *   tol: stop when ||b_I - S_II x_I||_2 <= tol ||b_I||_2 (recurrence residual,
+ *        App. "CG stopping criterion"; in FP32_REFINE mode the FP64 residual).
+ *   x  : device f64[n] out, 0 on the active set.
+ *   iters, relres_true (||b - S x||/||b|| recomputed in FP64), cond_E: host
+ *   outs (may be NULL).  iters counts CG iterations (all sweeps). */
+int adef2_solve(adef2_ctx *ctx, const double *b, const double *x0, double tol,
+                double *x, int32_t *iters, double *relres_true, double *cond_E);
+
+/* Batched solve of B independent instances in one launch sequence (shared S
+ * and Z; per-instance masks, operator scales and right-hand sides).
+ *   masks: device uint8[B*n]; b, x: device f64[B*n] (instance-major).
+ *   a, c : host f64[B] operator scales (S_m = a_m S_ref + c_m I), or NULL (1, 0).
+ *   tol  : relative tolerance, as in adef2_solve.
+ *   iters, status (enum adef2_status per instance), relres_true, cond_E,
+ *   n_inactive: host arrays of B entries (each may be NULL).
+ * Returns the most severe per-instance status. */
+int adef2_solve_batched(adef2_ctx *ctx, int32_t B, const uint8_t *masks,
+                        const double *b, const double *a, const double *c,
+                        double tol, double *x, int32_t *iters, int32_t *status,
+                        double *relres_true, double *cond_E, int64_t *n_inactive);
+
+/* y = S_II x on the current restriction (global layout, FP64); test hook for
+ * the restricted operator.  x, y: device f64[n]. */
+int adef2_apply_restricted(adef2_ctx *ctx, const double *x, double *y);
+
+/* Coarse data of the current restriction: E in the orthonormalised basis of
+ * the kept columns (host f64[k*k], leading k_eff x k_eff block, column-major),
+ * kept column flags (host int32[k]).  Either may be NULL. */
+int adef2_coarse_info(adef2_ctx *ctx, double *E, int32_t *kept, int32_t *k_eff,
+                      double *cond_E);
+
+typedef struct {
+  int32_t n_kernels;            /* entries filled                           */
+  const char *name[16];
+  int64_t launches[16];
+  double total_ms[16];          /* HIP-event time summed over launches      */
+  double alg_bytes[16];         /* algorithmic bytes summed over launches   */
+} adef2_stats;
+
+/* Per-kernel timings collected while opts.profile = 1. */
+int adef2_get_stats(adef2_ctx *ctx, adef2_stats *stats);
+int adef2_reset_stats(adef2_ctx *ctx);
+
+/* Message of the last error on ctx (or of the last failed create when ctx is
+ * NULL).  Valid until the next call on ctx. */
+const char *adef2_last_error(const adef2_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADEF2_H */

@@ -1,0 +1,263 @@
+"""Python binding of libadef2 (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module moves arrays to the
+GPU with torch, passes raw device pointers through the C ABI declared in
+include/adef2.h, and converts results back.  There is no fallback: importing
+this module fails when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadef2.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      f"`python -m paper_2606_17971_amd.build` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, E_ARG, E_STATE, E_HIP, E_NOMEM, E_NOT_SPD, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+W_FALLBACK, W_MAXIT = 1, 2
+FP64, FP32_REFINE = 0, 1
+JACOBI, NONE = 0, 1
+MAX_K = 64
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("tau_cond", ctypes.c_double),
+        ("drop_rel", ctypes.c_double),
+        ("maxit", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
+        ("inner_rtol", ctypes.c_double),
+        ("max_sweeps", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("rows_per_thread", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_kernels", ctypes.c_int32),
+        ("name", ctypes.c_char_p * 16),
+        ("launches", ctypes.c_int64 * 16),
+        ("total_ms", ctypes.c_double * 16),
+        ("alg_bytes", ctypes.c_double * 16),
+    ]
+
+
+_P = ctypes.c_void_p
+_i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_Pi32, _Pi64, _Pf64 = (ctypes.POINTER(t) for t in (_i32, _i64, _f64))
+
+_sig = {
+    "adef2_default_opts": (None, [ctypes.POINTER(Opts)]),
+    "adef2_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(Opts), _P]),
+    "adef2_destroy": (ctypes.c_int, [_P]),
+    "adef2_set_opts": (ctypes.c_int, [_P, ctypes.POINTER(Opts)]),
+    "adef2_set_reference": (ctypes.c_int, [_P, _i64, _P, _P, _P, _i64, _i32, _P]),
+    "adef2_set_operator_scale": (ctypes.c_int, [_P, _f64, _f64]),
+    "adef2_compact": (ctypes.c_int, [_P, _P, _i64, _P, _P, _Pi64]),
+    "adef2_restrict": (ctypes.c_int, [_P, _P, _Pi64, _Pi32, _Pf64]),
+    "adef2_solve": (ctypes.c_int, [_P, _P, _P, _f64, _P, _Pi32, _Pf64, _Pf64]),
+    "adef2_solve_batched": (ctypes.c_int, [_P, _i32, _P, _P, _P, _P, _f64, _P, _P, _P, _P, _P, _P]),
+    "adef2_apply_restricted": (ctypes.c_int, [_P, _P, _P]),
+    "adef2_coarse_info": (ctypes.c_int, [_P, _P, _P, _Pi32, _Pf64]),
+    "adef2_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
+    "adef2_reset_stats": (ctypes.c_int, [_P]),
+    "adef2_last_error": (ctypes.c_char_p, [_P]),
+}
+EXPORTS = tuple(_sig)
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class Adef2Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"adef2 error {code}: {msg}")
+        self.code = code
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    _lib.adef2_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _dev(x, dtype) -> torch.Tensor:
+    """Contiguous device tensor of the given dtype (copies host data)."""
+    if isinstance(x, torch.Tensor):
+        t = x.to(device="cuda", dtype=dtype)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+    return t.contiguous()
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class SolveOut:
+    x: torch.Tensor
+    iters: int
+    relres_true: float
+    cond_E: float
+    status: int
+
+
+class Solver:
+    """One library context bound to the current torch stream."""
+
+    def __init__(self, stream: torch.cuda.Stream | None = None, **opts):
+        if not torch.cuda.is_available():
+            raise RuntimeError("adef2 needs a GPU (HIP device)")
+        self.stream = stream or torch.cuda.current_stream()
+        self._ctx = _P()
+        self.opts = default_opts(**opts)
+        rc = _lib.adef2_create(ctypes.byref(self._ctx), ctypes.byref(self.opts),
+                               _P(self.stream.cuda_stream))
+        if rc != OK:
+            raise Adef2Error(rc, _lib.adef2_last_error(None).decode())
+        self._keep = []
+        self.n = 0
+        self.k = 0
+
+    def close(self):
+        if self._ctx:
+            _lib.adef2_destroy(self._ctx)
+            self._ctx = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, allow=(OK, W_FALLBACK, W_MAXIT)) -> int:
+        if rc not in allow:
+            raise Adef2Error(rc, _lib.adef2_last_error(self._ctx).decode())
+        return rc
+
+    def set_opts(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opts, k, v)
+        self._check(_lib.adef2_set_opts(self._ctx, ctypes.byref(self.opts)))
+
+    # --- reference -------------------------------------------------------
+    def set_reference(self, S, Z=None):
+        """S: scipy CSR (symmetric positive definite); Z: N x k array or None."""
+        n = S.shape[0]
+        rp = _dev(np.asarray(S.indptr, dtype=np.int64), torch.int64)
+        ci = _dev(np.asarray(S.indices, dtype=np.int32), torch.int32)
+        va = _dev(np.asarray(S.data, dtype=np.float64), torch.float64)
+        k = 0 if Z is None else int(Z.shape[1])
+        Zt = None
+        if k > 0:
+            Zt = _dev(np.asfortranarray(Z, dtype=np.float64).ravel(order="F"), torch.float64)
+        rc = _lib.adef2_set_reference(self._ctx, n, _ptr(rp), _ptr(ci), _ptr(va), int(S.nnz), k,
+                                      _ptr(Zt))
+        self._check(rc, allow=(OK,))
+        self.n, self.k = n, k
+
+    def set_operator_scale(self, a: float, c: float):
+        self._check(_lib.adef2_set_operator_scale(self._ctx, float(a), float(c)), allow=(OK,))
+
+    # --- compaction / restriction ----------------------------------------
+    def compact(self, mask):
+        m = _dev(mask, torch.uint8)
+        n = m.numel()
+        I = torch.empty(n, dtype=torch.int32, device="cuda")
+        g2l = torch.empty(n, dtype=torch.int32, device="cuda")
+        nI = _i64(0)
+        self._check(_lib.adef2_compact(self._ctx, _ptr(m), n, _ptr(I), _ptr(g2l), ctypes.byref(nI)),
+                    allow=(OK,))
+        return I[: nI.value], g2l, nI.value
+
+    def restrict(self, mask):
+        m = _dev(mask, torch.uint8)
+        nI, ke, cond = _i64(0), _i32(0), _f64(0.0)
+        rc = _lib.adef2_restrict(self._ctx, _ptr(m), ctypes.byref(nI), ctypes.byref(ke),
+                                 ctypes.byref(cond))
+        self._check(rc, allow=(OK, W_FALLBACK))
+        return nI.value, ke.value, cond.value, rc
+
+    # --- solves ------------------------------------------------------------
+    def solve(self, b, tol: float, x0=None) -> SolveOut:
+        bt = _dev(b, torch.float64)
+        x0t = None if x0 is None else _dev(x0, torch.float64)
+        x = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        it, rel, cond = _i32(0), _f64(0.0), _f64(0.0)
+        rc = _lib.adef2_solve(self._ctx, _ptr(bt), _ptr(x0t), float(tol), _ptr(x), ctypes.byref(it),
+                              ctypes.byref(rel), ctypes.byref(cond))
+        self._check(rc)
+        return SolveOut(x, it.value, rel.value, cond.value, rc)
+
+    def solve_batched(self, masks, b, tol: float, a=None, c=None):
+        M = _dev(masks, torch.uint8)
+        Bt = _dev(b, torch.float64)
+        B = M.shape[0]
+        x = torch.empty((B, self.n), dtype=torch.float64, device="cuda")
+        a_h = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        c_h = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+        iters = np.zeros(B, np.int32)
+        status = np.zeros(B, np.int32)
+        rel = np.zeros(B, np.float64)
+        cond = np.zeros(B, np.float64)
+        nI = np.zeros(B, np.int64)
+        hp = lambda arr: None if arr is None else arr.ctypes.data  # noqa: E731
+        rc = _lib.adef2_solve_batched(self._ctx, B, _ptr(M), _ptr(Bt), hp(a_h), hp(c_h), float(tol),
+                                      _ptr(x), hp(iters), hp(status), hp(rel), hp(cond), hp(nI))
+        self._check(rc)
+        return dict(x=x, iters=iters, status=status, relres_true=rel, cond_E=cond, n_inactive=nI,
+                    rc=rc)
+
+    def apply_restricted(self, x) -> torch.Tensor:
+        xt = _dev(x, torch.float64)
+        y = torch.empty_like(xt)
+        self._check(_lib.adef2_apply_restricted(self._ctx, _ptr(xt), _ptr(y)), allow=(OK,))
+        return y
+
+    def coarse_info(self):
+        k = max(self.k, 1)
+        E = np.zeros(k * k)
+        kept = np.zeros(k, np.int32)
+        ke, cond = _i32(0), _f64(0.0)
+        self._check(_lib.adef2_coarse_info(self._ctx, E.ctypes.data, kept.ctypes.data,
+                                           ctypes.byref(ke), ctypes.byref(cond)), allow=(OK,))
+        kk = ke.value
+        Em = E.reshape(k, k, order="F")[:kk, :kk] if self.k else np.zeros((0, 0))
+        return Em, kept[: self.k], kk, cond.value
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(_lib.adef2_get_stats(self._ctx, ctypes.byref(s)), allow=(OK,))
+        return {s.name[i].decode(): dict(launches=s.launches[i], ms=s.total_ms[i],
+                                         alg_bytes=s.alg_bytes[i]) for i in range(s.n_kernels)}
+
+    def reset_stats(self):
+        self._check(_lib.adef2_reset_stats(self._ctx), allow=(OK,))
+
+
+def status_name(code: int) -> str:
+    return {OK: "ok", E_ARG: "e_arg", E_STATE: "e_state", E_HIP: "e_hip", E_NOMEM: "e_nomem",
+            E_NOT_SPD: "e_not_spd", E_UNSUPPORTED: "e_unsupported", W_FALLBACK: "w_fallback",
+            W_MAXIT: "w_maxit"}.get(code, str(code))
+
+
+__all__ = ["Solver", "Opts", "default_opts", "Adef2Error", "EXPORTS", "LIB_PATH", "status_name"]

@@ -1,0 +1,951 @@
+// Host runtime and C ABI of the restricted A-DEF2 solver (see include/adef2.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/adef2.h"
+#include "dev_setup.h"
+
+using namespace adef2;
+
+namespace {
+
+std::string g_create_error;
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int round8(int k) { return (k + 7) & ~7; }
+
+enum KernelId { KI_INIT = 0, KI_INIT2, KI_PUPDATE, KI_SPMV, KI_UPDATE, KI_RESID, KI_ACCUM,
+                KI_GRAM, KI_COARSE, KI_COMPACT, KI_COUNT };
+const char* kKernelNames[KI_COUNT] = {"init", "init2", "pupdate", "spmv", "update", "resid64",
+                                      "accumulate", "spmm_gram", "coarse", "compact"};
+
+}  // namespace
+
+struct adef2_ctx {
+  adef2_opts o{};
+  hipStream_t st = nullptr;
+  int dev = 0;
+  std::string err;
+
+  // reference operator and modes
+  bool have_ref = false;
+  int64_t N = 0;
+  int D = 0, H = 0, k = 0, KP = 0;
+  std::vector<int> offs;
+  double* dia64 = nullptr;
+  float* dia32 = nullptr;
+  double* diag = nullptr;
+  double* Z64 = nullptr;
+  float* Z32 = nullptr;
+  double scale_a = 1.0, scale_c = 0.0;
+
+  // restriction / batch state
+  bool restricted = false;
+  int B = 0, Bcap = 0, prec = ADEF2_FP64;
+  int64_t vs = 0;
+  uint8_t* masks = nullptr;
+  int* I = nullptr;
+  int* g2l = nullptr;
+  int* ccount = nullptr;
+  int* cofs = nullptr;
+  long long* ntot = nullptr;
+  Inst* inst = nullptr;
+  Inst* inst_h = nullptr;        // pinned mirror
+  double* C = nullptr;
+  double* Finfo = nullptr;
+  int* kept = nullptr;
+  double* gram = nullptr;
+  double* v64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  float* v32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* W64 = nullptr;
+  float* W32 = nullptr;
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  double* x64 = nullptr;         // padded (refinement mode)
+  double* r64 = nullptr;         // unpadded [B][N]
+  double* x0pad = nullptr;       // padded warm start
+  double* part = nullptr;
+  unsigned* ctr = nullptr;
+  size_t part_elems = 0, ctr_elems = 0;
+  std::vector<size_t> bytes;     // allocation sizes (for growth)
+
+  // geometry of the streaming kernels
+  int rpt = 2;
+  int ntiles = 0, ntiles_pad = 0;
+  RedGeom g_iter{};
+  int gram_blocks = 0;
+  RedGeom g_gram{};
+
+  // profiling
+  struct Ev { int id; hipEvent_t a, b; double bytes; };
+  std::vector<Ev> ev_pending;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t st_launch[KI_COUNT] = {};
+  double st_ms[KI_COUNT] = {};
+  double st_bytes[KI_COUNT] = {};
+  std::vector<long long> nI_host;
+};
+
+namespace {
+
+int fail(adef2_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, ADEF2_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+int dalloc(adef2_ctx* c, T** p, size_t count) {
+  if (*p) { hipFree(*p); *p = nullptr; }
+  if (count == 0) return ADEF2_OK;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, ADEF2_E_NOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                                      " bytes failed: " + hipGetErrorString(e));
+  }
+  return ADEF2_OK;
+}
+
+RedGeom make_geom(int nleaf) {
+  RedGeom g{};
+  int n = nleaf, l = 0, p = 0, c = 0;
+  g.n[0] = n;
+  g.pofs[0] = 0;
+  g.cofs[0] = 0;
+  p += n;
+  while (n > 1) {
+    n = (int)cdiv(n, RED_FAN);
+    ++l;
+    g.n[l] = n;
+    g.pofs[l] = p;
+    g.cofs[l] = c;
+    p += n;
+    c += n;
+  }
+  g.nlev = l + 1;
+  g.ptotal = p;
+  g.ctotal = c;
+  return g;
+}
+
+// padded vectors hold H zeros before and after each instance's N entries;
+// kernels receive the address of instance 0's first interior entry
+template <typename T>
+T* interior(const adef2_ctx* c, T* base) { return base ? base + c->H : nullptr; }
+
+OpGeom op_geom(const adef2_ctx* c) {
+  OpGeom g{};
+  g.N = c->N;
+  g.D = c->D;
+  g.ntiles = c->ntiles;
+  g.ntiles_pad = c->ntiles_pad;
+  for (int d = 0; d < c->D; ++d) g.offs[d] = c->offs[d];
+  return g;
+}
+
+void free_all(adef2_ctx* c) {
+  auto F = [](void* p) { if (p) hipFree(p); };
+  F(c->dia64); F(c->dia32); F(c->diag); F(c->Z64); F(c->Z32);
+  F(c->masks); F(c->I); F(c->g2l); F(c->ccount); F(c->cofs); F(c->ntot); F(c->inst);
+  F(c->C); F(c->Finfo); F(c->kept); F(c->gram);
+  for (int j = 0; j < 5; ++j) { F(c->v64[j]); F(c->v32[j]); }
+  F(c->W64); F(c->W32); F(c->dinv64); F(c->dinv32); F(c->x64); F(c->r64); F(c->x0pad);
+  F(c->part); F(c->ctr);
+  if (c->inst_h) hipHostFree(c->inst_h);
+  for (auto& e : c->ev_pending) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
+  for (auto e : c->ev_pool) hipEventDestroy(e);
+}
+
+// ---------------------------------------------------------------- profiling
+hipEvent_t ev_get(adef2_ctx* c) {
+  if (!c->ev_pool.empty()) { hipEvent_t e = c->ev_pool.back(); c->ev_pool.pop_back(); return e; }
+  hipEvent_t e;
+  hipEventCreate(&e);
+  return e;
+}
+
+void ev_harvest(adef2_ctx* c) {
+  for (auto& e : c->ev_pending) {
+    float ms = 0.f;
+    hipEventSynchronize(e.b);
+    hipEventElapsedTime(&ms, e.a, e.b);
+    c->st_launch[e.id] += 1;
+    c->st_ms[e.id] += ms;
+    c->st_bytes[e.id] += e.bytes;
+    c->ev_pool.push_back(e.a);
+    c->ev_pool.push_back(e.b);
+  }
+  c->ev_pending.clear();
+}
+
+template <typename F>
+void timed(adef2_ctx* c, int id, double bytes, F&& launch) {
+  if (!c->o.profile) { launch(); return; }
+  hipEvent_t a = ev_get(c), b = ev_get(c);
+  hipEventRecord(a, c->st);
+  launch();
+  hipEventRecord(b, c->st);
+  c->ev_pending.push_back({id, a, b, bytes});
+  if (c->ev_pending.size() >= 2048) ev_harvest(c);
+}
+
+// ------------------------------------------------------------ kernel tables
+template <typename V>
+struct KTab {
+  void (*init)(IterArgs<V>);
+  void (*init2)(IterArgs<V>);
+  void (*pupdate)(IterArgs<V>);
+  void (*spmv)(IterArgs<V>);
+  void (*update)(IterArgs<V>);
+};
+
+template <typename V, int KP, int RPT>
+KTab<V> make_tab() {
+  return {k_init<V, KP, RPT>, k_init2<V, KP, RPT>, k_pupdate<V, KP, RPT>, k_spmv<V, KP, RPT>,
+          k_update<V, KP, RPT>};
+}
+
+template <typename V, int RPT>
+KTab<V> pick_kp(int KP) {
+  switch (KP) {
+    case 0: return make_tab<V, 0, RPT>();
+    case 8: return make_tab<V, 8, RPT>();
+    case 16: return make_tab<V, 16, RPT>();
+    case 24: return make_tab<V, 24, RPT>();
+    case 32: return make_tab<V, 32, RPT>();
+    case 40: return make_tab<V, 40, RPT>();
+    case 48: return make_tab<V, 48, RPT>();
+    case 56: return make_tab<V, 56, RPT>();
+    default: return make_tab<V, 64, RPT>();
+  }
+}
+
+template <typename V>
+KTab<V> pick(int KP, int rpt) {
+  if (rpt == 1) return pick_kp<V, 1>(KP);
+  if (rpt == 4) return pick_kp<V, 4>(KP);
+  return pick_kp<V, 2>(KP);
+}
+
+template <int RPT>
+void (*pick_resid(void))(ResidArgs) { return k_resid64<RPT>; }
+
+void (*resid_fn(int rpt))(ResidArgs) {
+  if (rpt == 1) return k_resid64<1>;
+  if (rpt == 4) return k_resid64<4>;
+  return k_resid64<2>;
+}
+void (*accum_fn(int rpt))(OpGeom, const uint8_t*, const float*, double*, int64_t, Inst*) {
+  if (rpt == 1) return k_accumulate<1>;
+  if (rpt == 4) return k_accumulate<4>;
+  return k_accumulate<2>;
+}
+
+template <typename V>
+void launch_gram(adef2_ctx* c, const V* dummy_tag, V* W) {
+  (void)dummy_tag;
+  OpGeom og = op_geom(c);
+  dim3 grid(c->gram_blocks, c->B);
+  int nsub = 0;
+#define GRAM_CASE(KPV)                                                                       \
+  case KPV:                                                                                  \
+    nsub = (int)cdiv(c->N, GramCfg<KPV>::GR);                                                \
+    hipLaunchKernelGGL((k_spmm_gram<V, KPV>), grid, dim3(TPB), 0, c->st, og, c->dia64, c->Z64, \
+                       c->masks, W, c->inst, c->part, c->ctr, c->g_gram, c->gram, nsub);      \
+    break;
+  switch (c->KP) {
+    GRAM_CASE(8) GRAM_CASE(16) GRAM_CASE(24) GRAM_CASE(32) GRAM_CASE(40) GRAM_CASE(48)
+    GRAM_CASE(56) GRAM_CASE(64)
+    default: break;
+  }
+#undef GRAM_CASE
+}
+
+void launch_coarse(adef2_ctx* c) {
+  CoarseArgs ca{};
+  ca.gram = c->gram;
+  ca.C = c->C;
+  ca.Finfo = c->Finfo;
+  ca.kept = c->kept;
+  ca.inst = c->inst;
+  ca.k = c->k;
+  ca.drop_rel = c->o.drop_rel;
+  ca.tau_cond = c->o.tau_cond;
+#define COARSE_CASE(KPV) \
+  case KPV: hipLaunchKernelGGL((k_coarse<KPV>), dim3(c->B), dim3(TPB), 0, c->st, ca); break;
+  switch (c->KP) {
+    COARSE_CASE(8) COARSE_CASE(16) COARSE_CASE(24) COARSE_CASE(32) COARSE_CASE(40)
+    COARSE_CASE(48) COARSE_CASE(56) COARSE_CASE(64)
+    default: break;
+  }
+#undef COARSE_CASE
+}
+
+// -------------------------------------------------------- buffer management
+int ensure_batch(adef2_ctx* c, int B, int prec) {
+  const int64_t N = c->N;
+  const int KP = c->KP;
+  c->rpt = (c->o.rows_per_thread == 1 || c->o.rows_per_thread == 4) ? c->o.rows_per_thread : 2;
+  c->ntiles = (int)cdiv(N, (int64_t)TPB * c->rpt);
+  c->ntiles_pad = (int)cdiv(c->ntiles, 8) * 8;
+  c->g_iter = make_geom(c->ntiles_pad);
+  const int64_t nsub_max = cdiv(N, 32);
+  int gb = (int)std::max<int64_t>(8, std::min<int64_t>(256, 2048 / std::max(B, 1)));
+  gb = (int)std::min<int64_t>(gb, nsub_max);
+  c->gram_blocks = std::max(gb, 1);
+  c->g_gram = make_geom(c->gram_blocks);
+  const bool same = (B <= c->Bcap) && (prec == c->prec) && c->vs == N + 2 * c->H;
+  c->B = B;
+  if (same) return ADEF2_OK;
+  int rc;
+  c->Bcap = B;
+  c->prec = prec;
+  c->vs = N + 2 * c->H;
+  const size_t BN = (size_t)B * N;
+  const size_t BV = (size_t)B * c->vs;
+  const int nchunks = (int)cdiv(N, CMP_CHUNK);
+  if ((rc = dalloc(c, &c->masks, BN))) return rc;
+  if ((rc = dalloc(c, &c->I, BN))) return rc;
+  if ((rc = dalloc(c, &c->g2l, BN))) return rc;
+  if ((rc = dalloc(c, &c->ccount, (size_t)B * nchunks))) return rc;
+  if ((rc = dalloc(c, &c->cofs, (size_t)B * nchunks))) return rc;
+  if ((rc = dalloc(c, &c->ntot, (size_t)B))) return rc;
+  if ((rc = dalloc(c, &c->inst, (size_t)B))) return rc;
+  if (c->inst_h) hipHostFree(c->inst_h);
+  c->inst_h = nullptr;
+  HIPCHK(c, hipHostMalloc((void**)&c->inst_h, sizeof(Inst) * B));
+  const size_t kk = (size_t)std::max(KP, 1) * std::max(KP, 1);
+  if ((rc = dalloc(c, &c->C, (size_t)B * kk))) return rc;
+  if ((rc = dalloc(c, &c->Finfo, (size_t)B * kk))) return rc;
+  if ((rc = dalloc(c, &c->kept, (size_t)B * std::max(KP, 1)))) return rc;
+  if ((rc = dalloc(c, &c->gram, (size_t)B * 2 * kk))) return rc;
+  for (int j = 0; j < 5; ++j) {
+    if ((rc = dalloc(c, &c->v64[j], prec == ADEF2_FP64 ? BV : 0))) return rc;
+    if ((rc = dalloc(c, &c->v32[j], prec == ADEF2_FP64 ? 0 : BV))) return rc;
+  }
+  if ((rc = dalloc(c, &c->W64, prec == ADEF2_FP64 ? BN * KP : 0))) return rc;
+  if ((rc = dalloc(c, &c->W32, prec == ADEF2_FP64 ? 0 : BN * KP))) return rc;
+  if ((rc = dalloc(c, &c->dinv64, prec == ADEF2_FP64 ? BN : 0))) return rc;
+  if ((rc = dalloc(c, &c->dinv32, prec == ADEF2_FP64 ? 0 : BN))) return rc;
+  if ((rc = dalloc(c, &c->x64, prec == ADEF2_FP64 ? 0 : BV))) return rc;
+  if ((rc = dalloc(c, &c->r64, prec == ADEF2_FP64 ? 0 : BN))) return rc;
+  if ((rc = dalloc(c, &c->x0pad, BV))) return rc;
+  // reduction scratch: enough for the iteration kernels (NV <= KP+2) and the
+  // Gram kernel (NV = 2 KP^2); geometry is recomputed per call from B
+  const size_t pi = (size_t)make_geom((int)cdiv(cdiv(N, TPB), 8) * 8).ptotal * (KP + 2);
+  const size_t pg = (size_t)make_geom(256).ptotal * 2 * kk;
+  c->part_elems = (size_t)B * std::max(pi, pg);
+  c->ctr_elems = (size_t)B * std::max(make_geom((int)cdiv(cdiv(N, TPB), 8) * 8).ctotal,
+                                      make_geom(256).ctotal) + 16;
+  if ((rc = dalloc(c, &c->part, c->part_elems))) return rc;
+  if ((rc = dalloc(c, &c->ctr, c->ctr_elems))) return rc;
+  HIPCHK(c, hipMemsetAsync(c->ctr, 0, c->ctr_elems * sizeof(unsigned), c->st));
+  return ADEF2_OK;
+}
+
+template <typename V>
+void fill(adef2_ctx* c, V* p, size_t n, V v) {
+  if (!p || n == 0) return;
+  int blocks = (int)std::min<int64_t>(cdiv((int64_t)n, 256), 8192);
+  hipLaunchKernelGGL((k_fill<V>), dim3(blocks), dim3(256), 0, c->st, p, (int64_t)n, v);
+}
+
+// restrict B instances whose masks are already in c->masks; a, c per instance
+int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
+  const int B = c->B;
+  const int64_t N = c->N;
+  const int nchunks = (int)cdiv(N, CMP_CHUNK);
+  // instance state
+  for (int m = 0; m < B; ++m) {
+    Inst& s = c->inst_h[m];
+    std::memset(&s, 0, sizeof(Inst));
+    s.a = a_h ? a_h[m] : c->scale_a;
+    s.c = c_h ? c_h[m] : c->scale_c;
+    s.cond = 1.0;
+    if (!(s.a > 0.0) || !std::isfinite(s.c)) return fail(c, ADEF2_E_ARG, "operator scale a must be > 0");
+  }
+  HIPCHK(c, hipMemcpyAsync(c->inst, c->inst_h, sizeof(Inst) * B, hipMemcpyHostToDevice, c->st));
+  // compaction
+  timed(c, KI_COMPACT, (double)B * (2.0 * N + 8.0 * N), [&] {
+    hipLaunchKernelGGL(k_compact_count, dim3(nchunks, B), dim3(TPB), 0, c->st, N, c->masks,
+                       c->ccount, nchunks);
+    hipLaunchKernelGGL(k_compact_scan, dim3(B), dim3(TPB), 0, c->st, c->ccount, c->cofs, nchunks,
+                       c->ntot, c->inst);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nchunks, B), dim3(TPB), 0, c->st, N, c->masks,
+                       c->cofs, nchunks, c->I, c->g2l);
+  });
+  // preconditioner and zeroed vectors
+  dim3 g1((unsigned)cdiv(N, 256), B);
+  const size_t BV = (size_t)B * c->vs;
+  if (c->prec == ADEF2_FP64) {
+    hipLaunchKernelGGL((k_dinv<double>), g1, dim3(256), 0, c->st, N, c->diag, c->masks, c->dinv64,
+                       c->inst, c->o.precond == ADEF2_NONE);
+    for (int j = 0; j < 5; ++j) fill<double>(c, c->v64[j], BV, 0.0);
+  } else {
+    hipLaunchKernelGGL((k_dinv<float>), g1, dim3(256), 0, c->st, N, c->diag, c->masks, c->dinv32,
+                       c->inst, c->o.precond == ADEF2_NONE);
+    for (int j = 0; j < 5; ++j) fill<float>(c, c->v32[j], BV, 0.0f);
+    fill<double>(c, c->x64, BV, 0.0);
+  }
+  fill<double>(c, c->x0pad, BV, 0.0);
+  // coarse space
+  if (c->KP > 0) {
+    const double wbytes = (c->prec == ADEF2_FP64 ? 8.0 : 4.0);
+    timed(c, KI_GRAM, (double)B * N * (c->D * 8.0 + c->KP * (8.0 + wbytes) + 1.0), [&] {
+      if (c->prec == ADEF2_FP64) launch_gram<double>(c, nullptr, c->W64);
+      else launch_gram<float>(c, nullptr, c->W32);
+    });
+    timed(c, KI_COARSE, 0.0, [&] { launch_coarse(c); });
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(c->inst_h, c->inst, sizeof(Inst) * B, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->restricted = true;
+  c->nI_host.assign(B, 0);
+  int worst = ADEF2_OK;
+  for (int m = 0; m < B; ++m) {
+    c->nI_host[m] = c->inst_h[m].n_inactive;
+    const int s = c->inst_h[m].setup_status;
+    if (s < 0) worst = std::min(worst, s);
+    else if (worst >= 0) worst = std::max(worst, s);
+  }
+  if (worst == ADEF2_E_NOT_SPD) {
+    c->restricted = false;
+    return fail(c, ADEF2_E_NOT_SPD, "restricted operator has a non-positive diagonal entry");
+  }
+  return worst;
+}
+
+template <typename V>
+IterArgs<V> iter_args(adef2_ctx* c) {
+  IterArgs<V> a{};
+  a.op = op_geom(c);
+  a.mask = c->masks;
+  a.inst = c->inst;
+  a.C = c->C;
+  a.part = c->part;
+  a.ctr = c->ctr;
+  a.g = c->g_iter;
+  a.maxit = c->o.maxit;
+  a.vs = c->vs;
+  if constexpr (sizeof(V) == 8) {
+    a.dia = (const V*)c->dia64;
+    a.dinv = (const V*)c->dinv64;
+    a.Z = (const V*)c->Z64;
+    a.W = (const V*)c->W64;
+    a.x = (V*)interior(c, c->v64[0]); a.r = (V*)interior(c, c->v64[1]);
+    a.z = (V*)interior(c, c->v64[2]); a.p = (V*)interior(c, c->v64[3]);
+    a.w = (V*)interior(c, c->v64[4]);
+  } else {
+    a.dia = (const V*)c->dia32;
+    a.dinv = (const V*)c->dinv32;
+    a.Z = (const V*)c->Z32;
+    a.W = (const V*)c->W32;
+    a.x = (V*)interior(c, c->v32[0]); a.r = (V*)interior(c, c->v32[1]);
+    a.z = (V*)interior(c, c->v32[2]); a.p = (V*)interior(c, c->v32[3]);
+    a.w = (V*)interior(c, c->v32[4]);
+  }
+  return a;
+}
+
+// algorithmic bytes per launch (per instance: inactive rows only)
+struct ByteModel { double init, init2, pupdate, spmv, update, resid, accum; };
+ByteModel byte_model(const adef2_ctx* c, int prec) {
+  const double w = (prec == ADEF2_FP64) ? 8.0 : 4.0;
+  const double k = c->KP > 0 ? (double)c->k : 0.0;
+  double nI = 0.0;
+  for (auto v : c->nI_host) nI += (double)v;
+  const double N = (double)c->N * c->B;
+  ByteModel b{};
+  b.init = nI * (8.0 + k * w + 2 * w) + N;
+  b.init2 = nI * (2 * k * w + 6 * w) + N;
+  b.pupdate = nI * (k * w + 3 * w) + N;            // z, Z (k), p -> p
+  b.spmv = nI * (c->D * w + 2 * w) + N;             // D diagonals, p, w
+  b.update = nI * (k * w + 8 * w) + N;              // W (k), x p r w dinv -> x r z
+  b.resid = nI * (c->D * 8.0 + 8.0 * 3) + N;
+  b.accum = nI * (4.0 + 16.0) + N;
+  return b;
+}
+
+int poll(adef2_ctx* c, bool outer, bool* all_done) {
+  HIPCHK(c, hipMemcpyAsync(c->inst_h, c->inst, sizeof(Inst) * c->B, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  bool ad = true;
+  for (int m = 0; m < c->B; ++m) {
+    const Inst& s = c->inst_h[m];
+    if (outer ? !s.outer_done : !(s.done || s.outer_done)) { ad = false; break; }
+  }
+  *all_done = ad;
+  return ADEF2_OK;
+}
+
+// run one A-DEF2 sweep in precision V for all instances: init, init2, then
+// chunks of iterations until every instance's sweep is done
+template <typename V>
+int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale) {
+  IterArgs<V> a = iter_args<V>(c);
+  a.src = src;
+  a.x0 = x0pad;
+  a.x0s = c->vs;
+  a.thresh_scale = thresh_scale;
+  KTab<V> kt = pick<V>(c->KP, c->rpt);
+  dim3 grid(c->ntiles_pad, c->B), blk(TPB);
+  const ByteModel bm = byte_model(c, sizeof(V) == 8 ? ADEF2_FP64 : ADEF2_FP32_REFINE);
+  timed(c, KI_INIT, bm.init, [&] { hipLaunchKernelGGL(kt.init, grid, blk, 0, c->st, a); });
+  timed(c, KI_INIT2, bm.init2, [&] { hipLaunchKernelGGL(kt.init2, grid, blk, 0, c->st, a); });
+  HIPCHK(c, hipGetLastError());
+  const int chunk = std::max(1, c->o.check_every);
+  int64_t launched = 0;
+  for (;;) {
+    bool ad = false;
+    int rc = poll(c, false, &ad);
+    if (rc) return rc;
+    if (ad) break;
+    // every instance stops at maxit on the device; this guards the host loop
+    if (launched > (int64_t)c->o.maxit + 2 * chunk)
+      return fail(c, ADEF2_E_HIP, "iteration kernels made no progress");
+    launched += chunk;
+    for (int it = 0; it < chunk; ++it) {
+      timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, c->st, a); });
+      timed(c, KI_SPMV, bm.spmv, [&] { hipLaunchKernelGGL(kt.spmv, grid, blk, 0, c->st, a); });
+      timed(c, KI_UPDATE, bm.update, [&] { hipLaunchKernelGGL(kt.update, grid, blk, 0, c->st, a); });
+    }
+    HIPCHK(c, hipGetLastError());
+  }
+  return ADEF2_OK;
+}
+
+int resid64(adef2_ctx* c, const double* b, const double* xpad, int first, int decide, double tol,
+            bool store) {
+  ResidArgs ra{};
+  ra.op = op_geom(c);
+  ra.dia = c->dia64;
+  ra.mask = c->masks;
+  ra.b = b;
+  ra.x = xpad;
+  ra.vs = c->vs;
+  ra.r64 = store ? c->r64 : nullptr;
+  ra.inst = c->inst;
+  ra.part = c->part;
+  ra.ctr = c->ctr;
+  ra.g = c->g_iter;
+  ra.first = first;
+  ra.decide = decide;
+  ra.tol2 = tol * tol;
+  ra.maxit = c->o.maxit;
+  ra.max_sweeps = c->o.max_sweeps;
+  const ByteModel bm = byte_model(c, ADEF2_FP64);
+  timed(c, KI_RESID, bm.resid, [&] {
+    hipLaunchKernelGGL(resid_fn(c->rpt), dim3(c->ntiles_pad, c->B), dim3(TPB), 0, c->st, ra);
+  });
+  HIPCHK(c, hipGetLastError());
+  return ADEF2_OK;
+}
+
+// Solve all B restricted instances; b, x instance-major unpadded [B][N].
+int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, double* x) {
+  const int B = c->B;
+  const int64_t N = c->N;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(c, ADEF2_E_ARG, "tol must be positive");
+  // reset per-solve state (keep restriction results)
+  for (int m = 0; m < B; ++m) {
+    Inst& s = c->inst_h[m];
+    s.iters = 0; s.sweep_iters = 0; s.done = 0; s.outer_done = 0; s.status = 0; s.sweeps = 0;
+    s.rr = 0; s.rr64 = 0; s.bb64 = 0;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->inst, c->inst_h, sizeof(Inst) * B, hipMemcpyHostToDevice, c->st));
+  dim3 gc((unsigned)cdiv(N, 256), B);
+  const double* x0p = nullptr;
+  if (x0) {
+    // warm start restricted to the inactive set (zero on active rows)
+    hipLaunchKernelGGL(k_mask_copy_padded, gc, dim3(256), 0, c->st, N, c->masks, x0,
+                       interior(c, c->x0pad), c->vs);
+    x0p = interior(c, c->x0pad);
+  }
+  int rc;
+  double* xres = nullptr;
+  if (c->prec == ADEF2_FP64) {
+    if ((rc = run_sweep<double>(c, b, x0p, tol * tol))) return rc;
+    xres = interior(c, c->v64[0]);
+    if ((rc = resid64(c, b, xres, 1, 0, tol, false))) return rc;
+  } else {
+    if (x0p) {
+      HIPCHK(c, hipMemcpyAsync(c->x64, c->x0pad, sizeof(double) * (size_t)B * c->vs,
+                               hipMemcpyDeviceToDevice, c->st));
+    } else {
+      fill<double>(c, c->x64, (size_t)B * c->vs, 0.0);
+    }
+    if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, tol, true))) return rc;
+    const double in2 = c->o.inner_rtol * c->o.inner_rtol;
+    const ByteModel bm = byte_model(c, ADEF2_FP32_REFINE);
+    for (int sweep = 0;; ++sweep) {
+      bool ad = false;
+      if ((rc = poll(c, true, &ad))) return rc;
+      if (ad) break;
+      if (sweep > c->o.max_sweeps + 1) return fail(c, ADEF2_E_HIP, "refinement made no progress");
+      if ((rc = run_sweep<float>(c, c->r64, nullptr, in2))) return rc;
+      timed(c, KI_ACCUM, bm.accum, [&] {
+        hipLaunchKernelGGL(accum_fn(c->rpt), dim3(c->ntiles_pad, B), dim3(TPB), 0, c->st,
+                           op_geom(c), c->masks, interior(c, c->v32[0]), interior(c, c->x64),
+                           c->vs, c->inst);
+      });
+      if ((rc = resid64(c, b, interior(c, c->x64), 0, 1, tol, true))) return rc;
+    }
+    xres = interior(c, c->x64);
+  }
+  hipLaunchKernelGGL(k_scatter_out, gc, dim3(256), 0, c->st, N, c->masks, xres, c->vs, x, c->inst);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(c->inst_h, c->inst, sizeof(Inst) * B, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (c->o.profile) ev_harvest(c);
+  return ADEF2_OK;
+}
+
+int combine_status(const Inst& s) {
+  if (s.status < 0) return s.status;
+  if (s.setup_status < 0) return s.setup_status;
+  return std::max(s.status, s.setup_status);
+}
+
+int worst_of(int a, int b) {
+  if (a < 0 || b < 0) return std::min(a, b);
+  return std::max(a, b);
+}
+
+bool valid_opts(const adef2_opts* o) {
+  return o->maxit > 0 && (o->precision == ADEF2_FP64 || o->precision == ADEF2_FP32_REFINE) &&
+         (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
+         o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0;
+}
+
+}  // namespace
+
+// =========================================================================
+// C ABI
+// =========================================================================
+extern "C" {
+
+void adef2_default_opts(adef2_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tau_cond = 1e10;
+  o->drop_rel = 1e-6;
+  o->maxit = 100000;
+  o->precision = ADEF2_FP64;
+  o->precond = ADEF2_JACOBI;
+  o->inner_rtol = 1e-4;
+  o->max_sweeps = 30;
+  o->check_every = 32;
+  o->rows_per_thread = 0;
+  o->profile = 0;
+}
+
+int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
+  if (!out) { g_create_error = "null context pointer"; return ADEF2_E_ARG; }
+  *out = nullptr;
+  adef2_opts o;
+  adef2_default_opts(&o);
+  if (opts) o = *opts;
+  if (!valid_opts(&o)) { g_create_error = "invalid options"; return ADEF2_E_ARG; }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { g_create_error = "no HIP device"; return ADEF2_E_HIP; }
+  adef2_ctx* c = new adef2_ctx();
+  c->o = o;
+  c->st = (hipStream_t)stream;
+  c->dev = dev;
+  *out = c;
+  return ADEF2_OK;
+}
+
+int adef2_destroy(adef2_ctx* c) {
+  if (!c) return ADEF2_E_ARG;
+  hipStreamSynchronize(c->st);
+  free_all(c);
+  delete c;
+  return ADEF2_OK;
+}
+
+int adef2_set_opts(adef2_ctx* c, const adef2_opts* o) {
+  if (!c || !o) return ADEF2_E_ARG;
+  if (!valid_opts(o)) return fail(c, ADEF2_E_ARG, "invalid options");
+  const bool prec_changed = o->precision != c->o.precision;
+  const bool rpt_changed = o->rows_per_thread != c->o.rows_per_thread;
+  const bool precond_changed = o->precond != c->o.precond;
+  const bool coarse_changed = o->tau_cond != c->o.tau_cond || o->drop_rel != c->o.drop_rel;
+  c->o = *o;
+  if (prec_changed || rpt_changed || precond_changed || coarse_changed) c->restricted = false;
+  return ADEF2_OK;
+}
+
+int adef2_set_reference(adef2_ctx* c, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                        const double* vals, int64_t nnz, int32_t k, const double* Z) {
+  if (!c) return ADEF2_E_ARG;
+  if (n <= 0 || n > (int64_t)1 << 30 || !row_ptr || !col_idx || !vals || nnz <= 0)
+    return fail(c, ADEF2_E_ARG, "invalid operator arguments");
+  if (k < 0 || k > ADEF2_MAX_K || (k > 0 && !Z)) return fail(c, ADEF2_E_ARG, "invalid k or Z");
+  c->have_ref = false;
+  c->restricted = false;
+  c->Bcap = 0;
+  // distinct diagonal offsets
+  const size_t nf = (size_t)(2 * n - 1);
+  uint8_t* flags = nullptr;
+  int* bad = nullptr;
+  int rc;
+  if ((rc = dalloc(c, &flags, nf))) return rc;
+  if ((rc = dalloc(c, &bad, 1))) { hipFree(flags); return rc; }
+  int* Iofs = nullptr;
+  int* cnt = nullptr;
+  int* ofs = nullptr;
+  long long* tot = nullptr;
+  const int nch = (int)cdiv((int64_t)nf, CMP_CHUNK);
+  auto cleanup = [&] { hipFree(flags); hipFree(bad); if (Iofs) hipFree(Iofs); if (cnt) hipFree(cnt);
+                       if (ofs) hipFree(ofs); if (tot) hipFree(tot); };
+  if ((rc = dalloc(c, &Iofs, nf)) || (rc = dalloc(c, &cnt, nch)) || (rc = dalloc(c, &ofs, nch)) ||
+      (rc = dalloc(c, &tot, 1))) { cleanup(); return rc; }
+  hipMemsetAsync(flags, 1, nf, c->st);
+  hipMemsetAsync(bad, 0, sizeof(int), c->st);
+  hipLaunchKernelGGL(k_mark_offsets, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->st, n, row_ptr,
+                     col_idx, flags, bad);
+  hipLaunchKernelGGL(k_compact_count, dim3(nch, 1), dim3(TPB), 0, c->st, (int64_t)nf, flags, cnt, nch);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(TPB), 0, c->st, cnt, ofs, nch, tot, (Inst*)nullptr);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nch, 1), dim3(TPB), 0, c->st, (int64_t)nf, flags, ofs,
+                     nch, Iofs, (int*)nullptr);
+  long long D = 0;
+  int badh = 0;
+  hipMemcpyAsync(&D, tot, sizeof(long long), hipMemcpyDeviceToHost, c->st);
+  hipMemcpyAsync(&badh, bad, sizeof(int), hipMemcpyDeviceToHost, c->st);
+  if (hipStreamSynchronize(c->st) != hipSuccess) { cleanup(); return fail(c, ADEF2_E_HIP, "sync failed"); }
+  if (badh) { cleanup(); return fail(c, ADEF2_E_ARG, "column index out of range"); }
+  if (D > ADEF2_MAX_DIAGS) {
+    cleanup();
+    return fail(c, ADEF2_E_UNSUPPORTED, "operator has " + std::to_string(D) +
+                                            " distinct diagonals (max " +
+                                            std::to_string(ADEF2_MAX_DIAGS) + ")");
+  }
+  std::vector<int> pos(D);
+  hipMemcpyAsync(pos.data(), Iofs, sizeof(int) * D, hipMemcpyDeviceToHost, c->st);
+  hipStreamSynchronize(c->st);
+  c->offs.resize(D);
+  int maxoff = 0;
+  bool has0 = false;
+  for (int d = 0; d < D; ++d) {
+    c->offs[d] = (int)(pos[d] - (n - 1));
+    maxoff = std::max(maxoff, std::abs(c->offs[d]));
+    has0 |= c->offs[d] == 0;
+  }
+  if (!has0) { cleanup(); return fail(c, ADEF2_E_NOT_SPD, "operator has no main diagonal"); }
+  c->N = n;
+  c->D = (int)D;
+  c->H = ((maxoff + 63) / 64) * 64;
+  c->k = k;
+  c->KP = round8(k);
+  if ((rc = dalloc(c, &c->dia64, (size_t)D * n)) || (rc = dalloc(c, &c->dia32, (size_t)D * n)) ||
+      (rc = dalloc(c, &c->diag, (size_t)n))) { cleanup(); return rc; }
+  hipMemsetAsync(c->dia64, 0, sizeof(double) * D * n, c->st);
+  hipMemsetAsync(c->dia32, 0, sizeof(float) * D * n, c->st);
+  OpGeom og{};
+  og.N = n;
+  og.D = (int)D;
+  for (int d = 0; d < D; ++d) og.offs[d] = c->offs[d];
+  hipMemsetAsync(bad, 0, sizeof(int), c->st);
+  hipLaunchKernelGGL(k_csr_to_dia, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->st, n, row_ptr,
+                     col_idx, vals, og, c->dia64, c->dia32, c->diag, bad);
+  if (c->KP > 0) {
+    if ((rc = dalloc(c, &c->Z64, (size_t)c->KP * n)) || (rc = dalloc(c, &c->Z32, (size_t)c->KP * n))) {
+      cleanup();
+      return rc;
+    }
+    hipLaunchKernelGGL(k_copy_modes, dim3((unsigned)cdiv(n, 256), c->KP), dim3(256), 0, c->st, n, k,
+                       c->KP, Z, c->Z64, c->Z32);
+  }
+  hipMemcpyAsync(&badh, bad, sizeof(int), hipMemcpyDeviceToHost, c->st);
+  hipError_t e = hipStreamSynchronize(c->st);
+  cleanup();
+  if (e != hipSuccess) return fail(c, ADEF2_E_HIP, std::string("set_reference: ") + hipGetErrorString(e));
+  if (badh == 2) return fail(c, ADEF2_E_ARG, "operator has non-finite values");
+  if (badh == 3) return fail(c, ADEF2_E_NOT_SPD, "operator has a non-positive diagonal entry");
+  if (badh) return fail(c, ADEF2_E_ARG, "inconsistent operator structure");
+  c->have_ref = true;
+  return ADEF2_OK;
+}
+
+int adef2_set_operator_scale(adef2_ctx* c, double a, double cc) {
+  if (!c) return ADEF2_E_ARG;
+  if (!(a > 0.0) || !std::isfinite(a) || !std::isfinite(cc)) return fail(c, ADEF2_E_ARG, "invalid scale");
+  c->scale_a = a;
+  c->scale_c = cc;
+  c->restricted = false;
+  return ADEF2_OK;
+}
+
+int adef2_compact(adef2_ctx* c, const uint8_t* mask, int64_t n, int32_t* I, int32_t* g2l,
+                  int64_t* n_inactive) {
+  if (!c || !mask || n < 0) return ADEF2_E_ARG;
+  if (n == 0) { if (n_inactive) *n_inactive = 0; return ADEF2_OK; }
+  const int nch = (int)cdiv(n, CMP_CHUNK);
+  int* cnt = nullptr;
+  int* ofs = nullptr;
+  long long* tot = nullptr;
+  int rc;
+  if ((rc = dalloc(c, &cnt, nch)) || (rc = dalloc(c, &ofs, nch)) || (rc = dalloc(c, &tot, 1))) {
+    if (cnt) hipFree(cnt);
+    if (ofs) hipFree(ofs);
+    return rc;
+  }
+  hipLaunchKernelGGL(k_compact_count, dim3(nch, 1), dim3(TPB), 0, c->st, n, mask, cnt, nch);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(TPB), 0, c->st, cnt, ofs, nch, tot, (Inst*)nullptr);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nch, 1), dim3(TPB), 0, c->st, n, mask, ofs, nch, I, g2l);
+  long long t = 0;
+  hipMemcpyAsync(&t, tot, sizeof(long long), hipMemcpyDeviceToHost, c->st);
+  hipError_t e = hipStreamSynchronize(c->st);
+  hipFree(cnt);
+  hipFree(ofs);
+  hipFree(tot);
+  if (e != hipSuccess) return fail(c, ADEF2_E_HIP, hipGetErrorString(e));
+  if (n_inactive) *n_inactive = t;
+  return ADEF2_OK;
+}
+
+int adef2_restrict(adef2_ctx* c, const uint8_t* mask, int64_t* n_inactive, int32_t* k_eff,
+                   double* cond_E) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_ref) return fail(c, ADEF2_E_STATE, "restrict before set_reference");
+  if (!mask) return fail(c, ADEF2_E_ARG, "null mask");
+  c->restricted = false;
+  int rc = ensure_batch(c, 1, c->o.precision);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->masks, mask, (size_t)c->N, hipMemcpyDeviceToDevice, c->st));
+  rc = restrict_batch(c, nullptr, nullptr);
+  if (rc < 0) return rc;
+  if (n_inactive) *n_inactive = c->inst_h[0].n_inactive;
+  if (k_eff) *k_eff = c->inst_h[0].k_eff;
+  if (cond_E) *cond_E = c->inst_h[0].cond;
+  return rc;
+}
+
+int adef2_solve(adef2_ctx* c, const double* b, const double* x0, double tol, double* x,
+                int32_t* iters, double* relres_true, double* cond_E) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->restricted || c->B != 1) return fail(c, ADEF2_E_STATE, "solve before restrict");
+  if (!b || !x) return fail(c, ADEF2_E_ARG, "null vector");
+  int rc = solve_batch(c, b, x0, tol, x);
+  if (rc) return rc;
+  const Inst& s = c->inst_h[0];
+  if (iters) *iters = s.iters;
+  if (relres_true) *relres_true = s.bb64 > 0 ? std::sqrt(s.rr64 / s.bb64) : 0.0;
+  if (cond_E) *cond_E = s.cond;
+  const int st = combine_status(s);
+  if (st == ADEF2_E_ARG) return fail(c, st, "non-finite right-hand side or residual");
+  if (st == ADEF2_E_NOT_SPD) return fail(c, st, "breakdown: p.Sp <= 0 (operator not SPD)");
+  return st;
+}
+
+int adef2_solve_batched(adef2_ctx* c, int32_t B, const uint8_t* masks, const double* b,
+                        const double* a, const double* cs, double tol, double* x, int32_t* iters,
+                        int32_t* status, double* relres_true, double* cond_E, int64_t* n_inactive) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_ref) return fail(c, ADEF2_E_STATE, "solve_batched before set_reference");
+  if (B <= 0 || !masks || !b || !x) return fail(c, ADEF2_E_ARG, "invalid batch arguments");
+  c->restricted = false;
+  int rc = ensure_batch(c, B, c->o.precision);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->masks, masks, (size_t)B * c->N, hipMemcpyDeviceToDevice, c->st));
+  rc = restrict_batch(c, a, cs);
+  if (rc < 0) return rc;
+  rc = solve_batch(c, b, nullptr, tol, x);
+  if (rc) return rc;
+  int worst = ADEF2_OK;
+  for (int m = 0; m < B; ++m) {
+    const Inst& s = c->inst_h[m];
+    const int st = combine_status(s);
+    worst = worst_of(worst, st);
+    if (iters) iters[m] = s.iters;
+    if (status) status[m] = st;
+    if (relres_true) relres_true[m] = s.bb64 > 0 ? std::sqrt(s.rr64 / s.bb64) : 0.0;
+    if (cond_E) cond_E[m] = s.cond;
+    if (n_inactive) n_inactive[m] = s.n_inactive;
+  }
+  return worst;
+}
+
+int adef2_apply_restricted(adef2_ctx* c, const double* x, double* y) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->restricted || c->B != 1) return fail(c, ADEF2_E_STATE, "apply before restrict");
+  if (!x || !y) return fail(c, ADEF2_E_ARG, "null vector");
+  const int64_t N = c->N;
+  double* tmp = nullptr;
+  int rc;
+  if ((rc = dalloc(c, &tmp, (size_t)c->vs))) return rc;
+  fill<double>(c, tmp, (size_t)c->vs, 0.0);
+  const dim3 g((unsigned)cdiv(N, 256), 1);
+  hipLaunchKernelGGL(k_mask_copy_padded, g, dim3(256), 0, c->st, N, c->masks, x, tmp + c->H, c->vs);
+  hipLaunchKernelGGL(k_apply64, g, dim3(256), 0, c->st, op_geom(c), c->dia64, c->masks, tmp + c->H,
+                     y, c->inst);
+  hipError_t e = hipStreamSynchronize(c->st);
+  hipFree(tmp);
+  if (e != hipSuccess) return fail(c, ADEF2_E_HIP, hipGetErrorString(e));
+  return ADEF2_OK;
+}
+
+int adef2_coarse_info(adef2_ctx* c, double* E, int32_t* kept, int32_t* k_eff, double* cond_E) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->restricted) return fail(c, ADEF2_E_STATE, "coarse_info before restrict");
+  const int KP = c->KP;
+  if (KP > 0 && E) {
+    std::vector<double> h((size_t)KP * KP);
+    HIPCHK(c, hipMemcpy(h.data(), c->Finfo, sizeof(double) * KP * KP, hipMemcpyDeviceToHost));
+    const int ke = c->inst_h[0].k_eff;
+    for (int j = 0; j < c->k; ++j)
+      for (int i = 0; i < c->k; ++i) E[(size_t)j * c->k + i] = (i < ke && j < ke) ? h[(size_t)j * KP + i] : 0.0;
+  }
+  if (KP > 0 && kept) {
+    std::vector<int> h(KP);
+    HIPCHK(c, hipMemcpy(h.data(), c->kept, sizeof(int) * KP, hipMemcpyDeviceToHost));
+    for (int j = 0; j < c->k; ++j) kept[j] = h[j];
+  }
+  if (k_eff) *k_eff = c->inst_h[0].k_eff;
+  if (cond_E) *cond_E = c->inst_h[0].cond;
+  return ADEF2_OK;
+}
+
+int adef2_get_stats(adef2_ctx* c, adef2_stats* s) {
+  if (!c || !s) return ADEF2_E_ARG;
+  ev_harvest(c);
+  std::memset(s, 0, sizeof(*s));
+  s->n_kernels = KI_COUNT;
+  for (int i = 0; i < KI_COUNT; ++i) {
+    s->name[i] = kKernelNames[i];
+    s->launches[i] = c->st_launch[i];
+    s->total_ms[i] = c->st_ms[i];
+    s->alg_bytes[i] = c->st_bytes[i];
+  }
+  return ADEF2_OK;
+}
+
+int adef2_reset_stats(adef2_ctx* c) {
+  if (!c) return ADEF2_E_ARG;
+  ev_harvest(c);
+  for (int i = 0; i < KI_COUNT; ++i) { c->st_launch[i] = 0; c->st_ms[i] = 0; c->st_bytes[i] = 0; }
+  return ADEF2_OK;
+}
+
+const char* adef2_last_error(const adef2_ctx* c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+}  // extern "C"

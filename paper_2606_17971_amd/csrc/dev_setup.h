@@ -1,0 +1,508 @@
+// Per-reference and per-restriction kernels: diagonal-format conversion,
+// inactive-set compaction, W = S_II Z_I with the Gram matrices Z_I^T Z_I and
+// Z_I^T W, and the one-workgroup k x k coarse setup.
+#pragma once
+#include "dev_kernels.h"
+
+namespace adef2 {
+
+// ---------------------------------------------------------------------------
+// compaction: I = { i : sel[i] == 0 } ascending, g2l, count   (exact)
+// Three passes: per-chunk counts, scan of the counts, per-chunk scatter.
+// ---------------------------------------------------------------------------
+constexpr int CMP_ITEMS = 16;                 // items per thread
+constexpr int CMP_CHUNK = TPB * CMP_ITEMS;    // items per block
+
+__global__ void __launch_bounds__(TPB) k_compact_count(int64_t n, const uint8_t* sel, int* counts,
+                                                       int nchunks) {
+  const int m = blockIdx.y;
+  const uint8_t* s = sel + (size_t)m * n;
+  const int64_t base = (int64_t)blockIdx.x * CMP_CHUNK + (int64_t)threadIdx.x * CMP_ITEMS;
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < CMP_ITEMS; ++j) {
+    const int64_t i = base + j;
+    if (i < n && s[i] == 0) ++c;
+  }
+  __shared__ int red[NWAVE];
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < NWAVE; ++w) t += red[w];
+    counts[(size_t)m * nchunks + blockIdx.x] = t;
+  }
+}
+
+// exclusive scan of counts (one block per instance); total -> totals[m]
+__global__ void __launch_bounds__(TPB) k_compact_scan(const int* counts, int* offsets, int nchunks,
+                                                      long long* totals, Inst* inst) {
+  const int m = blockIdx.x;
+  const int* c = counts + (size_t)m * nchunks;
+  int* o = offsets + (size_t)m * nchunks;
+  __shared__ int wsum[NWAVE];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int base = 0; base < nchunks; base += TPB) {
+    const int j = base + threadIdx.x;
+    const int v = j < nchunks ? c[j] : 0;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int before = carry;
+    for (int w = 0; w < wid; ++w) before += wsum[w];
+    if (j < nchunks) o[j] = before + incl - v;
+    __syncthreads();
+    if (threadIdx.x == TPB - 1) carry = before + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (totals) totals[m] = carry;
+    if (inst) inst[m].n_inactive = carry;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_compact_scatter(int64_t n, const uint8_t* sel,
+                                                         const int* offsets, int nchunks, int* I,
+                                                         int* g2l) {
+  const int m = blockIdx.y;
+  const uint8_t* s = sel + (size_t)m * n;
+  const int64_t base = (int64_t)blockIdx.x * CMP_CHUNK + (int64_t)threadIdx.x * CMP_ITEMS;
+  uint8_t f[CMP_ITEMS];
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < CMP_ITEMS; ++j) {
+    const int64_t i = base + j;
+    f[j] = (i < n) ? (s[i] == 0) : 0;
+    c += f[j];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int incl = c;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  __shared__ int wsum[NWAVE];
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int pos = offsets[(size_t)m * nchunks + blockIdx.x] + incl - c;
+  for (int w = 0; w < wid; ++w) pos += wsum[w];
+  int* Im = I ? I + (size_t)m * n : nullptr;
+  int* Gm = g2l ? g2l + (size_t)m * n : nullptr;
+#pragma unroll
+  for (int j = 0; j < CMP_ITEMS; ++j) {
+    const int64_t i = base + j;
+    if (i < n) {
+      if (f[j]) {
+        if (Im) Im[pos] = (int)i;
+        if (Gm) Gm[i] = pos;
+        ++pos;
+      } else if (Gm) {
+        Gm[i] = -1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CSR -> diagonal format
+// ---------------------------------------------------------------------------
+// flags[off + n - 1] = 0 for every diagonal offset present (flags preset to 1)
+__global__ void k_mark_offsets(int64_t n, const int64_t* rp, const int* col, uint8_t* flags,
+                               int* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+    const int64_t j = col[e];
+    if (j < 0 || j >= n) { *bad = 1; continue; }
+    flags[j - i + n - 1] = 0;
+  }
+}
+
+__global__ void k_csr_to_dia(int64_t n, const int64_t* rp, const int* col, const double* val,
+                             OpGeom op, double* dia64, float* dia32, double* diag, int* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double dg = 0.0;
+  for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+    const int off = (int)((int64_t)col[e] - i);
+    int lo = 0, hi = op.D - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (op.offs[mid] < off) lo = mid + 1; else hi = mid;
+    }
+    if (op.offs[lo] != off) { *bad = 1; continue; }
+    const double v = val[e];
+    if (!(v == v) || v == INFINITY || v == -INFINITY) *bad = 2;
+    dia64[(size_t)lo * n + i] = v;
+    dia32[(size_t)lo * n + i] = (float)v;
+    if (off == 0) dg = v;
+  }
+  diag[i] = dg;
+  if (!(dg > 0.0)) *bad = 3;
+}
+
+// Z (column-major n x k, FP64) -> Z64 / Z32 (column-major n x KP, zero padded)
+__global__ void k_copy_modes(int64_t n, int k, int KP, const double* Z, double* Z64, float* Z32) {
+  const int q = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = (q < k) ? Z[(size_t)q * n + i] : 0.0;
+  if (!(v == v)) return;
+  Z64[(size_t)q * n + i] = v;
+  Z32[(size_t)q * n + i] = (float)v;
+}
+
+// ---------------------------------------------------------------------------
+// W = S_II Z_I (stored as V), and per instance the Gram matrices
+//   G = Z_I^T Z_I,  E = Z_I^T W   (FP64, deterministic tree reduction)
+// Each block walks sub-tiles of GR rows; the Gram outputs are distributed over
+// the threads (OPT outputs each) and accumulated in registers.
+// ---------------------------------------------------------------------------
+template <int KP> struct GramCfg {
+  static constexpr int GR = KP > 32 ? 32 : 64;                 // rows per sub-tile
+  static constexpr int NOUT = 2 * KP * KP;
+  static constexpr int OPT = (NOUT + TPB - 1) / TPB;           // outputs per thread
+  static constexpr int CG = TPB / GR;                          // column groups
+  static constexpr int CPG = (KP + CG - 1) / CG;               // columns per group
+  static constexpr int LDS = (2 * GR * KP > NOUT ? 2 * GR * KP : NOUT);
+};
+
+template <typename V, int KP>
+__global__ void __launch_bounds__(TPB) k_spmm_gram(OpGeom op, const double* dia64, const double* Z64,
+                                                    const uint8_t* mask, V* W, Inst* inst,
+                                                    double* part, unsigned* ctr, RedGeom g,
+                                                    double* gram, int nsub) {
+  using C = GramCfg<KP>;
+  __shared__ double lds[C::LDS];
+  double* zt = lds;                 // [GR][KP]
+  double* wt = lds + C::GR * KP;    // [GR][KP]
+  const int m = blockIdx.y;
+  const Inst* S = inst + m;
+  const int64_t N = op.N;
+  const uint8_t* mk = mask + (size_t)m * N;
+  V* Wm = W + (size_t)m * KP * N;
+  const double sa = S->a, sc = S->c;
+  double acc[C::OPT];
+#pragma unroll
+  for (int o = 0; o < C::OPT; ++o) acc[o] = 0.0;
+  const int row = threadIdx.x % C::GR;
+  const int cg = threadIdx.x / C::GR;
+  for (int st = blockIdx.x; st < nsub; st += gridDim.x) {
+    const int64_t i = (int64_t)st * C::GR + row;
+    const bool act = (i >= N) || mk[i] != 0;
+#pragma unroll
+    for (int cc = 0; cc < C::CPG; ++cc) {
+      const int q = cg * C::CPG + cc;
+      if (q < KP) {
+        double wv = 0.0, zv = 0.0;
+        if (!act) {
+          const double* Zq = Z64 + (size_t)q * N;
+          double s = 0.0;
+          for (int d = 0; d < op.D; ++d) {
+            const int64_t j = i + op.offs[d];
+            if (j >= 0 && j < N && mk[j] == 0) s += dia64[(size_t)d * N + i] * Zq[j];
+          }
+          zv = Zq[i];
+          wv = sa * s + sc * zv;
+          Wm[(size_t)q * N + i] = (V)wv;
+        } else if (i < N) {
+          Wm[(size_t)q * N + i] = (V)0;
+        }
+        zt[row * KP + q] = zv;
+        wt[row * KP + q] = wv;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < C::OPT; ++o) {
+      const int idx = threadIdx.x + o * TPB;
+      if (idx < C::NOUT) {
+        const bool isE = idx >= KP * KP;
+        const int e = isE ? idx - KP * KP : idx;
+        const int jr = e / KP, jc = e % KP;
+        const double* rhs = isE ? wt : zt;
+        double s = 0.0;
+        for (int r2 = 0; r2 < C::GR; ++r2) s += zt[r2 * KP + jr] * rhs[r2 * KP + jc];
+        acc[o] += s;
+      }
+    }
+    __syncthreads();
+  }
+  // block partial: each output owned by exactly one thread
+#pragma unroll
+  for (int o = 0; o < C::OPT; ++o) {
+    const int idx = threadIdx.x + o * TPB;
+    if (idx < C::NOUT) lds[idx] = acc[o];
+  }
+  __syncthreads();
+  double* pm = part + (size_t)m * g.ptotal * C::NOUT;
+  unsigned* cm = ctr + (size_t)m * g.ctotal;
+  tree_reduce(g, blockIdx.x, C::NOUT, pm, cm, lds, gram + (size_t)m * C::NOUT);
+}
+
+// ---------------------------------------------------------------------------
+// One-workgroup coarse setup per instance (k x k, FP64, LDS):
+//   R = chol(G) with column dropping; T = R^{-1};  F = T^T E T (E of the
+//   orthonormal basis Z_I T); cond(F) by cyclic Jacobi; F = L L^T;
+//   C = T F^{-1} T^T (= E_raw^{-1} on the kept columns).
+// Fallback (kk = 0, C = 0) when cond(F) > tau_cond or Cholesky fails.
+// ---------------------------------------------------------------------------
+struct CoarseArgs {
+  const double* gram;    // [B][2][KP][KP]  (G, then E; row-major)
+  double* C;             // [B][KP][KP]
+  double* Finfo;         // [B][KP][KP] column-major, leading k' x k'
+  int* kept;             // [B][KP]
+  Inst* inst;
+  int k;                 // true number of modes (<= KP)
+  double drop_rel;
+  double tau_cond;
+};
+
+template <int KP>
+__global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
+  constexpr int K = KP > 0 ? KP : 1;
+  __shared__ double A0[K * K];   // G -> R, later tmp / Jacobi work / X
+  __shared__ double A1[K * K];   // T
+  __shared__ double A2[K * K];   // E -> F -> L
+  __shared__ int kidx[K];
+  __shared__ int s_keep, s_kp, s_fail;
+  __shared__ double s_d;
+  __shared__ double rc[K / 2 + 1], rs[K / 2 + 1];
+  __shared__ int rp_[K / 2 + 1], rq_[K / 2 + 1];
+  __shared__ double red[NWAVE];
+  __shared__ double gdiag[K];
+  const int m = blockIdx.x;
+  const int tid = threadIdx.x;
+  Inst* S = ca.inst + m;
+  const double* G = ca.gram + (size_t)m * 2 * KP * KP;
+  const double* E = G + KP * KP;
+  const int k = ca.k;
+  for (int e = tid; e < KP * KP; e += TPB) A0[e] = G[e];
+  for (int e = tid; e < KP; e += TPB) gdiag[e] = G[e * KP + e];
+  __syncthreads();
+
+  // --- Cholesky of G with column dropping (upper R, row j = R[j][:]) ---
+  int kp = 0;
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      const double d = A0[j * KP + j];
+      const double g0 = gdiag[j];
+      const double thr = ca.drop_rel * ca.drop_rel * g0;
+      s_keep = (g0 > 0.0) && (d > thr) && (d == d);
+      s_d = s_keep ? sqrt(d) : 0.0;
+      if (s_keep) kidx[kp] = j;
+    }
+    __syncthreads();
+    const bool keep = s_keep;
+    const double rjj = s_d;
+    if (keep) {
+      for (int l = j + 1 + tid; l < k; l += TPB) A0[j * KP + l] /= rjj;
+      if (tid == 0) A0[j * KP + j] = rjj;
+      __syncthreads();
+      const int rem = k - j - 1;
+      for (int e = tid; e < rem * rem; e += TPB) {
+        const int l = j + 1 + e / rem, mm = j + 1 + e % rem;
+        if (mm >= l) A0[l * KP + mm] -= A0[j * KP + l] * A0[j * KP + mm];
+      }
+      ++kp;
+    } else {
+      for (int l = tid; l < k; l += TPB) A0[j * KP + l] = 0.0;
+    }
+    __syncthreads();
+  }
+  // --- compact R to kept columns: Rc[a][b] = R[kidx[a]][kidx[b]] -> A1 temp ---
+  for (int e = tid; e < kp * kp; e += TPB) {
+    const int aa = e / kp, bb = e % kp;
+    A1[aa * KP + bb] = (bb >= aa) ? A0[kidx[aa] * KP + kidx[bb]] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < kp * kp; e += TPB) A0[(e / kp) * KP + e % kp] = A1[(e / kp) * KP + e % kp];
+  __syncthreads();
+  // --- T = R^{-1} (upper), one column per thread ---
+  for (int c = tid; c < kp; c += TPB) {
+    for (int i = 0; i < kp; ++i) A1[i * KP + c] = 0.0;
+    A1[c * KP + c] = 1.0 / A0[c * KP + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int mm = i + 1; mm <= c; ++mm) s += A0[i * KP + mm] * A1[mm * KP + c];
+      A1[i * KP + c] = -s / A0[i * KP + i];
+    }
+  }
+  // --- E on kept columns -> A2 ---
+  for (int e = tid; e < kp * kp; e += TPB) {
+    const int aa = e / kp, bb = e % kp;
+    A2[aa * KP + bb] = 0.5 * (E[kidx[aa] * KP + kidx[bb]] + E[kidx[bb] * KP + kidx[aa]]);
+  }
+  __syncthreads();
+  // --- tmp = E T (A0), F = T^T tmp (A2) ---
+  for (int e = tid; e < kp * kp; e += TPB) {
+    const int aa = e / kp, bb = e % kp;
+    double s = 0.0;
+    for (int mm = 0; mm <= bb; ++mm) s += A2[aa * KP + mm] * A1[mm * KP + bb];
+    A0[aa * KP + bb] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < kp * kp; e += TPB) {
+    const int aa = e / kp, bb = e % kp;
+    double s = 0.0;
+    for (int mm = 0; mm <= aa; ++mm) s += A1[mm * KP + aa] * A0[mm * KP + bb];
+    A2[aa * KP + bb] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < kp * kp; e += TPB) {      // symmetrise, export, Jacobi copy
+    const int aa = e / kp, bb = e % kp;
+    const double v = 0.5 * (A2[aa * KP + bb] + A2[bb * KP + aa]);
+    A0[aa * KP + bb] = v;
+    ca.Finfo[(size_t)m * KP * KP + bb * KP + aa] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < kp * kp; e += TPB) A2[(e / kp) * KP + e % kp] = A0[(e / kp) * KP + e % kp];
+  for (int j = tid; j < KP; j += TPB) {
+    int f = 0;
+    for (int a2 = 0; a2 < kp; ++a2) f |= (kidx[a2] == j);
+    ca.kept[(size_t)m * KP + j] = f;
+  }
+  __syncthreads();
+
+  // --- cyclic Jacobi eigenvalues of F (A0), parallel round-robin ordering ---
+  double cond = 1.0;
+  if (kp > 0) {
+    const int M = (kp + 1) & ~1;
+    const int npair = M / 2;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      // off-diagonal mass
+      double off = 0.0, dia = 0.0;
+      for (int e = tid; e < kp * kp; e += TPB) {
+        const int aa = e / kp, bb = e % kp;
+        const double v = A0[aa * KP + bb];
+        if (aa != bb) off += v * v; else dia += v * v;
+      }
+      off = wave_sum(off);
+      dia = wave_sum(dia);
+      if ((tid & 63) == 0) red[tid >> 6] = off;
+      __syncthreads();
+      double offt = 0.0;
+      for (int w = 0; w < NWAVE; ++w) offt += red[w];
+      __syncthreads();
+      if ((tid & 63) == 0) red[tid >> 6] = dia;
+      __syncthreads();
+      double diat = 0.0;
+      for (int w = 0; w < NWAVE; ++w) diat += red[w];
+      __syncthreads();
+      if (!(offt > 1e-30 * diat)) break;
+      for (int rnd = 0; rnd < M - 1; ++rnd) {
+        for (int t = tid; t < npair; t += TPB) {
+          int p, q;
+          if (t == 0) { p = rnd; q = M - 1; }
+          else { p = (rnd + t) % (M - 1); q = (rnd - t + (M - 1)) % (M - 1); }
+          if (p > q) { const int tt = p; p = q; q = tt; }
+          double c = 1.0, s = 0.0;
+          if (q < kp) {
+            const double apq = A0[p * KP + q];
+            if (fabs(apq) > 1e-300) {
+              const double app = A0[p * KP + p], aqq = A0[q * KP + q];
+              const double tau = (aqq - app) / (2.0 * apq);
+              const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+              c = 1.0 / sqrt(1.0 + tt * tt);
+              s = tt * c;
+            }
+          }
+          rp_[t] = p; rq_[t] = q; rc[t] = c; rs[t] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < npair * kp; e += TPB) {      // A <- A J (columns)
+          const int t = e / kp, i = e % kp;
+          const int p = rp_[t], q = rq_[t];
+          if (q < kp) {
+            const double c = rc[t], s = rs[t];
+            const double aip = A0[i * KP + p], aiq = A0[i * KP + q];
+            A0[i * KP + p] = c * aip - s * aiq;
+            A0[i * KP + q] = s * aip + c * aiq;
+          }
+        }
+        __syncthreads();
+        for (int e = tid; e < npair * kp; e += TPB) {      // A <- J^T A (rows)
+          const int t = e / kp, j = e % kp;
+          const int p = rp_[t], q = rq_[t];
+          if (q < kp) {
+            const double c = rc[t], s = rs[t];
+            const double apj = A0[p * KP + j], aqj = A0[q * KP + j];
+            A0[p * KP + j] = c * apj - s * aqj;
+            A0[q * KP + j] = s * apj + c * aqj;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    double lmin = INFINITY, lmax = -INFINITY;
+    for (int i = 0; i < kp; ++i) {
+      lmin = fmin(lmin, A0[i * KP + i]);
+      lmax = fmax(lmax, A0[i * KP + i]);
+    }
+    cond = (lmin > 0.0) ? lmax / lmin : INFINITY;
+  }
+  __syncthreads();
+
+  // --- Cholesky F = L L^T (lower, in A2) ---
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+  for (int j = 0; j < kp; ++j) {
+    if (tid == 0) {
+      const double d = A2[j * KP + j];
+      if (!(d > 0.0) || !(d < INFINITY)) s_fail = 1;
+      s_d = s_fail ? 1.0 : sqrt(d);
+    }
+    __syncthreads();
+    if (s_fail) break;
+    const double ljj = s_d;
+    for (int l = j + 1 + tid; l < kp; l += TPB) A2[l * KP + j] /= ljj;
+    if (tid == 0) A2[j * KP + j] = ljj;
+    __syncthreads();
+    const int rem = kp - j - 1;
+    for (int e = tid; e < rem * rem; e += TPB) {
+      const int l = j + 1 + e / rem, mm = j + 1 + e % rem;
+      if (mm <= l) A2[l * KP + mm] -= A2[l * KP + j] * A2[mm * KP + j];
+    }
+    __syncthreads();
+  }
+  const bool fallback = (kp == 0) || s_fail || !(cond <= ca.tau_cond);
+  // --- X = L^{-1} T^T (A0), one column per thread ---
+  if (!fallback) {
+    for (int c = tid; c < kp; c += TPB) {
+      for (int i = 0; i < kp; ++i) {
+        double s = A1[c * KP + i];                 // (T^T)[i][c] = T[c][i]
+        for (int mm = 0; mm < i; ++mm) s -= A2[i * KP + mm] * A0[mm * KP + c];
+        A0[i * KP + c] = s / A2[i * KP + i];
+      }
+    }
+  }
+  __syncthreads();
+  // --- C = X^T X scattered to KP x KP ---
+  double* Cm = ca.C + (size_t)m * KP * KP;
+  for (int e = tid; e < KP * KP; e += TPB) Cm[e] = 0.0;
+  __syncthreads();
+  if (!fallback) {
+    for (int e = tid; e < kp * kp; e += TPB) {
+      const int aa = e / kp, bb = e % kp;
+      double s = 0.0;
+      for (int i = 0; i < kp; ++i) s += A0[i * KP + aa] * A0[i * KP + bb];
+      Cm[kidx[aa] * KP + kidx[bb]] = s;
+    }
+  }
+  if (tid == 0) {
+    S->cond = (kp > 0 && s_fail) ? INFINITY : cond;
+    S->k_eff = kp;
+    S->kk = fallback ? 0 : kp;
+    if (fallback && k > 0 && S->setup_status == 0) S->setup_status = 1;
+  }
+}
+
+}  // namespace adef2

@@ -1,0 +1,305 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same seeded inputs.
+
+Bars: compaction bit-exact; FP64 solve e_rel <= max(1e-8, 2 * oracle e_rel)
+against x* (Cholesky + double-double refinement), iteration counts within 2 of
+the oracle (the paper reports CPU/GPU counts within 1 for identical
+algorithms); FP32 inner sweeps with FP64 refinement e_rel <= 1e-6 (floor) and
+the FP64 bar as target.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _xstar(S, mask, b):
+    I, _, _ = oracle.compact(mask)
+    S_II, _ = oracle.restrict(S, I)
+    return I, oracle.exact_solution(S_II, b[I])
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = gen.c1_workload(n=63, k=16, seeds=(0, 1, 2))
+    return w, w.op.S()
+
+
+# ---------------------------------------------------------------------------
+# compaction
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["blob", "random", "all_active", "all_inactive", "ragged", "large"])
+def test_compaction_bit_exact(lib, kind):
+    rng = np.random.default_rng(7)
+    if kind == "blob":
+        mask = gen.mask_top_fraction(gen.sinusoid_field(63, 3), 0.3)
+    elif kind == "random":
+        mask = (rng.uniform(size=10000) < 0.4).astype(np.uint8)
+    elif kind == "all_active":
+        mask = np.ones(5000, np.uint8)
+    elif kind == "all_inactive":
+        mask = np.zeros(5000, np.uint8)
+    elif kind == "ragged":
+        mask = (rng.uniform(size=4096 * 3 + 17) < 0.5).astype(np.uint8)
+    else:
+        mask = gen.mask_top_fraction(gen.sinusoid_field(511, 100), 0.25)
+    case(f"compaction {kind} N={mask.size}")
+    s = lib.Solver()
+    I, g2l, nI = s.compact(mask)
+    Io, g2lo, nIo = oracle.compact(mask)
+    assert nI == nIo
+    np.testing.assert_array_equal(I.cpu().numpy().astype(np.int64), Io)
+    np.testing.assert_array_equal(g2l.cpu().numpy().astype(np.int64), g2lo)
+
+
+# ---------------------------------------------------------------------------
+# restricted operator and coarse space
+# ---------------------------------------------------------------------------
+def test_apply_restricted_matches_oracle(lib, c1):
+    w, S = c1
+    inst = w.instances[0]
+    case("apply_restricted c1 n=63")
+    s = lib.Solver()
+    s.set_reference(S, w.Z)
+    s.restrict(inst.mask)
+    x = np.random.default_rng(3).standard_normal(S.shape[0])
+    y = s.apply_restricted(x).cpu().numpy()
+    I, _, _ = oracle.compact(inst.mask)
+    S_II, _ = oracle.restrict(S, I)
+    yo = S_II @ x[I]
+    assert np.all(y[inst.mask == 1] == 0.0)
+    assert np.linalg.norm(y[I] - yo) <= 1e-14 * np.linalg.norm(yo) * 10
+
+
+def test_coarse_space_matches_oracle(lib, c1):
+    w, S = c1
+    for m, inst in enumerate(w.instances):
+        case(f"coarse c1 seed {m}")
+        s = lib.Solver()
+        s.set_reference(S, w.Z)
+        nI, keff, cond, rc = s.restrict(inst.mask)
+        I, _, nIo = oracle.compact(inst.mask)
+        S_II, _ = oracle.restrict(S, I)
+        Zo, kept = oracle.restricted_basis(w.Z, I)
+        cs, fb = oracle.coarse_setup(S_II, Zo)
+        assert nI == nIo and keff == len(kept) and rc == 0 and not fb
+        assert abs(cond / cs.cond - 1) < 1e-8, (cond, cs.cond)
+        E, keptg, kk, _ = s.coarse_info()
+        np.testing.assert_array_equal(np.flatnonzero(keptg), kept)
+        np.testing.assert_allclose(np.linalg.eigvalsh(E), np.linalg.eigvalsh(cs.E), rtol=1e-9)
+
+
+def test_dependent_and_zero_columns_dropped(lib, c1):
+    w, S = c1
+    inst = w.instances[0]
+    Z = np.column_stack([w.Z[:, :5], w.Z[:, 2], np.zeros(S.shape[0]), w.Z[:, 5:10]])
+    case("coarse with duplicated and zero columns")
+    s = lib.Solver()
+    s.set_reference(S, Z)
+    nI, keff, cond, rc = s.restrict(inst.mask)
+    I, _, _ = oracle.compact(inst.mask)
+    Zo, kept = oracle.restricted_basis(Z, I)
+    assert keff == len(kept) == 10
+    _, keptg, _, _ = s.coarse_info()
+    np.testing.assert_array_equal(np.flatnonzero(keptg), kept)
+
+
+# ---------------------------------------------------------------------------
+# FP64 solves
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [16, 0])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_solve_fp64_c1(lib, c1, k, seed):
+    w, S = c1
+    inst = w.instances[seed]
+    Z = w.Z[:, :k]
+    tol = 1e-10
+    case(f"solve fp64 c1 n=63 k={k} seed={seed}")
+    s = lib.Solver()
+    s.set_reference(S, Z if k else None)
+    s.restrict(inst.mask)
+    out = s.solve(inst.b, tol)
+    ref = oracle.solve_instance(S, Z, inst.mask, inst.b, tol)
+    I, xs = _xstar(S, inst.mask, inst.b)
+    x = out.x.cpu().numpy()
+    e_gpu = oracle.rel_err(x[I], xs)
+    e_ora = oracle.rel_err(ref.x[I], xs)
+    assert out.status == 0
+    assert abs(out.iters - ref.iters) <= 2, (out.iters, ref.iters)
+    assert e_gpu <= max(1e-8, 2 * e_ora), (e_gpu, e_ora)
+    assert out.relres_true <= 5 * tol
+    assert np.all(x[inst.mask == 1] == 0.0)
+
+
+@pytest.mark.parametrize("n,k", [(95, 24), (127, 32)])
+def test_solve_fp64_convection_diffusion_multi_tile(lib, n, k):
+    """C2-type upwind operator at sizes that span many tiles with a ragged tail."""
+    w = gen.c2_workload(n=n, k=k, B=2)
+    S = w.op.S()
+    for m, inst in enumerate(w.instances):
+        case(f"solve fp64 cd2d n={n} k={k} inst={m}")
+        s = lib.Solver()
+        s.set_reference(S, w.Z)
+        s.restrict(inst.mask)
+        out = s.solve(inst.b, 1e-10)
+        ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
+        I, xs = _xstar(S, inst.mask, inst.b)
+        x = out.x.cpu().numpy()
+        e_gpu, e_ora = oracle.rel_err(x[I], xs), oracle.rel_err(ref.x[I], xs)
+        assert abs(out.iters - ref.iters) <= max(2, ref.iters // 50), (out.iters, ref.iters)
+        assert e_gpu <= max(1e-8, 2 * e_ora), (e_gpu, e_ora)
+
+
+def test_deterministic_rerun(lib, c1):
+    w, S = c1
+    inst = w.instances[0]
+    case("determinism c1")
+    s = lib.Solver()
+    s.set_reference(S, w.Z)
+    s.restrict(inst.mask)
+    a = s.solve(inst.b, 1e-10)
+    xa = a.x.cpu().numpy().copy()
+    s.restrict(inst.mask)
+    b = s.solve(inst.b, 1e-10)
+    assert a.iters == b.iters
+    np.testing.assert_array_equal(xa, b.x.cpu().numpy())
+
+
+def test_warm_start_from_solution(lib, c1):
+    w, S = c1
+    inst = w.instances[1]
+    I, xs = _xstar(S, inst.mask, inst.b)
+    x0 = np.zeros(S.shape[0])
+    x0[I] = xs
+    x0[inst.mask == 1] = 123.0          # ignored on the active set
+    case("warm start c1")
+    s = lib.Solver()
+    s.set_reference(S, w.Z)
+    s.restrict(inst.mask)
+    out = s.solve(inst.b, 1e-8, x0=x0)
+    assert out.iters == 0
+    assert oracle.rel_err(out.x.cpu().numpy()[I], xs) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# FP32 inner sweeps + FP64 refinement
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1])
+def test_solve_fp32_refine_c1(lib, c1, seed):
+    w, S = c1
+    inst = w.instances[seed]
+    case(f"solve fp32+refine c1 seed={seed}")
+    s = lib.Solver(precision=lib.FP32_REFINE, inner_rtol=1e-4)
+    s.set_reference(S, w.Z)
+    s.restrict(inst.mask)
+    out = s.solve(inst.b, 1e-10)
+    ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
+    I, xs = _xstar(S, inst.mask, inst.b)
+    e = oracle.rel_err(out.x.cpu().numpy()[I], xs)
+    assert out.status == 0
+    assert out.relres_true <= 1e-10
+    assert e <= 1e-6
+    assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), e
+
+
+# ---------------------------------------------------------------------------
+# batched
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_matches_single(lib, prec):
+    w = gen.c2_workload(n=95, k=16, B=4)
+    S = w.op.S()
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case(f"batched B=4 cd2d n=95 {prec}")
+    s = lib.Solver(precision=lib.FP64 if prec == "fp64" else lib.FP32_REFINE)
+    s.set_reference(S, w.Z)
+    out = s.solve_batched(masks, bs, 1e-10)
+    X = out["x"].cpu().numpy()
+    for m, inst in enumerate(w.instances):
+        ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
+        I, xs = _xstar(S, inst.mask, inst.b)
+        e = oracle.rel_err(X[m, I], xs)
+        assert out["status"][m] == 0
+        assert out["n_inactive"][m] == ref.n_I
+        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), (m, e)
+        if prec == "fp64":
+            assert abs(int(out["iters"][m]) - ref.iters) <= 2
+        assert np.all(X[m, inst.mask == 1] == 0.0)
+
+
+def test_batched_operator_scales(lib):
+    w = gen.c3_workload(n=31, k=8, B=3)
+    S0 = w.op.S()
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    a = np.array([i.a for i in w.instances])
+    c = np.array([i.c for i in w.instances]) - a * w.op.shift
+    case("batched operator scales c3 n=31")
+    s = lib.Solver()
+    s.set_reference(S0, w.Z)
+    out = s.solve_batched(masks, bs, 1e-10, a=a, c=c)
+    X = out["x"].cpu().numpy()
+    for m, inst in enumerate(w.instances):
+        Sm = w.op.S(a=inst.a, c=inst.c)
+        I, xs = _xstar(Sm, inst.mask, inst.b)
+        ref = oracle.solve_instance(Sm, w.Z, inst.mask, inst.b, 1e-10)
+        assert oracle.rel_err(X[m, I], xs) <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs))
+        assert abs(int(out["iters"][m]) - ref.iters) <= 2
+
+
+# ---------------------------------------------------------------------------
+# status paths
+# ---------------------------------------------------------------------------
+def test_forced_fallback_is_plain_pcg(lib, c1):
+    w, S = c1
+    inst = w.instances[0]
+    case("forced fallback tau_cond=1")
+    s = lib.Solver(tau_cond=1.0)
+    s.set_reference(S, w.Z)
+    nI, keff, cond, rc = s.restrict(inst.mask)
+    assert rc == lib.W_FALLBACK
+    out = s.solve(inst.b, 1e-10)
+    ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10, tau_cond=1.0)
+    assert out.status == lib.W_FALLBACK and ref.status == oracle.STATUS_FALLBACK
+    assert abs(out.iters - ref.iters) <= 2
+
+
+def test_maxit_status(lib, c1):
+    w, S = c1
+    inst = w.instances[0]
+    case("maxit=3")
+    s = lib.Solver(maxit=3)
+    s.set_reference(S, w.Z)
+    s.restrict(inst.mask)
+    out = s.solve(inst.b, 1e-12)
+    assert out.status == lib.W_MAXIT and out.iters == 3
+
+
+def test_error_paths(lib, c1):
+    w, S = c1
+    inst = w.instances[0]
+    case("error paths")
+    s = lib.Solver()
+    with pytest.raises(lib.Adef2Error) as e:
+        s.restrict(inst.mask)
+    assert e.value.code == lib.E_STATE
+    s.set_reference(S, w.Z)
+    with pytest.raises(lib.Adef2Error) as e:
+        s.solve(inst.b, 1e-8)
+    assert e.value.code == lib.E_STATE
+    s.restrict(inst.mask)
+    b = inst.b.copy()
+    b[np.flatnonzero(inst.mask == 0)[5]] = np.nan
+    with pytest.raises(lib.Adef2Error) as e:
+        s.solve(b, 1e-8)
+    assert e.value.code == lib.E_ARG
+    # zero right-hand side: x = 0 without iterations
+    out = s.solve(np.zeros(S.shape[0]), 1e-8)
+    assert out.iters == 0 and float(out.x.abs().max()) == 0.0
