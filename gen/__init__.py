@@ -48,14 +48,18 @@ __all__ = [
 class Operator:
     """Full-domain operator family  S(a, c) = a * B + c * I  on an n^d grid.
 
-    ``B`` is the assembled squared-stencil part (CSR, FP64) and ``shift`` the
-    default identity coefficient; ``S`` is the default member (a = 1).
+    ``B = alpha A^T A`` is the squared-stencil part, ``A`` the (FE-scaled) state
+    operator and ``shift`` the default identity coefficient, i.e. the paper's
+    M = alpha A^T A + I in its mass-weighted form; ``S`` is the default member
+    (a = 1), assembled as CSR in FP64.
     """
     n: int
     dim: int
     B: sp.csr_matrix
     shift: float
     name: str
+    A: sp.csr_matrix | None = None
+    alpha: float = 1.0
 
     @property
     def N(self) -> int:
@@ -400,9 +404,9 @@ def c1_workload(n: int = 63, k: int = 16, seeds=(0,), active: float = 0.2) -> Wo
     sinusoid field; b ~ N(0, 1) from the same seed.
     """
     h = 1.0 / (n + 1)
-    K = laplacian_2d(n)
+    K = canonical_csr(laplacian_2d(n))
     B = canonical_csr(1e-2 * (K @ K) / (h * h))
-    op = Operator(n=n, dim=2, B=B, shift=h * h, name=f"lap2d_sq_{n}")
+    op = Operator(n=n, dim=2, B=B, shift=h * h, name=f"lap2d_sq_{n}", A=K, alpha=1e-2 / (h * h))
     Z, pairs, sig = sine_modes_2d(n, k) if k > 0 else (np.zeros((n * n, 0), order="F"), [], np.zeros(0))
     insts = []
     for s in seeds:
@@ -416,9 +420,10 @@ def c1_workload(n: int = 63, k: int = 16, seeds=(0,), active: float = 0.2) -> Wo
 def c2_operator(n: int = 511, theta: float = math.pi / 6, peclet: float = 50.0):
     h = 1.0 / (n + 1)
     beta = peclet * np.array([math.cos(theta), math.sin(theta)])
-    K = (laplacian_2d(n) + upwind_2d(n, beta)).tocsr()
+    K = canonical_csr(laplacian_2d(n) + upwind_2d(n, beta))
     B = canonical_csr((K.T @ K) / (h * h))
-    op = Operator(n=n, dim=2, B=B, shift=1e-2 * h * h, name=f"cd2d_upwind_{n}")
+    op = Operator(n=n, dim=2, B=B, shift=1e-2 * h * h, name=f"cd2d_upwind_{n}", A=K,
+                  alpha=1.0 / (h * h))
     return op, K
 
 
@@ -449,9 +454,9 @@ def c2_workload(n: int = 511, k: int = 32, B: int = 16, theta: float = math.pi /
 def c3_operator(n: int = 255, seed: int = 300):
     h = 1.0 / (n + 1)
     G = gaussian_field_2d(n, seed)
-    KG = diffusion_2d(np.exp(G))
+    KG = canonical_csr(diffusion_2d(np.exp(G)))
     B = canonical_csr(1e-2 * (KG @ KG) / (h * h))
-    op = Operator(n=n, dim=2, B=B, shift=h * h, name=f"hetdiff2d_{n}")
+    op = Operator(n=n, dim=2, B=B, shift=h * h, name=f"hetdiff2d_{n}", A=KG, alpha=1e-2 / (h * h))
     return op, KG
 
 
@@ -491,9 +496,9 @@ def c3_workload(n: int = 255, k: int = 32, B: int = 256, theta_seed: int = 310,
 def c5_operator(n: int = 127, seed: int = 600):
     h = 1.0 / (n + 1)
     kap = inclusion_field_3d(n, seed)
-    K = diffusion_3d(kap)
+    K = canonical_csr(diffusion_3d(kap))
     B = canonical_csr((K @ K) / h ** 3)
-    op = Operator(n=n, dim=3, B=B, shift=1e-2 * h ** 3, name=f"cht3d_{n}")
+    op = Operator(n=n, dim=3, B=B, shift=1e-2 * h ** 3, name=f"cht3d_{n}", A=K, alpha=1.0 / h ** 3)
     return op, K
 
 

@@ -79,9 +79,13 @@ typedef struct {
                            100000 (App. "CG stopping criterion")             */
   int32_t precision;    /* enum adef2_precision                              */
   int32_t precond;      /* enum adef2_precond                                */
-  double inner_rtol;    /* FP32 sweep stops when ||r32|| <= inner_rtol times
-                           the FP64 residual it started from; 1e-4          */
-  int32_t max_sweeps;   /* FP32_REFINE: cap on refinement sweeps; 30         */
+  double inner_rtol;    /* FP32_REFINE: an FP32 segment ends when its
+                           recurrence residual fell to inner_rtol times the
+                           FP64 residual it started from (or below tol/2
+                           relative to ||b_I||); the FP64 residual b - S x
+                           then replaces it and the search direction carries
+                           on (residual replacement); 1e-2                   */
+  int32_t max_sweeps;   /* FP32_REFINE: cap on segments; 500                 */
   int32_t check_every;  /* iterations between host polls of convergence; 32 */
   int32_t rows_per_thread; /* 0 = autotuned; else 1, 2 or 4                  */
   int32_t profile;      /* 1 = time kernels with HIP events (adef2_get_stats) */
@@ -111,8 +115,24 @@ int adef2_set_reference(adef2_ctx *ctx, int64_t n, const int64_t *row_ptr,
                         const int32_t *col_idx, const double *vals, int64_t nnz,
                         int32_t k, const double *Z);
 
-/* Operator family S = a * S_ref + c * I applied to later restrict/solve calls
- * (a > 0, a + c*... must keep S SPD).  Default a = 1, c = 0. */
+/* Reference operator given in the paper's Schur-complement form
+ * M = alpha A^T A + shift I (Sec. "Reduced inactive set system", eq. schur,
+ * with the mass-weighted scaling folded into alpha and shift).
+ *   row_ptr, col_idx, vals: device CSR of the state operator A (n x n, any
+ *   sparsity with at most 32 distinct diagonals; need not be symmetric).
+ *   alpha > 0, shift >= 0; A must have full column rank when shift == 0.
+ *   k, Z: as in adef2_set_reference.
+ * The restricted operator is applied as S_II v = alpha A[:,I]^T (A[:,I] v) +
+ * shift v (two stencil passes).  Its rounding error grows with cond(A) rather
+ * than cond(A^T A), which keeps FP32 sweeps usable when cond(S) exceeds
+ * 1 / FP32 unit roundoff.  Invalidates any restriction. */
+int adef2_set_reference_factored(adef2_ctx *ctx, int64_t n, const int64_t *row_ptr,
+                                 const int32_t *col_idx, const double *vals, int64_t nnz,
+                                 double alpha, double shift, int32_t k, const double *Z);
+
+/* Operator family S = a * S_ref + c * I applied to later restrict/solve calls,
+ * S_ref being the operator of the last set_reference call (a > 0; S must stay
+ * positive definite).  Default a = 1, c = 0. */
 int adef2_set_operator_scale(adef2_ctx *ctx, double a, double c);
 
 /* Inactive-set compaction (eq. reduced; App. "Matrix assembly and active set

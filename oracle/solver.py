@@ -27,13 +27,17 @@ Spectral Deflation for State Constrained Optimal Control Problems"):
 Reading of Alg. 1 (listed in the design doc): as printed, the loop advances x along
 the *unprojected* preconditioned residual while the step length uses the
 projected operator, so x drifts inside range(Z) and the unprojected residual
-used by the stopping test stops decreasing.  The oracle uses the standard
-A-DEF2 recurrence the algorithm cites (Gaul et al. 2014; Tang et al. 2009):
-the preconditioned residual is projected, y = P K r with
-P = I - Z E^{-1} Z^T M_II (eq. proj), before it enters the search direction.
-Then the recurrence residual *is* the unprojected residual b - M_II x, Z^T r
-stays zero, and one residual serves both the recurrence and the stopping
-test, exactly as the appendix on stopping describes.
+used by the stopping test stops decreasing.  The oracle uses the A-DEF2
+recurrence of the works the algorithm cites (Tang et al. 2009; Gaul et al.
+2014): CG preconditioned by  P K + Q  with P = I - Z E^{-1} Z^T M_II
+(eq. proj) and Q = Z E^{-1} Z^T (eq. coarse), started from the deflated
+initial guess.  The search direction is built from y = P K r + Q r.  In exact
+arithmetic Z^T r = 0, so Q r vanishes and y = P K r; the Q r term is kept
+because it removes the rounding drift of Z^T r, which the projected
+iteration cannot reduce otherwise (it is the additive coarse term that makes
+A-DEF2 robust to inexact coarse solves).  The recurrence residual is the
+unprojected residual b - M_II x, one residual serves both the recurrence and
+the stopping test, as the appendix on stopping describes.
 """
 from __future__ import annotations
 
@@ -48,6 +52,7 @@ __all__ = [
     "compact", "restrict", "restricted_basis", "CoarseSpace", "coarse_setup",
     "apply_projector", "adef2", "jacobi_pcg", "SolveResult", "solve_instance",
     "two_sum", "two_prod", "dd_residual", "exact_solution", "rel_err",
+    "FactoredOp", "restrict_factored", "restricted_operator",
     "STATUS_OK", "STATUS_FALLBACK", "STATUS_MAXIT",
 ]
 
@@ -82,6 +87,53 @@ def restrict(S: sp.spmatrix, I: np.ndarray):
     S_II = S[I, :][:, I].tocsr()
     d_I = S.diagonal()[I].copy()
     return S_II, d_I
+
+
+class FactoredOp:
+    """M_II = alpha A[:, I]^T A[:, I] + shift I, the restriction of the paper's
+    M = alpha A^T A + I (eq. schur, mass-weighted) to the inactive set.
+
+    (A^T A)[I, I] = A[:, I]^T A[:, I] because every row of A contributes; the
+    product is applied as two sparse matrix-vector products and never formed,
+    except by ``assembled()`` (used only to factorise a preconditioner).
+    """
+
+    def __init__(self, A, alpha: float, shift: float, I):
+        self.A_I = sp.csr_matrix(A)[:, I].tocsr()
+        self.alpha = float(alpha)
+        self.shift = float(shift)
+        n = len(I)
+        self.shape = (n, n)
+        self.T = self
+
+    def __matmul__(self, x):
+        x = np.asarray(x)
+        return self.alpha * (self.A_I.T @ (self.A_I @ x)) + self.shift * x
+
+    def diagonal(self):
+        col2 = np.asarray(self.A_I.multiply(self.A_I).sum(axis=0)).ravel()
+        return self.alpha * col2 + self.shift
+
+    def assembled(self) -> sp.csr_matrix:
+        M = self.alpha * (self.A_I.T @ self.A_I) + self.shift * sp.identity(self.shape[0])
+        return sp.csr_matrix(M)
+
+    def toarray(self):
+        return self.assembled().toarray()
+
+
+def restrict_factored(A, alpha: float, shift: float, I):
+    """M_II of M = alpha A^T A + shift I, and its diagonal."""
+    op = FactoredOp(A, alpha, shift, I)
+    return op, op.diagonal()
+
+
+def restricted_operator(spec, I):
+    """M_II for an operator given either as an assembled sparse matrix or as
+    ("factored", A, alpha, shift)."""
+    if isinstance(spec, tuple) and spec and spec[0] == "factored":
+        return restrict_factored(spec[1], spec[2], spec[3], I)
+    return restrict(spec, I)
 
 
 def restricted_basis(Z: np.ndarray, I: np.ndarray, drop_rel: float = 1e-6):
@@ -167,6 +219,14 @@ def coarse_coefficients(cs: CoarseSpace, r: np.ndarray) -> np.ndarray:
     return cs.solve(cs.Z.T @ r)
 
 
+def preconditioned_residual(cs: CoarseSpace, z: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """y = P K r + Q r with z = K r: the A-DEF2 preconditioner (P^T_D M^-1 + Q
+    in the notation of Tang et al. 2009) applied to r."""
+    if cs.k == 0:
+        return z
+    return apply_projector(cs, z) + cs.Z @ coarse_coefficients(cs, r)
+
+
 # ---------------------------------------------------------------------------
 # A-DEF2 deflated PCG (Alg. 1, projected reading)
 # ---------------------------------------------------------------------------
@@ -182,15 +242,16 @@ def adef2(S_II, b, cs: CoarseSpace, tol: float, maxit: int = 100000, x0=None,
           d_inv=None, record: bool = False) -> LoopResult:
     """A-DEF2 deflated preconditioned CG on M_II x = b.
 
-    Steps (Alg. 1 with projected search directions, see module docstring):
+    Steps (Alg. 1 with the A-DEF2 preconditioner, see module docstring):
       c0  = E^{-1} Z^T (b - M x0)
       x   = x0 + Z c0                             deflated initial guess
       r   = (b - M x0) - W c0                     unprojected residual b - M x
-      z   = K r,  y = P z,  p = y,  rho = r.z     K = diag(M_II)^{-1}
+      z   = K r,  y = P z + Q r,  p = y           K = diag(M_II)^{-1}
+      rho = r.y
       while ||r|| > tol ||b|| and it < maxit:     eq. (cg_stop), max 1e5
           w = M p;  alpha = rho / p.w
           x += alpha p;  r -= alpha w
-          z = K r;  rho' = r.z;  y = P z
+          z = K r;  y = P z + Q r;  rho' = r.y
           p = y + (rho'/rho) p;  rho = rho'
     ``d_inv`` defaults to the Jacobi preconditioner; pass ones for none.
     With ``record`` the iterates and residuals are kept (tiny problems only).
@@ -217,8 +278,9 @@ def adef2(S_II, b, cs: CoarseSpace, tol: float, maxit: int = 100000, x0=None,
     if bnorm == 0.0:
         return LoopResult(np.zeros(n), 0, True, hist)
     z = d_inv * r
-    rho = float(r @ z)
-    p = apply_projector(cs, z)
+    y = preconditioned_residual(cs, z, r)
+    rho = float(r @ y)
+    p = y
     it = 0
     while float(np.linalg.norm(r)) > tol * bnorm and it < maxit:
         w = S_II @ p
@@ -226,8 +288,8 @@ def adef2(S_II, b, cs: CoarseSpace, tol: float, maxit: int = 100000, x0=None,
         x = x + alpha * p
         r = r - alpha * w
         z = d_inv * r
-        rho_new = float(r @ z)
-        y = apply_projector(cs, z)
+        y = preconditioned_residual(cs, z, r)
+        rho_new = float(r @ y)
         p = y + (rho_new / rho) * p
         rho = rho_new
         it += 1
@@ -263,11 +325,12 @@ def solve_instance(S, Z, mask, b, tol: float, tau_cond: float = 1e10,
                    maxit: int = 100000, x0=None, precond: str = "jacobi") -> SolveResult:
     """Restrict, build the coarse space, solve and scatter one instance.
 
-    b and x are global (length N); b on the active set is ignored and x there
-    is returned as zero.  ``x0`` (global) is an optional warm start.
+    S is an assembled sparse matrix or ("factored", A, alpha, shift).  b and x
+    are global (length N); b on the active set is ignored and x there is
+    returned as zero.  ``x0`` (global) is an optional warm start.
     """
     I, _, n_I = compact(mask)
-    S_II, d_I = restrict(S, I)
+    S_II, d_I = restricted_operator(S, I)
     b_I = np.asarray(b, dtype=np.float64)[I]
     Zo, kept = restricted_basis(Z, I)
     cs, fallback = coarse_setup(S_II, Zo, tau_cond)
@@ -318,25 +381,51 @@ def two_prod(a, b):
     return p, e
 
 
-def dd_residual(A: sp.spmatrix, x: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """b - A x accumulated in double-double, rounded once to FP64."""
+def _dd_add(hi, lo, p, e):
+    """(hi, lo) + (p, e) in double-double."""
+    s1, e1 = two_sum(hi, p)
+    e1 = e1 + (lo + e)
+    return two_sum(s1, e1)
+
+
+def dd_matvec(A: sp.spmatrix, x_hi: np.ndarray, x_lo=None, acc=None):
+    """acc + A (x_hi + x_lo) in double-double; returns (hi, lo)."""
     A = sp.csr_matrix(A)
     n = A.shape[0]
-    hi = np.array(b, dtype=np.float64)
-    lo = np.zeros(n)
+    hi = np.zeros(n) if acc is None else np.array(acc[0], dtype=np.float64)
+    lo = np.zeros(n) if acc is None else np.array(acc[1], dtype=np.float64)
     counts = np.diff(A.indptr)
     rows = np.repeat(np.arange(n), counts)
     slot = np.arange(A.nnz) - np.repeat(A.indptr[:-1], counts)
-    for s in range(int(counts.max()) if n else 0):
+    for s in range(int(counts.max()) if n and A.nnz else 0):
         sel = slot == s
         rr = rows[sel]
-        p, e = two_prod(A.data[sel], x[A.indices[sel]])
-        s1, e1 = two_sum(hi[rr], -p)
-        e1 = e1 + (lo[rr] - e)
-        h2, l2 = two_sum(s1, e1)
-        hi[rr] = h2
-        lo[rr] = l2
-    return hi + lo
+        a = A.data[sel]
+        p, e = two_prod(a, x_hi[A.indices[sel]])
+        if x_lo is not None:
+            e = e + a * x_lo[A.indices[sel]]
+        hi[rr], lo[rr] = _dd_add(hi[rr], lo[rr], p, e)
+    return hi, lo
+
+
+def dd_residual(A, x: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """b - A x accumulated in double-double, rounded once to FP64.
+
+    A is a sparse matrix or a FactoredOp (then b - alpha A_I^T (A_I x) - shift x
+    with every product and sum in double-double)."""
+    x = np.asarray(x, dtype=np.float64)
+    if isinstance(A, FactoredOp):
+        t_hi, t_lo = dd_matvec(A.A_I, x)
+        u_hi, u_lo = dd_matvec(sp.csr_matrix(A.A_I.T), t_hi, t_lo)
+        p, e = two_prod(np.full_like(u_hi, A.alpha), u_hi)
+        e = e + A.alpha * u_lo
+        q, f = two_prod(np.full_like(x, A.shift), x)
+        hi, lo = _dd_add(np.array(b, dtype=np.float64), np.zeros_like(x), -p, -e)
+        hi, lo = _dd_add(hi, lo, -q, -f)
+        return hi + lo
+    neg_hi, neg_lo = dd_matvec(-sp.csr_matrix(A), x, acc=(np.array(b, dtype=np.float64),
+                                                         np.zeros(len(b))))
+    return neg_hi + neg_lo
 
 
 def exact_solution(A: sp.spmatrix, b: np.ndarray, max_refine: int = 20,
@@ -349,7 +438,8 @@ def exact_solution(A: sp.spmatrix, b: np.ndarray, max_refine: int = 20,
     extra precision the limiting forward error is of the order of the working
     precision when cond(A) u < 1).
     """
-    A = sp.csr_matrix(A)
+    Ares = A
+    A = A.assembled() if isinstance(A, FactoredOp) else sp.csr_matrix(A)
     n = A.shape[0]
     if n == 0:
         return np.zeros(0)
@@ -367,7 +457,7 @@ def exact_solution(A: sp.spmatrix, b: np.ndarray, max_refine: int = 20,
         solve = lambda r: sla.cho_solve_banded((cb, True), r)  # noqa: E731
     x = solve(b)
     for _ in range(max_refine):
-        d = solve(dd_residual(A, x, b))
+        d = solve(dd_residual(Ares, x, b))
         x = x + d
         if np.linalg.norm(d) <= 1e-16 * np.linalg.norm(x):
             break

@@ -65,6 +65,7 @@ _sig = {
     "adef2_destroy": (ctypes.c_int, [_P]),
     "adef2_set_opts": (ctypes.c_int, [_P, ctypes.POINTER(Opts)]),
     "adef2_set_reference": (ctypes.c_int, [_P, _i64, _P, _P, _P, _i64, _i32, _P]),
+    "adef2_set_reference_factored": (ctypes.c_int, [_P, _i64, _P, _P, _P, _i64, _f64, _f64, _i32, _P]),
     "adef2_set_operator_scale": (ctypes.c_int, [_P, _f64, _f64]),
     "adef2_compact": (ctypes.c_int, [_P, _P, _i64, _P, _P, _Pi64]),
     "adef2_restrict": (ctypes.c_int, [_P, _P, _Pi64, _Pi32, _Pf64]),
@@ -174,6 +175,28 @@ class Solver:
                                       _ptr(Zt))
         self._check(rc, allow=(OK,))
         self.n, self.k = n, k
+
+    def set_reference_factored(self, A, alpha: float, shift: float, Z=None):
+        """S = alpha A^T A + shift I with A a scipy CSR matrix; Z: N x k or None."""
+        n = A.shape[0]
+        rp = _dev(np.asarray(A.indptr, dtype=np.int64), torch.int64)
+        ci = _dev(np.asarray(A.indices, dtype=np.int32), torch.int32)
+        va = _dev(np.asarray(A.data, dtype=np.float64), torch.float64)
+        k = 0 if Z is None else int(Z.shape[1])
+        Zt = None
+        if k > 0:
+            Zt = _dev(np.asfortranarray(Z, dtype=np.float64).ravel(order="F"), torch.float64)
+        rc = _lib.adef2_set_reference_factored(self._ctx, n, _ptr(rp), _ptr(ci), _ptr(va),
+                                               int(A.nnz), float(alpha), float(shift), k, _ptr(Zt))
+        self._check(rc, allow=(OK,))
+        self.n, self.k = n, k
+
+    def set_operator(self, op, Z=None, factored: bool = True):
+        """Reference operator from a gen.Operator (factored form when it has one)."""
+        if factored and getattr(op, "A", None) is not None:
+            self.set_reference_factored(op.A, op.alpha, op.shift, Z)
+        else:
+            self.set_reference(op.S(), Z)
 
     def set_operator_scale(self, a: float, c: float):
         self._check(_lib.adef2_set_operator_scale(self._ctx, float(a), float(c)), allow=(OK,))

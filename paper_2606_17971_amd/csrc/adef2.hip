@@ -45,6 +45,14 @@ struct adef2_ctx {
   double* Z64 = nullptr;
   float* Z32 = nullptr;
   double scale_a = 1.0, scale_c = 0.0;
+  // factored operator S = alpha A^T A + shift I: inner stencil A (dia1),
+  // outer stencil A^T (dia64/dia32 above, offsets offs)
+  bool factored = false;
+  int D1 = 0;
+  std::vector<int> offs1;
+  double* dia1_64 = nullptr;
+  float* dia1_32 = nullptr;
+  double alpha_ref = 1.0, shift_ref = 0.0;
 
   // restriction / batch state
   bool restricted = false;
@@ -71,6 +79,9 @@ struct adef2_ctx {
   double* x64 = nullptr;         // padded (refinement mode)
   double* r64 = nullptr;         // unpadded [B][N]
   double* x0pad = nullptr;       // padded warm start
+  double* t64 = nullptr;         // padded A v (factored operator, FP64)
+  float* t32 = nullptr;          // padded A v (factored operator, FP32 sweeps)
+  double* Tm = nullptr;          // [B][KP][N] A Ztilde (factored operator setup)
   double* part = nullptr;
   unsigned* ctr = nullptr;
   size_t part_elems = 0, ctr_elems = 0;
@@ -154,6 +165,8 @@ OpGeom op_geom(const adef2_ctx* c) {
   g.ntiles = c->ntiles;
   g.ntiles_pad = c->ntiles_pad;
   for (int d = 0; d < c->D; ++d) g.offs[d] = c->offs[d];
+  g.D1 = c->factored ? c->D1 : 0;
+  for (int d = 0; d < g.D1; ++d) g.offs1[d] = c->offs1[d];
   return g;
 }
 
@@ -164,6 +177,7 @@ void free_all(adef2_ctx* c) {
   F(c->C); F(c->Finfo); F(c->kept); F(c->gram);
   for (int j = 0; j < 5; ++j) { F(c->v64[j]); F(c->v32[j]); }
   F(c->W64); F(c->W32); F(c->dinv64); F(c->dinv32); F(c->x64); F(c->r64); F(c->x0pad);
+  F(c->t64); F(c->t32); F(c->Tm); F(c->dia1_64); F(c->dia1_32);
   F(c->part); F(c->ctr);
   if (c->inst_h) hipHostFree(c->inst_h);
   for (auto& e : c->ev_pending) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
@@ -249,6 +263,13 @@ void (*resid_fn(int rpt))(ResidArgs) {
   if (rpt == 4) return k_resid64<4>;
   return k_resid64<2>;
 }
+template <typename VM, typename VI, typename VO>
+void (*stencil1_fn(int rpt))(OpGeom, const VM*, const VI*, VO*, int64_t, const Inst*, int) {
+  if (rpt == 1) return k_stencil1<VM, VI, VO, 1>;
+  if (rpt == 4) return k_stencil1<VM, VI, VO, 4>;
+  return k_stencil1<VM, VI, VO, 2>;
+}
+
 void (*accum_fn(int rpt))(OpGeom, const uint8_t*, const float*, double*, int64_t, Inst*) {
   if (rpt == 1) return k_accumulate<1>;
   if (rpt == 4) return k_accumulate<4>;
@@ -265,7 +286,8 @@ void launch_gram(adef2_ctx* c, const V* dummy_tag, V* W) {
   case KPV:                                                                                  \
     nsub = (int)cdiv(c->N, GramCfg<KPV>::GR);                                                \
     hipLaunchKernelGGL((k_spmm_gram<V, KPV>), grid, dim3(TPB), 0, c->st, og, c->dia64, c->Z64, \
-                       c->masks, W, c->inst, c->part, c->ctr, c->g_gram, c->gram, nsub);      \
+                       c->Tm, (int)c->factored, c->masks, W, c->inst, c->part, c->ctr,        \
+                       c->g_gram, c->gram, nsub);                                            \
     break;
   switch (c->KP) {
     GRAM_CASE(8) GRAM_CASE(16) GRAM_CASE(24) GRAM_CASE(32) GRAM_CASE(40) GRAM_CASE(48)
@@ -299,8 +321,8 @@ void launch_coarse(adef2_ctx* c) {
 int ensure_batch(adef2_ctx* c, int B, int prec) {
   const int64_t N = c->N;
   const int KP = c->KP;
-  c->rpt = (c->o.rows_per_thread == 1 || c->o.rows_per_thread == 4) ? c->o.rows_per_thread : 2;
-  c->ntiles = (int)cdiv(N, (int64_t)TPB * c->rpt);
+  c->rpt = (c->o.rows_per_thread == 2 || c->o.rows_per_thread == 4) ? c->o.rows_per_thread : 1;
+  c->ntiles = (int)cdiv(N, (int64_t)IPB * c->rpt);
   c->ntiles_pad = (int)cdiv(c->ntiles, 8) * 8;
   c->g_iter = make_geom(c->ntiles_pad);
   const int64_t nsub_max = cdiv(N, 32);
@@ -344,12 +366,15 @@ int ensure_batch(adef2_ctx* c, int B, int prec) {
   if ((rc = dalloc(c, &c->x64, prec == ADEF2_FP64 ? 0 : BV))) return rc;
   if ((rc = dalloc(c, &c->r64, prec == ADEF2_FP64 ? 0 : BN))) return rc;
   if ((rc = dalloc(c, &c->x0pad, BV))) return rc;
+  if ((rc = dalloc(c, &c->t64, c->factored ? BV : 0))) return rc;
+  if ((rc = dalloc(c, &c->t32, (c->factored && prec != ADEF2_FP64) ? BV : 0))) return rc;
+  if ((rc = dalloc(c, &c->Tm, c->factored ? BN * KP : 0))) return rc;
   // reduction scratch: enough for the iteration kernels (NV <= KP+2) and the
   // Gram kernel (NV = 2 KP^2); geometry is recomputed per call from B
-  const size_t pi = (size_t)make_geom((int)cdiv(cdiv(N, TPB), 8) * 8).ptotal * (KP + 2);
+  const size_t pi = (size_t)make_geom((int)cdiv(cdiv(N, IPB), 8) * 8).ptotal * (2 * KP + 2);
   const size_t pg = (size_t)make_geom(256).ptotal * 2 * kk;
   c->part_elems = (size_t)B * std::max(pi, pg);
-  c->ctr_elems = (size_t)B * std::max(make_geom((int)cdiv(cdiv(N, TPB), 8) * 8).ctotal,
+  c->ctr_elems = (size_t)B * std::max(make_geom((int)cdiv(cdiv(N, IPB), 8) * 8).ctotal,
                                       make_geom(256).ctotal) + 16;
   if ((rc = dalloc(c, &c->part, c->part_elems))) return rc;
   if ((rc = dalloc(c, &c->ctr, c->ctr_elems))) return rc;
@@ -373,10 +398,14 @@ int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
   for (int m = 0; m < B; ++m) {
     Inst& s = c->inst_h[m];
     std::memset(&s, 0, sizeof(Inst));
-    s.a = a_h ? a_h[m] : c->scale_a;
-    s.c = c_h ? c_h[m] : c->scale_c;
+    const double ua = a_h ? a_h[m] : c->scale_a;
+    const double uc = c_h ? c_h[m] : c->scale_c;
+    if (!(ua > 0.0) || !std::isfinite(ua) || !std::isfinite(uc))
+      return fail(c, ADEF2_E_ARG, "operator scale a must be > 0");
+    // kernels apply S = s.a * (stencil) + s.c * I
+    s.a = c->factored ? ua * c->alpha_ref : ua;
+    s.c = c->factored ? ua * c->shift_ref + uc : uc;
     s.cond = 1.0;
-    if (!(s.a > 0.0) || !std::isfinite(s.c)) return fail(c, ADEF2_E_ARG, "operator scale a must be > 0");
   }
   HIPCHK(c, hipMemcpyAsync(c->inst, c->inst_h, sizeof(Inst) * B, hipMemcpyHostToDevice, c->st));
   // compaction
@@ -400,12 +429,18 @@ int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
                        c->inst, c->o.precond == ADEF2_NONE);
     for (int j = 0; j < 5; ++j) fill<float>(c, c->v32[j], BV, 0.0f);
     fill<double>(c, c->x64, BV, 0.0);
+    fill<float>(c, c->t32, BV, 0.0f);
   }
   fill<double>(c, c->x0pad, BV, 0.0);
+  fill<double>(c, c->t64, BV, 0.0);
   // coarse space
   if (c->KP > 0) {
     const double wbytes = (c->prec == ADEF2_FP64 ? 8.0 : 4.0);
     timed(c, KI_GRAM, (double)B * N * (c->D * 8.0 + c->KP * (8.0 + wbytes) + 1.0), [&] {
+      if (c->factored) {
+        hipLaunchKernelGGL(k_stencil_modes, dim3((unsigned)cdiv(N, 256), c->KP, B), dim3(256), 0,
+                           c->st, op_geom(c), c->dia1_64, c->Z64, c->masks, c->KP, c->Tm);
+      }
       if (c->prec == ADEF2_FP64) launch_gram<double>(c, nullptr, c->W64);
       else launch_gram<float>(c, nullptr, c->W32);
     });
@@ -443,6 +478,8 @@ IterArgs<V> iter_args(adef2_ctx* c) {
   a.maxit = c->o.maxit;
   a.vs = c->vs;
   if constexpr (sizeof(V) == 8) {
+    a.dia1 = (const V*)c->dia1_64;
+    a.t = (V*)interior(c, c->t64);
     a.dia = (const V*)c->dia64;
     a.dinv = (const V*)c->dinv64;
     a.Z = (const V*)c->Z64;
@@ -451,6 +488,8 @@ IterArgs<V> iter_args(adef2_ctx* c) {
     a.z = (V*)interior(c, c->v64[2]); a.p = (V*)interior(c, c->v64[3]);
     a.w = (V*)interior(c, c->v64[4]);
   } else {
+    a.dia1 = (const V*)c->dia1_32;
+    a.t = (V*)interior(c, c->t32);
     a.dia = (const V*)c->dia32;
     a.dinv = (const V*)c->dinv32;
     a.Z = (const V*)c->Z32;
@@ -472,11 +511,18 @@ ByteModel byte_model(const adef2_ctx* c, int prec) {
   const double N = (double)c->N * c->B;
   ByteModel b{};
   b.init = nI * (8.0 + k * w + 2 * w) + N;
-  b.init2 = nI * (2 * k * w + 6 * w) + N;
+  b.init2 = nI * (3 * k * w + 6 * w) + N;
   b.pupdate = nI * (k * w + 3 * w) + N;            // z, Z (k), p -> p
-  b.spmv = nI * (c->D * w + 2 * w) + N;             // D diagonals, p, w
-  b.update = nI * (k * w + 8 * w) + N;              // W (k), x p r w dinv -> x r z
-  b.resid = nI * (c->D * 8.0 + 8.0 * 3) + N;
+  if (c->factored) {
+    // inner pass t = A p on all rows (D1 diagonals, p, t), outer pass on
+    // inactive rows (D diagonals of A^T, t, p, w)
+    b.spmv = N * (c->D1 * w + 2 * w) + nI * (c->D * w + 3 * w) + N;
+    b.resid = N * (c->D1 * 8.0 + 16.0) + nI * (c->D * 8.0 + 8.0 * 4) + N;
+  } else {
+    b.spmv = nI * (c->D * w + 2 * w) + N;           // D diagonals, p, w
+    b.resid = nI * (c->D * 8.0 + 8.0 * 3) + N;
+  }
+  b.update = nI * (2 * k * w + 8 * w) + N;          // W, Z (k each), x p r w dinv -> x r z
   b.accum = nI * (4.0 + 16.0) + N;
   return b;
 }
@@ -496,15 +542,27 @@ int poll(adef2_ctx* c, bool outer, bool* all_done) {
 // run one A-DEF2 sweep in precision V for all instances: init, init2, then
 // chunks of iterations until every instance's sweep is done
 template <typename V>
-int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale) {
+int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale,
+              double thresh_floor, int carry_dir) {
   IterArgs<V> a = iter_args<V>(c);
   a.src = src;
   a.x0 = x0pad;
   a.x0s = c->vs;
   a.thresh_scale = thresh_scale;
+  a.thresh_floor = thresh_floor;
+  a.carry_dir = carry_dir;
   KTab<V> kt = pick<V>(c->KP, c->rpt);
-  dim3 grid(c->ntiles_pad, c->B), blk(TPB);
+  dim3 grid(c->ntiles_pad, c->B), blk(IPB);
   const ByteModel bm = byte_model(c, sizeof(V) == 8 ? ADEF2_FP64 : ADEF2_FP32_REFINE);
+  const OpGeom og = a.op;
+  auto st1 = stencil1_fn<V, V, V>(c->rpt);
+  a.x0sv = x0pad;
+  if (x0pad && c->factored) {
+    // S x0 needs t = A x0 first (FP64 warm start, FP64 sweeps only)
+    hipLaunchKernelGGL((stencil1_fn<double, double, double>(c->rpt)), grid, blk, 0, c->st, og,
+                       c->dia1_64, x0pad, interior(c, c->t64), c->vs, c->inst, 2);
+    a.x0sv = interior(c, c->t64);
+  }
   timed(c, KI_INIT, bm.init, [&] { hipLaunchKernelGGL(kt.init, grid, blk, 0, c->st, a); });
   timed(c, KI_INIT2, bm.init2, [&] { hipLaunchKernelGGL(kt.init2, grid, blk, 0, c->st, a); });
   HIPCHK(c, hipGetLastError());
@@ -521,7 +579,11 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
     launched += chunk;
     for (int it = 0; it < chunk; ++it) {
       timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, c->st, a); });
-      timed(c, KI_SPMV, bm.spmv, [&] { hipLaunchKernelGGL(kt.spmv, grid, blk, 0, c->st, a); });
+      timed(c, KI_SPMV, bm.spmv, [&] {
+        if (c->factored)
+          hipLaunchKernelGGL(st1, grid, blk, 0, c->st, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
+        hipLaunchKernelGGL(kt.spmv, grid, blk, 0, c->st, a);
+      });
       timed(c, KI_UPDATE, bm.update, [&] { hipLaunchKernelGGL(kt.update, grid, blk, 0, c->st, a); });
     }
     HIPCHK(c, hipGetLastError());
@@ -537,6 +599,7 @@ int resid64(adef2_ctx* c, const double* b, const double* xpad, int first, int de
   ra.mask = c->masks;
   ra.b = b;
   ra.x = xpad;
+  ra.sv = xpad;
   ra.vs = c->vs;
   ra.r64 = store ? c->r64 : nullptr;
   ra.inst = c->inst;
@@ -550,7 +613,13 @@ int resid64(adef2_ctx* c, const double* b, const double* xpad, int first, int de
   ra.max_sweeps = c->o.max_sweeps;
   const ByteModel bm = byte_model(c, ADEF2_FP64);
   timed(c, KI_RESID, bm.resid, [&] {
-    hipLaunchKernelGGL(resid_fn(c->rpt), dim3(c->ntiles_pad, c->B), dim3(TPB), 0, c->st, ra);
+    if (c->factored) {
+      hipLaunchKernelGGL((stencil1_fn<double, double, double>(c->rpt)), dim3(c->ntiles_pad, c->B),
+                         dim3(IPB), 0, c->st, ra.op, c->dia1_64, xpad, interior(c, c->t64), c->vs,
+                         c->inst, decide ? 2 : 0);
+      ra.sv = interior(c, c->t64);
+    }
+    hipLaunchKernelGGL(resid_fn(c->rpt), dim3(c->ntiles_pad, c->B), dim3(IPB), 0, c->st, ra);
   });
   HIPCHK(c, hipGetLastError());
   return ADEF2_OK;
@@ -565,6 +634,7 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
   for (int m = 0; m < B; ++m) {
     Inst& s = c->inst_h[m];
     s.iters = 0; s.sweep_iters = 0; s.done = 0; s.outer_done = 0; s.status = 0; s.sweeps = 0;
+    s.has_dir = 0; s.rho_end = 0.0;
     s.rr = 0; s.rr64 = 0; s.bb64 = 0;
   }
   HIPCHK(c, hipMemcpyAsync(c->inst, c->inst_h, sizeof(Inst) * B, hipMemcpyHostToDevice, c->st));
@@ -579,7 +649,7 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
   int rc;
   double* xres = nullptr;
   if (c->prec == ADEF2_FP64) {
-    if ((rc = run_sweep<double>(c, b, x0p, tol * tol))) return rc;
+    if ((rc = run_sweep<double>(c, b, x0p, tol * tol, 0.0, 0))) return rc;
     xres = interior(c, c->v64[0]);
     if ((rc = resid64(c, b, xres, 1, 0, tol, false))) return rc;
   } else {
@@ -597,9 +667,12 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
       if ((rc = poll(c, true, &ad))) return rc;
       if (ad) break;
       if (sweep > c->o.max_sweeps + 1) return fail(c, ADEF2_E_HIP, "refinement made no progress");
-      if ((rc = run_sweep<float>(c, c->r64, nullptr, in2))) return rc;
+      // FP32 segment on the correction equation S d = r64; it ends when its
+      // recurrence residual fell by inner_rtol (or below tol ||b|| / 2); the
+      // FP64 residual then replaces it and the search direction carries on
+      if ((rc = run_sweep<float>(c, c->r64, nullptr, in2, 0.25 * tol * tol, sweep > 0))) return rc;
       timed(c, KI_ACCUM, bm.accum, [&] {
-        hipLaunchKernelGGL(accum_fn(c->rpt), dim3(c->ntiles_pad, B), dim3(TPB), 0, c->st,
+        hipLaunchKernelGGL(accum_fn(c->rpt), dim3(c->ntiles_pad, B), dim3(IPB), 0, c->st,
                            op_geom(c), c->masks, interior(c, c->v32[0]), interior(c, c->x64),
                            c->vs, c->inst);
       });
@@ -647,8 +720,8 @@ void adef2_default_opts(adef2_opts* o) {
   o->maxit = 100000;
   o->precision = ADEF2_FP64;
   o->precond = ADEF2_JACOBI;
-  o->inner_rtol = 1e-4;
-  o->max_sweeps = 30;
+  o->inner_rtol = 1e-2;
+  o->max_sweeps = 500;
   o->check_every = 32;
   o->rows_per_thread = 0;
   o->profile = 0;
@@ -691,31 +764,38 @@ int adef2_set_opts(adef2_ctx* c, const adef2_opts* o) {
   return ADEF2_OK;
 }
 
-int adef2_set_reference(adef2_ctx* c, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
-                        const double* vals, int64_t nnz, int32_t k, const double* Z) {
-  if (!c) return ADEF2_E_ARG;
-  if (n <= 0 || n > (int64_t)1 << 30 || !row_ptr || !col_idx || !vals || nnz <= 0)
-    return fail(c, ADEF2_E_ARG, "invalid operator arguments");
-  if (k < 0 || k > ADEF2_MAX_K || (k > 0 && !Z)) return fail(c, ADEF2_E_ARG, "invalid k or Z");
-  c->have_ref = false;
-  c->restricted = false;
-  c->Bcap = 0;
-  // distinct diagonal offsets
+}  // extern "C"
+
+namespace {
+
+// CSR (device) -> diagonal format.  Finds the distinct column-row offsets on
+// the device (flag array + compaction), then scatters the values.
+// which = 0: assembled S (c->offs, c->dia64/32, c->diag); which = 1: factor A
+// (c->offs1, c->dia1_64/32).
+int load_dia(adef2_ctx* c, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+             const double* vals, int which) {
   const size_t nf = (size_t)(2 * n - 1);
   uint8_t* flags = nullptr;
   int* bad = nullptr;
-  int rc;
-  if ((rc = dalloc(c, &flags, nf))) return rc;
-  if ((rc = dalloc(c, &bad, 1))) { hipFree(flags); return rc; }
   int* Iofs = nullptr;
   int* cnt = nullptr;
   int* ofs = nullptr;
   long long* tot = nullptr;
   const int nch = (int)cdiv((int64_t)nf, CMP_CHUNK);
-  auto cleanup = [&] { hipFree(flags); hipFree(bad); if (Iofs) hipFree(Iofs); if (cnt) hipFree(cnt);
-                       if (ofs) hipFree(ofs); if (tot) hipFree(tot); };
-  if ((rc = dalloc(c, &Iofs, nf)) || (rc = dalloc(c, &cnt, nch)) || (rc = dalloc(c, &ofs, nch)) ||
-      (rc = dalloc(c, &tot, 1))) { cleanup(); return rc; }
+  auto cleanup = [&] {
+    if (flags) hipFree(flags);
+    if (bad) hipFree(bad);
+    if (Iofs) hipFree(Iofs);
+    if (cnt) hipFree(cnt);
+    if (ofs) hipFree(ofs);
+    if (tot) hipFree(tot);
+  };
+  int rc;
+  if ((rc = dalloc(c, &flags, nf)) || (rc = dalloc(c, &bad, 1)) || (rc = dalloc(c, &Iofs, nf)) ||
+      (rc = dalloc(c, &cnt, nch)) || (rc = dalloc(c, &ofs, nch)) || (rc = dalloc(c, &tot, 1))) {
+    cleanup();
+    return rc;
+  }
   hipMemsetAsync(flags, 1, nf, c->st);
   hipMemsetAsync(bad, 0, sizeof(int), c->st);
   hipLaunchKernelGGL(k_mark_offsets, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->st, n, row_ptr,
@@ -730,48 +810,44 @@ int adef2_set_reference(adef2_ctx* c, int64_t n, const int64_t* row_ptr, const i
   hipMemcpyAsync(&badh, bad, sizeof(int), hipMemcpyDeviceToHost, c->st);
   if (hipStreamSynchronize(c->st) != hipSuccess) { cleanup(); return fail(c, ADEF2_E_HIP, "sync failed"); }
   if (badh) { cleanup(); return fail(c, ADEF2_E_ARG, "column index out of range"); }
-  if (D > ADEF2_MAX_DIAGS) {
+  const int dmax = which ? MAXD1 : ADEF2_MAX_DIAGS;
+  if (D > dmax || D <= 0) {
     cleanup();
     return fail(c, ADEF2_E_UNSUPPORTED, "operator has " + std::to_string(D) +
-                                            " distinct diagonals (max " +
-                                            std::to_string(ADEF2_MAX_DIAGS) + ")");
+                                            " distinct diagonals (max " + std::to_string(dmax) + ")");
   }
   std::vector<int> pos(D);
   hipMemcpyAsync(pos.data(), Iofs, sizeof(int) * D, hipMemcpyDeviceToHost, c->st);
   hipStreamSynchronize(c->st);
-  c->offs.resize(D);
-  int maxoff = 0;
+  std::vector<int>& off = which ? c->offs1 : c->offs;
+  off.resize(D);
   bool has0 = false;
   for (int d = 0; d < D; ++d) {
-    c->offs[d] = (int)(pos[d] - (n - 1));
-    maxoff = std::max(maxoff, std::abs(c->offs[d]));
-    has0 |= c->offs[d] == 0;
+    off[d] = (int)(pos[d] - (n - 1));
+    has0 |= off[d] == 0;
   }
-  if (!has0) { cleanup(); return fail(c, ADEF2_E_NOT_SPD, "operator has no main diagonal"); }
-  c->N = n;
-  c->D = (int)D;
-  c->H = ((maxoff + 63) / 64) * 64;
-  c->k = k;
-  c->KP = round8(k);
-  if ((rc = dalloc(c, &c->dia64, (size_t)D * n)) || (rc = dalloc(c, &c->dia32, (size_t)D * n)) ||
-      (rc = dalloc(c, &c->diag, (size_t)n))) { cleanup(); return rc; }
-  hipMemsetAsync(c->dia64, 0, sizeof(double) * D * n, c->st);
-  hipMemsetAsync(c->dia32, 0, sizeof(float) * D * n, c->st);
+  if (!which && !has0) { cleanup(); return fail(c, ADEF2_E_NOT_SPD, "operator has no main diagonal"); }
+  double** d64 = which ? &c->dia1_64 : &c->dia64;
+  float** d32 = which ? &c->dia1_32 : &c->dia32;
+  if ((rc = dalloc(c, d64, (size_t)D * n)) || (rc = dalloc(c, d32, (size_t)D * n)) ||
+      (!which && (rc = dalloc(c, &c->diag, (size_t)n)))) {
+    cleanup();
+    return rc;
+  }
+  hipMemsetAsync(*d64, 0, sizeof(double) * D * n, c->st);
+  hipMemsetAsync(*d32, 0, sizeof(float) * D * n, c->st);
   OpGeom og{};
   og.N = n;
-  og.D = (int)D;
-  for (int d = 0; d < D; ++d) og.offs[d] = c->offs[d];
+  if (which) {
+    og.D1 = (int)D;
+    for (int d = 0; d < D; ++d) og.offs1[d] = off[d];
+  } else {
+    og.D = (int)D;
+    for (int d = 0; d < D; ++d) og.offs[d] = off[d];
+  }
   hipMemsetAsync(bad, 0, sizeof(int), c->st);
   hipLaunchKernelGGL(k_csr_to_dia, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->st, n, row_ptr,
-                     col_idx, vals, og, c->dia64, c->dia32, c->diag, bad);
-  if (c->KP > 0) {
-    if ((rc = dalloc(c, &c->Z64, (size_t)c->KP * n)) || (rc = dalloc(c, &c->Z32, (size_t)c->KP * n))) {
-      cleanup();
-      return rc;
-    }
-    hipLaunchKernelGGL(k_copy_modes, dim3((unsigned)cdiv(n, 256), c->KP), dim3(256), 0, c->st, n, k,
-                       c->KP, Z, c->Z64, c->Z32);
-  }
+                     col_idx, vals, og, which, *d64, *d32, c->diag, bad);
   hipMemcpyAsync(&badh, bad, sizeof(int), hipMemcpyDeviceToHost, c->st);
   hipError_t e = hipStreamSynchronize(c->st);
   cleanup();
@@ -779,6 +855,90 @@ int adef2_set_reference(adef2_ctx* c, int64_t n, const int64_t* row_ptr, const i
   if (badh == 2) return fail(c, ADEF2_E_ARG, "operator has non-finite values");
   if (badh == 3) return fail(c, ADEF2_E_NOT_SPD, "operator has a non-positive diagonal entry");
   if (badh) return fail(c, ADEF2_E_ARG, "inconsistent operator structure");
+  return ADEF2_OK;
+}
+
+int load_modes(adef2_ctx* c, int64_t n, int32_t k, const double* Z) {
+  c->k = k;
+  c->KP = round8(k);
+  int rc;
+  if (c->KP > 0) {
+    if ((rc = dalloc(c, &c->Z64, (size_t)c->KP * n)) || (rc = dalloc(c, &c->Z32, (size_t)c->KP * n)))
+      return rc;
+    hipLaunchKernelGGL(k_copy_modes, dim3((unsigned)cdiv(n, 256), c->KP), dim3(256), 0, c->st, n, k,
+                       c->KP, Z, c->Z64, c->Z32);
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  }
+  return ADEF2_OK;
+}
+
+int check_ref_args(adef2_ctx* c, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                   const double* vals, int64_t nnz, int32_t k, const double* Z) {
+  if (n <= 0 || n > (int64_t)1 << 30 || !row_ptr || !col_idx || !vals || nnz <= 0)
+    return fail(c, ADEF2_E_ARG, "invalid operator arguments");
+  if (k < 0 || k > ADEF2_MAX_K || (k > 0 && !Z)) return fail(c, ADEF2_E_ARG, "invalid k or Z");
+  return ADEF2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int adef2_set_reference(adef2_ctx* c, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                        const double* vals, int64_t nnz, int32_t k, const double* Z) {
+  if (!c) return ADEF2_E_ARG;
+  int rc = check_ref_args(c, n, row_ptr, col_idx, vals, nnz, k, Z);
+  if (rc) return rc;
+  c->have_ref = false;
+  c->restricted = false;
+  c->Bcap = 0;
+  c->factored = false;
+  c->N = n;
+  if ((rc = load_dia(c, n, row_ptr, col_idx, vals, 0))) return rc;
+  c->D = (int)c->offs.size();
+  c->D1 = 0;
+  int maxoff = 0;
+  for (int o : c->offs) maxoff = std::max(maxoff, std::abs(o));
+  c->H = ((maxoff + 63) / 64) * 64;
+  if ((rc = load_modes(c, n, k, Z))) return rc;
+  c->have_ref = true;
+  return ADEF2_OK;
+}
+
+int adef2_set_reference_factored(adef2_ctx* c, int64_t n, const int64_t* row_ptr,
+                                 const int32_t* col_idx, const double* vals, int64_t nnz,
+                                 double alpha, double shift, int32_t k, const double* Z) {
+  if (!c) return ADEF2_E_ARG;
+  int rc = check_ref_args(c, n, row_ptr, col_idx, vals, nnz, k, Z);
+  if (rc) return rc;
+  if (!(alpha > 0.0) || !std::isfinite(alpha) || !(shift >= 0.0) || !std::isfinite(shift))
+    return fail(c, ADEF2_E_ARG, "alpha must be > 0 and shift >= 0");
+  c->have_ref = false;
+  c->restricted = false;
+  c->Bcap = 0;
+  c->factored = true;
+  c->N = n;
+  if ((rc = load_dia(c, n, row_ptr, col_idx, vals, 1))) return rc;
+  c->D1 = (int)c->offs1.size();
+  c->D = c->D1;
+  c->offs.resize(c->D);
+  for (int d = 0; d < c->D; ++d) c->offs[d] = -c->offs1[c->D1 - 1 - d];
+  if ((rc = dalloc(c, &c->dia64, (size_t)c->D * n)) || (rc = dalloc(c, &c->dia32, (size_t)c->D * n)) ||
+      (rc = dalloc(c, &c->diag, (size_t)n)))
+    return rc;
+  OpGeom og{};
+  og.N = n;
+  og.D1 = c->D1;
+  for (int d = 0; d < c->D1; ++d) og.offs1[d] = c->offs1[d];
+  hipLaunchKernelGGL(k_dia_transpose, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->st, og,
+                     c->dia1_64, c->dia64, c->dia32, c->diag);
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  int maxoff = 0;
+  for (int o : c->offs1) maxoff = std::max(maxoff, std::abs(o));
+  c->H = ((maxoff + 63) / 64) * 64;
+  c->alpha_ref = alpha;
+  c->shift_ref = shift;
+  if ((rc = load_modes(c, n, k, Z))) return rc;
   c->have_ref = true;
   return ADEF2_OK;
 }
@@ -893,8 +1053,15 @@ int adef2_apply_restricted(adef2_ctx* c, const double* x, double* y) {
   fill<double>(c, tmp, (size_t)c->vs, 0.0);
   const dim3 g((unsigned)cdiv(N, 256), 1);
   hipLaunchKernelGGL(k_mask_copy_padded, g, dim3(256), 0, c->st, N, c->masks, x, tmp + c->H, c->vs);
+  const double* sv = tmp + c->H;
+  if (c->factored) {
+    hipLaunchKernelGGL((stencil1_fn<double, double, double>(c->rpt)), dim3(c->ntiles_pad, 1),
+                       dim3(IPB), 0, c->st, op_geom(c), c->dia1_64, tmp + c->H,
+                       interior(c, c->t64), c->vs, c->inst, 0);
+    sv = interior(c, c->t64);
+  }
   hipLaunchKernelGGL(k_apply64, g, dim3(256), 0, c->st, op_geom(c), c->dia64, c->masks, tmp + c->H,
-                     y, c->inst);
+                     sv, y, c->inst);
   hipError_t e = hipStreamSynchronize(c->st);
   hipFree(tmp);
   if (e != hipSuccess) return fail(c, ADEF2_E_HIP, hipGetErrorString(e));

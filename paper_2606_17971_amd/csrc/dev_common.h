@@ -6,8 +6,10 @@
 
 namespace adef2 {
 
-constexpr int TPB = 256;            // threads per block of the streaming kernels
+constexpr int TPB = 256;            // threads per block of the setup kernels
 constexpr int NWAVE = TPB / 64;     // wave64
+constexpr int IPB = 1024;           // threads per block of the iteration kernels
+constexpr int NIWAVE = IPB / 64;
 constexpr int KMAX = 64;            // max deflation rank (padded to a multiple of 8)
 constexpr int RED_FAN = 16;         // fan-in of the reduction tree
 constexpr int RED_MAXLEV = 6;
@@ -25,6 +27,7 @@ struct Inst {
   double pw;            // p.Sp of the last iteration
   double cond;          // cond(E) of the orthonormalised coarse basis
   double bb64;          // ||b_I||^2 (FP64, outer)
+  double rho_end;       // r.y at the end of the last sweep (direction carried over)
   double rr64;          // ||b_I - S_II x||^2 of the last outer residual
   int32_t iters;        // CG iterations, all sweeps
   int32_t sweep_iters;
@@ -37,7 +40,7 @@ struct Inst {
   int32_t n_inactive;
   int32_t k_eff;        // kept restricted modes
   int32_t sweeps;
-  int32_t pad_;
+  int32_t has_dir;      // a search direction from the previous sweep exists
   double coef[KMAX];    // coarse coefficients of the next x / p update
 };
 
@@ -52,12 +55,17 @@ struct RedGeom {
   int ctotal;               // counters per instance
 };
 
+// Agent-scope (all XCDs) loads and stores of reduction partials.  They bypass
+// the non-coherent per-XCD L2 state for these addresses only, so the
+// reduction needs no L2-wide writeback/invalidate fence.
 __device__ __forceinline__ double ld_coherent(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coherent(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// wait until this thread's outstanding memory operations have completed
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -67,7 +75,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Block-wide sums of NV per-thread values.  The result lands in out[0..NV)
 // (LDS), valid after the call for every thread.  red: LDS [NWAVE * NV].
-template <int NV>
+template <int NV, int NW = NWAVE>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red, double* out) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -79,7 +87,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red, double* 
   for (int j = threadIdx.x; j < NV; j += blockDim.x) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < NWAVE; ++w) s += red[w * NV + j];
+    for (int w = 0; w < NW; ++w) s += red[w * NV + j];
     out[j] = s;
   }
   __syncthreads();
@@ -87,9 +95,13 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red, double* 
 
 // Deterministic multi-block reduction.  Every block of a launch calls this
 // once with its block sums in bval[0..nv) (LDS).  The block that completes the
-// tree returns true with the totals in out[0..nv) (LDS); all others return
-// false.  Partial sums are combined in a fixed order (node index), so results
-// do not depend on block scheduling.  Counters are reset by their finisher.
+// tree returns true with the totals in out[0..nv); all others return false.
+// Partial sums are combined in a fixed order (node index), so results do not
+// depend on block scheduling.  Counters are reset by their finisher.
+// Publication protocol: partials are written with agent-scope stores and each
+// thread waits for their completion before the block's barrier; only then is
+// the node counter incremented (agent-scope atomic).  The block that observes
+// the last arrival reads the partials with agent-scope loads.
 __device__ inline bool tree_reduce(const RedGeom& g, int tile, int nv, double* part,
                                    unsigned* ctr, const double* bval, double* out) {
   __shared__ int s_last;
@@ -102,18 +114,18 @@ __device__ inline bool tree_reduce(const RedGeom& g, int tile, int nv, double* p
   for (int j = threadIdx.x; j < nv; j += blockDim.x)
     st_coherent(&part[(size_t)(g.pofs[0] + node) * nv + j], bval[j]);
   for (int l = 1; l < g.nlev; ++l) {
-    __threadfence();
+    wait_mem();
     __syncthreads();
     const int parent = node / RED_FAN;
     const int first = parent * RED_FAN;
     const int cnt = min(RED_FAN, g.n[l - 1] - first);
     if (threadIdx.x == 0) {
-      unsigned old = atomicAdd(&ctr[g.cofs[l] + parent], 1u);
+      unsigned old = __hip_atomic_fetch_add(&ctr[g.cofs[l] + parent], 1u, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
       s_last = (old == (unsigned)(cnt - 1));
     }
     __syncthreads();
     if (!s_last) return false;
-    __threadfence();
     if (threadIdx.x == 0) __hip_atomic_store(&ctr[g.cofs[l] + parent], 0u, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
     const bool top = (l == g.nlev - 1);

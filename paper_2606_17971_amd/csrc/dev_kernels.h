@@ -1,7 +1,10 @@
 // Streaming kernels of the restricted A-DEF2 solve (gfx950, wave64).
 //
 // Data layout (all in HBM, global node order, lexicographic, x fastest):
-//   S     : diagonal format, dia[d * N + i] = S[i, i + offs[d]] (0 if absent)
+//   S     : diagonal format, dia[d * N + i] = S[i, i + offs[d]] (0 if absent),
+//           or, for S = alpha A^T A + c I, the two stencils A (dia1, offs1) and
+//           A^T (dia, offs): S_II v = alpha (A^T (A v))_I + c v for v zero on
+//           the active set, applied as t = A v on all rows, then A^T t
 //   Z     : column-major N x KP (shared by all instances, zero padded columns)
 //   W     : per instance, column-major N x KP, W = S_II Z_I
 //   x,r,z,p,w : per instance, length N + 2H with H zero halo entries on both
@@ -15,19 +18,24 @@
 namespace adef2 {
 
 constexpr int MAXD = 64;
+constexpr int MAXD1 = 32;
 
 struct OpGeom {
   int64_t N;
-  int D;
+  int D;             // outer stencil: S (assembled) or A^T (factored)
+  int D1;            // inner stencil A (factored), 0 when assembled
   int ntiles;        // tiles covering N rows
   int ntiles_pad;    // multiple of 8 (XCD mapping)
   int offs[MAXD];
+  int offs1[MAXD1];
 };
 
 template <typename V>
 struct IterArgs {
   OpGeom op;
-  const V* dia;            // [D][N]
+  const V* dia;            // [D][N] outer stencil
+  const V* dia1;           // [D1][N] inner stencil (factored operator)
+  V* t;                    // padded inner product A p (factored operator)
   const uint8_t* mask;     // [B][N]
   const V* dinv;           // [B][N]
   const V* Z;              // [KP][N]
@@ -43,29 +51,43 @@ struct IterArgs {
   // init only
   const double* src;       // [B][N] right-hand side of the sweep
   const double* x0;        // padded FP64 warm start (stride x0s) or null
+  const double* x0sv;      // stencil source for S x0: x0, or A x0 (factored)
   int64_t x0s;
-  double thresh_scale;     // thresh2 = thresh_scale * ||src_I||^2
+  double thresh_scale;     // thresh2 = max(thresh_scale * ||src_I||^2,
+  double thresh_floor;     //               thresh_floor * ||b_I||^2)
+  int32_t carry_dir;       // keep the previous sweep's search direction
 };
 
-template <int RPT> struct Rows { static constexpr int PB = TPB * RPT; };
+template <int RPT> struct Rows { static constexpr int PB = IPB * RPT; };
 
-// coef[q] = sum_l C[q][l] g[l]  (finisher only; g, coef in LDS/global)
-template <int KP>
-__device__ __forceinline__ void coarse_apply(const double* Cm, const double* g, double* coef) {
-  for (int q = threadIdx.x; q < KP; q += blockDim.x) {
-    double s = 0.0;
-    for (int l = 0; l < KP; ++l) s += Cm[q * KP + l] * g[l];
-    coef[q] = s;
-  }
+// Row tile of one iteration block: IPB * RPT consecutive rows starting at
+// base; thread t owns rows base + t + j * IPB.  Panel reductions (M^T v over
+// the k columns of Z or W) are split over the waves: wave w takes columns
+// w, w + NIWAVE, ..., and each lane walks the tile rows lane, lane + 64, ...
+// with the vector read from LDS, so every column load is a coalesced 512-byte
+// wave access and each lane keeps one accumulator.
+template <typename V, int RPT>
+__device__ __forceinline__ double panel_dot(const V* col, int64_t base, const double* vec,
+                                            const uint8_t* act) {
+  constexpr int R = Rows<RPT>::PB;
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int j = lane; j < R; j += 64)
+    if (!act[j]) acc += (double)col[base + j] * vec[j];
+  return wave_sum(acc);
 }
 
 // ---------------------------------------------------------------------------
 // init: r0 = src - S x0 (or src), g = Z^T r0, ||src||^2;  finisher: c0 = C g
 // ---------------------------------------------------------------------------
 template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(TPB) k_init(IterArgs<V> a) {
+__global__ void __launch_bounds__(IPB) k_init(IterArgs<V> a) {
+  constexpr int R = Rows<RPT>::PB;
   constexpr int NV = KP + 1;
-  __shared__ double red[NWAVE * NV];
+  __shared__ double vl[R];
+  __shared__ uint8_t act[R];
+  __shared__ double red[NIWAVE];
   __shared__ double bv[NV];
   __shared__ double tot[NV];
   const int m = blockIdx.y;
@@ -73,61 +95,143 @@ __global__ void __launch_bounds__(TPB) k_init(IterArgs<V> a) {
   if (S->outer_done) return;
   const int tile = xcd_tile(blockIdx.x, a.op.ntiles_pad);
   const int64_t N = a.op.N;
+  const int64_t base = (int64_t)tile * R;
   const uint8_t* mk = a.mask + (size_t)m * N;
   const double* src = a.src + (size_t)m * N;
   V* x = a.x + m * a.vs;
   V* r = a.r + m * a.vs;
   const double sa = S->a, sc = S->c;
-  double v[NV];
+  double bb = 0.0;
 #pragma unroll
-  for (int j = 0; j < NV; ++j) v[j] = 0.0;
-  if (tile < a.op.ntiles) {
-#pragma unroll
-    for (int rr = 0; rr < RPT; ++rr) {
-      const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * TPB + threadIdx.x;
-      if (i < N && mk[i] == 0) {
-        const double s = src[i];
-        double r0 = s, xv = 0.0;
-        if (a.x0) {
-          const double* x0 = a.x0 + m * a.x0s;
-          double acc = 0.0;
-          for (int d = 0; d < a.op.D; ++d) acc += (double)a.dia[(size_t)d * N + i] * x0[i + a.op.offs[d]];
-          xv = x0[i];
-          r0 = s - (sa * acc + sc * xv);
-        }
-        x[i] = (V)xv;
-        r[i] = (V)r0;
-        v[KP] += s * s;
-#pragma unroll
-        for (int q = 0; q < KP; ++q) v[q] += (double)a.Z[(size_t)q * N + i] * r0;
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int j = rr * IPB + threadIdx.x;
+    const int64_t i = base + j;
+    const bool on = (tile < a.op.ntiles) && i < N && mk[i] == 0;
+    double r0 = 0.0;
+    if (on) {
+      const double s = src[i];
+      double xv = 0.0;
+      r0 = s;
+      if (a.x0) {
+        const double* x0 = a.x0 + m * a.x0s;
+        const double* sv = a.x0sv + m * a.x0s;
+        double acc = 0.0;
+        for (int d = 0; d < a.op.D; ++d) acc += (double)a.dia[(size_t)d * N + i] * sv[i + a.op.offs[d]];
+        xv = x0[i];
+        r0 = s - (sa * acc + sc * xv);
       }
+      x[i] = (V)xv;
+      r[i] = (V)r0;
+      bb += s * s;
     }
+    vl[j] = r0;
+    act[j] = !on;
   }
-  block_sum<NV>(v, red, bv);
+  {
+    double v1[1] = {bb};
+    block_sum<1, NIWAVE>(v1, red, bv + KP);
+  }
+  const int wid = threadIdx.x >> 6;
+  for (int q = wid; q < KP; q += NIWAVE) {
+    const double s = panel_dot<V, RPT>(a.Z + (size_t)q * N, base, vl, act);
+    if ((threadIdx.x & 63) == 0) bv[q] = s;
+  }
+  __syncthreads();
   double* part = a.part + (size_t)m * a.g.ptotal * NV;
   unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
   if (!tree_reduce(a.g, tile, NV, part, ctr, bv, tot)) return;
   if (threadIdx.x == 0) {
-    const double bb = tot[KP];
-    S->bb = bb;
-    S->thresh2 = a.thresh_scale * bb;
+    const double b2 = tot[KP];
+    S->bb = b2;
+    S->thresh2 = fmax(a.thresh_scale * b2, a.thresh_floor * S->bb64);
     S->done = 0;
     S->sweep_iters = 0;
     S->fresh = 1;
-    if (!(bb < INFINITY)) { S->done = 1; S->outer_done = 1; S->status = -1; }
-    else if (bb == 0.0) { S->done = 1; }
+    if (!(b2 < INFINITY)) { S->done = 1; S->outer_done = 1; S->status = -1; }
+    else if (b2 == 0.0) { S->done = 1; }
   }
-  if (S->kk > 0) coarse_apply<KP>(a.C + (size_t)m * KP * KP, tot, S->coef);
-  else for (int q = threadIdx.x; q < KP; q += blockDim.x) S->coef[q] = 0.0;
+  const double* Cm = a.C + (size_t)m * KP * KP;
+  for (int q = threadIdx.x; q < KP; q += blockDim.x) {
+    double s = 0.0;
+    if (S->kk > 0)
+      for (int l = 0; l < KP; ++l) s += Cm[q * KP + l] * tot[l];
+    S->coef[q] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// init2: x += Z c0, r -= W c0, z = K r;  rho = r.z, ||r||^2, g = W^T z
+// A-DEF2 preconditioned residual y = P K r + Q r  (P = I - Z E^-1 W^T,
+// Q = Z E^-1 Z^T): its coarse coordinates are c = E^-1 (W^T z - Z^T r) and
+// y = z - Z c.  The finisher of a reduction holding
+//   tot = [W^T z (KP) | Z^T r (KP) | r.z | r.r]
+// forms c (stored in S->coef) and returns r.y = r.z - (Z^T r).c.
+// ---------------------------------------------------------------------------
+template <int KP>
+__device__ __forceinline__ double adef2_direction(const double* Cm, const double* tot, Inst* S,
+                                                  bool defl) {
+  constexpr int K1 = KP > 0 ? KP : 1;
+  __shared__ double gl[K1], cl[K1];
+  __shared__ double s_rho;
+  if (defl) {
+    for (int q = threadIdx.x; q < KP; q += blockDim.x) gl[q] = tot[q] - tot[KP + q];
+    __syncthreads();
+    for (int q = threadIdx.x; q < KP; q += blockDim.x) {
+      double s = 0.0;
+      for (int l = 0; l < KP; ++l) s += Cm[q * KP + l] * gl[l];
+      cl[q] = s;
+      S->coef[q] = s;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double corr = 0.0;
+    if (defl)
+      for (int q = 0; q < KP; ++q) corr += tot[KP + q] * cl[q];
+    s_rho = tot[2 * KP] - corr;
+  }
+  __syncthreads();
+  return s_rho;
+}
+
+// Second half of init2 / update: block sums of [W^T z | Z^T r | r.z | r.r]
+// for the tile (z, r already in LDS), then the reduction tree.
+template <typename V, int KP, int RPT>
+__device__ __forceinline__ bool reduce_directions(const IterArgs<V>& a, int m, int tile, int64_t base,
+                                                  const V* W, bool defl, double rz, double rr2,
+                                                  const double* zl, const double* rl,
+                                                  const uint8_t* act, double* red, double* bv,
+                                                  double* tot) {
+  constexpr int NV = 2 * KP + 2;
+  {
+    double v2[2] = {rz, rr2};
+    block_sum<2, NIWAVE>(v2, red, bv + 2 * KP);
+  }
+  const int wid = threadIdx.x >> 6;
+  const int64_t N = a.op.N;
+  for (int q = wid; q < 2 * KP; q += NIWAVE) {
+    double s = 0.0;
+    if (defl) {
+      s = (q < KP) ? panel_dot<V, RPT>(W + (size_t)q * N, base, zl, act)
+                   : panel_dot<V, RPT>(a.Z + (size_t)(q - KP) * N, base, rl, act);
+    }
+    if ((threadIdx.x & 63) == 0) bv[q] = s;
+  }
+  __syncthreads();
+  double* part = a.part + (size_t)m * a.g.ptotal * NV;
+  unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
+  return tree_reduce(a.g, tile, NV, part, ctr, bv, tot);
+}
+
+// ---------------------------------------------------------------------------
+// init2: x += Z c0, r -= W c0, z = K r;  W^T z, Z^T r, r.z, ||r||^2
 // ---------------------------------------------------------------------------
 template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(TPB) k_init2(IterArgs<V> a) {
-  constexpr int NV = KP + 2;
-  __shared__ double red[NWAVE * NV];
+__global__ void __launch_bounds__(IPB) k_init2(IterArgs<V> a) {
+  constexpr int R = Rows<RPT>::PB;
+  constexpr int NV = 2 * KP + 2;
+  __shared__ double zl[R], rl[R];
+  __shared__ uint8_t act[R];
+  __shared__ double red[NIWAVE * 2];
   __shared__ double bv[NV];
   __shared__ double tot[NV];
   __shared__ double cf[KP > 0 ? KP : 1];
@@ -136,12 +240,13 @@ __global__ void __launch_bounds__(TPB) k_init2(IterArgs<V> a) {
   if (S->outer_done) return;
   const int tile = xcd_tile(blockIdx.x, a.op.ntiles_pad);
   const int64_t N = a.op.N;
+  const int64_t base = (int64_t)tile * R;
   const uint8_t* mk = a.mask + (size_t)m * N;
   V* x = a.x + m * a.vs;
   if (S->done) {   // zero right-hand side: x = 0 is the solution
     if (S->bb == 0.0 && tile < a.op.ntiles) {
       for (int rr = 0; rr < RPT; ++rr) {
-        const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * TPB + threadIdx.x;
+        const int64_t i = base + rr * IPB + threadIdx.x;
         if (i < N) x[i] = (V)0;
       }
     }
@@ -154,56 +259,59 @@ __global__ void __launch_bounds__(TPB) k_init2(IterArgs<V> a) {
   const bool defl = S->kk > 0;
   for (int q = threadIdx.x; q < KP; q += blockDim.x) cf[q] = S->coef[q];
   __syncthreads();
-  double v[NV];
+  double rz = 0.0, rr2 = 0.0;
 #pragma unroll
-  for (int j = 0; j < NV; ++j) v[j] = 0.0;
-  if (tile < a.op.ntiles) {
-#pragma unroll
-    for (int rr = 0; rr < RPT; ++rr) {
-      const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * TPB + threadIdx.x;
-      if (i < N && mk[i] == 0) {
-        double xv = (double)x[i], rv = (double)r[i];
-        if (defl) {
-#pragma unroll
-          for (int q = 0; q < KP; ++q) {
-            xv += (double)a.Z[(size_t)q * N + i] * cf[q];
-            rv -= (double)W[(size_t)q * N + i] * cf[q];
-          }
-        }
-        const double zv = (double)dinv[i] * rv;
-        x[i] = (V)xv;
-        r[i] = (V)rv;
-        z[i] = (V)zv;
-        const double zq = (double)(V)zv;
-        v[KP] += rv * zq;
-        v[KP + 1] += rv * rv;
-        if (defl) {
-#pragma unroll
-          for (int q = 0; q < KP; ++q) v[q] += (double)W[(size_t)q * N + i] * zq;
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int j = rr * IPB + threadIdx.x;
+    const int64_t i = base + j;
+    const bool on = (tile < a.op.ntiles) && i < N && mk[i] == 0;
+    double rv = 0.0, zv = 0.0;
+    if (on) {
+      double xv = (double)x[i];
+      rv = (double)r[i];
+      if (defl) {
+#pragma unroll 8
+        for (int q = 0; q < KP; ++q) {
+          xv += (double)a.Z[(size_t)q * N + i] * cf[q];
+          rv -= (double)W[(size_t)q * N + i] * cf[q];
         }
       }
+      const V rq = (V)rv;
+      const V zq = (V)((double)dinv[i] * (double)rq);
+      x[i] = (V)xv;
+      r[i] = rq;
+      z[i] = zq;
+      rv = (double)rq;
+      zv = (double)zq;
+      rz += rv * zv;
+      rr2 += rv * rv;
     }
+    zl[j] = zv;
+    rl[j] = rv;
+    act[j] = !on;
   }
-  block_sum<NV>(v, red, bv);
-  double* part = a.part + (size_t)m * a.g.ptotal * NV;
-  unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
-  if (!tree_reduce(a.g, tile, NV, part, ctr, bv, tot)) return;
-  const bool stop = !(tot[KP + 1] > S->thresh2);
+  __syncthreads();
+  if (!reduce_directions<V, KP, RPT>(a, m, tile, base, W, defl, rz, rr2, zl, rl, act, red, bv, tot))
+    return;
+  const bool stop = !(tot[2 * KP + 1] > S->thresh2);
+  double rho = 0.0;
+  if (!stop) rho = adef2_direction<KP>(a.C + (size_t)m * KP * KP, tot, S, defl);
   if (threadIdx.x == 0) {
-    S->rho = tot[KP];
-    S->rr = tot[KP + 1];
-    S->beta = 0.0;
-    S->fresh = 1;
+    S->rr = tot[2 * KP + 1];
+    // residual replacement: continue the previous direction, p = y + beta p
+    const bool carry = a.carry_dir && S->has_dir && S->rho_end > 0.0 && rho > 0.0;
+    S->beta = carry ? rho / S->rho_end : 0.0;
+    S->fresh = carry ? 0 : 1;
+    S->rho = rho;
     if (stop) S->done = 1;
   }
-  if (!stop && defl) coarse_apply<KP>(a.C + (size_t)m * KP * KP, tot, S->coef);
 }
 
 // ---------------------------------------------------------------------------
-// p = z - Z c + beta p   (A-DEF2 projected search direction)
+// p = z - Z c + beta p   (A-DEF2 search direction)
 // ---------------------------------------------------------------------------
 template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(TPB) k_pupdate(IterArgs<V> a) {
+__global__ void __launch_bounds__(IPB) k_pupdate(IterArgs<V> a) {
   __shared__ double cf[KP > 0 ? KP : 1];
   const int m = blockIdx.y;
   const Inst* S = a.inst + m;
@@ -221,11 +329,11 @@ __global__ void __launch_bounds__(TPB) k_pupdate(IterArgs<V> a) {
   __syncthreads();
 #pragma unroll
   for (int rr = 0; rr < RPT; ++rr) {
-    const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * TPB + threadIdx.x;
+    const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
     if (i < N && mk[i] == 0) {
       double pv = (double)z[i];
       if (defl) {
-#pragma unroll
+#pragma unroll 8
         for (int q = 0; q < KP; ++q) pv -= (double)a.Z[(size_t)q * N + i] * cf[q];
       }
       if (keep) pv += beta * (double)p[i];
@@ -238,8 +346,8 @@ __global__ void __launch_bounds__(TPB) k_pupdate(IterArgs<V> a) {
 // w = S_II p, p.w;  finisher: alpha = rho / p.w
 // ---------------------------------------------------------------------------
 template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(TPB) k_spmv(IterArgs<V> a) {
-  __shared__ double red[NWAVE];
+__global__ void __launch_bounds__(IPB) k_spmv(IterArgs<V> a) {
+  __shared__ double red[NIWAVE];
   __shared__ double bv[1];
   __shared__ double tot[1];
   const int m = blockIdx.y;
@@ -249,17 +357,18 @@ __global__ void __launch_bounds__(TPB) k_spmv(IterArgs<V> a) {
   const int64_t N = a.op.N;
   const uint8_t* mk = a.mask + (size_t)m * N;
   const V* p = a.p + m * a.vs;
+  const V* sv = (a.op.D1 ? a.t : a.p) + m * a.vs;
   V* w = a.w + m * a.vs;
   const double sa = S->a, sc = S->c;
   double v[1] = {0.0};
   if (tile < a.op.ntiles) {
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
-      const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * TPB + threadIdx.x;
+      const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
       if (i < N && mk[i] == 0) {
         double acc = 0.0;
         for (int d = 0; d < a.op.D; ++d)
-          acc += (double)a.dia[(size_t)d * N + i] * (double)p[i + a.op.offs[d]];
+          acc += (double)a.dia[(size_t)d * N + i] * (double)sv[i + a.op.offs[d]];
         const double pi = (double)p[i];
         const double wv = sa * acc + sc * pi;
         w[i] = (V)wv;
@@ -267,7 +376,7 @@ __global__ void __launch_bounds__(TPB) k_spmv(IterArgs<V> a) {
       }
     }
   }
-  block_sum<1>(v, red, bv);
+  block_sum<1, NIWAVE>(v, red, bv);
   double* part = a.part + (size_t)m * a.g.ptotal * 1;
   unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
   if (!tree_reduce(a.g, tile, 1, part, ctr, bv, tot)) return;
@@ -285,13 +394,16 @@ __global__ void __launch_bounds__(TPB) k_spmv(IterArgs<V> a) {
 }
 
 // ---------------------------------------------------------------------------
-// x += alpha p, r -= alpha w, z = K r;  r.z, ||r||^2, g = W^T z
-// finisher: stopping test, beta, coef = C g
+// x += alpha p, r -= alpha w, z = K r;  W^T z, Z^T r, r.z, ||r||^2
+// finisher: stopping test on ||r||, beta = r.y / rho, coarse coordinates
 // ---------------------------------------------------------------------------
 template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(TPB) k_update(IterArgs<V> a) {
-  constexpr int NV = KP + 2;
-  __shared__ double red[NWAVE * NV];
+__global__ void __launch_bounds__(IPB) k_update(IterArgs<V> a) {
+  constexpr int R = Rows<RPT>::PB;
+  constexpr int NV = 2 * KP + 2;
+  __shared__ double zl[R], rl[R];
+  __shared__ uint8_t act[R];
+  __shared__ double red[NIWAVE * 2];
   __shared__ double bv[NV];
   __shared__ double tot[NV];
   const int m = blockIdx.y;
@@ -299,6 +411,7 @@ __global__ void __launch_bounds__(TPB) k_update(IterArgs<V> a) {
   if (S->done) return;
   const int tile = xcd_tile(blockIdx.x, a.op.ntiles_pad);
   const int64_t N = a.op.N;
+  const int64_t base = (int64_t)tile * R;
   const uint8_t* mk = a.mask + (size_t)m * N;
   V* x = a.x + m * a.vs;
   V* r = a.r + m * a.vs;
@@ -309,58 +422,65 @@ __global__ void __launch_bounds__(TPB) k_update(IterArgs<V> a) {
   const V* W = a.W + (size_t)m * KP * N;
   const bool defl = S->kk > 0;
   const double alpha = S->alpha;
-  double v[NV];
+  double rz = 0.0, rr2 = 0.0;
 #pragma unroll
-  for (int j = 0; j < NV; ++j) v[j] = 0.0;
-  if (tile < a.op.ntiles) {
-#pragma unroll
-    for (int rr = 0; rr < RPT; ++rr) {
-      const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * TPB + threadIdx.x;
-      if (i < N && mk[i] == 0) {
-        const double xv = (double)x[i] + alpha * (double)p[i];
-        const double rv = (double)r[i] - alpha * (double)w[i];
-        const V rq = (V)rv;
-        const V zq = (V)((double)dinv[i] * (double)rq);
-        x[i] = (V)xv;
-        r[i] = rq;
-        z[i] = zq;
-        v[KP] += (double)rq * (double)zq;
-        v[KP + 1] += (double)rq * (double)rq;
-        if (defl) {
-#pragma unroll
-          for (int q = 0; q < KP; ++q) v[q] += (double)W[(size_t)q * N + i] * (double)zq;
-        }
-      }
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int j = rr * IPB + threadIdx.x;
+    const int64_t i = base + j;
+    const bool on = (tile < a.op.ntiles) && i < N && mk[i] == 0;
+    double rv = 0.0, zv = 0.0;
+    if (on) {
+      const double xv = (double)x[i] + alpha * (double)p[i];
+      const V rq = (V)((double)r[i] - alpha * (double)w[i]);
+      const V zq = (V)((double)dinv[i] * (double)rq);
+      x[i] = (V)xv;
+      r[i] = rq;
+      z[i] = zq;
+      rv = (double)rq;
+      zv = (double)zq;
+      rz += rv * zv;
+      rr2 += rv * rv;
     }
+    zl[j] = zv;
+    rl[j] = rv;
+    act[j] = !on;
   }
-  block_sum<NV>(v, red, bv);
-  double* part = a.part + (size_t)m * a.g.ptotal * NV;
-  unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
-  if (!tree_reduce(a.g, tile, NV, part, ctr, bv, tot)) return;
+  __syncthreads();
+  if (!reduce_directions<V, KP, RPT>(a, m, tile, base, W, defl, rz, rr2, zl, rl, act, red, bv, tot))
+    return;
   __shared__ int s_go;
   if (threadIdx.x == 0) {
-    const double rz = tot[KP], rr = tot[KP + 1];
+    const double rrt = tot[2 * KP + 1];
     S->iters += 1;
     S->sweep_iters += 1;
-    S->rr = rr;
+    S->rr = rrt;
     int go = 0;
-    if (!(rr > S->thresh2)) {
+    if (!(rrt > S->thresh2)) {
       S->done = 1;
-      if (!(rr < INFINITY)) { S->outer_done = 1; S->status = -5; }
+      go = 2;                       // sweep ends: keep r.y for the next sweep
+      if (!(rrt < INFINITY)) { S->outer_done = 1; S->status = -5; go = 0; }
     } else if (S->iters >= a.maxit) {
       S->done = 1;
       S->outer_done = 1;
       S->status = 2;
     } else {
-      S->beta = rz / S->rho;
-      S->rho = rz;
-      S->fresh = 0;
       go = 1;
     }
     s_go = go;
   }
   __syncthreads();
-  if (s_go && defl) coarse_apply<KP>(a.C + (size_t)m * KP * KP, tot, S->coef);
+  if (!s_go) return;
+  const double rho = adef2_direction<KP>(a.C + (size_t)m * KP * KP, tot, S, defl);
+  if (threadIdx.x == 0) {
+    if (s_go == 1) {
+      S->beta = rho / S->rho;
+      S->rho = rho;
+      S->fresh = 0;
+    } else {
+      S->rho_end = rho;
+      S->has_dir = 1;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -373,6 +493,7 @@ struct ResidArgs {
   const uint8_t* mask;
   const double* b;         // [B][N]
   const double* x;         // padded FP64 [B][vs]
+  const double* sv;        // stencil source: x, or A x (factored)
   int64_t vs;
   double* r64;             // [B][N] or null
   Inst* inst;
@@ -384,8 +505,8 @@ struct ResidArgs {
 };
 
 template <int RPT>
-__global__ void __launch_bounds__(TPB) k_resid64(ResidArgs a) {
-  __shared__ double red[NWAVE * 2];
+__global__ void __launch_bounds__(IPB) k_resid64(ResidArgs a) {
+  __shared__ double red[NIWAVE * 2];
   __shared__ double bv[2];
   __shared__ double tot[2];
   const int m = blockIdx.y;
@@ -396,15 +517,16 @@ __global__ void __launch_bounds__(TPB) k_resid64(ResidArgs a) {
   const uint8_t* mk = a.mask + (size_t)m * N;
   const double* b = a.b + (size_t)m * N;
   const double* x = a.x + m * a.vs;
+  const double* sv = a.sv + m * a.vs;
   const double sa = S->a, sc = S->c;
   double v[2] = {0.0, 0.0};
   if (tile < a.op.ntiles) {
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
-      const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * TPB + threadIdx.x;
+      const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
       if (i < N && mk[i] == 0) {
         double acc = 0.0;
-        for (int d = 0; d < a.op.D; ++d) acc += a.dia[(size_t)d * N + i] * x[i + a.op.offs[d]];
+        for (int d = 0; d < a.op.D; ++d) acc += a.dia[(size_t)d * N + i] * sv[i + a.op.offs[d]];
         const double bi = b[i];
         const double rv = bi - (sa * acc + sc * x[i]);
         if (a.r64) a.r64[(size_t)m * N + i] = rv;
@@ -413,7 +535,7 @@ __global__ void __launch_bounds__(TPB) k_resid64(ResidArgs a) {
       }
     }
   }
-  block_sum<2>(v, red, bv);
+  block_sum<2, NIWAVE>(v, red, bv);
   double* part = a.part + (size_t)m * a.g.ptotal * 2;
   unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
   if (!tree_reduce(a.g, tile, 2, part, ctr, bv, tot)) return;
@@ -430,9 +552,34 @@ __global__ void __launch_bounds__(TPB) k_resid64(ResidArgs a) {
   }
 }
 
+// Inner stencil of the factored operator on all rows: t = A v (v is zero on
+// the active set, so t = A[:, I] v_I).  skip: 1 = skip instances whose sweep is
+// done, 2 = skip finished solves, 0 = none.
+template <typename VM, typename VI, typename VO, int RPT>
+__global__ void __launch_bounds__(IPB) k_stencil1(OpGeom op, const VM* dia1, const VI* v, VO* t,
+                                                  int64_t vs, const Inst* inst, int skip) {
+  const int m = blockIdx.y;
+  const Inst* S = inst + m;
+  if ((skip == 1 && S->done) || (skip == 2 && S->outer_done)) return;
+  const int tile = xcd_tile(blockIdx.x, op.ntiles_pad);
+  if (tile >= op.ntiles) return;
+  const int64_t N = op.N;
+  const VI* vm = v + m * vs;
+  VO* tm = t + m * vs;
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
+    if (i < N) {
+      double acc = 0.0;
+      for (int e = 0; e < op.D1; ++e) acc += (double)dia1[(size_t)e * N + i] * (double)vm[i + op.offs1[e]];
+      tm[i] = (VO)acc;
+    }
+  }
+}
+
 // x64 += d (FP32 correction of the last sweep)
 template <int RPT>
-__global__ void __launch_bounds__(TPB) k_accumulate(OpGeom op, const uint8_t* mask, const float* d,
+__global__ void __launch_bounds__(IPB) k_accumulate(OpGeom op, const uint8_t* mask, const float* d,
                                                     double* x64, int64_t vs, Inst* inst) {
   const int m = blockIdx.y;
   Inst* S = inst + m;
@@ -443,7 +590,7 @@ __global__ void __launch_bounds__(TPB) k_accumulate(OpGeom op, const uint8_t* ma
   const uint8_t* mk = mask + (size_t)m * N;
 #pragma unroll
   for (int rr = 0; rr < RPT; ++rr) {
-    const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * TPB + threadIdx.x;
+    const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
     if (i < N && mk[i] == 0) x64[m * vs + i] += (double)d[m * vs + i];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) S->sweeps += 1;
@@ -484,14 +631,14 @@ __global__ void k_mask_copy_padded(int64_t N, const uint8_t* mask, const double*
 
 // y = S_II x (global layout, FP64): x padded with zeros on the active set
 __global__ void k_apply64(OpGeom op, const double* dia, const uint8_t* mask, const double* x,
-                          double* y, const Inst* inst) {
+                          const double* sv, double* y, const Inst* inst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = op.N;
   if (i >= N) return;
   double v = 0.0;
   if (mask[i] == 0) {
     double acc = 0.0;
-    for (int d = 0; d < op.D; ++d) acc += dia[(size_t)d * N + i] * x[i + op.offs[d]];
+    for (int d = 0; d < op.D; ++d) acc += dia[(size_t)d * N + i] * sv[i + op.offs[d]];
     v = inst->a * acc + inst->c * x[i];
   }
   y[i] = v;

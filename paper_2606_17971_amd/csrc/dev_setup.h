@@ -126,27 +126,74 @@ __global__ void k_mark_offsets(int64_t n, const int64_t* rp, const int* col, uin
   }
 }
 
+// which = 0: offsets op.offs (assembled S, diag = main diagonal, must be > 0);
+// which = 1: offsets op.offs1 (factor A of S = alpha A^T A + c I; diag unused)
 __global__ void k_csr_to_dia(int64_t n, const int64_t* rp, const int* col, const double* val,
-                             OpGeom op, double* dia64, float* dia32, double* diag, int* bad) {
+                             OpGeom op, int which, double* dia64, float* dia32, double* diag,
+                             int* bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int D = which ? op.D1 : op.D;
+  const int* offs = which ? op.offs1 : op.offs;
   double dg = 0.0;
   for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
     const int off = (int)((int64_t)col[e] - i);
-    int lo = 0, hi = op.D - 1;
+    int lo = 0, hi = D - 1;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (op.offs[mid] < off) lo = mid + 1; else hi = mid;
+      if (offs[mid] < off) lo = mid + 1; else hi = mid;
     }
-    if (op.offs[lo] != off) { *bad = 1; continue; }
+    if (offs[lo] != off) { *bad = 1; continue; }
     const double v = val[e];
     if (!(v == v) || v == INFINITY || v == -INFINITY) *bad = 2;
     dia64[(size_t)lo * n + i] = v;
     dia32[(size_t)lo * n + i] = (float)v;
     if (off == 0) dg = v;
   }
-  diag[i] = dg;
-  if (!(dg > 0.0)) *bad = 3;
+  if (!which) {
+    diag[i] = dg;
+    if (!(dg > 0.0)) *bad = 3;
+  }
+}
+
+// A^T in diagonal format from A: A^T[i, i - o] = A[i - o, i], and row i - o
+// of A holds that entry in its diagonal d (offset o = offs1[d]) at position
+// i - o; so diagonal d' = D1-1-d of A^T (offset -offs1[d]) holds
+// A[d][i - offs1[d]].  Also the diagonal of A^T A (squared column norms of A)
+// for the Jacobi preconditioner.
+__global__ void k_dia_transpose(OpGeom op, const double* A64, double* AT64, float* AT32, double* diag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = op.N;
+  if (i >= n) return;
+  double cn = 0.0;
+  for (int d = 0; d < op.D1; ++d) {
+    const int64_t j = i - op.offs1[d];
+    const double v = (j >= 0 && j < n) ? A64[(size_t)d * n + j] : 0.0;
+    const int dt = op.D1 - 1 - d;
+    AT64[(size_t)dt * n + i] = v;
+    AT32[(size_t)dt * n + i] = (float)v;
+    cn += v * v;
+  }
+  diag[i] = cn;
+}
+
+// T[m][q] = A Ztilde[q] on all rows, Ztilde = Z with the active rows of
+// instance m set to zero (factored operator, setup of W).
+__global__ void k_stencil_modes(OpGeom op, const double* A64, const double* Z64, const uint8_t* mask,
+                                int KP, double* T) {
+  const int q = blockIdx.y;
+  const int m = blockIdx.z;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = op.N;
+  if (i >= N) return;
+  const uint8_t* mk = mask + (size_t)m * N;
+  const double* Zq = Z64 + (size_t)q * N;
+  double acc = 0.0;
+  for (int e = 0; e < op.D1; ++e) {
+    const int64_t j = i + op.offs1[e];
+    if (j >= 0 && j < N && mk[j] == 0) acc += A64[(size_t)e * N + i] * Zq[j];
+  }
+  T[((size_t)m * KP + q) * N + i] = acc;
 }
 
 // Z (column-major n x k, FP64) -> Z64 / Z32 (column-major n x KP, zero padded)
@@ -175,8 +222,11 @@ template <int KP> struct GramCfg {
   static constexpr int LDS = (2 * GR * KP > NOUT ? 2 * GR * KP : NOUT);
 };
 
+// src: stencil source columns, Z itself (assembled operator; read masked) or
+// T = A Ztilde of this instance (factored operator; read unmasked).
 template <typename V, int KP>
 __global__ void __launch_bounds__(TPB) k_spmm_gram(OpGeom op, const double* dia64, const double* Z64,
+                                                    const double* src, int factored,
                                                     const uint8_t* mask, V* W, Inst* inst,
                                                     double* part, unsigned* ctr, RedGeom g,
                                                     double* gram, int nsub) {
@@ -205,10 +255,11 @@ __global__ void __launch_bounds__(TPB) k_spmm_gram(OpGeom op, const double* dia6
         double wv = 0.0, zv = 0.0;
         if (!act) {
           const double* Zq = Z64 + (size_t)q * N;
+          const double* Sq = factored ? src + ((size_t)m * KP + q) * N : Zq;
           double s = 0.0;
           for (int d = 0; d < op.D; ++d) {
             const int64_t j = i + op.offs[d];
-            if (j >= 0 && j < N && mk[j] == 0) s += dia64[(size_t)d * N + i] * Zq[j];
+            if (j >= 0 && j < N && (factored || mk[j] == 0)) s += dia64[(size_t)d * N + i] * Sq[j];
           }
           zv = Zq[i];
           wv = sa * s + sc * zv;

@@ -20,9 +20,27 @@ def case(msg):
 
 
 def _xstar(S, mask, b):
+    """x* of the restricted system; S is a sparse matrix or an oracle spec."""
     I, _, _ = oracle.compact(mask)
-    S_II, _ = oracle.restrict(S, I)
+    S_II, _ = oracle.restricted_operator(S, I)
     return I, oracle.exact_solution(S_II, b[I])
+
+
+def spec(op, form, a=1.0, c=None):
+    """Oracle operator for gen.Operator op in the given form, scaled a*S + c'."""
+    c = op.shift if c is None else c
+    if form == "factored":
+        return ("factored", op.A, a * op.alpha, c)
+    return op.S(a=a, c=c)
+
+
+def solver(lib, op, Z, form, **opts):
+    s = lib.Solver(**opts)
+    if form == "factored":
+        s.set_reference_factored(op.A, op.alpha, op.shift, Z)
+    else:
+        s.set_reference(op.S(), Z)
+    return s
 
 
 @pytest.fixture(scope="module")
@@ -77,6 +95,21 @@ def test_apply_restricted_matches_oracle(lib, c1):
     assert np.linalg.norm(y[I] - yo) <= 1e-14 * np.linalg.norm(yo) * 10
 
 
+def test_apply_restricted_factored_matches_oracle(lib):
+    w = gen.c2_workload(n=63, k=8, B=1)
+    inst = w.instances[0]
+    case("apply_restricted factored cd2d n=63")
+    s = solver(lib, w.op, w.Z, "factored")
+    s.restrict(inst.mask)
+    x = np.random.default_rng(5).standard_normal(w.op.N)
+    y = s.apply_restricted(x).cpu().numpy()
+    I, _, _ = oracle.compact(inst.mask)
+    F, _ = oracle.restrict_factored(w.op.A, w.op.alpha, w.op.shift, I)
+    yo = F @ x[I]
+    assert np.all(y[inst.mask == 1] == 0.0)
+    assert np.linalg.norm(y[I] - yo) <= 1e-13 * np.linalg.norm(yo)
+
+
 def test_coarse_space_matches_oracle(lib, c1):
     w, S = c1
     for m, inst in enumerate(w.instances):
@@ -113,16 +146,17 @@ def test_dependent_and_zero_columns_dropped(lib, c1):
 # ---------------------------------------------------------------------------
 # FP64 solves
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["assembled", "factored"])
 @pytest.mark.parametrize("k", [16, 0])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_solve_fp64_c1(lib, c1, k, seed):
-    w, S = c1
+def test_solve_fp64_c1(lib, c1, k, seed, form):
+    w, _ = c1
+    S = spec(w.op, form)
     inst = w.instances[seed]
     Z = w.Z[:, :k]
     tol = 1e-10
-    case(f"solve fp64 c1 n=63 k={k} seed={seed}")
-    s = lib.Solver()
-    s.set_reference(S, Z if k else None)
+    case(f"solve fp64 c1 n=63 k={k} seed={seed} {form}")
+    s = solver(lib, w.op, Z if k else None, form)
     s.restrict(inst.mask)
     out = s.solve(inst.b, tol)
     ref = oracle.solve_instance(S, Z, inst.mask, inst.b, tol)
@@ -137,15 +171,15 @@ def test_solve_fp64_c1(lib, c1, k, seed):
     assert np.all(x[inst.mask == 1] == 0.0)
 
 
+@pytest.mark.parametrize("form", ["assembled", "factored"])
 @pytest.mark.parametrize("n,k", [(95, 24), (127, 32)])
-def test_solve_fp64_convection_diffusion_multi_tile(lib, n, k):
+def test_solve_fp64_convection_diffusion_multi_tile(lib, n, k, form):
     """C2-type upwind operator at sizes that span many tiles with a ragged tail."""
     w = gen.c2_workload(n=n, k=k, B=2)
-    S = w.op.S()
+    S = spec(w.op, form)
     for m, inst in enumerate(w.instances):
-        case(f"solve fp64 cd2d n={n} k={k} inst={m}")
-        s = lib.Solver()
-        s.set_reference(S, w.Z)
+        case(f"solve fp64 cd2d n={n} k={k} inst={m} {form}")
+        s = solver(lib, w.op, w.Z, form)
         s.restrict(inst.mask)
         out = s.solve(inst.b, 1e-10)
         ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
@@ -190,13 +224,14 @@ def test_warm_start_from_solution(lib, c1):
 # ---------------------------------------------------------------------------
 # FP32 inner sweeps + FP64 refinement
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["assembled", "factored"])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_solve_fp32_refine_c1(lib, c1, seed):
-    w, S = c1
+def test_solve_fp32_refine_c1(lib, c1, seed, form):
+    w, _ = c1
+    S = spec(w.op, form)
     inst = w.instances[seed]
-    case(f"solve fp32+refine c1 seed={seed}")
-    s = lib.Solver(precision=lib.FP32_REFINE, inner_rtol=1e-4)
-    s.set_reference(S, w.Z)
+    case(f"solve fp32+refine c1 seed={seed} {form}")
+    s = solver(lib, w.op, w.Z, form, precision=lib.FP32_REFINE, inner_rtol=1e-4)
     s.restrict(inst.mask)
     out = s.solve(inst.b, 1e-10)
     ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
@@ -211,15 +246,15 @@ def test_solve_fp32_refine_c1(lib, c1, seed):
 # ---------------------------------------------------------------------------
 # batched
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["assembled", "factored"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batched_matches_single(lib, prec):
+def test_batched_matches_single(lib, prec, form):
     w = gen.c2_workload(n=95, k=16, B=4)
-    S = w.op.S()
+    S = spec(w.op, form)
     masks = np.stack([i.mask for i in w.instances])
     bs = np.stack([i.b for i in w.instances])
-    case(f"batched B=4 cd2d n=95 {prec}")
-    s = lib.Solver(precision=lib.FP64 if prec == "fp64" else lib.FP32_REFINE)
-    s.set_reference(S, w.Z)
+    case(f"batched B=4 cd2d n=95 {prec} {form}")
+    s = solver(lib, w.op, w.Z, form, precision=lib.FP64 if prec == "fp64" else lib.FP32_REFINE)
     out = s.solve_batched(masks, bs, 1e-10)
     X = out["x"].cpu().numpy()
     for m, inst in enumerate(w.instances):
@@ -234,20 +269,19 @@ def test_batched_matches_single(lib, prec):
         assert np.all(X[m, inst.mask == 1] == 0.0)
 
 
-def test_batched_operator_scales(lib):
+@pytest.mark.parametrize("form", ["assembled", "factored"])
+def test_batched_operator_scales(lib, form):
     w = gen.c3_workload(n=31, k=8, B=3)
-    S0 = w.op.S()
     masks = np.stack([i.mask for i in w.instances])
     bs = np.stack([i.b for i in w.instances])
     a = np.array([i.a for i in w.instances])
     c = np.array([i.c for i in w.instances]) - a * w.op.shift
-    case("batched operator scales c3 n=31")
-    s = lib.Solver()
-    s.set_reference(S0, w.Z)
+    case(f"batched operator scales c3 n=31 {form}")
+    s = solver(lib, w.op, w.Z, form)
     out = s.solve_batched(masks, bs, 1e-10, a=a, c=c)
     X = out["x"].cpu().numpy()
     for m, inst in enumerate(w.instances):
-        Sm = w.op.S(a=inst.a, c=inst.c)
+        Sm = spec(w.op, form, a=inst.a, c=inst.c)
         I, xs = _xstar(Sm, inst.mask, inst.b)
         ref = oracle.solve_instance(Sm, w.Z, inst.mask, inst.b, 1e-10)
         assert oracle.rel_err(X[m, I], xs) <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs))

@@ -387,3 +387,67 @@ def test_planted_coarse_correction_mistake_is_detected(monkeypatch):
                         else -cs.solve(cs.Z.T @ r))
     S_II, b, Zo, res, xs = _run_recorded(tol=1e-12)
     assert _invariant_violations(S_II, b, Zo, res, xs) != []
+
+
+# ---------------------------------------------------------------------------
+# factored operator M = alpha A^T A + shift I (eq. schur)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("maker", ["c1", "c2", "c3"])
+def test_factored_restriction_equals_assembled_submatrix(maker):
+    """(A^T A)[I, I] = A[:, I]^T A[:, I]: the factored restricted operator agrees
+    with the submatrix of the assembled full-domain operator."""
+    if maker == "c1":
+        op = gen.c1_workload(n=15, k=0).op
+    elif maker == "c2":
+        op, _ = gen.c2_operator(n=15)
+    else:
+        op, _ = gen.c3_operator(n=15)
+    mask = gen.mask_top_fraction(gen.sinusoid_field(15, 4), 0.3)
+    I, _, nI = oracle.compact(mask)
+    S_II, d_I = oracle.restrict(op.S(), I)
+    F, dF = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
+    x = np.random.default_rng(2).standard_normal(nI)
+    np.testing.assert_allclose(F @ x, S_II @ x, rtol=0, atol=1e-12 * abs(S_II).max() * np.abs(x).max() * 20)
+    np.testing.assert_allclose(dF, d_I, rtol=1e-13)
+    np.testing.assert_allclose(F.toarray(), S_II.toarray(), rtol=0, atol=1e-12 * abs(S_II).max())
+
+
+def test_factored_dd_residual_against_exact_rationals():
+    rng = np.random.default_rng(8)
+    A = sp.random(10, 10, density=0.4, random_state=9, format="csr") + sp.identity(10)
+    I = np.array([0, 2, 3, 5, 6, 9])
+    F = oa.FactoredOp(A, 0.37, 1.25e-3, I)
+    x = rng.standard_normal(len(I))
+    b = F @ x + 1e-13 * rng.standard_normal(len(I))
+    r = oracle.dd_residual(F, x, b)
+    AI = A.toarray()[:, I]
+    fa, fs = Fraction(0.37), Fraction(1.25e-3)
+    for i in range(len(I)):
+        acc = Fraction(0)
+        for j in range(len(I)):
+            mij = sum(Fraction(AI[l, i]) * Fraction(AI[l, j]) for l in range(10))
+            acc += mij * Fraction(x[j])
+        exact = Fraction(b[i]) - fa * acc - fs * Fraction(x[i])
+        assert abs(Fraction(r[i]) - exact) <= abs(exact) * Fraction(1e-15) + Fraction(1e-300)
+
+
+def test_factored_exact_solution_is_the_factored_operators():
+    """x* of the factored operator has a residual, evaluated in exact rational
+    arithmetic, at the level of one rounding of x (not of cond(M) u)."""
+    w = gen.c2_workload(n=7, k=0, B=1)
+    op = w.op
+    inst = w.instances[0]
+    I, _, nI = oracle.compact(inst.mask)
+    F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
+    b = inst.b[I]
+    x = oracle.exact_solution(F, b)
+    AI = op.A.toarray()[:, I]
+    fa, fs = Fraction(op.alpha), Fraction(op.shift)
+    xf = [Fraction(v) for v in x]
+    t = [sum(Fraction(AI[l, j]) * xf[j] for j in range(nI) if AI[l, j] != 0) for l in range(AI.shape[0])]
+    res = []
+    for i in range(nI):
+        u = sum(Fraction(AI[l, i]) * t[l] for l in range(AI.shape[0]) if AI[l, i] != 0)
+        res.append(float(Fraction(b[i]) - fa * u - fs * xf[i]))
+    Mx = np.abs(F.toarray()) @ np.abs(x)
+    assert np.all(np.abs(res) <= 8 * 2.2e-16 * Mx)
