@@ -52,16 +52,30 @@ enum adef2_status {
   ADEF2_W_FALLBACK = 1,     /* cond(E) > tau_cond or Cholesky of E failed:
                                solved as plain Jacobi-PCG (Alg. 3, Remark
                                tau_cond)                                     */
-  ADEF2_W_MAXIT = 2         /* not converged within maxit; x = last iterate  */
+  ADEF2_W_MAXIT = 2,        /* not converged within maxit; x = last iterate  */
+  ADEF2_W_STAGNATED = 3     /* refinement modes: the FP64 residual b - S x
+                               stopped decreasing (its best value did not halve
+                               over 4 outer steps) above tol: the attainable
+                               accuracy of FP64 x was reached (when cond(S_II)
+                               is ~1e10 the FP64 rounding of the exact solution
+                               already has a relative residual ~1e-10); x is
+                               the last iterate                              */
 };
 
 enum adef2_precision {
   ADEF2_FP64 = 0,           /* all vectors, S, Z and W in FP64 (the paper's
                                setting, App. "GPU implementation")           */
-  ADEF2_FP32_REFINE = 1     /* inner A-DEF2 sweeps with FP32 S, Z, W and
+  ADEF2_FP32_REFINE = 1,    /* inner A-DEF2 segments with FP32 S, Z, W and
                                vectors (FP64 accumulation of dot products);
                                FP64 outer residual b - S x and FP64 x; the
                                k x k coarse algebra stays FP64               */
+  ADEF2_MIXED_REFINE = 2    /* as FP32_REFINE but with FP64 vectors: the
+                               operator values and the Z / W panels (most of
+                               the bytes) are FP32, every vector and every
+                               accumulation FP64.  Needed when cond(S) is
+                               beyond 1 / FP32 roundoff: an FP32 vector's own
+                               rounding noise is then amplified by
+                               lambda_max / lambda of the modes it carries  */
 };
 
 enum adef2_precond {
@@ -85,7 +99,11 @@ typedef struct {
                            relative to ||b_I||); the FP64 residual b - S x
                            then replaces it and the search direction carries
                            on (residual replacement); 1e-2                   */
-  int32_t max_sweeps;   /* FP32_REFINE: cap on segments; 500                 */
+  int32_t max_sweeps;   /* FP32_REFINE: cap on segments; 2000                */
+  int32_t segment_maxit; /* FP32_REFINE: a segment also ends after this many
+                           iterations (periodic residual replacement); the
+                           direction is carried only while the FP64 residual
+                           decreases, else the next segment restarts; 1000   */
   int32_t check_every;  /* iterations between host polls of convergence; 32 */
   int32_t rows_per_thread; /* 0 = autotuned; else 1, 2 or 4                  */
   int32_t profile;      /* 1 = time kernels with HIP events (adef2_get_stats) */

@@ -24,8 +24,8 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, E_ARG, E_STATE, E_HIP, E_NOMEM, E_NOT_SPD, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-W_FALLBACK, W_MAXIT = 1, 2
-FP64, FP32_REFINE = 0, 1
+W_FALLBACK, W_MAXIT, W_STAGNATED = 1, 2, 3
+FP64, FP32_REFINE, MIXED_REFINE = 0, 1, 2
 JACOBI, NONE = 0, 1
 MAX_K = 64
 
@@ -39,6 +39,7 @@ class Opts(ctypes.Structure):
         ("precond", ctypes.c_int32),
         ("inner_rtol", ctypes.c_double),
         ("max_sweeps", ctypes.c_int32),
+        ("segment_maxit", ctypes.c_int32),
         ("check_every", ctypes.c_int32),
         ("rows_per_thread", ctypes.c_int32),
         ("profile", ctypes.c_int32),
@@ -150,7 +151,7 @@ class Solver:
         except Exception:
             pass
 
-    def _check(self, rc: int, allow=(OK, W_FALLBACK, W_MAXIT)) -> int:
+    def _check(self, rc: int, allow=(OK, W_FALLBACK, W_MAXIT, W_STAGNATED)) -> int:
         if rc not in allow:
             raise Adef2Error(rc, _lib.adef2_last_error(self._ctx).decode())
         return rc
@@ -280,7 +281,7 @@ class Solver:
 def status_name(code: int) -> str:
     return {OK: "ok", E_ARG: "e_arg", E_STATE: "e_state", E_HIP: "e_hip", E_NOMEM: "e_nomem",
             E_NOT_SPD: "e_not_spd", E_UNSUPPORTED: "e_unsupported", W_FALLBACK: "w_fallback",
-            W_MAXIT: "w_maxit"}.get(code, str(code))
+            W_MAXIT: "w_maxit", W_STAGNATED: "w_stagnated"}.get(code, str(code))
 
 
 __all__ = ["Solver", "Opts", "default_opts", "Adef2Error", "EXPORTS", "LIB_PATH", "status_name"]

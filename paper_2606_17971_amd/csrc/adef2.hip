@@ -167,6 +167,9 @@ OpGeom op_geom(const adef2_ctx* c) {
   for (int d = 0; d < c->D; ++d) g.offs[d] = c->offs[d];
   g.D1 = c->factored ? c->D1 : 0;
   for (int d = 0; d < g.D1; ++d) g.offs1[d] = c->offs1[d];
+  g.d0 = g.d01 = -1;
+  for (int d = 0; d < g.D; ++d) if (g.offs[d] == 0) g.d0 = d;
+  for (int d = 0; d < g.D1; ++d) if (g.offs1[d] == 0) g.d01 = d;
   return g;
 }
 
@@ -218,62 +221,64 @@ void timed(adef2_ctx* c, int id, double bytes, F&& launch) {
 }
 
 // ------------------------------------------------------------ kernel tables
-template <typename V>
+// precision modes: vectors FP64 unless FP32_REFINE; operator values and Z/W
+// panels FP64 only in FP64 mode
+inline bool vec64(int prec) { return prec != ADEF2_FP32_REFINE; }
+inline bool mat64(int prec) { return prec == ADEF2_FP64; }
+
+template <typename V, typename M>
 struct KTab {
-  void (*init)(IterArgs<V>);
-  void (*init2)(IterArgs<V>);
-  void (*pupdate)(IterArgs<V>);
-  void (*spmv)(IterArgs<V>);
-  void (*update)(IterArgs<V>);
+  void (*init)(IterArgs<V, M>);
+  void (*init2)(IterArgs<V, M>);
+  void (*pupdate)(IterArgs<V, M>);
+  void (*spmv)(IterArgs<V, M>);
+  void (*update)(IterArgs<V, M>);
 };
 
-template <typename V, int KP, int RPT>
-KTab<V> make_tab() {
-  return {k_init<V, KP, RPT>, k_init2<V, KP, RPT>, k_pupdate<V, KP, RPT>, k_spmv<V, KP, RPT>,
-          k_update<V, KP, RPT>};
+template <typename V, typename M, int KP, int RPT>
+KTab<V, M> make_tab() {
+  return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
+          k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>};
 }
 
-template <typename V, int RPT>
-KTab<V> pick_kp(int KP) {
+template <typename V, typename M, int RPT>
+KTab<V, M> pick_kp(int KP) {
   switch (KP) {
-    case 0: return make_tab<V, 0, RPT>();
-    case 8: return make_tab<V, 8, RPT>();
-    case 16: return make_tab<V, 16, RPT>();
-    case 24: return make_tab<V, 24, RPT>();
-    case 32: return make_tab<V, 32, RPT>();
-    case 40: return make_tab<V, 40, RPT>();
-    case 48: return make_tab<V, 48, RPT>();
-    case 56: return make_tab<V, 56, RPT>();
-    default: return make_tab<V, 64, RPT>();
+    case 0: return make_tab<V, M, 0, RPT>();
+    case 8: return make_tab<V, M, 8, RPT>();
+    case 16: return make_tab<V, M, 16, RPT>();
+    case 24: return make_tab<V, M, 24, RPT>();
+    case 32: return make_tab<V, M, 32, RPT>();
+    case 40: return make_tab<V, M, 40, RPT>();
+    case 48: return make_tab<V, M, 48, RPT>();
+    case 56: return make_tab<V, M, 56, RPT>();
+    default: return make_tab<V, M, 64, RPT>();
   }
 }
 
-template <typename V>
-KTab<V> pick(int KP, int rpt) {
-  if (rpt == 1) return pick_kp<V, 1>(KP);
-  if (rpt == 4) return pick_kp<V, 4>(KP);
-  return pick_kp<V, 2>(KP);
+template <typename V, typename M>
+KTab<V, M> pick(int KP, int rpt) {
+  if (rpt == 2) return pick_kp<V, M, 2>(KP);
+  return pick_kp<V, M, 1>(KP);
 }
 
 template <int RPT>
 void (*pick_resid(void))(ResidArgs) { return k_resid64<RPT>; }
 
 void (*resid_fn(int rpt))(ResidArgs) {
-  if (rpt == 1) return k_resid64<1>;
-  if (rpt == 4) return k_resid64<4>;
-  return k_resid64<2>;
+  if (rpt == 2) return k_resid64<2>;
+  return k_resid64<1>;
 }
 template <typename VM, typename VI, typename VO>
 void (*stencil1_fn(int rpt))(OpGeom, const VM*, const VI*, VO*, int64_t, const Inst*, int) {
-  if (rpt == 1) return k_stencil1<VM, VI, VO, 1>;
-  if (rpt == 4) return k_stencil1<VM, VI, VO, 4>;
-  return k_stencil1<VM, VI, VO, 2>;
+  if (rpt == 2) return k_stencil1<VM, VI, VO, 2>;
+  return k_stencil1<VM, VI, VO, 1>;
 }
 
-void (*accum_fn(int rpt))(OpGeom, const uint8_t*, const float*, double*, int64_t, Inst*) {
-  if (rpt == 1) return k_accumulate<1>;
-  if (rpt == 4) return k_accumulate<4>;
-  return k_accumulate<2>;
+template <typename V>
+void (*accum_fn(int rpt))(OpGeom, const uint8_t*, const V*, double*, int64_t, Inst*) {
+  if (rpt == 2) return k_accumulate<V, 2>;
+  return k_accumulate<V, 1>;
 }
 
 template <typename V>
@@ -321,7 +326,7 @@ void launch_coarse(adef2_ctx* c) {
 int ensure_batch(adef2_ctx* c, int B, int prec) {
   const int64_t N = c->N;
   const int KP = c->KP;
-  c->rpt = (c->o.rows_per_thread == 2 || c->o.rows_per_thread == 4) ? c->o.rows_per_thread : 1;
+  c->rpt = (c->o.rows_per_thread == 2) ? 2 : 1;
   c->ntiles = (int)cdiv(N, (int64_t)IPB * c->rpt);
   c->ntiles_pad = (int)cdiv(c->ntiles, 8) * 8;
   c->g_iter = make_geom(c->ntiles_pad);
@@ -355,19 +360,20 @@ int ensure_batch(adef2_ctx* c, int B, int prec) {
   if ((rc = dalloc(c, &c->Finfo, (size_t)B * kk))) return rc;
   if ((rc = dalloc(c, &c->kept, (size_t)B * std::max(KP, 1)))) return rc;
   if ((rc = dalloc(c, &c->gram, (size_t)B * 2 * kk))) return rc;
+  const bool v64 = vec64(prec), m64 = mat64(prec);
   for (int j = 0; j < 5; ++j) {
-    if ((rc = dalloc(c, &c->v64[j], prec == ADEF2_FP64 ? BV : 0))) return rc;
-    if ((rc = dalloc(c, &c->v32[j], prec == ADEF2_FP64 ? 0 : BV))) return rc;
+    if ((rc = dalloc(c, &c->v64[j], v64 ? BV : 0))) return rc;
+    if ((rc = dalloc(c, &c->v32[j], v64 ? 0 : BV))) return rc;
   }
-  if ((rc = dalloc(c, &c->W64, prec == ADEF2_FP64 ? BN * KP : 0))) return rc;
-  if ((rc = dalloc(c, &c->W32, prec == ADEF2_FP64 ? 0 : BN * KP))) return rc;
-  if ((rc = dalloc(c, &c->dinv64, prec == ADEF2_FP64 ? BN : 0))) return rc;
-  if ((rc = dalloc(c, &c->dinv32, prec == ADEF2_FP64 ? 0 : BN))) return rc;
+  if ((rc = dalloc(c, &c->W64, m64 ? BN * KP : 0))) return rc;
+  if ((rc = dalloc(c, &c->W32, m64 ? 0 : BN * KP))) return rc;
+  if ((rc = dalloc(c, &c->dinv64, v64 ? BN : 0))) return rc;
+  if ((rc = dalloc(c, &c->dinv32, v64 ? 0 : BN))) return rc;
   if ((rc = dalloc(c, &c->x64, prec == ADEF2_FP64 ? 0 : BV))) return rc;
   if ((rc = dalloc(c, &c->r64, prec == ADEF2_FP64 ? 0 : BN))) return rc;
   if ((rc = dalloc(c, &c->x0pad, BV))) return rc;
   if ((rc = dalloc(c, &c->t64, c->factored ? BV : 0))) return rc;
-  if ((rc = dalloc(c, &c->t32, (c->factored && prec != ADEF2_FP64) ? BV : 0))) return rc;
+  if ((rc = dalloc(c, &c->t32, (c->factored && !v64) ? BV : 0))) return rc;
   if ((rc = dalloc(c, &c->Tm, c->factored ? BN * KP : 0))) return rc;
   // reduction scratch: enough for the iteration kernels (NV <= KP+2) and the
   // Gram kernel (NV = 2 KP^2); geometry is recomputed per call from B
@@ -420,7 +426,8 @@ int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
   // preconditioner and zeroed vectors
   dim3 g1((unsigned)cdiv(N, 256), B);
   const size_t BV = (size_t)B * c->vs;
-  if (c->prec == ADEF2_FP64) {
+  if (c->prec != ADEF2_FP64) fill<double>(c, c->x64, BV, 0.0);
+  if (vec64(c->prec)) {
     hipLaunchKernelGGL((k_dinv<double>), g1, dim3(256), 0, c->st, N, c->diag, c->masks, c->dinv64,
                        c->inst, c->o.precond == ADEF2_NONE);
     for (int j = 0; j < 5; ++j) fill<double>(c, c->v64[j], BV, 0.0);
@@ -435,13 +442,13 @@ int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
   fill<double>(c, c->t64, BV, 0.0);
   // coarse space
   if (c->KP > 0) {
-    const double wbytes = (c->prec == ADEF2_FP64 ? 8.0 : 4.0);
+    const double wbytes = (mat64(c->prec) ? 8.0 : 4.0);
     timed(c, KI_GRAM, (double)B * N * (c->D * 8.0 + c->KP * (8.0 + wbytes) + 1.0), [&] {
       if (c->factored) {
         hipLaunchKernelGGL(k_stencil_modes, dim3((unsigned)cdiv(N, 256), c->KP, B), dim3(256), 0,
                            c->st, op_geom(c), c->dia1_64, c->Z64, c->masks, c->KP, c->Tm);
       }
-      if (c->prec == ADEF2_FP64) launch_gram<double>(c, nullptr, c->W64);
+      if (mat64(c->prec)) launch_gram<double>(c, nullptr, c->W64);
       else launch_gram<float>(c, nullptr, c->W32);
     });
     timed(c, KI_COARSE, 0.0, [&] { launch_coarse(c); });
@@ -465,9 +472,9 @@ int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
   return worst;
 }
 
-template <typename V>
-IterArgs<V> iter_args(adef2_ctx* c) {
-  IterArgs<V> a{};
+template <typename V, typename M>
+IterArgs<V, M> iter_args(adef2_ctx* c) {
+  IterArgs<V, M> a{};
   a.op = op_geom(c);
   a.mask = c->masks;
   a.inst = c->inst;
@@ -477,23 +484,26 @@ IterArgs<V> iter_args(adef2_ctx* c) {
   a.g = c->g_iter;
   a.maxit = c->o.maxit;
   a.vs = c->vs;
+  if constexpr (sizeof(M) == 8) {
+    a.dia1 = (const M*)c->dia1_64;
+    a.dia = (const M*)c->dia64;
+    a.Z = (const M*)c->Z64;
+    a.W = (const M*)c->W64;
+  } else {
+    a.dia1 = (const M*)c->dia1_32;
+    a.dia = (const M*)c->dia32;
+    a.Z = (const M*)c->Z32;
+    a.W = (const M*)c->W32;
+  }
   if constexpr (sizeof(V) == 8) {
-    a.dia1 = (const V*)c->dia1_64;
     a.t = (V*)interior(c, c->t64);
-    a.dia = (const V*)c->dia64;
     a.dinv = (const V*)c->dinv64;
-    a.Z = (const V*)c->Z64;
-    a.W = (const V*)c->W64;
     a.x = (V*)interior(c, c->v64[0]); a.r = (V*)interior(c, c->v64[1]);
     a.z = (V*)interior(c, c->v64[2]); a.p = (V*)interior(c, c->v64[3]);
     a.w = (V*)interior(c, c->v64[4]);
   } else {
-    a.dia1 = (const V*)c->dia1_32;
     a.t = (V*)interior(c, c->t32);
-    a.dia = (const V*)c->dia32;
     a.dinv = (const V*)c->dinv32;
-    a.Z = (const V*)c->Z32;
-    a.W = (const V*)c->W32;
     a.x = (V*)interior(c, c->v32[0]); a.r = (V*)interior(c, c->v32[1]);
     a.z = (V*)interior(c, c->v32[2]); a.p = (V*)interior(c, c->v32[3]);
     a.w = (V*)interior(c, c->v32[4]);
@@ -501,29 +511,36 @@ IterArgs<V> iter_args(adef2_ctx* c) {
   return a;
 }
 
-// algorithmic bytes per launch (per instance: inactive rows only)
+// algorithmic bytes per launch (per instance: inactive rows only); wv / wm =
+// bytes per vector entry / per operator or panel entry
 struct ByteModel { double init, init2, pupdate, spmv, update, resid, accum; };
-ByteModel byte_model(const adef2_ctx* c, int prec) {
-  const double w = (prec == ADEF2_FP64) ? 8.0 : 4.0;
+// Only instances still iterating at the last poll are counted (a finished
+// instance's blocks exit at their first instruction).
+ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active = true) {
   const double k = c->KP > 0 ? (double)c->k : 0.0;
   double nI = 0.0;
-  for (auto v : c->nI_host) nI += (double)v;
-  const double N = (double)c->N * c->B;
+  int nact = 0;
+  for (int m = 0; m < c->B; ++m) {
+    const Inst& s = c->inst_h[m];
+    const bool act = sweep_active ? !(s.done || s.outer_done) : !s.outer_done;
+    if (act && m < (int)c->nI_host.size()) { nI += (double)c->nI_host[m]; ++nact; }
+  }
+  const double N = (double)c->N * nact;
   ByteModel b{};
-  b.init = nI * (8.0 + k * w + 2 * w) + N;
-  b.init2 = nI * (3 * k * w + 6 * w) + N;
-  b.pupdate = nI * (k * w + 3 * w) + N;            // z, Z (k), p -> p
+  b.init = nI * (8.0 + k * wm + 2 * wv) + N;
+  b.init2 = nI * (3 * k * wm + 6 * wv) + N;
+  b.pupdate = nI * (k * wm + 3 * wv) + N;            // z, Z (k), p -> p
   if (c->factored) {
     // inner pass t = A p on all rows (D1 diagonals, p, t), outer pass on
     // inactive rows (D diagonals of A^T, t, p, w)
-    b.spmv = N * (c->D1 * w + 2 * w) + nI * (c->D * w + 3 * w) + N;
+    b.spmv = N * (c->D1 * wm + 2 * wv) + nI * (c->D * wm + 3 * wv) + N;
     b.resid = N * (c->D1 * 8.0 + 16.0) + nI * (c->D * 8.0 + 8.0 * 4) + N;
   } else {
-    b.spmv = nI * (c->D * w + 2 * w) + N;           // D diagonals, p, w
+    b.spmv = nI * (c->D * wm + 2 * wv) + N;           // D diagonals, p, w
     b.resid = nI * (c->D * 8.0 + 8.0 * 3) + N;
   }
-  b.update = nI * (2 * k * w + 8 * w) + N;          // W, Z (k each), x p r w dinv -> x r z
-  b.accum = nI * (4.0 + 16.0) + N;
+  b.update = nI * (2 * k * wm + 8 * wv) + N;          // W, Z (k each), x p r w dinv -> x r z
+  b.accum = nI * (wv + 16.0) + N;
   return b;
 }
 
@@ -541,21 +558,22 @@ int poll(adef2_ctx* c, bool outer, bool* all_done) {
 
 // run one A-DEF2 sweep in precision V for all instances: init, init2, then
 // chunks of iterations until every instance's sweep is done
-template <typename V>
+template <typename V, typename M>
 int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale,
               double thresh_floor, int carry_dir) {
-  IterArgs<V> a = iter_args<V>(c);
+  IterArgs<V, M> a = iter_args<V, M>(c);
   a.src = src;
   a.x0 = x0pad;
   a.x0s = c->vs;
   a.thresh_scale = thresh_scale;
   a.thresh_floor = thresh_floor;
   a.carry_dir = carry_dir;
-  KTab<V> kt = pick<V>(c->KP, c->rpt);
-  dim3 grid(c->ntiles_pad, c->B), blk(IPB);
-  const ByteModel bm = byte_model(c, sizeof(V) == 8 ? ADEF2_FP64 : ADEF2_FP32_REFINE);
+  a.seg_maxit = (c->prec == ADEF2_FP64) ? 0 : c->o.segment_maxit;
+  KTab<V, M> kt = pick<V, M>(c->KP, c->rpt);
+  dim3 grid(c->ntiles_pad * c->B), blk(IPB);
+  ByteModel bm = byte_model(c, (double)sizeof(V), (double)sizeof(M), false);
   const OpGeom og = a.op;
-  auto st1 = stencil1_fn<V, V, V>(c->rpt);
+  auto st1 = stencil1_fn<M, V, V>(c->rpt);
   a.x0sv = x0pad;
   if (x0pad && c->factored) {
     // S x0 needs t = A x0 first (FP64 warm start, FP64 sweeps only)
@@ -577,6 +595,7 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
     if (launched > (int64_t)c->o.maxit + 2 * chunk)
       return fail(c, ADEF2_E_HIP, "iteration kernels made no progress");
     launched += chunk;
+    if (c->o.profile) bm = byte_model(c, (double)sizeof(V), (double)sizeof(M), true);
     for (int it = 0; it < chunk; ++it) {
       timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, c->st, a); });
       timed(c, KI_SPMV, bm.spmv, [&] {
@@ -611,15 +630,16 @@ int resid64(adef2_ctx* c, const double* b, const double* xpad, int first, int de
   ra.tol2 = tol * tol;
   ra.maxit = c->o.maxit;
   ra.max_sweeps = c->o.max_sweeps;
-  const ByteModel bm = byte_model(c, ADEF2_FP64);
+  ra.stall_steps = 4;
+  const ByteModel bm = byte_model(c, 8.0, 8.0, false);
   timed(c, KI_RESID, bm.resid, [&] {
     if (c->factored) {
-      hipLaunchKernelGGL((stencil1_fn<double, double, double>(c->rpt)), dim3(c->ntiles_pad, c->B),
+      hipLaunchKernelGGL((stencil1_fn<double, double, double>(c->rpt)), dim3(c->ntiles_pad * c->B),
                          dim3(IPB), 0, c->st, ra.op, c->dia1_64, xpad, interior(c, c->t64), c->vs,
                          c->inst, decide ? 2 : 0);
       ra.sv = interior(c, c->t64);
     }
-    hipLaunchKernelGGL(resid_fn(c->rpt), dim3(c->ntiles_pad, c->B), dim3(IPB), 0, c->st, ra);
+    hipLaunchKernelGGL(resid_fn(c->rpt), dim3(c->ntiles_pad * c->B), dim3(IPB), 0, c->st, ra);
   });
   HIPCHK(c, hipGetLastError());
   return ADEF2_OK;
@@ -634,7 +654,7 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
   for (int m = 0; m < B; ++m) {
     Inst& s = c->inst_h[m];
     s.iters = 0; s.sweep_iters = 0; s.done = 0; s.outer_done = 0; s.status = 0; s.sweeps = 0;
-    s.has_dir = 0; s.rho_end = 0.0;
+    s.has_dir = 0; s.rho_end = 0.0; s.stall = 0; s.rr64_best = INFINITY;
     s.rr = 0; s.rr64 = 0; s.bb64 = 0;
   }
   HIPCHK(c, hipMemcpyAsync(c->inst, c->inst_h, sizeof(Inst) * B, hipMemcpyHostToDevice, c->st));
@@ -649,7 +669,7 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
   int rc;
   double* xres = nullptr;
   if (c->prec == ADEF2_FP64) {
-    if ((rc = run_sweep<double>(c, b, x0p, tol * tol, 0.0, 0))) return rc;
+    if ((rc = run_sweep<double, double>(c, b, x0p, tol * tol, 0.0, 0))) return rc;
     xres = interior(c, c->v64[0]);
     if ((rc = resid64(c, b, xres, 1, 0, tol, false))) return rc;
   } else {
@@ -661,20 +681,29 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
     }
     if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, tol, true))) return rc;
     const double in2 = c->o.inner_rtol * c->o.inner_rtol;
-    const ByteModel bm = byte_model(c, ADEF2_FP32_REFINE);
+    const bool v64 = vec64(c->prec);
+    ByteModel bm = byte_model(c, v64 ? 8.0 : 4.0, 4.0, false);
     for (int sweep = 0;; ++sweep) {
       bool ad = false;
       if ((rc = poll(c, true, &ad))) return rc;
       if (ad) break;
       if (sweep > c->o.max_sweeps + 1) return fail(c, ADEF2_E_HIP, "refinement made no progress");
+      bm = byte_model(c, v64 ? 8.0 : 4.0, 4.0, false);
       // FP32 segment on the correction equation S d = r64; it ends when its
       // recurrence residual fell by inner_rtol (or below tol ||b|| / 2); the
       // FP64 residual then replaces it and the search direction carries on
-      if ((rc = run_sweep<float>(c, c->r64, nullptr, in2, 0.25 * tol * tol, sweep > 0))) return rc;
+      rc = v64 ? run_sweep<double, float>(c, c->r64, nullptr, in2, 0.25 * tol * tol, sweep > 0)
+               : run_sweep<float, float>(c, c->r64, nullptr, in2, 0.25 * tol * tol, sweep > 0);
+      if (rc) return rc;
       timed(c, KI_ACCUM, bm.accum, [&] {
-        hipLaunchKernelGGL(accum_fn(c->rpt), dim3(c->ntiles_pad, B), dim3(IPB), 0, c->st,
-                           op_geom(c), c->masks, interior(c, c->v32[0]), interior(c, c->x64),
-                           c->vs, c->inst);
+        if (v64)
+          hipLaunchKernelGGL(accum_fn<double>(c->rpt), dim3(c->ntiles_pad * B), dim3(IPB), 0, c->st,
+                             op_geom(c), c->masks, interior(c, c->v64[0]), interior(c, c->x64),
+                             c->vs, c->inst);
+        else
+          hipLaunchKernelGGL(accum_fn<float>(c->rpt), dim3(c->ntiles_pad * B), dim3(IPB), 0, c->st,
+                             op_geom(c), c->masks, interior(c, c->v32[0]), interior(c, c->x64),
+                             c->vs, c->inst);
       });
       if ((rc = resid64(c, b, interior(c, c->x64), 0, 1, tol, true))) return rc;
     }
@@ -700,9 +729,12 @@ int worst_of(int a, int b) {
 }
 
 bool valid_opts(const adef2_opts* o) {
-  return o->maxit > 0 && (o->precision == ADEF2_FP64 || o->precision == ADEF2_FP32_REFINE) &&
+  return o->maxit > 0 &&
+         (o->precision == ADEF2_FP64 || o->precision == ADEF2_FP32_REFINE ||
+          o->precision == ADEF2_MIXED_REFINE) &&
          (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
-         o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0;
+         o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0 &&
+         o->segment_maxit >= 0;
 }
 
 }  // namespace
@@ -721,8 +753,9 @@ void adef2_default_opts(adef2_opts* o) {
   o->precision = ADEF2_FP64;
   o->precond = ADEF2_JACOBI;
   o->inner_rtol = 1e-2;
-  o->max_sweeps = 500;
+  o->max_sweeps = 2000;
   o->check_every = 32;
+  o->segment_maxit = 1000;
   o->rows_per_thread = 0;
   o->profile = 0;
 }
@@ -1055,7 +1088,7 @@ int adef2_apply_restricted(adef2_ctx* c, const double* x, double* y) {
   hipLaunchKernelGGL(k_mask_copy_padded, g, dim3(256), 0, c->st, N, c->masks, x, tmp + c->H, c->vs);
   const double* sv = tmp + c->H;
   if (c->factored) {
-    hipLaunchKernelGGL((stencil1_fn<double, double, double>(c->rpt)), dim3(c->ntiles_pad, 1),
+    hipLaunchKernelGGL((stencil1_fn<double, double, double>(c->rpt)), dim3(c->ntiles_pad),
                        dim3(IPB), 0, c->st, op_geom(c), c->dia1_64, tmp + c->H,
                        interior(c, c->t64), c->vs, c->inst, 0);
     sv = interior(c, c->t64);

@@ -28,6 +28,8 @@ struct Inst {
   double cond;          // cond(E) of the orthonormalised coarse basis
   double bb64;          // ||b_I||^2 (FP64, outer)
   double rho_end;       // r.y at the end of the last sweep (direction carried over)
+  double rr64_prev;     // outer residual before the last one
+  double rr64_best;     // smallest outer residual so far
   double rr64;          // ||b_I - S_II x||^2 of the last outer residual
   int32_t iters;        // CG iterations, all sweeps
   int32_t sweep_iters;
@@ -41,6 +43,8 @@ struct Inst {
   int32_t k_eff;        // kept restricted modes
   int32_t sweeps;
   int32_t has_dir;      // a search direction from the previous sweep exists
+  int32_t stall;        // outer steps since the best residual last halved
+  int32_t pad2_;
   double coef[KMAX];    // coarse coefficients of the next x / p update
 };
 
@@ -147,6 +151,20 @@ __device__ inline bool tree_reduce(const RedGeom& g, int tile, int nv, double* p
 __device__ __forceinline__ int xcd_tile(int bid, int ntiles_pad) {
   const int per = ntiles_pad >> 3;
   return (bid & 7) * per + (bid >> 3);
+}
+
+// Block -> (tile, instance) for the batched iteration kernels, launched with
+// ntiles_pad * B one-dimensional blocks.  XCD x (blocks are dispatched to the
+// 8 XCDs round-robin) owns a contiguous range of tiles, and within an XCD the
+// B instances of one tile run back to back: the operator stencils and the
+// shared Z panel of a tile are then fetched from HBM about once per XCD and
+// re-used from its L2 by the other instances.
+__device__ __forceinline__ void tile_inst(int ntiles_pad, int& tile, int& m) {
+  const int B = gridDim.x / ntiles_pad;
+  const int bid = blockIdx.x;
+  const int j = bid >> 3;
+  tile = (bid & 7) * (ntiles_pad >> 3) + j / B;
+  m = j % B;
 }
 
 }  // namespace adef2

@@ -11,7 +11,7 @@
 //           sides, so the stencil reads i + offs[d] need no bounds test;
 //           entries on the active set are kept at exactly 0, which makes
 //           S (masked vector) restricted to inactive rows equal to S_II.
-// Every kernel processes rows of one instance per blockIdx.y.
+// Tile kernels map blocks to (tile, instance) with tile_inst().
 #pragma once
 #include "dev_common.h"
 
@@ -28,18 +28,48 @@ struct OpGeom {
   int ntiles_pad;    // multiple of 8 (XCD mapping)
   int offs[MAXD];
   int offs1[MAXD1];
+  int d0;            // slot of offset 0 in the outer stencil (-1: none)
+  int d01;           // slot of offset 0 in the inner stencil (-1: none)
 };
 
-template <typename V>
+// One row of a diagonal-format stencil, sum_d a_d[i] v[i + o_d].  FP32
+// coefficient arrays store, in the offset-0 slot, the row sum of the FP64
+// row instead of its diagonal entry, and are applied in difference form
+//   rowsum_i v_i + sum_{d != 0} a_d[i] (v[i + o_d] - v_i)
+// (the same value in exact arithmetic).  Rounding a coefficient to FP32 then
+// perturbs only a flux a_d (v_j - v_i), which is small on smooth v; in the
+// direct form the rounded coefficients no longer cancel (zero row sums of the
+// interior rows of a conservative stencil) and add an O(u32) zeroth-order
+// term that swamps the smallest eigenvalues of A^T A.
+template <typename M, typename VI>
+__device__ __forceinline__ double stencil_row(const M* dia, const int* offs, int D, int d0,
+                                              int64_t N, int64_t i, const VI* v) {
+  double acc = 0.0;
+  if constexpr (sizeof(M) == 4) {
+    if (d0 >= 0) {
+      const double vi = (double)v[i];
+      acc = (double)dia[(size_t)d0 * N + i] * vi;
+      for (int d = 0; d < D; ++d)
+        if (d != d0) acc += (double)dia[(size_t)d * N + i] * ((double)v[i + offs[d]] - vi);
+      return acc;
+    }
+  }
+  for (int d = 0; d < D; ++d) acc += (double)dia[(size_t)d * N + i] * (double)v[i + offs[d]];
+  return acc;
+}
+
+// V: type of the per-instance vectors; M: type of the operator values and of
+// the Z / W panels (FP32 in the mixed-precision modes).
+template <typename V, typename M>
 struct IterArgs {
   OpGeom op;
-  const V* dia;            // [D][N] outer stencil
-  const V* dia1;           // [D1][N] inner stencil (factored operator)
+  const M* dia;            // [D][N] outer stencil
+  const M* dia1;           // [D1][N] inner stencil (factored operator)
   V* t;                    // padded inner product A p (factored operator)
   const uint8_t* mask;     // [B][N]
   const V* dinv;           // [B][N]
-  const V* Z;              // [KP][N]
-  const V* W;              // [B][KP][N]
+  const M* Z;              // [KP][N]
+  const M* W;              // [B][KP][N]
   V* x; V* r; V* z; V* p; V* w;   // padded, pointer to instance 0 interior
   int64_t vs;              // padded vector stride
   Inst* inst;              // [B]
@@ -56,6 +86,7 @@ struct IterArgs {
   double thresh_scale;     // thresh2 = max(thresh_scale * ||src_I||^2,
   double thresh_floor;     //               thresh_floor * ||b_I||^2)
   int32_t carry_dir;       // keep the previous sweep's search direction
+  int32_t seg_maxit;       // a sweep ends after this many iterations (0 = none)
 };
 
 template <int RPT> struct Rows { static constexpr int PB = IPB * RPT; };
@@ -66,8 +97,8 @@ template <int RPT> struct Rows { static constexpr int PB = IPB * RPT; };
 // w, w + NIWAVE, ..., and each lane walks the tile rows lane, lane + 64, ...
 // with the vector read from LDS, so every column load is a coalesced 512-byte
 // wave access and each lane keeps one accumulator.
-template <typename V, int RPT>
-__device__ __forceinline__ double panel_dot(const V* col, int64_t base, const double* vec,
+template <typename M, int RPT>
+__device__ __forceinline__ double panel_dot(const M* col, int64_t base, const double* vec,
                                             const uint8_t* act) {
   constexpr int R = Rows<RPT>::PB;
   const int lane = threadIdx.x & 63;
@@ -81,8 +112,8 @@ __device__ __forceinline__ double panel_dot(const V* col, int64_t base, const do
 // ---------------------------------------------------------------------------
 // init: r0 = src - S x0 (or src), g = Z^T r0, ||src||^2;  finisher: c0 = C g
 // ---------------------------------------------------------------------------
-template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(IPB) k_init(IterArgs<V> a) {
+template <typename V, typename M, int KP, int RPT>
+__global__ void __launch_bounds__(IPB) k_init(IterArgs<V, M> a) {
   constexpr int R = Rows<RPT>::PB;
   constexpr int NV = KP + 1;
   __shared__ double vl[R];
@@ -90,10 +121,10 @@ __global__ void __launch_bounds__(IPB) k_init(IterArgs<V> a) {
   __shared__ double red[NIWAVE];
   __shared__ double bv[NV];
   __shared__ double tot[NV];
-  const int m = blockIdx.y;
+  int tile, m;
+  tile_inst(a.op.ntiles_pad, tile, m);
   Inst* S = a.inst + m;
   if (S->outer_done) return;
-  const int tile = xcd_tile(blockIdx.x, a.op.ntiles_pad);
   const int64_t N = a.op.N;
   const int64_t base = (int64_t)tile * R;
   const uint8_t* mk = a.mask + (size_t)m * N;
@@ -133,7 +164,7 @@ __global__ void __launch_bounds__(IPB) k_init(IterArgs<V> a) {
   }
   const int wid = threadIdx.x >> 6;
   for (int q = wid; q < KP; q += NIWAVE) {
-    const double s = panel_dot<V, RPT>(a.Z + (size_t)q * N, base, vl, act);
+    const double s = panel_dot<M, RPT>(a.Z + (size_t)q * N, base, vl, act);
     if ((threadIdx.x & 63) == 0) bv[q] = s;
   }
   __syncthreads();
@@ -195,9 +226,9 @@ __device__ __forceinline__ double adef2_direction(const double* Cm, const double
 
 // Second half of init2 / update: block sums of [W^T z | Z^T r | r.z | r.r]
 // for the tile (z, r already in LDS), then the reduction tree.
-template <typename V, int KP, int RPT>
-__device__ __forceinline__ bool reduce_directions(const IterArgs<V>& a, int m, int tile, int64_t base,
-                                                  const V* W, bool defl, double rz, double rr2,
+template <typename V, typename M, int KP, int RPT>
+__device__ __forceinline__ bool reduce_directions(const IterArgs<V, M>& a, int m, int tile, int64_t base,
+                                                  const M* W, bool defl, double rz, double rr2,
                                                   const double* zl, const double* rl,
                                                   const uint8_t* act, double* red, double* bv,
                                                   double* tot) {
@@ -211,8 +242,8 @@ __device__ __forceinline__ bool reduce_directions(const IterArgs<V>& a, int m, i
   for (int q = wid; q < 2 * KP; q += NIWAVE) {
     double s = 0.0;
     if (defl) {
-      s = (q < KP) ? panel_dot<V, RPT>(W + (size_t)q * N, base, zl, act)
-                   : panel_dot<V, RPT>(a.Z + (size_t)(q - KP) * N, base, rl, act);
+      s = (q < KP) ? panel_dot<M, RPT>(W + (size_t)q * N, base, zl, act)
+                   : panel_dot<M, RPT>(a.Z + (size_t)(q - KP) * N, base, rl, act);
     }
     if ((threadIdx.x & 63) == 0) bv[q] = s;
   }
@@ -225,8 +256,8 @@ __device__ __forceinline__ bool reduce_directions(const IterArgs<V>& a, int m, i
 // ---------------------------------------------------------------------------
 // init2: x += Z c0, r -= W c0, z = K r;  W^T z, Z^T r, r.z, ||r||^2
 // ---------------------------------------------------------------------------
-template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(IPB) k_init2(IterArgs<V> a) {
+template <typename V, typename M, int KP, int RPT>
+__global__ void __launch_bounds__(IPB) k_init2(IterArgs<V, M> a) {
   constexpr int R = Rows<RPT>::PB;
   constexpr int NV = 2 * KP + 2;
   __shared__ double zl[R], rl[R];
@@ -235,10 +266,10 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V> a) {
   __shared__ double bv[NV];
   __shared__ double tot[NV];
   __shared__ double cf[KP > 0 ? KP : 1];
-  const int m = blockIdx.y;
+  int tile, m;
+  tile_inst(a.op.ntiles_pad, tile, m);
   Inst* S = a.inst + m;
   if (S->outer_done) return;
-  const int tile = xcd_tile(blockIdx.x, a.op.ntiles_pad);
   const int64_t N = a.op.N;
   const int64_t base = (int64_t)tile * R;
   const uint8_t* mk = a.mask + (size_t)m * N;
@@ -255,7 +286,7 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V> a) {
   V* r = a.r + m * a.vs;
   V* z = a.z + m * a.vs;
   const V* dinv = a.dinv + (size_t)m * N;
-  const V* W = a.W + (size_t)m * KP * N;
+  const M* W = a.W + (size_t)m * KP * N;
   const bool defl = S->kk > 0;
   for (int q = threadIdx.x; q < KP; q += blockDim.x) cf[q] = S->coef[q];
   __syncthreads();
@@ -291,7 +322,7 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V> a) {
     act[j] = !on;
   }
   __syncthreads();
-  if (!reduce_directions<V, KP, RPT>(a, m, tile, base, W, defl, rz, rr2, zl, rl, act, red, bv, tot))
+  if (!reduce_directions<V, M, KP, RPT>(a, m, tile, base, W, defl, rz, rr2, zl, rl, act, red, bv, tot))
     return;
   const bool stop = !(tot[2 * KP + 1] > S->thresh2);
   double rho = 0.0;
@@ -299,7 +330,9 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V> a) {
   if (threadIdx.x == 0) {
     S->rr = tot[2 * KP + 1];
     // residual replacement: continue the previous direction, p = y + beta p
-    const bool carry = a.carry_dir && S->has_dir && S->rho_end > 0.0 && rho > 0.0;
+    // carried only while the FP64 residual keeps decreasing
+    const bool carry = a.carry_dir && S->has_dir && S->rho_end > 0.0 && rho > 0.0 &&
+                       S->rr64 < S->rr64_prev;
     S->beta = carry ? rho / S->rho_end : 0.0;
     S->fresh = carry ? 0 : 1;
     S->rho = rho;
@@ -310,13 +343,13 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V> a) {
 // ---------------------------------------------------------------------------
 // p = z - Z c + beta p   (A-DEF2 search direction)
 // ---------------------------------------------------------------------------
-template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(IPB) k_pupdate(IterArgs<V> a) {
+template <typename V, typename M, int KP, int RPT>
+__global__ void __launch_bounds__(IPB) k_pupdate(IterArgs<V, M> a) {
   __shared__ double cf[KP > 0 ? KP : 1];
-  const int m = blockIdx.y;
+  int tile, m;
+  tile_inst(a.op.ntiles_pad, tile, m);
   const Inst* S = a.inst + m;
   if (S->done) return;
-  const int tile = xcd_tile(blockIdx.x, a.op.ntiles_pad);
   if (tile >= a.op.ntiles) return;
   const int64_t N = a.op.N;
   const uint8_t* mk = a.mask + (size_t)m * N;
@@ -345,15 +378,15 @@ __global__ void __launch_bounds__(IPB) k_pupdate(IterArgs<V> a) {
 // ---------------------------------------------------------------------------
 // w = S_II p, p.w;  finisher: alpha = rho / p.w
 // ---------------------------------------------------------------------------
-template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(IPB) k_spmv(IterArgs<V> a) {
+template <typename V, typename M, int KP, int RPT>
+__global__ void __launch_bounds__(IPB) k_spmv(IterArgs<V, M> a) {
   __shared__ double red[NIWAVE];
   __shared__ double bv[1];
   __shared__ double tot[1];
-  const int m = blockIdx.y;
+  int tile, m;
+  tile_inst(a.op.ntiles_pad, tile, m);
   Inst* S = a.inst + m;
   if (S->done) return;
-  const int tile = xcd_tile(blockIdx.x, a.op.ntiles_pad);
   const int64_t N = a.op.N;
   const uint8_t* mk = a.mask + (size_t)m * N;
   const V* p = a.p + m * a.vs;
@@ -366,9 +399,7 @@ __global__ void __launch_bounds__(IPB) k_spmv(IterArgs<V> a) {
     for (int rr = 0; rr < RPT; ++rr) {
       const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
       if (i < N && mk[i] == 0) {
-        double acc = 0.0;
-        for (int d = 0; d < a.op.D; ++d)
-          acc += (double)a.dia[(size_t)d * N + i] * (double)sv[i + a.op.offs[d]];
+        const double acc = stencil_row(a.dia, a.op.offs, a.op.D, a.op.d0, N, i, sv);
         const double pi = (double)p[i];
         const double wv = sa * acc + sc * pi;
         w[i] = (V)wv;
@@ -397,8 +428,8 @@ __global__ void __launch_bounds__(IPB) k_spmv(IterArgs<V> a) {
 // x += alpha p, r -= alpha w, z = K r;  W^T z, Z^T r, r.z, ||r||^2
 // finisher: stopping test on ||r||, beta = r.y / rho, coarse coordinates
 // ---------------------------------------------------------------------------
-template <typename V, int KP, int RPT>
-__global__ void __launch_bounds__(IPB) k_update(IterArgs<V> a) {
+template <typename V, typename M, int KP, int RPT>
+__global__ void __launch_bounds__(IPB) k_update(IterArgs<V, M> a) {
   constexpr int R = Rows<RPT>::PB;
   constexpr int NV = 2 * KP + 2;
   __shared__ double zl[R], rl[R];
@@ -406,10 +437,10 @@ __global__ void __launch_bounds__(IPB) k_update(IterArgs<V> a) {
   __shared__ double red[NIWAVE * 2];
   __shared__ double bv[NV];
   __shared__ double tot[NV];
-  const int m = blockIdx.y;
+  int tile, m;
+  tile_inst(a.op.ntiles_pad, tile, m);
   Inst* S = a.inst + m;
   if (S->done) return;
-  const int tile = xcd_tile(blockIdx.x, a.op.ntiles_pad);
   const int64_t N = a.op.N;
   const int64_t base = (int64_t)tile * R;
   const uint8_t* mk = a.mask + (size_t)m * N;
@@ -419,7 +450,7 @@ __global__ void __launch_bounds__(IPB) k_update(IterArgs<V> a) {
   const V* p = a.p + m * a.vs;
   const V* w = a.w + m * a.vs;
   const V* dinv = a.dinv + (size_t)m * N;
-  const V* W = a.W + (size_t)m * KP * N;
+  const M* W = a.W + (size_t)m * KP * N;
   const bool defl = S->kk > 0;
   const double alpha = S->alpha;
   double rz = 0.0, rr2 = 0.0;
@@ -446,7 +477,7 @@ __global__ void __launch_bounds__(IPB) k_update(IterArgs<V> a) {
     act[j] = !on;
   }
   __syncthreads();
-  if (!reduce_directions<V, KP, RPT>(a, m, tile, base, W, defl, rz, rr2, zl, rl, act, red, bv, tot))
+  if (!reduce_directions<V, M, KP, RPT>(a, m, tile, base, W, defl, rz, rr2, zl, rl, act, red, bv, tot))
     return;
   __shared__ int s_go;
   if (threadIdx.x == 0) {
@@ -455,7 +486,7 @@ __global__ void __launch_bounds__(IPB) k_update(IterArgs<V> a) {
     S->sweep_iters += 1;
     S->rr = rrt;
     int go = 0;
-    if (!(rrt > S->thresh2)) {
+    if (!(rrt > S->thresh2) || (a.seg_maxit > 0 && S->sweep_iters >= a.seg_maxit)) {
       S->done = 1;
       go = 2;                       // sweep ends: keep r.y for the next sweep
       if (!(rrt < INFINITY)) { S->outer_done = 1; S->status = -5; go = 0; }
@@ -502,6 +533,7 @@ struct ResidArgs {
   int32_t decide;          // apply the outer stopping rule
   double tol2;
   int32_t maxit, max_sweeps;
+  int32_t stall_steps;     // outer steps without halving before W_STAGNATED
 };
 
 template <int RPT>
@@ -509,10 +541,10 @@ __global__ void __launch_bounds__(IPB) k_resid64(ResidArgs a) {
   __shared__ double red[NIWAVE * 2];
   __shared__ double bv[2];
   __shared__ double tot[2];
-  const int m = blockIdx.y;
+  int tile, m;
+  tile_inst(a.op.ntiles_pad, tile, m);
   Inst* S = a.inst + m;
   if (S->outer_done && a.decide) return;
-  const int tile = xcd_tile(blockIdx.x, a.op.ntiles_pad);
   const int64_t N = a.op.N;
   const uint8_t* mk = a.mask + (size_t)m * N;
   const double* b = a.b + (size_t)m * N;
@@ -540,12 +572,19 @@ __global__ void __launch_bounds__(IPB) k_resid64(ResidArgs a) {
   unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
   if (!tree_reduce(a.g, tile, 2, part, ctr, bv, tot)) return;
   if (threadIdx.x == 0) {
+    S->rr64_prev = a.first ? INFINITY : S->rr64;
     S->rr64 = tot[0];
     if (a.first) S->bb64 = tot[1];
     if (a.decide) {
       const double bb = S->bb64;
-      if (!(bb < INFINITY) || !(tot[0] < INFINITY)) { S->outer_done = 1; S->status = -1; }
-      else if (!(tot[0] > a.tol2 * bb)) { S->outer_done = 1; }
+      const double r2 = tot[0];
+      // attainable-accuracy guard: the best FP64 residual has not halved
+      // over the last STALL_STEPS outer steps
+      if (a.first || r2 < 0.25 * S->rr64_best) { S->rr64_best = r2; S->stall = 0; }
+      else S->stall += 1;
+      if (!(bb < INFINITY) || !(r2 < INFINITY)) { S->outer_done = 1; S->status = -1; }
+      else if (!(r2 > a.tol2 * bb)) { S->outer_done = 1; }
+      else if (S->stall >= a.stall_steps) { S->outer_done = 1; S->status = 3; }
       else if (S->iters >= a.maxit || S->sweeps >= a.max_sweeps) { S->outer_done = 1; S->status = 2; }
       S->done = 1;
     }
@@ -558,10 +597,10 @@ __global__ void __launch_bounds__(IPB) k_resid64(ResidArgs a) {
 template <typename VM, typename VI, typename VO, int RPT>
 __global__ void __launch_bounds__(IPB) k_stencil1(OpGeom op, const VM* dia1, const VI* v, VO* t,
                                                   int64_t vs, const Inst* inst, int skip) {
-  const int m = blockIdx.y;
+  int tile, m;
+  tile_inst(op.ntiles_pad, tile, m);
   const Inst* S = inst + m;
   if ((skip == 1 && S->done) || (skip == 2 && S->outer_done)) return;
-  const int tile = xcd_tile(blockIdx.x, op.ntiles_pad);
   if (tile >= op.ntiles) return;
   const int64_t N = op.N;
   const VI* vm = v + m * vs;
@@ -570,21 +609,19 @@ __global__ void __launch_bounds__(IPB) k_stencil1(OpGeom op, const VM* dia1, con
   for (int rr = 0; rr < RPT; ++rr) {
     const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
     if (i < N) {
-      double acc = 0.0;
-      for (int e = 0; e < op.D1; ++e) acc += (double)dia1[(size_t)e * N + i] * (double)vm[i + op.offs1[e]];
-      tm[i] = (VO)acc;
+      tm[i] = (VO)stencil_row(dia1, op.offs1, op.D1, op.d01, N, i, vm);
     }
   }
 }
 
 // x64 += d (FP32 correction of the last sweep)
-template <int RPT>
-__global__ void __launch_bounds__(IPB) k_accumulate(OpGeom op, const uint8_t* mask, const float* d,
+template <typename V, int RPT>
+__global__ void __launch_bounds__(IPB) k_accumulate(OpGeom op, const uint8_t* mask, const V* d,
                                                     double* x64, int64_t vs, Inst* inst) {
-  const int m = blockIdx.y;
+  int tile, m;
+  tile_inst(op.ntiles_pad, tile, m);
   Inst* S = inst + m;
   if (S->outer_done) return;
-  const int tile = xcd_tile(blockIdx.x, op.ntiles_pad);
   if (tile >= op.ntiles) return;
   const int64_t N = op.N;
   const uint8_t* mk = mask + (size_t)m * N;
@@ -593,7 +630,7 @@ __global__ void __launch_bounds__(IPB) k_accumulate(OpGeom op, const uint8_t* ma
     const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
     if (i < N && mk[i] == 0) x64[m * vs + i] += (double)d[m * vs + i];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) S->sweeps += 1;
+  if (tile == 0 && threadIdx.x == 0) S->sweeps += 1;
 }
 
 // out[i] = x[i] on inactive rows, 0 on active rows (instance-major, unpadded)

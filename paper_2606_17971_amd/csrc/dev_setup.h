@@ -135,7 +135,8 @@ __global__ void k_csr_to_dia(int64_t n, const int64_t* rp, const int* col, const
   if (i >= n) return;
   const int D = which ? op.D1 : op.D;
   const int* offs = which ? op.offs1 : op.offs;
-  double dg = 0.0;
+  double dg = 0.0, rs = 0.0;
+  int slot0 = -1;
   for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
     const int off = (int)((int64_t)col[e] - i);
     int lo = 0, hi = D - 1;
@@ -148,8 +149,14 @@ __global__ void k_csr_to_dia(int64_t n, const int64_t* rp, const int* col, const
     if (!(v == v) || v == INFINITY || v == -INFINITY) *bad = 2;
     dia64[(size_t)lo * n + i] = v;
     dia32[(size_t)lo * n + i] = (float)v;
-    if (off == 0) dg = v;
+    rs += v;
+    if (off == 0) { dg = v; slot0 = lo; }
   }
+  // FP32 copy in difference form: the offset-0 slot holds the FP64 row sum
+  // (also for a row that has no diagonal entry of its own)
+  for (int d = 0; d < D; ++d)
+    if (offs[d] == 0) slot0 = d;
+  if (slot0 >= 0) dia32[(size_t)slot0 * n + i] = (float)rs;
   if (!which) {
     diag[i] = dg;
     if (!(dg > 0.0)) *bad = 3;
@@ -165,7 +172,8 @@ __global__ void k_dia_transpose(OpGeom op, const double* A64, double* AT64, floa
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = op.N;
   if (i >= n) return;
-  double cn = 0.0;
+  double cn = 0.0, rs = 0.0;
+  int slot0 = -1;
   for (int d = 0; d < op.D1; ++d) {
     const int64_t j = i - op.offs1[d];
     const double v = (j >= 0 && j < n) ? A64[(size_t)d * n + j] : 0.0;
@@ -173,7 +181,11 @@ __global__ void k_dia_transpose(OpGeom op, const double* A64, double* AT64, floa
     AT64[(size_t)dt * n + i] = v;
     AT32[(size_t)dt * n + i] = (float)v;
     cn += v * v;
+    rs += v;
+    if (op.offs1[d] == 0) slot0 = dt;   // offsets of A^T are -offs1: offset 0 maps to itself
   }
+  // FP32 copy in difference form (row sum of A^T in the offset-0 slot)
+  if (slot0 >= 0) AT32[(size_t)slot0 * n + i] = (float)rs;
   diag[i] = cn;
 }
 
