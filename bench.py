@@ -2,11 +2,17 @@
 convection-diffusion Schur complement (k = 32 reference modes, 16 instances
 with 10-40 % active, rel. residual 1e-10).
 
-One step = restrict + coarse setup + solve for all 16 instances.
-  headline : all 16 instances in one batched launch sequence (precision per
-             --precision, default mixed: FP32 operator and panels, FP64
-             vectors, FP64 residual replacement)
+One step = MLP inference + basis enrichment + restrict + coarse setup +
+solve for all 16 instances.
+  headline : all 16 instances in one batched launch sequence with the
+             learned enrichment (8 vectors from the problem parameters) and
+             precision per --precision (default mixed: FP32 operator and
+             panels, FP64 vectors, FP64 residual replacement)
+  batched  : the same without enrichment (reference modes only)
   plain    : FP64 A-DEF2, one instance at a time
+Before timing, the enrichment is fitted once: GPU solves of --train family
+members (snapshots), their POD on the GPU, and --train-steps Adam steps of
+the MLP on the GPU.
 Prints one JSON line (see the contract in the repository README / DESIGN).
 """
 from __future__ import annotations
@@ -38,6 +44,13 @@ def parse():
     ap.add_argument("--precision", choices=["mixed", "fp32", "fp64"], default="mixed")
     ap.add_argument("--inner-rtol", type=float, default=1e-2)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batched-compare", action="store_true")
+    ap.add_argument("--train", type=int, default=40, help="snapshot solves for the enrichment")
+    ap.add_argument("--pod", type=int, default=32, help="POD modes the MLP combines")
+    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--snap-tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=200,
                     help="oracle iterations timed for the CPU baseline sample")
@@ -70,6 +83,40 @@ def cpu_baseline(w, S_spec, iters_ref: float, n_iter: int):
             "seconds_per_solve": per_solve}
 
 
+def fit_enrichment(solver, args, lib):
+    """Fit the learned enrichment of solver on GPU data: snapshot solves of
+    args.train family members (parameter seed 700, disjoint from the timed
+    instances), POD of the snapshots, MLP training.  Returns a summary."""
+    import torch
+
+    import gen
+    t0 = time.perf_counter()
+    th = gen.c2_thetas(args.train, 700)
+    insts = [gen.c2_family_instance(args.n, t) for t in th]
+    m_tr = torch.as_tensor(np.stack([i.mask for i in insts]), device="cuda")
+    b_tr = torch.as_tensor(np.stack([i.b for i in insts]), device="cuda")
+    th_tr = torch.as_tensor(th.astype(np.float32), device="cuda")
+    t1 = time.perf_counter()
+    snap = solver.solve_batched(m_tr, b_tr, args.snap_tol)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"[bench] {args.train} snapshot solves in {t2 - t1:.1f}s", file=sys.stderr, flush=True)
+    X = snap["x"]
+    Phi, sig = solver.pod(X.T, args.pod)
+    solver.learned_set_params(gen.mlp_params(1))
+    solver.learned_prepare(m_tr, b_tr, X, th_tr)
+    hist = solver.learned_train(args.train_steps, lr=args.lr)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    print(f"[bench] POD + {args.train_steps} training steps in {t3 - t2:.1f}s "
+          f"(loss {hist[0]:.4f} -> {hist[-1]:.4f})", file=sys.stderr, flush=True)
+    return {"snapshots": args.train, "snapshot_tol": args.snap_tol, "pod_modes": args.pod,
+            "sigma_ratio_last": float(sig[-1] / sig[0]), "train_steps": args.train_steps,
+            "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+            "snapshot_s": round(t2 - t1, 2), "fit_s": round(t3 - t2, 2),
+            "inputs_s": round(t1 - t0, 2)}, Phi
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -94,9 +141,12 @@ def main():
 
     head = lib.Solver(precision=prec, inner_rtol=args.inner_rtol)
     head.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    thetas = torch.as_tensor(np.stack([i.theta for i in w.instances]).astype(np.float32), device="cuda")
+    learned, Phi = (None, None) if args.no_learned else fit_enrichment(head, args, lib)
+    use_theta = None if args.no_learned else thetas
 
     def head_step():
-        return head.solve_batched(masks, bs, args.tol)
+        return head.solve_batched(masks, bs, args.tol, theta=use_theta)
 
     for _ in range(args.warmup):
         out = head_step()
@@ -110,6 +160,18 @@ def main():
     head_iters = np.asarray(out["iters"])
     head_rel = np.asarray(out["relres_true"])
     X_head = out["x"].clone()
+
+    batched = None
+    if learned is not None and not args.no_batched_compare:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ob = head.solve_batched(masks, bs, args.tol)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        bi = np.asarray(ob["iters"])
+        batched = {"solves_per_s": B / t_b, "ms_per_step": t_b * 1e3, "iters_mean": float(bi.mean()),
+                   "iters_max": int(bi.max()), "relres_true_max": float(np.asarray(ob["relres_true"]).max())}
+        print(f"[bench] batched (reference modes only) done ({t_b:.2f}s)", file=sys.stderr, flush=True)
 
     plain = None
     if not args.no_plain:
@@ -142,7 +204,10 @@ def main():
     # roofline: one instrumented headline step, HIP events around every launch
     prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1)
     prof.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
-    prof.solve_batched(masks, bs, args.tol)
+    if learned is not None:
+        prof.set_pod_modes(Phi)
+        prof.learned_set_params(head.learned_get_params())
+    prof.solve_batched(masks, bs, args.tol, theta=use_theta)
     st = prof.stats()
     dom = max(st, key=lambda k: st[k]["ms"])
     d = st[dom]
@@ -171,10 +236,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"cd2d_upwind_{args.n}x{args.n}_k{args.k}_B{B}", "grid": args.n,
                    "N": op.N, "k": args.k, "instances": B, "tol": args.tol,
-                   "mode": "batched", "precision": args.precision,
+                   "mode": "batched" if args.no_learned else "batched+learned",
+                   "precision": args.precision,
                    "operator": "S = alpha A^T A + shift I (A: 5-point upwind, factored)"},
         "iters": {"mean": float(head_iters.mean()), "min": int(head_iters.min()),
                   "max": int(head_iters.max())},
+        "learned_used": (int(np.asarray(out["learned"]).sum()) if learned is not None else 0),
+        "learned_fit": learned,
+        "batched_reference_modes": batched,
         "relres_true_max": float(head_rel.max()),
         "plain": plain,
         "speedup_vs_plain": (round(value / plain["solves_per_s"], 3) if plain else None),

@@ -36,7 +36,7 @@ __all__ = [
     "laplacian_2d", "upwind_2d", "diffusion_2d", "diffusion_3d",
     "sinusoid_field", "gaussian_field_2d", "inclusion_field_3d",
     "mask_top_fraction", "gaussian_bump", "sine_modes_2d",
-    "c1_workload", "c2_workload", "c3_workload", "c5_workload",
+    "c1_workload", "c2_workload", "c2_family_instance", "c2_thetas", "mlp_params", "c3_workload", "c5_workload",
     "cache_dir",
 ]
 
@@ -427,28 +427,59 @@ def c2_operator(n: int = 511, theta: float = math.pi / 6, peclet: float = 50.0):
     return op, K
 
 
+def c2_family_instance(n: int, theta, field_seed: int = 100) -> Instance:
+    """One member of the 4-parameter convection-diffusion family.
+
+    theta in [0, 1]^4: active fraction 0.10 + 0.30 theta0 (top quantile of one
+    fixed sinusoid field, seed 100, shifted in phase by 2 pi theta3), source
+    centre (0.2 + 0.6 theta1, 0.2 + 0.6 theta2), Gaussian bump of width 0.05.
+    """
+    t = np.asarray(theta, dtype=np.float64)
+    rho = 0.10 + 0.30 * t[0]
+    f = sinusoid_field(n, field_seed, phase_shift=2.0 * np.pi * t[3])
+    mask = mask_top_fraction(f, rho)
+    b = gaussian_bump(n, (0.2 + 0.6 * t[1], 0.2 + 0.6 * t[2]))
+    return Instance(mask=mask, b=b, theta=t.copy())
+
+
+def c2_thetas(count: int, seed: int, spread_rho: bool = False) -> np.ndarray:
+    th = np.random.default_rng(seed).uniform(0.0, 1.0, size=(count, 4))
+    if spread_rho:
+        th[:, 0] = np.arange(count) / max(count - 1, 1)
+    return th
+
+
 def c2_workload(n: int = 511, k: int = 32, B: int = 16, theta: float = math.pi / 6,
-                peclet: float = 50.0, seed0: int = 100) -> Workload:
+                peclet: float = 50.0, seed0: int = 200) -> Workload:
     """2D convection-diffusion, upwind K, S = K^T M_L^{-1} K + 1e-2 M_L.
 
-    Instance m: mask = top rho_m of the sinusoid field with seed 100+m,
-    rho_m = 0.10 + 0.30 m/(B-1); b_m = Gaussian bump of width 0.05 centred at
-    c_m ~ U[0.2, 0.8]^2 (seed 200+m).  Z = k lowest eigenvectors of S.
+    B instances of the 4-parameter family (c2_family_instance) with active
+    fractions spread evenly over 10-40 % (theta0 = m/(B-1)) and the other
+    parameters ~ U[0,1] (seed 200).  Z = k lowest eigenvectors of S.
     """
     op, K = c2_operator(n, theta, peclet)
     Z = _cached(f"c2_Z_n{n}_k{k}_t{theta:.6f}_pe{peclet:g}",
                 lambda: _low_right_singular(K, k)) if k > 0 else np.zeros((op.N, 0), order="F")
     Z = np.asfortranarray(Z)
-    insts = []
-    for m in range(B):
-        rho = 0.10 + 0.30 * m / max(B - 1, 1)
-        mask = mask_top_fraction(sinusoid_field(n, seed0 + m), rho)
-        cen = np.random.default_rng(seed0 + 100 + m).uniform(0.2, 0.8, size=2)
-        b = gaussian_bump(n, cen)
-        th = np.array([rho, cen[0], cen[1], 0.0])
-        insts.append(Instance(mask=mask, b=b, theta=th))
+    insts = [c2_family_instance(n, th) for th in c2_thetas(B, seed0, spread_rho=True)]
     return Workload(name=f"c2_cd2d_n{n}_k{k}_B{B}", op=op, Z=Z, instances=insts, tol=1e-10,
                     meta={"theta": theta, "peclet": peclet})
+
+
+MLP_DIMS = (4, 128, 128, 512)
+
+
+def mlp_params(seed: int = 0) -> np.ndarray:
+    """Seeded initial parameters of the theta -> C network, packed FP32:
+    W1 (128x4), b1, W2 (128x128), b2, W3 (512x128), b3, weights row-major
+    [out][in].  He-uniform weights (last layer scaled by 0.1), zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(3):
+        lim = math.sqrt(6.0 / MLP_DIMS[l]) * (0.1 if l == 2 else 1.0)
+        W = rng.uniform(-lim, lim, size=(MLP_DIMS[l + 1], MLP_DIMS[l])).astype(np.float32)
+        parts += [W.ravel(), np.zeros(MLP_DIMS[l + 1], dtype=np.float32)]
+    return np.concatenate(parts)
 
 
 def c3_operator(n: int = 255, seed: int = 300):

@@ -187,14 +187,62 @@ int adef2_solve(adef2_ctx *ctx, const double *b, const double *x0, double tol,
  * and Z; per-instance masks, operator scales and right-hand sides).
  *   masks: device uint8[B*n]; b, x: device f64[B*n] (instance-major).
  *   a, c : host f64[B] operator scales (S_m = a_m S_ref + c_m I), or NULL (1, 0).
+ *   theta: device f32[B*4] problem parameters, or NULL.  When given (after
+ *          adef2_pod / adef2_set_pod_modes and adef2_learned_set_params), each
+ *          instance's coarse basis is [Z_I, V_I] with V = Phi C(theta)^T, the 8
+ *          learned enrichment vectors; if cond(E) of that basis exceeds
+ *          tau_learned (or its setup fails) the instance falls back to the
+ *          plain restricted reference modes (Alg. 2's conditioning guard used
+ *          as the safeguard of the learned addition).
  *   tol  : relative tolerance, as in adef2_solve.
  *   iters, status (enum adef2_status per instance), relres_true, cond_E,
- *   n_inactive: host arrays of B entries (each may be NULL).
+ *   n_inactive, learned (1 = learned vectors in use): host arrays of B entries
+ *   (each may be NULL).
  * Returns the most severe per-instance status. */
 int adef2_solve_batched(adef2_ctx *ctx, int32_t B, const uint8_t *masks,
                         const double *b, const double *a, const double *c,
-                        double tol, double *x, int32_t *iters, int32_t *status,
-                        double *relres_true, double *cond_E, int64_t *n_inactive);
+                        const float *theta, double tol, double *x, int32_t *iters,
+                        int32_t *status, double *relres_true, double *cond_E,
+                        int64_t *n_inactive, int32_t *learned);
+
+/* ---- learned coarse-space enrichment (offline training on the device) ----
+ * The enrichment vectors are V = Phi C^T, Phi = p POD modes of solution
+ * snapshots (Sec. "Online POD enrichment": SVD of the mean-centred snapshot
+ * matrix), C = MLP(theta) (8 x p; MLP 4 -> 128 -> 128 -> 8p, erf-GELU, BF16
+ * weights, FP32 accumulation).  Training minimises the fraction of the
+ * solution's energy norm that the A-DEF2 coarse correction with [Z_I, V_I]
+ * leaves unresolved, L = 1 - (b_Z^T G_ZZ^-1 b_Z + s^T (C H C^T)^-1 s) / b^T x
+ * (H, s defined from the Grams of [Z_I, Phi_I] under S_II).  Requires the
+ * factored operator.  Parameter vector: 83200 FP32 values, packed
+ * W1[128][4], b1[128], W2[128][128], b2[128], W3[512][128], b3[512]. */
+
+/* POD modes of M snapshot columns X (device f64[n*M], column-major; 2 <= M
+ * <= 256, 1 <= p < M, p <= 64), by the method of snapshots (Gram of the
+ * centred snapshots, cyclic Jacobi eigensolver).  Keeps Phi in the context;
+ * Phi_out (device f64[n*p]) and sigma (host f64[p]) may be NULL. */
+int adef2_pod(adef2_ctx *ctx, int32_t M, const double *X, int32_t p, double *Phi_out,
+              double *sigma);
+/* Use given POD modes (device f64[n*p], column-major) instead. */
+int adef2_set_pod_modes(adef2_ctx *ctx, int32_t p, const double *Phi);
+/* MLP parameters (host f32[83200]); resets the Adam state.  tau_learned: the
+ * cond(E) bound of the enriched basis (>= 1; 1e8 in the learned workload). */
+int adef2_learned_set_params(adef2_ctx *ctx, const float *params, double tau_learned);
+int adef2_learned_get_params(adef2_ctx *ctx, float *params);
+/* Training samples: masks (device u8[M*n]), right-hand sides b and solutions
+ * xsol (device f64[M*n]), theta (device f32[M*4]), operator scales (host, or
+ * NULL).  Computes per sample H (p x p), g (p), b_Z^T G_ZZ^-1 b_Z, b^T x. */
+int adef2_learned_prepare(adef2_ctx *ctx, int32_t M, const uint8_t *masks, const double *b,
+                          const double *xsol, const float *theta, const double *a,
+                          const double *c);
+/* Loss per prepared sample (host f64[M]) and the gradient of the mean loss
+ * w.r.t. the parameters (host f32[83200]) at the current parameters. */
+int adef2_learned_loss_grad(adef2_ctx *ctx, double *loss, float *grad);
+/* steps full-batch Adam steps (Kingma & Ba 2015; beta 0.9/0.999, eps 1e-8);
+ * loss_hist (host f64[steps], may be NULL) receives the mean loss per step. */
+int adef2_learned_train(adef2_ctx *ctx, int32_t steps, float lr, double *loss_hist);
+/* MLP outputs for M parameter vectors: theta device f32[M*4] -> out device
+ * f32[M*512] (C row-major 8 x 64 per sample). */
+int adef2_learned_forward(adef2_ctx *ctx, int32_t M, const float *theta, float *out);
 
 /* y = S_II x on the current restriction (global layout, FP64); test hook for
  * the restricted operator.  x, y: device f64[n]. */

@@ -71,7 +71,15 @@ _sig = {
     "adef2_compact": (ctypes.c_int, [_P, _P, _i64, _P, _P, _Pi64]),
     "adef2_restrict": (ctypes.c_int, [_P, _P, _Pi64, _Pi32, _Pf64]),
     "adef2_solve": (ctypes.c_int, [_P, _P, _P, _f64, _P, _Pi32, _Pf64, _Pf64]),
-    "adef2_solve_batched": (ctypes.c_int, [_P, _i32, _P, _P, _P, _P, _f64, _P, _P, _P, _P, _P, _P]),
+    "adef2_solve_batched": (ctypes.c_int, [_P, _i32, _P, _P, _P, _P, _P, _f64, _P, _P, _P, _P, _P, _P, _P]),
+    "adef2_pod": (ctypes.c_int, [_P, _i32, _P, _i32, _P, _P]),
+    "adef2_set_pod_modes": (ctypes.c_int, [_P, _i32, _P]),
+    "adef2_learned_set_params": (ctypes.c_int, [_P, _P, _f64]),
+    "adef2_learned_get_params": (ctypes.c_int, [_P, _P]),
+    "adef2_learned_prepare": (ctypes.c_int, [_P, _i32, _P, _P, _P, _P, _P, _P]),
+    "adef2_learned_loss_grad": (ctypes.c_int, [_P, _P, _P]),
+    "adef2_learned_train": (ctypes.c_int, [_P, _i32, ctypes.c_float, _P]),
+    "adef2_learned_forward": (ctypes.c_int, [_P, _i32, _P, _P]),
     "adef2_apply_restricted": (ctypes.c_int, [_P, _P, _P]),
     "adef2_coarse_info": (ctypes.c_int, [_P, _P, _P, _Pi32, _Pf64]),
     "adef2_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
@@ -232,9 +240,10 @@ class Solver:
         self._check(rc)
         return SolveOut(x, it.value, rel.value, cond.value, rc)
 
-    def solve_batched(self, masks, b, tol: float, a=None, c=None):
+    def solve_batched(self, masks, b, tol: float, a=None, c=None, theta=None):
         M = _dev(masks, torch.uint8)
         Bt = _dev(b, torch.float64)
+        Th = None if theta is None else _dev(theta, torch.float32)
         B = M.shape[0]
         x = torch.empty((B, self.n), dtype=torch.float64, device="cuda")
         a_h = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
@@ -244,12 +253,75 @@ class Solver:
         rel = np.zeros(B, np.float64)
         cond = np.zeros(B, np.float64)
         nI = np.zeros(B, np.int64)
+        lrn = np.zeros(B, np.int32)
         hp = lambda arr: None if arr is None else arr.ctypes.data  # noqa: E731
-        rc = _lib.adef2_solve_batched(self._ctx, B, _ptr(M), _ptr(Bt), hp(a_h), hp(c_h), float(tol),
-                                      _ptr(x), hp(iters), hp(status), hp(rel), hp(cond), hp(nI))
+        rc = _lib.adef2_solve_batched(self._ctx, B, _ptr(M), _ptr(Bt), hp(a_h), hp(c_h), _ptr(Th),
+                                      float(tol), _ptr(x), hp(iters), hp(status), hp(rel), hp(cond),
+                                      hp(nI), hp(lrn))
         self._check(rc)
         return dict(x=x, iters=iters, status=status, relres_true=rel, cond_E=cond, n_inactive=nI,
-                    rc=rc)
+                    learned=lrn, rc=rc)
+
+    # --- learned enrichment ----------------------------------------------------
+    NPARAM = 83200
+
+    def pod(self, X, p: int):
+        """POD modes of the snapshot columns of X (N x M)."""
+        Xt = _dev(np.asfortranarray(X).ravel(order="F") if not isinstance(X, torch.Tensor)
+                  else X.T.contiguous().reshape(-1), torch.float64)
+        M = int(X.shape[1])
+        Phi = torch.empty(self.n * p, dtype=torch.float64, device="cuda")
+        sig = np.zeros(p)
+        self._check(_lib.adef2_pod(self._ctx, M, _ptr(Xt), p, _ptr(Phi), sig.ctypes.data), allow=(OK,))
+        return Phi.reshape(p, self.n).T, sig
+
+    def set_pod_modes(self, Phi):
+        Pt = _dev(np.asfortranarray(Phi).ravel(order="F") if not isinstance(Phi, torch.Tensor)
+                  else Phi.T.contiguous().reshape(-1), torch.float64)
+        self._check(_lib.adef2_set_pod_modes(self._ctx, int(Phi.shape[1]), _ptr(Pt)), allow=(OK,))
+
+    def learned_set_params(self, params: np.ndarray, tau_learned: float = 1e8):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.NPARAM
+        self._check(_lib.adef2_learned_set_params(self._ctx, p.ctypes.data, float(tau_learned)),
+                    allow=(OK,))
+
+    def learned_get_params(self) -> np.ndarray:
+        p = np.zeros(self.NPARAM, np.float32)
+        self._check(_lib.adef2_learned_get_params(self._ctx, p.ctypes.data), allow=(OK,))
+        return p
+
+    def learned_prepare(self, masks, b, xsol, theta, a=None, c=None):
+        M = _dev(masks, torch.uint8)
+        Bt = _dev(b, torch.float64)
+        Xt = _dev(xsol, torch.float64)
+        Th = _dev(theta, torch.float32)
+        a_h = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        c_h = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+        hp = lambda arr: None if arr is None else arr.ctypes.data  # noqa: E731
+        self._check(_lib.adef2_learned_prepare(self._ctx, int(M.shape[0]), _ptr(M), _ptr(Bt), _ptr(Xt),
+                                               _ptr(Th), hp(a_h), hp(c_h)), allow=(OK,))
+        self._mtr = int(M.shape[0])
+
+    def learned_loss_grad(self):
+        loss = np.zeros(self._mtr)
+        grad = np.zeros(self.NPARAM, np.float32)
+        self._check(_lib.adef2_learned_loss_grad(self._ctx, loss.ctypes.data, grad.ctypes.data),
+                    allow=(OK,))
+        return loss, grad
+
+    def learned_train(self, steps: int, lr: float = 1e-3):
+        hist = np.zeros(steps)
+        self._check(_lib.adef2_learned_train(self._ctx, int(steps), float(lr), hist.ctypes.data),
+                    allow=(OK,))
+        return hist
+
+    def learned_forward(self, theta):
+        Th = _dev(theta, torch.float32)
+        out = torch.empty((Th.shape[0], 512), dtype=torch.float32, device="cuda")
+        self._check(_lib.adef2_learned_forward(self._ctx, int(Th.shape[0]), _ptr(Th), _ptr(out)),
+                    allow=(OK,))
+        return out
 
     def apply_restricted(self, x) -> torch.Tensor:
         xt = _dev(x, torch.float64)

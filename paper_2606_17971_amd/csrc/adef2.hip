@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "../../include/adef2.h"
-#include "dev_setup.h"
+#include "dev_learned.h"
 
 using namespace adef2;
 
@@ -53,6 +53,32 @@ struct adef2_ctx {
   double* dia1_64 = nullptr;
   float* dia1_32 = nullptr;
   double alpha_ref = 1.0, shift_ref = 0.0;
+  // current coarse basis: shared reference modes (zs = 0) or a per-instance
+  // basis [Z | V_m] of the learned enrichment (zs = KP * N, k_base = k of Z)
+  int64_t zs = 0;
+  int k_base = 0;
+  int KPalloc = -1;
+
+  // learned enrichment: POD pool Phi (N x p), MLP parameters, training data
+  int p = 0;
+  double* Phi = nullptr;
+  float* mlp = nullptr;          // FP32 master parameters (packed)
+  uint16_t* mlp_bf = nullptr;    // BF16 compute copy (same layout)
+  float* mlp_g = nullptr;        // gradients
+  float* mlp_m = nullptr;        // Adam first moments
+  float* mlp_v = nullptr;        // Adam second moments
+  int adam_t = 0;
+  bool have_mlp = false;
+  int Mtr = 0;
+  float* theta_tr = nullptr;
+  double *Htr = nullptr, *gtr = nullptr, *e0tr = nullptr, *bxtr = nullptr;
+  float *act = nullptr, *mout = nullptr, *dout = nullptr, *dA1 = nullptr, *dA2 = nullptr;
+  double* lossv = nullptr;
+  int Mcap_mlp = 0;
+  double* Zb64 = nullptr;        // [B][KP][N] per-instance basis
+  float* Zb32 = nullptr;
+  size_t zb_cap = 0;             // elements allocated in Zb64 / Zb32
+  double tau_learned = 1e8;
 
   // restriction / batch state
   bool restricted = false;
@@ -182,6 +208,9 @@ void free_all(adef2_ctx* c) {
   F(c->W64); F(c->W32); F(c->dinv64); F(c->dinv32); F(c->x64); F(c->r64); F(c->x0pad);
   F(c->t64); F(c->t32); F(c->Tm); F(c->dia1_64); F(c->dia1_32);
   F(c->part); F(c->ctr);
+  F(c->Phi); F(c->mlp); F(c->mlp_bf); F(c->mlp_g); F(c->mlp_m); F(c->mlp_v); F(c->theta_tr);
+  F(c->Htr); F(c->gtr); F(c->e0tr); F(c->bxtr); F(c->act); F(c->mout); F(c->dout); F(c->dA1);
+  F(c->dA2); F(c->lossv); F(c->Zb64); F(c->Zb32);
   if (c->inst_h) hipHostFree(c->inst_h);
   for (auto& e : c->ev_pending) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
   for (auto e : c->ev_pool) hipEventDestroy(e);
@@ -291,7 +320,7 @@ void launch_gram(adef2_ctx* c, const V* dummy_tag, V* W) {
   case KPV:                                                                                  \
     nsub = (int)cdiv(c->N, GramCfg<KPV>::GR);                                                \
     hipLaunchKernelGGL((k_spmm_gram<V, KPV>), grid, dim3(TPB), 0, c->st, og, c->dia64, c->Z64, \
-                       c->Tm, (int)c->factored, c->masks, W, c->inst, c->part, c->ctr,        \
+                       c->zs, c->Tm, (int)c->factored, c->masks, W, c->inst, c->part, c->ctr,        \
                        c->g_gram, c->gram, nsub);                                            \
     break;
   switch (c->KP) {
@@ -312,6 +341,8 @@ void launch_coarse(adef2_ctx* c) {
   ca.k = c->k;
   ca.drop_rel = c->o.drop_rel;
   ca.tau_cond = c->o.tau_cond;
+  ca.k_base = c->k_base;
+  ca.tau_learned = c->tau_learned;
 #define COARSE_CASE(KPV) \
   case KPV: hipLaunchKernelGGL((k_coarse<KPV>), dim3(c->B), dim3(TPB), 0, c->st, ca); break;
   switch (c->KP) {
@@ -335,11 +366,12 @@ int ensure_batch(adef2_ctx* c, int B, int prec) {
   gb = (int)std::min<int64_t>(gb, nsub_max);
   c->gram_blocks = std::max(gb, 1);
   c->g_gram = make_geom(c->gram_blocks);
-  const bool same = (B <= c->Bcap) && (prec == c->prec) && c->vs == N + 2 * c->H;
+  const bool same = (B <= c->Bcap) && (prec == c->prec) && c->vs == N + 2 * c->H && KP == c->KPalloc;
   c->B = B;
   if (same) return ADEF2_OK;
   int rc;
   c->Bcap = B;
+  c->KPalloc = KP;
   c->prec = prec;
   c->vs = N + 2 * c->H;
   const size_t BN = (size_t)B * N;
@@ -446,7 +478,7 @@ int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
     timed(c, KI_GRAM, (double)B * N * (c->D * 8.0 + c->KP * (8.0 + wbytes) + 1.0), [&] {
       if (c->factored) {
         hipLaunchKernelGGL(k_stencil_modes, dim3((unsigned)cdiv(N, 256), c->KP, B), dim3(256), 0,
-                           c->st, op_geom(c), c->dia1_64, c->Z64, c->masks, c->KP, c->Tm);
+                           c->st, op_geom(c), c->dia1_64, c->Z64, c->zs, c->masks, c->KP, c->Tm);
       }
       if (mat64(c->prec)) launch_gram<double>(c, nullptr, c->W64);
       else launch_gram<float>(c, nullptr, c->W32);
@@ -484,6 +516,7 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.g = c->g_iter;
   a.maxit = c->o.maxit;
   a.vs = c->vs;
+  a.zs = c->zs;
   if constexpr (sizeof(M) == 8) {
     a.dia1 = (const M*)c->dia1_64;
     a.dia = (const M*)c->dia64;
@@ -738,6 +771,90 @@ bool valid_opts(const adef2_opts* o) {
 }
 
 }  // namespace
+
+// Packed MLP parameter layout (FP32 master / BF16 copy share offsets)
+constexpr int OW1 = 0, OB1 = OW1 + MD1 * MD0, OW2 = OB1 + MD1, OB2 = OW2 + MD2 * MD1,
+              OW3 = OB2 + MD2, OB3 = OW3 + MD3 * MD2, NPARAM = OB3 + MD3;
+
+MLPW mlp_view(const adef2_ctx* c) {
+  MLPW w;
+  w.W1 = c->mlp_bf + OW1; w.b1 = c->mlp + OB1;
+  w.W2 = c->mlp_bf + OW2; w.b2 = c->mlp + OB2;
+  w.W3 = c->mlp_bf + OW3; w.b3 = c->mlp + OB3;
+  return w;
+}
+
+int ensure_mlp_batch(adef2_ctx* c, int M) {
+  if (M <= c->Mcap_mlp) return ADEF2_OK;
+  int rc;
+  if ((rc = dalloc(c, &c->act, (size_t)M * 4 * MD1)) || (rc = dalloc(c, &c->mout, (size_t)M * MD3)) ||
+      (rc = dalloc(c, &c->dout, (size_t)M * MD3)) || (rc = dalloc(c, &c->dA1, (size_t)M * MD1)) ||
+      (rc = dalloc(c, &c->dA2, (size_t)M * MD2)) || (rc = dalloc(c, &c->lossv, (size_t)M)))
+    return rc;
+  c->Mcap_mlp = M;
+  return ADEF2_OK;
+}
+
+void mlp_forward_launch(adef2_ctx* c, int M, const float* theta) {
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(M), dim3(512), 0, c->st, M, theta, mlp_view(c), c->act, c->mout);
+}
+
+// fwd + loss gradient + backward over the M prepared samples; gradient of the
+// mean loss in c->mlp_g
+void mlp_grad_launch(adef2_ctx* c, int M) {
+  mlp_forward_launch(c, M, c->theta_tr);
+  hipLaunchKernelGGL(k_loss_grad, dim3(M), dim3(512), 0, c->st, M, c->p, c->mout, c->Htr, c->gtr, c->e0tr,
+                     c->bxtr, 0.0, 1.0f / (float)M, c->dout, c->lossv);
+  hipLaunchKernelGGL(k_mlp_bwd_act, dim3(M), dim3(128), 0, c->st, M, mlp_view(c), c->act, c->dout,
+                     c->dA2, c->dA1);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)cdiv(MD3 * MD2, 256)), dim3(256), 0, c->st, M, MD3, MD2,
+                     c->dout, MD3, c->act, 4 * MD1, 3 * MD1, c->mlp_g + OW3, c->mlp_g + OB3);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)cdiv(MD2 * MD1, 256)), dim3(256), 0, c->st, M, MD2, MD1,
+                     c->dA2, MD2, c->act, 4 * MD1, MD1, c->mlp_g + OW2, c->mlp_g + OB2);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)cdiv(MD1 * MD0, 256)), dim3(256), 0, c->st, M, MD1, MD0,
+                     c->dA1, MD1, c->theta_tr, MD0, 0, c->mlp_g + OW1, c->mlp_g + OB1);
+}
+
+// Swaps the shared reference basis for the per-instance enriched basis
+// [Z | Phi C_m^T] for the duration of one batched solve.
+struct BasisSwap {
+  adef2_ctx* c;
+  bool active = false;
+  double* Z64s = nullptr;
+  float* Z32s = nullptr;
+  int k0 = 0, KP0 = 0;
+  explicit BasisSwap(adef2_ctx* cc) : c(cc) {}
+  int enrich(int B, const float* theta) {
+    int rc;
+    if ((rc = ensure_mlp_batch(c, B))) return rc;
+    mlp_forward_launch(c, B, theta);
+    const int k = c->k, KPe = round8(k + MLP_NV);
+    const size_t need = (size_t)B * KPe * c->N;
+    if (need > c->zb_cap) {
+      c->zb_cap = 0;
+      if ((rc = dalloc(c, &c->Zb64, need)) || (rc = dalloc(c, &c->Zb32, need))) return rc;
+      c->zb_cap = need;
+    }
+    hipLaunchKernelGGL(k_expand_basis, dim3((unsigned)cdiv(c->N, 256), KPe, B), dim3(256), 0, c->st,
+                       c->N, k, KPe, c->p, c->Z64, c->Phi, c->mout, c->Zb64, c->Zb32);
+    HIPCHK(c, hipGetLastError());
+    Z64s = c->Z64; Z32s = c->Z32; k0 = c->k; KP0 = c->KP;
+    c->Z64 = c->Zb64; c->Z32 = c->Zb32;
+    c->k_base = k;
+    c->k = k + MLP_NV;
+    c->KP = KPe;
+    c->zs = (int64_t)KPe * c->N;
+    active = true;
+    return ADEF2_OK;
+  }
+  ~BasisSwap() {
+    if (!active) return;
+    c->Z64 = Z64s; c->Z32 = Z32s;
+    c->k = k0; c->KP = KP0;
+    c->k_base = 0;
+    c->zs = 0;
+  }
+};
 
 // =========================================================================
 // C ABI
@@ -1048,13 +1165,23 @@ int adef2_solve(adef2_ctx* c, const double* b, const double* x0, double tol, dou
 }
 
 int adef2_solve_batched(adef2_ctx* c, int32_t B, const uint8_t* masks, const double* b,
-                        const double* a, const double* cs, double tol, double* x, int32_t* iters,
-                        int32_t* status, double* relres_true, double* cond_E, int64_t* n_inactive) {
+                        const double* a, const double* cs, const float* theta, double tol, double* x,
+                        int32_t* iters, int32_t* status, double* relres_true, double* cond_E,
+                        int64_t* n_inactive, int32_t* learned) {
   if (!c) return ADEF2_E_ARG;
   if (!c->have_ref) return fail(c, ADEF2_E_STATE, "solve_batched before set_reference");
   if (B <= 0 || !masks || !b || !x) return fail(c, ADEF2_E_ARG, "invalid batch arguments");
+  if (theta && (!c->have_mlp || c->p <= 0))
+    return fail(c, ADEF2_E_STATE, "learned enrichment requested before POD modes and MLP parameters");
+  if (theta && c->k + MLP_NV > ADEF2_MAX_K)
+    return fail(c, ADEF2_E_ARG, "k + 8 learned vectors exceeds ADEF2_MAX_K");
   c->restricted = false;
-  int rc = ensure_batch(c, B, c->o.precision);
+  int rc;
+  BasisSwap swap(c);
+  if (theta) {
+    if ((rc = swap.enrich(B, theta))) return rc;
+  }
+  rc = ensure_batch(c, B, c->o.precision);
   if (rc) return rc;
   HIPCHK(c, hipMemcpyAsync(c->masks, masks, (size_t)B * c->N, hipMemcpyDeviceToDevice, c->st));
   rc = restrict_batch(c, a, cs);
@@ -1062,6 +1189,8 @@ int adef2_solve_batched(adef2_ctx* c, int32_t B, const uint8_t* masks, const dou
   rc = solve_batch(c, b, nullptr, tol, x);
   if (rc) return rc;
   int worst = ADEF2_OK;
+  for (int m = 0; m < B; ++m)
+    if (learned) learned[m] = c->inst_h[m].learned;
   for (int m = 0; m < B; ++m) {
     const Inst& s = c->inst_h[m];
     const int st = combine_status(s);
@@ -1140,6 +1269,209 @@ int adef2_reset_stats(adef2_ctx* c) {
   if (!c) return ADEF2_E_ARG;
   ev_harvest(c);
   for (int i = 0; i < KI_COUNT; ++i) { c->st_launch[i] = 0; c->st_ms[i] = 0; c->st_bytes[i] = 0; }
+  return ADEF2_OK;
+}
+
+int adef2_pod(adef2_ctx* c, int32_t M, const double* X, int32_t p, double* Phi_out, double* sigma) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_ref) return fail(c, ADEF2_E_STATE, "pod before set_reference");
+  if (M < 2 || M > JMAX || p < 1 || p > MLP_P || p >= M || !X)
+    return fail(c, ADEF2_E_ARG, "need 2 <= M <= 256 snapshots and 1 <= p < M, p <= 64");
+  const int64_t N = c->N;
+  double *Xc = nullptr, *part = nullptr, *G = nullptr, *V = nullptr, *ev = nullptr;
+  int* sel = nullptr;
+  const int rpb = 4096;
+  const int nrb = (int)cdiv(N, rpb);
+  const int nt = (int)cdiv(M, GT);
+  auto cleanup = [&] { for (void* q : {(void*)Xc, (void*)part, (void*)G, (void*)V, (void*)ev, (void*)sel}) if (q) hipFree(q); };
+  int rc;
+  if ((rc = dalloc(c, &Xc, (size_t)N * M)) || (rc = dalloc(c, &part, (size_t)nrb * M * M)) ||
+      (rc = dalloc(c, &G, (size_t)M * M)) || (rc = dalloc(c, &V, (size_t)M * M)) ||
+      (rc = dalloc(c, &ev, (size_t)M)) || (rc = dalloc(c, &sel, (size_t)p))) { cleanup(); return rc; }
+  hipLaunchKernelGGL(k_center, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, c->st, N, M, X, Xc);
+  hipLaunchKernelGGL(k_gram_ts, dim3(nrb, nt * nt, 1), dim3(TPB), 0, c->st, N, M, M, Xc, (int64_t)0, Xc,
+                     (int64_t)0, (const uint8_t*)nullptr, (int64_t)0, rpb, part);
+  hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)cdiv(M * M, 256), 1), dim3(256), 0, c->st, nrb, M, M,
+                     part, G);
+  hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(1024), 0, c->st, M, G, V, ev);
+  std::vector<double> evh(M);
+  hipMemcpyAsync(evh.data(), ev, sizeof(double) * M, hipMemcpyDeviceToHost, c->st);
+  if (hipStreamSynchronize(c->st) != hipSuccess) { cleanup(); return fail(c, ADEF2_E_HIP, "pod sync"); }
+  // order the eigenvalues (descending) on the host: p indices only
+  std::vector<int> idx(M);
+  for (int i = 0; i < M; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) { return evh[i] > evh[j]; });
+  hipMemcpyAsync(sel, idx.data(), sizeof(int) * p, hipMemcpyHostToDevice, c->st);
+  if ((rc = dalloc(c, &c->Phi, (size_t)N * p))) { cleanup(); return rc; }
+  hipLaunchKernelGGL(k_pod_modes, dim3((unsigned)cdiv(N, 256), p), dim3(256), 0, c->st, N, M, p, Xc, V, sel,
+                     ev, c->Phi);
+  if (Phi_out) hipMemcpyAsync(Phi_out, c->Phi, sizeof(double) * N * p, hipMemcpyDeviceToDevice, c->st);
+  hipError_t e = hipStreamSynchronize(c->st);
+  cleanup();
+  if (e != hipSuccess) return fail(c, ADEF2_E_HIP, hipGetErrorString(e));
+  if (sigma) for (int j = 0; j < p; ++j) sigma[j] = evh[idx[j]] > 0 ? std::sqrt(evh[idx[j]]) : 0.0;
+  c->p = p;
+  return ADEF2_OK;
+}
+
+int adef2_set_pod_modes(adef2_ctx* c, int32_t p, const double* Phi) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_ref) return fail(c, ADEF2_E_STATE, "set_pod_modes before set_reference");
+  if (p < 1 || p > MLP_P || !Phi) return fail(c, ADEF2_E_ARG, "1 <= p <= 64 and Phi required");
+  int rc;
+  if ((rc = dalloc(c, &c->Phi, (size_t)c->N * p))) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->Phi, Phi, sizeof(double) * c->N * p, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->p = p;
+  return ADEF2_OK;
+}
+
+int adef2_learned_set_params(adef2_ctx* c, const float* params, double tau_learned) {
+  if (!c || !params) return ADEF2_E_ARG;
+  if (!(tau_learned >= 1.0)) return fail(c, ADEF2_E_ARG, "tau_learned must be >= 1");
+  int rc;
+  if (!c->mlp) {
+    if ((rc = dalloc(c, &c->mlp, NPARAM)) || (rc = dalloc(c, &c->mlp_bf, NPARAM)) ||
+        (rc = dalloc(c, &c->mlp_g, NPARAM)) || (rc = dalloc(c, &c->mlp_m, NPARAM)) ||
+        (rc = dalloc(c, &c->mlp_v, NPARAM)))
+      return rc;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->mlp, params, sizeof(float) * NPARAM, hipMemcpyHostToDevice, c->st));
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)cdiv(NPARAM, 256)), dim3(256), 0, c->st, NPARAM, c->mlp, c->mlp_bf);
+  HIPCHK(c, hipMemsetAsync(c->mlp_m, 0, sizeof(float) * NPARAM, c->st));
+  HIPCHK(c, hipMemsetAsync(c->mlp_v, 0, sizeof(float) * NPARAM, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->adam_t = 0;
+  c->tau_learned = tau_learned;
+  c->have_mlp = true;
+  return ADEF2_OK;
+}
+
+int adef2_learned_get_params(adef2_ctx* c, float* params) {
+  if (!c || !params) return ADEF2_E_ARG;
+  if (!c->have_mlp) return fail(c, ADEF2_E_STATE, "no MLP parameters");
+  HIPCHK(c, hipMemcpy(params, c->mlp, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+  return ADEF2_OK;
+}
+
+int adef2_learned_prepare(adef2_ctx* c, int32_t M, const uint8_t* masks, const double* b,
+                          const double* xsol, const float* theta, const double* a_h, const double* c_h) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_ref || c->p <= 0) return fail(c, ADEF2_E_STATE, "learned_prepare needs set_reference and POD modes");
+  if (!c->factored) return fail(c, ADEF2_E_UNSUPPORTED, "learned enrichment needs the factored operator");
+  if (M <= 0 || !masks || !b || !xsol || !theta) return fail(c, ADEF2_E_ARG, "invalid training arguments");
+  const int64_t N = c->N;
+  const int k = c->k, p = c->p, nb = k + p;
+  if (sizeof(double) * ((size_t)k * k + (size_t)k * (p + 1)) > 65536)
+    return fail(c, ADEF2_E_UNSUPPORTED, "learned_prepare: k*k + k*(p+1) must fit 8192 doubles");
+  int rc;
+  if ((rc = dalloc(c, &c->theta_tr, (size_t)M * MD0)) || (rc = dalloc(c, &c->Htr, (size_t)M * p * p)) ||
+      (rc = dalloc(c, &c->gtr, (size_t)M * p)) || (rc = dalloc(c, &c->e0tr, (size_t)M)) ||
+      (rc = dalloc(c, &c->bxtr, (size_t)M)))
+    return rc;
+  HIPCHK(c, hipMemcpyAsync(c->theta_tr, theta, sizeof(float) * M * MD0, hipMemcpyDeviceToDevice, c->st));
+  double *VB = nullptr, *T = nullptr, *Wv = nullptr, *part = nullptr, *G = nullptr, *bz = nullptr, *bx1 = nullptr;
+  Inst* one = nullptr;
+  const int rpb = 4096;
+  const int nrb = (int)cdiv(N, rpb);
+  const int nt = (int)cdiv(nb, GT);
+  auto cleanup = [&] {
+    for (void* q : {(void*)VB, (void*)T, (void*)Wv, (void*)part, (void*)G, (void*)bz, (void*)bx1, (void*)one})
+      if (q) hipFree(q);
+  };
+  if ((rc = dalloc(c, &VB, (size_t)N * nb)) || (rc = dalloc(c, &T, (size_t)N * nb)) ||
+      (rc = dalloc(c, &Wv, (size_t)N * nb)) || (rc = dalloc(c, &part, (size_t)nrb * nb * nb)) ||
+      (rc = dalloc(c, &G, (size_t)nb * nb)) || (rc = dalloc(c, &bz, (size_t)nb)) ||
+      (rc = dalloc(c, &bx1, 1)) || (rc = dalloc(c, &one, 1))) { cleanup(); return rc; }
+  // [Z | Phi] (k reference modes first)
+  HIPCHK(c, hipMemcpyAsync(VB, c->Z64, sizeof(double) * N * k, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(VB + (size_t)N * k, c->Phi, sizeof(double) * N * p, hipMemcpyDeviceToDevice, c->st));
+  OpGeom og = op_geom(c);
+  std::vector<double> bxh(M);
+  for (int m = 0; m < M; ++m) {
+    const uint8_t* mk = masks + (size_t)m * N;
+    Inst ih{};
+    const double ua = a_h ? a_h[m] : c->scale_a, uc = c_h ? c_h[m] : c->scale_c;
+    ih.a = ua * c->alpha_ref;
+    ih.c = ua * c->shift_ref + uc;
+    hipMemcpyAsync(one, &ih, sizeof(Inst), hipMemcpyHostToDevice, c->st);
+    // S_II [Z | Phi] restricted: T = A Vtilde on all rows, W = a A^T T + c Vtilde (inactive rows)
+    hipLaunchKernelGGL(k_stencil_modes, dim3((unsigned)cdiv(N, 256), nb, 1), dim3(256), 0, c->st, og,
+                       c->dia1_64, VB, (int64_t)0, mk, nb, T);
+    hipLaunchKernelGGL(k_outer_cols, dim3((unsigned)cdiv(N, 256), nb), dim3(256), 0, c->st, og, c->dia64,
+                       T, VB, mk, one, Wv);
+    hipLaunchKernelGGL(k_gram_ts, dim3(nrb, nt * nt, 1), dim3(TPB), 0, c->st, N, nb, nb, VB, (int64_t)0,
+                       Wv, (int64_t)0, mk, (int64_t)0, rpb, part);
+    hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)cdiv(nb * nb, 256), 1), dim3(256), 0, c->st, nrb, nb,
+                       nb, part, G);
+    hipLaunchKernelGGL(k_gram_ts, dim3(nrb, nt, 1), dim3(TPB), 0, c->st, N, nb, 1, VB, (int64_t)0,
+                       b + (size_t)m * N, (int64_t)0, mk, (int64_t)0, rpb, part);
+    hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)cdiv(nb, 256), 1), dim3(256), 0, c->st, nrb, nb, 1,
+                       part, bz);
+    hipLaunchKernelGGL(k_gram_ts, dim3(nrb, 1, 1), dim3(TPB), 0, c->st, N, 1, 1, b + (size_t)m * N,
+                       (int64_t)0, xsol + (size_t)m * N, (int64_t)0, mk, (int64_t)0, rpb, part);
+    hipLaunchKernelGGL(k_gram_finish, dim3(1, 1), dim3(256), 0, c->st, nrb, 1, 1, part, c->bxtr + m);
+    const size_t lds = sizeof(double) * ((size_t)k * k + (size_t)k * (p + 1));
+    // the kernel indexes its one sample through blockIdx.x = 0; shift the outputs
+    hipLaunchKernelGGL(k_loss_data, dim3(1), dim3(1024), lds, c->st, k, p, G, bz, c->Htr + (size_t)m * p * p,
+                       c->gtr + (size_t)m * p, c->e0tr + m, c->o.drop_rel);
+  }
+  hipError_t e = hipStreamSynchronize(c->st);
+  cleanup();
+  if (e != hipSuccess) return fail(c, ADEF2_E_HIP, std::string("learned_prepare: ") + hipGetErrorString(e));
+  c->Mtr = M;
+  return ADEF2_OK;
+}
+
+int adef2_learned_loss_grad(adef2_ctx* c, double* loss, float* grad) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_mlp || c->Mtr <= 0) return fail(c, ADEF2_E_STATE, "learned_loss_grad needs parameters and prepared samples");
+  int rc;
+  if ((rc = ensure_mlp_batch(c, c->Mtr))) return rc;
+  mlp_grad_launch(c, c->Mtr);
+  HIPCHK(c, hipGetLastError());
+  if (loss) HIPCHK(c, hipMemcpyAsync(loss, c->lossv, sizeof(double) * c->Mtr, hipMemcpyDeviceToHost, c->st));
+  if (grad) HIPCHK(c, hipMemcpyAsync(grad, c->mlp_g, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return ADEF2_OK;
+}
+
+int adef2_learned_train(adef2_ctx* c, int32_t steps, float lr, double* loss_hist) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_mlp || c->Mtr <= 0) return fail(c, ADEF2_E_STATE, "learned_train needs parameters and prepared samples");
+  if (steps < 0 || !(lr > 0.0f)) return fail(c, ADEF2_E_ARG, "invalid training arguments");
+  int rc;
+  const int M = c->Mtr;
+  if ((rc = ensure_mlp_batch(c, M))) return rc;
+  std::vector<double> lh(M);
+  const float b1 = 0.9f, b2 = 0.999f;
+  for (int it = 0; it < steps; ++it) {
+    mlp_grad_launch(c, M);
+    c->adam_t += 1;
+    const float c1 = 1.0f - std::pow(b1, (float)c->adam_t), c2 = 1.0f - std::pow(b2, (float)c->adam_t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)cdiv(NPARAM, 256)), dim3(256), 0, c->st, NPARAM, c->mlp,
+                       c->mlp_g, c->mlp_m, c->mlp_v, c->mlp_bf, lr, b1, b2, 1e-8f, c1, c2);
+    if (loss_hist) {
+      HIPCHK(c, hipMemcpyAsync(lh.data(), c->lossv, sizeof(double) * M, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+      double sum = 0.0;
+      for (double v : lh) sum += v;
+      loss_hist[it] = sum / M;
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return ADEF2_OK;
+}
+
+int adef2_learned_forward(adef2_ctx* c, int32_t M, const float* theta, float* out) {
+  if (!c || M <= 0 || !theta || !out) return ADEF2_E_ARG;
+  if (!c->have_mlp) return fail(c, ADEF2_E_STATE, "no MLP parameters");
+  int rc;
+  if ((rc = ensure_mlp_batch(c, M))) return rc;
+  mlp_forward_launch(c, M, theta);
+  HIPCHK(c, hipMemcpyAsync(out, c->mout, sizeof(float) * M * MD3, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
   return ADEF2_OK;
 }
 

@@ -44,7 +44,7 @@ struct Inst {
   int32_t sweeps;
   int32_t has_dir;      // a search direction from the previous sweep exists
   int32_t stall;        // outer steps since the best residual last halved
-  int32_t pad2_;
+  int32_t learned;      // the learned enrichment vectors are in the coarse space
   double coef[KMAX];    // coarse coefficients of the next x / p update
 };
 

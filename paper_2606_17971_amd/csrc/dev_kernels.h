@@ -68,7 +68,8 @@ struct IterArgs {
   V* t;                    // padded inner product A p (factored operator)
   const uint8_t* mask;     // [B][N]
   const V* dinv;           // [B][N]
-  const M* Z;              // [KP][N]
+  const M* Z;              // [KP][N] shared, or [B][KP][N] per instance
+  int64_t zs;              // instance stride of Z (0: shared by all instances)
   const M* W;              // [B][KP][N]
   V* x; V* r; V* z; V* p; V* w;   // padded, pointer to instance 0 interior
   int64_t vs;              // padded vector stride
@@ -164,7 +165,7 @@ __global__ void __launch_bounds__(IPB) k_init(IterArgs<V, M> a) {
   }
   const int wid = threadIdx.x >> 6;
   for (int q = wid; q < KP; q += NIWAVE) {
-    const double s = panel_dot<M, RPT>(a.Z + (size_t)q * N, base, vl, act);
+    const double s = panel_dot<M, RPT>(a.Z + (size_t)m * a.zs + (size_t)q * N, base, vl, act);
     if ((threadIdx.x & 63) == 0) bv[q] = s;
   }
   __syncthreads();
@@ -243,7 +244,7 @@ __device__ __forceinline__ bool reduce_directions(const IterArgs<V, M>& a, int m
     double s = 0.0;
     if (defl) {
       s = (q < KP) ? panel_dot<M, RPT>(W + (size_t)q * N, base, zl, act)
-                   : panel_dot<M, RPT>(a.Z + (size_t)(q - KP) * N, base, rl, act);
+                   : panel_dot<M, RPT>(a.Z + (size_t)m * a.zs + (size_t)(q - KP) * N, base, rl, act);
     }
     if ((threadIdx.x & 63) == 0) bv[q] = s;
   }
@@ -303,7 +304,7 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V, M> a) {
       if (defl) {
 #pragma unroll 8
         for (int q = 0; q < KP; ++q) {
-          xv += (double)a.Z[(size_t)q * N + i] * cf[q];
+          xv += (double)a.Z[(size_t)m * a.zs + (size_t)q * N + i] * cf[q];
           rv -= (double)W[(size_t)q * N + i] * cf[q];
         }
       }
@@ -367,7 +368,7 @@ __global__ void __launch_bounds__(IPB) k_pupdate(IterArgs<V, M> a) {
       double pv = (double)z[i];
       if (defl) {
 #pragma unroll 8
-        for (int q = 0; q < KP; ++q) pv -= (double)a.Z[(size_t)q * N + i] * cf[q];
+        for (int q = 0; q < KP; ++q) pv -= (double)a.Z[(size_t)m * a.zs + (size_t)q * N + i] * cf[q];
       }
       if (keep) pv += beta * (double)p[i];
       p[i] = (V)pv;

@@ -191,15 +191,15 @@ __global__ void k_dia_transpose(OpGeom op, const double* A64, double* AT64, floa
 
 // T[m][q] = A Ztilde[q] on all rows, Ztilde = Z with the active rows of
 // instance m set to zero (factored operator, setup of W).
-__global__ void k_stencil_modes(OpGeom op, const double* A64, const double* Z64, const uint8_t* mask,
-                                int KP, double* T) {
+__global__ void k_stencil_modes(OpGeom op, const double* A64, const double* Z64, int64_t zs,
+                                const uint8_t* mask, int KP, double* T) {
   const int q = blockIdx.y;
   const int m = blockIdx.z;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = op.N;
   if (i >= N) return;
   const uint8_t* mk = mask + (size_t)m * N;
-  const double* Zq = Z64 + (size_t)q * N;
+  const double* Zq = Z64 + (size_t)m * zs + (size_t)q * N;
   double acc = 0.0;
   for (int e = 0; e < op.D1; ++e) {
     const int64_t j = i + op.offs1[e];
@@ -238,7 +238,7 @@ template <int KP> struct GramCfg {
 // T = A Ztilde of this instance (factored operator; read unmasked).
 template <typename V, int KP>
 __global__ void __launch_bounds__(TPB) k_spmm_gram(OpGeom op, const double* dia64, const double* Z64,
-                                                    const double* src, int factored,
+                                                    int64_t zs, const double* src, int factored,
                                                     const uint8_t* mask, V* W, Inst* inst,
                                                     double* part, unsigned* ctr, RedGeom g,
                                                     double* gram, int nsub) {
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(TPB) k_spmm_gram(OpGeom op, const double* dia6
       if (q < KP) {
         double wv = 0.0, zv = 0.0;
         if (!act) {
-          const double* Zq = Z64 + (size_t)q * N;
+          const double* Zq = Z64 + (size_t)m * zs + (size_t)q * N;
           const double* Sq = factored ? src + ((size_t)m * KP + q) * N : Zq;
           double s = 0.0;
           for (int d = 0; d < op.D; ++d) {
@@ -327,6 +327,9 @@ struct CoarseArgs {
   int k;                 // true number of modes (<= KP)
   double drop_rel;
   double tau_cond;
+  int k_base;            // > 0: columns k_base.. are learned enrichment vectors;
+  double tau_learned;    //   if cond(E) exceeds tau_learned (or the setup fails)
+                         //   the instance retries with the first k_base columns
 };
 
 template <int KP>
@@ -347,7 +350,9 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
   Inst* S = ca.inst + m;
   const double* G = ca.gram + (size_t)m * 2 * KP * KP;
   const double* E = G + KP * KP;
-  const int k = ca.k;
+  __shared__ int s_retry;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+  const int k = attempt == 0 ? ca.k : ca.k_base;
   for (int e = tid; e < KP * KP; e += TPB) A0[e] = G[e];
   for (int e = tid; e < KP; e += TPB) gdiag[e] = G[e * KP + e];
   __syncthreads();
@@ -536,7 +541,12 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
     }
     __syncthreads();
   }
-  const bool fallback = (kp == 0) || s_fail || !(cond <= ca.tau_cond);
+  const bool enriched = attempt == 0 && ca.k_base > 0 && ca.k_base < ca.k;
+  const double tau = enriched ? fmin(ca.tau_cond, ca.tau_learned) : ca.tau_cond;
+  const bool fallback = (kp == 0) || s_fail || !(cond <= tau);
+  if (tid == 0) s_retry = enriched && fallback;
+  __syncthreads();
+  if (s_retry) continue;     // plain reference basis as fallback (uniform)
   // --- X = L^{-1} T^T (A0), one column per thread ---
   if (!fallback) {
     for (int c = tid; c < kp; c += TPB) {
@@ -564,7 +574,10 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
     S->cond = (kp > 0 && s_fail) ? INFINITY : cond;
     S->k_eff = kp;
     S->kk = fallback ? 0 : kp;
+    S->learned = enriched && !fallback;
     if (fallback && k > 0 && S->setup_status == 0) S->setup_status = 1;
+  }
+  break;
   }
 }
 

@@ -75,3 +75,27 @@ def test_csr_canonical():
     for i in range(S.shape[0]):
         cols = S.indices[S.indptr[i]:S.indptr[i + 1]]
         assert np.all(np.diff(cols) > 0)
+
+
+def test_mlp_params_match_oracle_init_layout():
+    from oracle import learned as OL
+    for seed in (0, 5):
+        prm = OL.mlp_init(seed)
+        flat = np.concatenate([prm["W1"].ravel(), prm["b1"], prm["W2"].ravel(), prm["b2"],
+                               prm["W3"].ravel(), prm["b3"]])
+        np.testing.assert_array_equal(gen.mlp_params(seed), flat)
+        assert flat.size == 83200
+
+
+def test_c2_family_members():
+    n = 31
+    th = gen.c2_thetas(5, 3, spread_rho=True)
+    assert np.allclose(th[:, 0], np.linspace(0, 1, 5))
+    for t in th:
+        inst = gen.c2_family_instance(n, t)
+        assert inst.mask.sum() == int(np.floor((0.10 + 0.30 * t[0]) * n * n))
+        assert np.argmax(inst.b) == np.argmax(gen.gaussian_bump(n, (0.2 + 0.6 * t[1], 0.2 + 0.6 * t[2])))
+    # phase 0 and phase 1 (a full period) give the same mask
+    a = gen.c2_family_instance(n, [0.5, 0.5, 0.5, 0.0]).mask
+    b = gen.c2_family_instance(n, [0.5, 0.5, 0.5, 1.0]).mask
+    assert (a != b).sum() <= 2

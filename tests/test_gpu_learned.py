@@ -1,0 +1,152 @@
+"""Learned enrichment on the GPU against the FP64 oracle.
+
+Snapshots are exact solutions computed by the oracle, so every input of the
+oracle side is independent of the HIP path.  Bars: POD singular values
+1e-8 relative; MLP outputs and per-sample losses to FP32/BF16 accuracy;
+parameter gradients within 2e-2 relative Frobenius (BF16 weights on both
+sides, FP32 vs FP64 arithmetic); enriched solves to the FP64 solve bar."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from oracle import learned as OL
+
+pytestmark = pytest.mark.gpu
+
+N_GRID, K, P, MTR = 63, 16, 24, 48
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    w = gen.c2_workload(n=N_GRID, k=K, B=1)
+    op = w.op
+    thetas = gen.c2_thetas(MTR + 12, 900)
+    insts = [gen.c2_family_instance(N_GRID, th) for th in thetas]
+    xs_full = []
+    for inst in insts:
+        I, _, _ = oracle.compact(inst.mask)
+        F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
+        x = np.zeros(op.N)
+        x[I] = oracle.exact_solution(F, inst.b[I])
+        xs_full.append(x)
+    X = np.column_stack(xs_full[:MTR])
+    Phi, sig = OL.pod_modes(X, P)
+    return w, op, thetas, insts, np.array(xs_full), X, Phi, sig
+
+
+def _params(seed):
+    prm = OL.mlp_init(seed)
+    flat = np.concatenate([prm["W1"].ravel(), prm["b1"], prm["W2"].ravel(), prm["b2"],
+                           prm["W3"].ravel(), prm["b3"]]).astype(np.float32)
+    return prm, flat
+
+
+def _oracle_loss_grad(prm, w, op, Phi, thetas, insts, xs):
+    """Mean loss and parameter gradients (FP64, BF16-rounded weights)."""
+    out, cache = OL.mlp_forward(prm, thetas)
+    M = len(insts)
+    losses = np.zeros(M)
+    dout = np.zeros_like(out)
+    for m, inst in enumerate(insts):
+        I, _, _ = oracle.compact(inst.mask)
+        F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
+        d = OL.loss_data(F, w.Z[I, :], Phi[I, :], inst.b[I], xs[m][I])
+        C = out[m].reshape(8, 64)[:, :P]   # leading P columns of each row are used
+        losses[m] = OL.loss(C, d)
+        G = OL.loss_grad(C, d) / M
+        g = np.zeros((8, 64))
+        g[:, :P] = G
+        dout[m] = g.ravel()
+    grads = OL.mlp_backward(cache, dout)
+    return losses, grads
+
+
+def test_pod_matches_oracle(lib, setup):
+    w, op, thetas, insts, xs, X, Phi, sig = setup
+    case(f"POD of {MTR} snapshots, p={P}")
+    s = lib.Solver()
+    s.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    Pg, sg = s.pod(X, P)
+    np.testing.assert_allclose(sg, sig, rtol=1e-8)
+    Pg = Pg.cpu().numpy()
+    # same modes up to sign (distinct singular values)
+    np.testing.assert_allclose(np.abs(np.sum(Pg * Phi, axis=0)), np.ones(P), atol=1e-6)
+
+
+def test_forward_loss_and_gradient_match_oracle(lib, setup):
+    w, op, thetas, insts, xs, X, Phi, sig = setup
+    case("MLP forward / loss / gradient parity")
+    prm, flat = _params(3)
+    s = lib.Solver()
+    s.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    s.set_pod_modes(Phi)
+    s.learned_set_params(flat)
+    sel = list(range(12))
+    th = thetas[sel].astype(np.float32)
+    masks = np.stack([insts[m].mask for m in sel])
+    bs = np.stack([insts[m].b for m in sel])
+    s.learned_prepare(masks, bs, xs[sel], th)
+    out_g = s.learned_forward(th).cpu().numpy()
+    out_o, _ = OL.mlp_forward(prm, th.astype(np.float64))
+    np.testing.assert_allclose(out_g, out_o, rtol=2e-3, atol=2e-4 * np.abs(out_o).max())
+    loss_g, grad_g = s.learned_loss_grad()
+    loss_o, grads_o = _oracle_loss_grad(prm, w, op, Phi, th.astype(np.float64), [insts[m] for m in sel],
+                                        xs[sel])
+    np.testing.assert_allclose(loss_g, loss_o, rtol=1e-3, atol=1e-5)
+    off = {"W1": 0, "b1": 512, "W2": 640, "b2": 17024, "W3": 17152, "b3": 82688}
+    for k, o in off.items():
+        go = grads_o[k].ravel()
+        gg = grad_g[o:o + go.size].astype(np.float64)
+        assert np.linalg.norm(gg - go) <= 2e-2 * np.linalg.norm(go) + 1e-12, k
+
+
+def test_training_enriched_solves_safeguard_and_gain(lib, setup):
+    w, op, thetas, insts, xs, X, Phi, sig = setup
+    case("train on 48 samples, enriched batched solves on 12 held-out instances")
+    prm, flat = _params(4)
+    s = lib.Solver()
+    s.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    s.set_pod_modes(Phi)
+    s.learned_set_params(flat)
+    th = thetas.astype(np.float32)
+    s.learned_prepare(np.stack([i.mask for i in insts[:MTR]]), np.stack([i.b for i in insts[:MTR]]),
+                      xs[:MTR], th[:MTR])
+    hist = s.learned_train(300, lr=3e-3)
+    assert hist[-1] < hist[0]
+    test = list(range(MTR, MTR + 12))
+    masks = np.stack([insts[m].mask for m in test])
+    bs = np.stack([insts[m].b for m in test])
+    plain = s.solve_batched(masks, bs, 1e-10)
+    lrn = s.solve_batched(masks, bs, 1e-10, theta=th[test])
+    params = s.learned_get_params()
+    P_o = {"W1": params[0:512].reshape(128, 4), "b1": params[512:640],
+           "W2": params[640:17024].reshape(128, 128), "b2": params[17024:17152],
+           "W3": params[17152:82688].reshape(512, 128), "b3": params[82688:83200]}
+    out_o, _ = OL.mlp_forward(P_o, th[test].astype(np.float64))
+    Xl = lrn["x"].cpu().numpy()
+    for j, m in enumerate(test):
+        inst = insts[m]
+        I, _, _ = oracle.compact(inst.mask)
+        spec = ("factored", op.A, op.alpha, op.shift)
+        V = Phi @ out_o[j].reshape(8, 64)[:, :P].T
+        ref = oracle.solve_instance(spec, np.column_stack([w.Z, V]), inst.mask, inst.b, 1e-10,
+                                    tau_cond=1e8)
+        e = oracle.rel_err(Xl[j, I], xs[m][I])
+        assert lrn["status"][j] == 0
+        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs[m][I]))
+        if lrn["learned"][j] and ref.status == 0:
+            assert abs(int(lrn["iters"][j]) - ref.iters) <= max(3, ref.iters // 20)
+    print(f"   iterations plain {plain['iters'].tolist()} learned {lrn['iters'].tolist()} "
+          f"learned-used {lrn['learned'].tolist()}", flush=True)
+    assert lrn["iters"].mean() <= plain["iters"].mean()
+    # safeguard: an unattainable conditioning bound falls back to the plain basis
+    s.learned_set_params(params, tau_learned=1.0)
+    fb = s.solve_batched(masks, bs, 1e-10, theta=th[test])
+    assert np.all(fb["learned"] == 0)
+    np.testing.assert_array_equal(fb["iters"], plain["iters"])
