@@ -105,8 +105,19 @@ typedef struct {
                            direction is carried only while the FP64 residual
                            decreases, else the next segment restarts; 1000   */
   int32_t check_every;  /* iterations between host polls of convergence; 32 */
-  int32_t rows_per_thread; /* 0 = autotuned; else 1, 2 or 4                  */
+  int32_t rows_per_thread; /* rows per thread of the iteration kernels (tile
+                           height 1024 or 2048 rows): 1 or 2, or 0 = tuned on
+                           the first solve of each configuration            */
   int32_t profile;      /* 1 = time kernels with HIP events (adef2_get_stats) */
+  int32_t w_mode;       /* how the iteration forms W^T z (W = S_II Z_I):
+                           1 = read the stored W; 2 = Z^T (S_II z), one more
+                           stencil pass instead of reading W; 0 = tuned on
+                           the first solve of each configuration.  Tuning runs
+                           every candidate for the first 64 iterations from
+                           the same start, keeps the fastest per context
+                           (batch size, precision, basis width, operator
+                           form, N) and reuses it, so repeated solves in one
+                           context are bitwise reproducible                 */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;

@@ -43,6 +43,7 @@ class Opts(ctypes.Structure):
         ("check_every", ctypes.c_int32),
         ("rows_per_thread", ctypes.c_int32),
         ("profile", ctypes.c_int32),
+        ("w_mode", ctypes.c_int32),
     ]
 
 

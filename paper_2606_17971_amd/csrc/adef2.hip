@@ -22,9 +22,10 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int round8(int k) { return (k + 7) & ~7; }
 
 enum KernelId { KI_INIT = 0, KI_INIT2, KI_PUPDATE, KI_SPMV, KI_UPDATE, KI_RESID, KI_ACCUM,
-                KI_GRAM, KI_COARSE, KI_COMPACT, KI_COUNT };
+                KI_GRAM, KI_COARSE, KI_COMPACT, KI_UPDATE_NW, KI_ZPROJ, KI_COUNT };
 const char* kKernelNames[KI_COUNT] = {"init", "init2", "pupdate", "spmv", "update", "resid64",
-                                      "accumulate", "spmm_gram", "coarse", "compact"};
+                                      "accumulate", "spmm_gram", "coarse", "compact", "update_nw",
+                                      "zproj"};
 
 }  // namespace
 
@@ -113,9 +114,12 @@ struct adef2_ctx {
   size_t part_elems = 0, ctr_elems = 0;
   std::vector<size_t> bytes;     // allocation sizes (for growth)
 
-  // geometry of the streaming kernels
+  // geometry and variant of the streaming kernels
   int rpt = 2;
+  int wfree = 0;                 // 1: W^T z as Z^T (S z), W not read per iteration
   int ntiles = 0, ntiles_pad = 0;
+  struct Tuned { int B, prec, KP, fact; int64_t N; int rpt, wfree; float ms[4]; };
+  std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
   int gram_blocks = 0;
   RedGeom g_gram{};
@@ -262,12 +266,15 @@ struct KTab {
   void (*pupdate)(IterArgs<V, M>);
   void (*spmv)(IterArgs<V, M>);
   void (*update)(IterArgs<V, M>);
+  void (*update_nw)(IterArgs<V, M>);
+  void (*zproj)(IterArgs<V, M>);
 };
 
 template <typename V, typename M, int KP, int RPT>
 KTab<V, M> make_tab() {
   return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
-          k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>};
+          k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, k_update_nw<V, M, KP, RPT>,
+          k_zproj<V, M, KP, RPT>};
 }
 
 template <typename V, typename M, int RPT>
@@ -354,13 +361,20 @@ void launch_coarse(adef2_ctx* c) {
 }
 
 // -------------------------------------------------------- buffer management
+// Tile geometry of the streaming kernels for rpt rows per thread (the
+// reduction scratch is sized for rpt = 1, the largest tile count).
+void set_variant(adef2_ctx* c, int rpt, int wfree) {
+  c->rpt = rpt;
+  c->wfree = wfree;
+  c->ntiles = (int)cdiv(c->N, (int64_t)IPB * rpt);
+  c->ntiles_pad = (int)cdiv(c->ntiles, 8) * 8;
+  c->g_iter = make_geom(c->ntiles_pad);
+}
+
 int ensure_batch(adef2_ctx* c, int B, int prec) {
   const int64_t N = c->N;
   const int KP = c->KP;
-  c->rpt = (c->o.rows_per_thread == 2) ? 2 : 1;
-  c->ntiles = (int)cdiv(N, (int64_t)IPB * c->rpt);
-  c->ntiles_pad = (int)cdiv(c->ntiles, 8) * 8;
-  c->g_iter = make_geom(c->ntiles_pad);
+  set_variant(c, (c->o.rows_per_thread == 2) ? 2 : 1, c->o.w_mode == 2 ? 1 : 0);
   const int64_t nsub_max = cdiv(N, 32);
   int gb = (int)std::max<int64_t>(8, std::min<int64_t>(256, 2048 / std::max(B, 1)));
   gb = (int)std::min<int64_t>(gb, nsub_max);
@@ -546,9 +560,13 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
 
 // algorithmic bytes per launch (per instance: inactive rows only); wv / wm =
 // bytes per vector entry / per operator or panel entry
-struct ByteModel { double init, init2, pupdate, spmv, update, resid, accum; };
-// Only instances still iterating at the last poll are counted (a finished
-// instance's blocks exit at their first instruction).
+struct ByteModel { double init, init2, pupdate, spmv, update, resid, accum, update_nw, zproj; };
+// Algorithmic bytes per launch.  Per-instance data (vectors, W, the mask) is
+// counted for every instance still iterating at the last poll (a finished
+// instance's blocks exit at their first instruction); operands shared by
+// all instances (Z, the stencil coefficients) are counted once per launch,
+// over min(N, total inactive rows) rows for Z and the outer stencil and N
+// rows for the inner stencil of the factored operator.
 ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active = true) {
   const double k = c->KP > 0 ? (double)c->k : 0.0;
   double nI = 0.0;
@@ -558,22 +576,27 @@ ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active
     const bool act = sweep_active ? !(s.done || s.outer_done) : !s.outer_done;
     if (act && m < (int)c->nI_host.size()) { nI += (double)c->nI_host[m]; ++nact; }
   }
-  const double N = (double)c->N * nact;
   ByteModel b{};
-  b.init = nI * (8.0 + k * wm + 2 * wv) + N;
-  b.init2 = nI * (3 * k * wm + 6 * wv) + N;
-  b.pupdate = nI * (k * wm + 3 * wv) + N;            // z, Z (k), p -> p
-  if (c->factored) {
-    // inner pass t = A p on all rows (D1 diagonals, p, t), outer pass on
-    // inactive rows (D diagonals of A^T, t, p, w)
-    b.spmv = N * (c->D1 * wm + 2 * wv) + nI * (c->D * wm + 3 * wv) + N;
-    b.resid = N * (c->D1 * 8.0 + 16.0) + nI * (c->D * 8.0 + 8.0 * 4) + N;
-  } else {
-    b.spmv = nI * (c->D * wm + 2 * wv) + N;           // D diagonals, p, w
-    b.resid = nI * (c->D * 8.0 + 8.0 * 3) + N;
-  }
-  b.update = nI * (2 * k * wm + 8 * wv) + N;          // W, Z (k each), x p r w dinv -> x r z
-  b.accum = nI * (wv + 16.0) + N;
+  if (nact == 0) return b;
+  const double N1 = (double)c->N;
+  const double Nall = N1 * nact;                     // mask bytes, inner-stencil rows
+  const double U = std::min(N1, nI);                 // rows of shared operands used
+  const double zsh = (c->zs ? nI : U) * k * wm;      // Z: shared, or per instance (learned basis)
+  const double D = c->D, D1 = c->D1;
+  b.init = nI * (8.0 + 2 * wv) + zsh + Nall;                   // src -> x, r; Z^T r
+  b.init2 = nI * (k * wm + 6 * wv) + zsh + Nall;               // W c0, x r z dinv
+  b.pupdate = nI * 3 * wv + zsh + Nall;                        // z, p -> p; Z c
+  const double outer = nI * 3 * wv + U * D * wm + Nall;        // t (or p), p -> w; A^T or S
+  const double inner = c->factored ? (Nall * 2 * wv + N1 * D1 * wm) : 0.0;   // t = A v
+  b.spmv = inner + outer;
+  b.update = nI * (k * wm + 8 * wv) + zsh + Nall;              // W, Z; x p r w dinv -> x r z
+  b.update_nw = nI * 8 * wv + Nall;                            // x p r w dinv -> x r z
+  b.zproj = inner + nI * 3 * wv + U * D * wm + zsh + Nall;     // (t = A z), z, r; Z^T u, Z^T r
+  if (c->factored)
+    b.resid = Nall * 16.0 + N1 * D1 * 8.0 + nI * 8.0 * 4 + U * D * 8.0 + Nall;
+  else
+    b.resid = nI * 8.0 * 3 + U * D * 8.0 + Nall;
+  b.accum = nI * (wv + 16.0) + Nall;
   return b;
 }
 
@@ -591,9 +614,11 @@ int poll(adef2_ctx* c, bool outer, bool* all_done) {
 
 // run one A-DEF2 sweep in precision V for all instances: init, init2, then
 // chunks of iterations until every instance's sweep is done
+// max_chunks > 0 stops after that many chunks (tuning trials).
 template <typename V, typename M>
 int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale,
-              double thresh_floor, int carry_dir) {
+              double thresh_floor, int carry_dir, int max_chunks = 0) {
+  const bool wfree = c->wfree && c->KP > 0;
   IterArgs<V, M> a = iter_args<V, M>(c);
   a.src = src;
   a.x0 = x0pad;
@@ -636,9 +661,20 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
           hipLaunchKernelGGL(st1, grid, blk, 0, c->st, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
         hipLaunchKernelGGL(kt.spmv, grid, blk, 0, c->st, a);
       });
-      timed(c, KI_UPDATE, bm.update, [&] { hipLaunchKernelGGL(kt.update, grid, blk, 0, c->st, a); });
+      if (!wfree) {
+        timed(c, KI_UPDATE, bm.update, [&] { hipLaunchKernelGGL(kt.update, grid, blk, 0, c->st, a); });
+      } else {
+        timed(c, KI_UPDATE_NW, bm.update_nw,
+              [&] { hipLaunchKernelGGL(kt.update_nw, grid, blk, 0, c->st, a); });
+        timed(c, KI_ZPROJ, bm.zproj, [&] {
+          if (c->factored)
+            hipLaunchKernelGGL(st1, grid, blk, 0, c->st, og, a.dia1, (const V*)a.z, a.t, c->vs, c->inst, 1);
+          hipLaunchKernelGGL(kt.zproj, grid, blk, 0, c->st, a);
+        });
+      }
     }
     HIPCHK(c, hipGetLastError());
+    if (max_chunks > 0 && launched >= (int64_t)max_chunks * chunk) break;
   }
   return ADEF2_OK;
 }
@@ -678,19 +714,88 @@ int resid64(adef2_ctx* c, const double* b, const double* xpad, int first, int de
   return ADEF2_OK;
 }
 
-// Solve all B restricted instances; b, x instance-major unpadded [B][N].
-int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, double* x) {
-  const int B = c->B;
-  const int64_t N = c->N;
-  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(c, ADEF2_E_ARG, "tol must be positive");
-  // reset per-solve state (keep restriction results)
-  for (int m = 0; m < B; ++m) {
+// reset per-solve state (keep restriction results)
+int reset_solve_state(adef2_ctx* c) {
+  for (int m = 0; m < c->B; ++m) {
     Inst& s = c->inst_h[m];
     s.iters = 0; s.sweep_iters = 0; s.done = 0; s.outer_done = 0; s.status = 0; s.sweeps = 0;
     s.has_dir = 0; s.rho_end = 0.0; s.stall = 0; s.rr64_best = INFINITY;
     s.rr = 0; s.rr64 = 0; s.bb64 = 0;
   }
-  HIPCHK(c, hipMemcpyAsync(c->inst, c->inst_h, sizeof(Inst) * B, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->inst, c->inst_h, sizeof(Inst) * c->B, hipMemcpyHostToDevice, c->st));
+  return ADEF2_OK;
+}
+
+// Variant of the iteration kernels: rows per thread (tile height) and
+// whether W is read each iteration.  Fixed by the options, or tuned once per
+// (batch size, precision, basis width, operator form, N) on the first solve:
+// every candidate runs the solve's first two chunks of iterations from the
+// same start and the fastest is kept for this context, so repeated solves of
+// one configuration use the same kernels (and give identical results).
+int choose_variant(adef2_ctx* c, const double* b, double tol) {
+  const int fr = c->o.rows_per_thread, fw = c->o.w_mode;
+  std::vector<int> rpts = (fr == 1 || fr == 2) ? std::vector<int>{fr} : std::vector<int>{1, 2};
+  std::vector<int> wfs = (fw == 1 || c->KP == 0) ? std::vector<int>{0}
+                         : (fw == 2 ? std::vector<int>{1} : std::vector<int>{0, 1});
+  if (rpts.size() * wfs.size() == 1) { set_variant(c, rpts[0], wfs[0]); return ADEF2_OK; }
+  const int fact = c->factored ? 1 : 0;
+  for (const auto& t : c->tuned)
+    if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N) {
+      set_variant(c, t.rpt, t.wfree);
+      return ADEF2_OK;
+    }
+  const int prof = c->o.profile;
+  c->o.profile = 0;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, c->N, rpts[0], wfs[0], {0, 0, 0, 0}};
+  float best_ms = INFINITY;
+  int rc = ADEF2_OK, ci = 0;
+  for (int rpt : rpts) {
+    for (int wf : wfs) {
+      set_variant(c, rpt, wf);
+      if ((rc = reset_solve_state(c))) break;
+      if (c->prec != ADEF2_FP64) {
+        fill<double>(c, c->x64, (size_t)c->B * c->vs, 0.0);
+        if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, tol, true))) break;
+      }
+      HIPCHK(c, hipEventRecord(e0, c->st));
+      if (c->prec == ADEF2_FP64)
+        rc = run_sweep<double, double>(c, b, nullptr, tol * tol, 0.0, 0, 2);
+      else if (vec64(c->prec))
+        rc = run_sweep<double, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol,
+                                      0.25 * tol * tol, 0, 2);
+      else
+        rc = run_sweep<float, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol,
+                                     0.25 * tol * tol, 0, 2);
+      if (rc) break;
+      HIPCHK(c, hipEventRecord(e1, c->st));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      best.ms[ci++] = ms;
+      if (ms < best_ms) { best_ms = ms; best.rpt = rpt; best.wfree = wf; }
+    }
+    if (rc) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->o.profile = prof;
+  if (rc) return rc;
+  c->tuned.push_back(best);
+  set_variant(c, best.rpt, best.wfree);
+  return ADEF2_OK;
+}
+
+// Solve all B restricted instances; b, x instance-major unpadded [B][N].
+int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, double* x) {
+  const int B = c->B;
+  const int64_t N = c->N;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(c, ADEF2_E_ARG, "tol must be positive");
+  int rc;
+  if ((rc = choose_variant(c, b, tol))) return rc;
+  if ((rc = reset_solve_state(c))) return rc;
   dim3 gc((unsigned)cdiv(N, 256), B);
   const double* x0p = nullptr;
   if (x0) {
@@ -699,7 +804,6 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
                        interior(c, c->x0pad), c->vs);
     x0p = interior(c, c->x0pad);
   }
-  int rc;
   double* xres = nullptr;
   if (c->prec == ADEF2_FP64) {
     if ((rc = run_sweep<double, double>(c, b, x0p, tol * tol, 0.0, 0))) return rc;
@@ -767,7 +871,8 @@ bool valid_opts(const adef2_opts* o) {
           o->precision == ADEF2_MIXED_REFINE) &&
          (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
          o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0 &&
-         o->segment_maxit >= 0;
+         o->segment_maxit >= 0 && o->rows_per_thread >= 0 && o->rows_per_thread <= 2 &&
+         o->w_mode >= 0 && o->w_mode <= 2;
 }
 
 }  // namespace
@@ -875,6 +980,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->segment_maxit = 1000;
   o->rows_per_thread = 0;
   o->profile = 0;
+  o->w_mode = 0;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {

@@ -425,6 +425,47 @@ __global__ void __launch_bounds__(IPB) k_spmv(IterArgs<V, M> a) {
   }
 }
 
+// Finisher of an iteration's last reduction, tot = [W^T z | Z^T r | r.z | r.r]:
+// iteration count, stopping tests (tolerance, segment cap, maxit), then the
+// next coarse coordinates and beta.
+template <int KP>
+__device__ __forceinline__ void update_finish(const double* Cm, const double* tot, Inst* S, bool defl,
+                                              int32_t maxit, int32_t seg_maxit) {
+  __shared__ int s_go;
+  if (threadIdx.x == 0) {
+    const double rrt = tot[2 * KP + 1];
+    S->iters += 1;
+    S->sweep_iters += 1;
+    S->rr = rrt;
+    int go = 0;
+    if (!(rrt > S->thresh2) || (seg_maxit > 0 && S->sweep_iters >= seg_maxit)) {
+      S->done = 1;
+      go = 2;                       // sweep ends: keep r.y for the next sweep
+      if (!(rrt < INFINITY)) { S->outer_done = 1; S->status = -5; go = 0; }
+    } else if (S->iters >= maxit) {
+      S->done = 1;
+      S->outer_done = 1;
+      S->status = 2;
+    } else {
+      go = 1;
+    }
+    s_go = go;
+  }
+  __syncthreads();
+  if (!s_go) return;
+  const double rho = adef2_direction<KP>(Cm, tot, S, defl);
+  if (threadIdx.x == 0) {
+    if (s_go == 1) {
+      S->beta = rho / S->rho;
+      S->rho = rho;
+      S->fresh = 0;
+    } else {
+      S->rho_end = rho;
+      S->has_dir = 1;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // x += alpha p, r -= alpha w, z = K r;  W^T z, Z^T r, r.z, ||r||^2
 // finisher: stopping test on ||r||, beta = r.y / rho, coarse coordinates
@@ -480,39 +521,116 @@ __global__ void __launch_bounds__(IPB) k_update(IterArgs<V, M> a) {
   __syncthreads();
   if (!reduce_directions<V, M, KP, RPT>(a, m, tile, base, W, defl, rz, rr2, zl, rl, act, red, bv, tot))
     return;
-  __shared__ int s_go;
-  if (threadIdx.x == 0) {
-    const double rrt = tot[2 * KP + 1];
-    S->iters += 1;
-    S->sweep_iters += 1;
-    S->rr = rrt;
-    int go = 0;
-    if (!(rrt > S->thresh2) || (a.seg_maxit > 0 && S->sweep_iters >= a.seg_maxit)) {
-      S->done = 1;
-      go = 2;                       // sweep ends: keep r.y for the next sweep
-      if (!(rrt < INFINITY)) { S->outer_done = 1; S->status = -5; go = 0; }
-    } else if (S->iters >= a.maxit) {
-      S->done = 1;
-      S->outer_done = 1;
-      S->status = 2;
-    } else {
-      go = 1;
+  update_finish<KP>(a.C + (size_t)m * KP * KP, tot, S, defl, a.maxit, a.seg_maxit);
+}
+
+// ---------------------------------------------------------------------------
+// W-free variant of the update: W^T z = Z^T (S_II z), so the per-instance
+// panel W is not read in the iteration.  k_update_nw streams x, r, z;
+// k_zproj then forms u = S_II z row by row (from t = A z for the factored
+// operator) and reduces [Z^T u | Z^T r | r.z | r.r] with one pass over Z.
+// ---------------------------------------------------------------------------
+template <typename V, typename M, int KP, int RPT>
+__global__ void __launch_bounds__(IPB) k_update_nw(IterArgs<V, M> a) {
+  int tile, m;
+  tile_inst(a.op.ntiles_pad, tile, m);
+  const Inst* S = a.inst + m;
+  if (S->done) return;
+  if (tile >= a.op.ntiles) return;
+  const int64_t N = a.op.N;
+  const uint8_t* mk = a.mask + (size_t)m * N;
+  V* x = a.x + m * a.vs;
+  V* r = a.r + m * a.vs;
+  V* z = a.z + m * a.vs;
+  const V* p = a.p + m * a.vs;
+  const V* w = a.w + m * a.vs;
+  const V* dinv = a.dinv + (size_t)m * N;
+  const double alpha = S->alpha;
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
+    if (i < N && mk[i] == 0) {
+      x[i] = (V)((double)x[i] + alpha * (double)p[i]);
+      const V rq = (V)((double)r[i] - alpha * (double)w[i]);
+      r[i] = rq;
+      z[i] = (V)((double)dinv[i] * (double)rq);
     }
-    s_go = go;
+  }
+}
+
+// sum over the tile rows of col * u and col * r (one read of the column)
+template <typename M, int RPT>
+__device__ __forceinline__ void panel_dot2(const M* col, int64_t base, const double* u, const double* r,
+                                           const uint8_t* act, double& su, double& sr) {
+  constexpr int R = Rows<RPT>::PB;
+  const int lane = threadIdx.x & 63;
+  double au = 0.0, ar = 0.0;
+#pragma unroll 4
+  for (int j = lane; j < R; j += 64)
+    if (!act[j]) {
+      const double c = (double)col[base + j];
+      au += c * u[j];
+      ar += c * r[j];
+    }
+  su = wave_sum(au);
+  sr = wave_sum(ar);
+}
+
+template <typename V, typename M, int KP, int RPT>
+__global__ void __launch_bounds__(IPB) k_zproj(IterArgs<V, M> a) {
+  constexpr int R = Rows<RPT>::PB;
+  constexpr int NV = 2 * KP + 2;
+  __shared__ double ul[R], rl[R];
+  __shared__ uint8_t act[R];
+  __shared__ double red[NIWAVE * 2];
+  __shared__ double bv[NV];
+  __shared__ double tot[NV];
+  int tile, m;
+  tile_inst(a.op.ntiles_pad, tile, m);
+  Inst* S = a.inst + m;
+  if (S->done) return;
+  const int64_t N = a.op.N;
+  const int64_t base = (int64_t)tile * R;
+  const uint8_t* mk = a.mask + (size_t)m * N;
+  const V* r = a.r + m * a.vs;
+  const V* z = a.z + m * a.vs;
+  const V* sv = (a.op.D1 ? a.t : a.z) + m * a.vs;
+  const bool defl = S->kk > 0;
+  const double sa = S->a, sc = S->c;
+  double rz = 0.0, rr2 = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int j = rr * IPB + threadIdx.x;
+    const int64_t i = base + j;
+    const bool on = (tile < a.op.ntiles) && i < N && mk[i] == 0;
+    double rv = 0.0, uv = 0.0;
+    if (on) {
+      const double zv = (double)z[i];
+      rv = (double)r[i];
+      rz += rv * zv;
+      rr2 += rv * rv;
+      if (defl) uv = sa * stencil_row(a.dia, a.op.offs, a.op.D, a.op.d0, N, i, sv) + sc * zv;
+    }
+    ul[j] = uv;
+    rl[j] = rv;
+    act[j] = !on;
   }
   __syncthreads();
-  if (!s_go) return;
-  const double rho = adef2_direction<KP>(a.C + (size_t)m * KP * KP, tot, S, defl);
-  if (threadIdx.x == 0) {
-    if (s_go == 1) {
-      S->beta = rho / S->rho;
-      S->rho = rho;
-      S->fresh = 0;
-    } else {
-      S->rho_end = rho;
-      S->has_dir = 1;
-    }
+  {
+    double v2[2] = {rz, rr2};
+    block_sum<2, NIWAVE>(v2, red, bv + 2 * KP);
   }
+  const int wid = threadIdx.x >> 6;
+  for (int q = wid; q < KP; q += NIWAVE) {
+    double su = 0.0, sr = 0.0;
+    if (defl) panel_dot2<M, RPT>(a.Z + (size_t)m * a.zs + (size_t)q * N, base, ul, rl, act, su, sr);
+    if ((threadIdx.x & 63) == 0) { bv[q] = su; bv[KP + q] = sr; }
+  }
+  __syncthreads();
+  double* part = a.part + (size_t)m * a.g.ptotal * NV;
+  unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
+  if (!tree_reduce(a.g, tile, NV, part, ctr, bv, tot)) return;
+  update_finish<KP>(a.C + (size_t)m * KP * KP, tot, S, defl, a.maxit, a.seg_maxit);
 }
 
 // ---------------------------------------------------------------------------

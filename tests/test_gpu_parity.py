@@ -337,3 +337,43 @@ def test_error_paths(lib, c1):
     # zero right-hand side: x = 0 without iterations
     out = s.solve(np.zeros(S.shape[0]), 1e-8)
     assert out.iters == 0 and float(out.x.abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# kernel variants: tile height (rows per thread) and W-free iterations
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["assembled", "factored"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("rpt,w_mode", [(1, 1), (1, 2), (2, 1), (2, 2)])
+def test_kernel_variants_match_oracle(lib, rpt, w_mode, prec, form):
+    w = gen.c2_workload(n=95, k=16, B=3)
+    S = spec(w.op, form)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case(f"variant rpt={rpt} w_mode={w_mode} {prec} {form} cd2d n=95 B=3")
+    p = lib.FP64 if prec == "fp64" else lib.MIXED_REFINE
+    s = solver(lib, w.op, w.Z, form, precision=p, rows_per_thread=rpt, w_mode=w_mode)
+    out = s.solve_batched(masks, bs, 1e-10)
+    X = out["x"].cpu().numpy()
+    for m, inst in enumerate(w.instances):
+        ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
+        I, xs = _xstar(S, inst.mask, inst.b)
+        e = oracle.rel_err(X[m, I], xs)
+        assert out["status"][m] == 0
+        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), (m, e)
+        if prec == "fp64":
+            assert abs(int(out["iters"][m]) - ref.iters) <= 2
+        else:
+            assert out["relres_true"][m] <= 1e-10
+
+
+def test_autotuned_variant_is_reused(lib):
+    w = gen.c2_workload(n=95, k=16, B=2)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case("autotuned variant reused within a context")
+    s = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE)
+    a = s.solve_batched(masks, bs, 1e-10)
+    b = s.solve_batched(masks, bs, 1e-10)
+    np.testing.assert_array_equal(a["iters"], b["iters"])
+    np.testing.assert_array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
