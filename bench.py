@@ -51,6 +51,15 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--snap-tol", type=float, default=1e-8)
+    ap.add_argument("--rpt", type=int, default=0, choices=[0, 1, 2],
+                    help="rows per thread of the iteration kernels (0 = tuned)")
+    ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2],
+                    help="1 = read W, 2 = W-free, 0 = tuned")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="short run for rocprofv3 counter passes: one headline solve capped at "
+                         "--counter-maxit iterations, then a 256 MiB device copy of known size; "
+                         "prints no benchmark line")
+    ap.add_argument("--counter-maxit", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=200,
                     help="oracle iterations timed for the CPU baseline sample")
@@ -139,7 +148,10 @@ def main():
     B = args.batch
     prec = {"mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE, "fp64": lib.FP64}[args.precision]
 
-    head = lib.Solver(precision=prec, inner_rtol=args.inner_rtol)
+    tune = dict(rows_per_thread=args.rpt, w_mode=args.w_mode)
+    if args.counter_run:
+        tune["maxit"] = args.counter_maxit
+    head = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
     head.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     thetas = torch.as_tensor(np.stack([i.theta for i in w.instances]).astype(np.float32), device="cuda")
     learned, Phi = (None, None) if args.no_learned else fit_enrichment(head, args, lib)
@@ -148,6 +160,17 @@ def main():
     def head_step():
         return head.solve_batched(masks, bs, args.tol, theta=use_theta)
 
+    if args.counter_run:
+        out = head_step()
+        torch.cuda.synchronize()
+        src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_run": True, "iters": np.asarray(out["iters"]).tolist(),
+                          "variant": list(head.variant()[:2]), "copy_bytes_each_way": src.numel() * 8}))
+        return
     for _ in range(args.warmup):
         out = head_step()
     torch.cuda.synchronize()
@@ -158,6 +181,7 @@ def main():
     torch.cuda.synchronize()
     t_head = (time.perf_counter() - t0) / args.steps
     head_iters = np.asarray(out["iters"])
+    v_rpt, v_wm, v_ms = head.variant()
     head_rel = np.asarray(out["relres_true"])
     X_head = out["x"].clone()
 
@@ -202,7 +226,8 @@ def main():
         print(f"[bench] plain step done ({t_plain:.2f}s)", file=sys.stderr, flush=True)
 
     # roofline: one instrumented headline step, HIP events around every launch
-    prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1)
+    prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1,
+                      rows_per_thread=v_rpt, w_mode=v_wm)
     prof.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     if learned is not None:
         prof.set_pod_modes(Phi)
@@ -241,6 +266,8 @@ def main():
                    "operator": "S = alpha A^T A + shift I (A: 5-point upwind, factored)"},
         "iters": {"mean": float(head_iters.mean()), "min": int(head_iters.min()),
                   "max": int(head_iters.max())},
+        "variant": {"rows_per_thread": v_rpt, "w_mode": v_wm, "tuned": args.rpt == 0 or args.w_mode == 0,
+                    "trial_ms": [round(float(t), 3) for t in v_ms]},
         "learned_used": (int(np.asarray(out["learned"]).sum()) if learned is not None else 0),
         "learned_fit": learned,
         "batched_reference_modes": batched,

@@ -54,8 +54,10 @@ enum adef2_status {
                                tau_cond)                                     */
   ADEF2_W_MAXIT = 2,        /* not converged within maxit; x = last iterate  */
   ADEF2_W_STAGNATED = 3     /* refinement modes: the FP64 residual b - S x
-                               stopped decreasing (its best value did not halve
-                               over 4 outer steps) above tol: the attainable
+                               stopped decreasing above tol (its best value did
+                               not halve over 4 outer steps whose segments
+                               converged on their own equation, i.e. were not
+                               stopped by segment_maxit): the attainable
                                accuracy of FP64 x was reached (when cond(S_II)
                                is ~1e10 the FP64 rounding of the exact solution
                                already has a relative residual ~1e-10); x is
@@ -100,10 +102,16 @@ typedef struct {
                            then replaces it and the search direction carries
                            on (residual replacement); 1e-2                   */
   int32_t max_sweeps;   /* FP32_REFINE: cap on segments; 2000                */
-  int32_t segment_maxit; /* FP32_REFINE: a segment also ends after this many
-                           iterations (periodic residual replacement); the
-                           direction is carried only while the FP64 residual
-                           decreases, else the next segment restarts; 1000   */
+  int32_t segment_maxit; /* refinement modes: a segment also ends after this
+                           many iterations (periodic residual replacement);
+                           < 0 = no cap, 0 = by precision (1000 with FP32
+                           vectors, which drift from the FP64 residual; none
+                           with FP64 vectors, where forced replacements
+                           perturb CG near the accuracy floor).  The
+                           direction is carried over unless the FP64
+                           residual exceeds the segment's final recurrence
+                           residual by more than 2x (drift), when the next
+                           segment restarts; 0                              */
   int32_t check_every;  /* iterations between host polls of convergence; 32 */
   int32_t rows_per_thread; /* rows per thread of the iteration kernels (tile
                            height 1024 or 2048 rows): 1 or 2, or 0 = tuned on
@@ -111,8 +119,11 @@ typedef struct {
   int32_t profile;      /* 1 = time kernels with HIP events (adef2_get_stats) */
   int32_t w_mode;       /* how the iteration forms W^T z (W = S_II Z_I):
                            1 = read the stored W; 2 = Z^T (S_II z), one more
-                           stencil pass instead of reading W; 0 = tuned on
-                           the first solve of each configuration.  Tuning runs
+                           stencil pass instead of reading W, with the FP64
+                           operator and modes (z is rough, so FP32 rounding of
+                           S or Z would be amplified by cond(S)); needs FP64
+                           vectors: E_UNSUPPORTED with FP32_REFINE; 0 = tuned
+                           on the first solve of each configuration.  Tuning runs
                            every candidate for the first 64 iterations from
                            the same start, keeps the fastest per context
                            (batch size, precision, basis width, operator
@@ -264,6 +275,14 @@ int adef2_apply_restricted(adef2_ctx *ctx, const double *x, double *y);
  * kept column flags (host int32[k]).  Either may be NULL. */
 int adef2_coarse_info(adef2_ctx *ctx, double *E, int32_t *kept, int32_t *k_eff,
                       double *cond_E);
+
+/* Iteration-kernel variant used by the last solve on ctx: rows per thread
+ * (1 or 2) and w_mode (1 = stored W read, 2 = W-free), whether fixed by the
+ * options or tuned.  ms (host f32[4], may be NULL) receives the trial times of
+ * the tuned candidates in the order (rpt 1, W), (rpt 1, W-free), (rpt 2, W),
+ * (rpt 2, W-free) restricted to the candidates tried, 0 when not tuned.
+ * E_STATE before the first solve. */
+int adef2_variant(adef2_ctx *ctx, int32_t *rows_per_thread, int32_t *w_mode, float *ms);
 
 typedef struct {
   int32_t n_kernels;            /* entries filled                           */

@@ -83,6 +83,7 @@ _sig = {
     "adef2_learned_forward": (ctypes.c_int, [_P, _i32, _P, _P]),
     "adef2_apply_restricted": (ctypes.c_int, [_P, _P, _P]),
     "adef2_coarse_info": (ctypes.c_int, [_P, _P, _P, _Pi32, _Pf64]),
+    "adef2_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _P]),
     "adef2_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "adef2_reset_stats": (ctypes.c_int, [_P]),
     "adef2_last_error": (ctypes.c_char_p, [_P]),
@@ -329,6 +330,14 @@ class Solver:
         y = torch.empty_like(xt)
         self._check(_lib.adef2_apply_restricted(self._ctx, _ptr(xt), _ptr(y)), allow=(OK,))
         return y
+
+    def variant(self):
+        """(rows_per_thread, w_mode, trial ms) of the last solve."""
+        r, wm = _i32(0), _i32(0)
+        ms = np.zeros(4, np.float32)
+        self._check(_lib.adef2_variant(self._ctx, ctypes.byref(r), ctypes.byref(wm), ms.ctypes.data),
+                    allow=(OK,))
+        return r.value, wm.value, ms
 
     def coarse_info(self):
         k = max(self.k, 1)

@@ -117,6 +117,7 @@ struct adef2_ctx {
   // geometry and variant of the streaming kernels
   int rpt = 2;
   int wfree = 0;                 // 1: W^T z as Z^T (S z), W not read per iteration
+  bool solved = false;           // a solve ran (variant is meaningful)
   int ntiles = 0, ntiles_pad = 0;
   struct Tuned { int B, prec, KP, fact; int64_t N; int rpt, wfree; float ms[4]; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
@@ -272,9 +273,13 @@ struct KTab {
 
 template <typename V, typename M, int KP, int RPT>
 KTab<V, M> make_tab() {
-  return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
-          k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, k_update_nw<V, M, KP, RPT>,
-          k_zproj<V, M, KP, RPT>};
+  if constexpr (sizeof(V) == 8)
+    return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
+            k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, k_update_nw<V, M, KP, RPT>,
+            k_zproj<V, M, KP, RPT>};
+  else
+    return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
+            k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, nullptr, nullptr};
 }
 
 template <typename V, typename M, int RPT>
@@ -531,6 +536,9 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.maxit = c->o.maxit;
   a.vs = c->vs;
   a.zs = c->zs;
+  a.dia64 = c->dia64;
+  a.dia1_64 = c->dia1_64;
+  a.Z64 = c->Z64;
   if constexpr (sizeof(M) == 8) {
     a.dia1 = (const M*)c->dia1_64;
     a.dia = (const M*)c->dia64;
@@ -591,7 +599,9 @@ ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active
   b.spmv = inner + outer;
   b.update = nI * (k * wm + 8 * wv) + zsh + Nall;              // W, Z; x p r w dinv -> x r z
   b.update_nw = nI * 8 * wv + Nall;                            // x p r w dinv -> x r z
-  b.zproj = inner + nI * 3 * wv + U * D * wm + zsh + Nall;     // (t = A z), z, r; Z^T u, Z^T r
+  // (t = A z), z, r; Z^T u, Z^T r with the FP64 operator and modes
+  const double inner64 = c->factored ? (Nall * 2 * wv + N1 * D1 * 8.0) : 0.0;
+  b.zproj = inner64 + nI * 3 * wv + U * D * 8.0 + zsh * (8.0 / wm) + Nall;
   if (c->factored)
     b.resid = Nall * 16.0 + N1 * D1 * 8.0 + nI * 8.0 * 4 + U * D * 8.0 + Nall;
   else
@@ -618,7 +628,7 @@ int poll(adef2_ctx* c, bool outer, bool* all_done) {
 template <typename V, typename M>
 int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale,
               double thresh_floor, int carry_dir, int max_chunks = 0) {
-  const bool wfree = c->wfree && c->KP > 0;
+  const bool wfree = c->wfree && c->KP > 0 && sizeof(V) == 8;
   IterArgs<V, M> a = iter_args<V, M>(c);
   a.src = src;
   a.x0 = x0pad;
@@ -626,7 +636,11 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   a.thresh_scale = thresh_scale;
   a.thresh_floor = thresh_floor;
   a.carry_dir = carry_dir;
-  a.seg_maxit = (c->prec == ADEF2_FP64) ? 0 : c->o.segment_maxit;
+  // segment cap: explicit (> 0), none (< 0), or by precision (0): FP32
+  // vectors drift from the FP64 residual and need periodic replacement, FP64
+  // vectors do not (forced replacements perturb CG near the accuracy floor)
+  const int sm = c->o.segment_maxit;
+  a.seg_maxit = (c->prec == ADEF2_FP64) ? 0 : (sm > 0 ? sm : (sm == 0 && !vec64(c->prec) ? 1000 : 0));
   KTab<V, M> kt = pick<V, M>(c->KP, c->rpt);
   dim3 grid(c->ntiles_pad * c->B), blk(IPB);
   ByteModel bm = byte_model(c, (double)sizeof(V), (double)sizeof(M), false);
@@ -668,7 +682,8 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
               [&] { hipLaunchKernelGGL(kt.update_nw, grid, blk, 0, c->st, a); });
         timed(c, KI_ZPROJ, bm.zproj, [&] {
           if (c->factored)
-            hipLaunchKernelGGL(st1, grid, blk, 0, c->st, og, a.dia1, (const V*)a.z, a.t, c->vs, c->inst, 1);
+            hipLaunchKernelGGL((stencil1_fn<double, V, V>(c->rpt)), grid, blk, 0, c->st, og, c->dia1_64,
+                               (const V*)a.z, a.t, c->vs, c->inst, 1);
           hipLaunchKernelGGL(kt.zproj, grid, blk, 0, c->st, a);
         });
       }
@@ -719,7 +734,8 @@ int reset_solve_state(adef2_ctx* c) {
   for (int m = 0; m < c->B; ++m) {
     Inst& s = c->inst_h[m];
     s.iters = 0; s.sweep_iters = 0; s.done = 0; s.outer_done = 0; s.status = 0; s.sweeps = 0;
-    s.has_dir = 0; s.rho_end = 0.0; s.stall = 0; s.rr64_best = INFINITY;
+    s.has_dir = 0; s.rho_end = 0.0; s.stall = 0; s.rr64_best = INFINITY; s.drift = 0;
+    s.capped = 0;
     s.rr = 0; s.rr64 = 0; s.bb64 = 0;
   }
   HIPCHK(c, hipMemcpyAsync(c->inst, c->inst_h, sizeof(Inst) * c->B, hipMemcpyHostToDevice, c->st));
@@ -734,8 +750,10 @@ int reset_solve_state(adef2_ctx* c) {
 // one configuration use the same kernels (and give identical results).
 int choose_variant(adef2_ctx* c, const double* b, double tol) {
   const int fr = c->o.rows_per_thread, fw = c->o.w_mode;
+  if (fw == 2 && !vec64(c->prec))
+    return fail(c, ADEF2_E_UNSUPPORTED, "W-free iterations need FP64 vectors (FP64 or MIXED_REFINE)");
   std::vector<int> rpts = (fr == 1 || fr == 2) ? std::vector<int>{fr} : std::vector<int>{1, 2};
-  std::vector<int> wfs = (fw == 1 || c->KP == 0) ? std::vector<int>{0}
+  std::vector<int> wfs = (fw == 1 || c->KP == 0 || !vec64(c->prec)) ? std::vector<int>{0}
                          : (fw == 2 ? std::vector<int>{1} : std::vector<int>{0, 1});
   if (rpts.size() * wfs.size() == 1) { set_variant(c, rpts[0], wfs[0]); return ADEF2_OK; }
   const int fact = c->factored ? 1 : 0;
@@ -851,6 +869,7 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
   HIPCHK(c, hipMemcpyAsync(c->inst_h, c->inst, sizeof(Inst) * B, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   if (c->o.profile) ev_harvest(c);
+  c->solved = true;
   return ADEF2_OK;
 }
 
@@ -871,7 +890,7 @@ bool valid_opts(const adef2_opts* o) {
           o->precision == ADEF2_MIXED_REFINE) &&
          (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
          o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0 &&
-         o->segment_maxit >= 0 && o->rows_per_thread >= 0 && o->rows_per_thread <= 2 &&
+         o->rows_per_thread >= 0 && o->rows_per_thread <= 2 &&
          o->w_mode >= 0 && o->w_mode <= 2;
 }
 
@@ -977,7 +996,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->inner_rtol = 1e-2;
   o->max_sweeps = 2000;
   o->check_every = 32;
-  o->segment_maxit = 1000;
+  o->segment_maxit = 0;
   o->rows_per_thread = 0;
   o->profile = 0;
   o->w_mode = 0;
@@ -1333,6 +1352,21 @@ int adef2_apply_restricted(adef2_ctx* c, const double* x, double* y) {
   hipError_t e = hipStreamSynchronize(c->st);
   hipFree(tmp);
   if (e != hipSuccess) return fail(c, ADEF2_E_HIP, hipGetErrorString(e));
+  return ADEF2_OK;
+}
+
+int adef2_variant(adef2_ctx* c, int32_t* rows_per_thread, int32_t* w_mode, float* ms) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->solved) return fail(c, ADEF2_E_STATE, "variant before the first solve");
+  if (rows_per_thread) *rows_per_thread = c->rpt;
+  if (w_mode) *w_mode = c->wfree ? 2 : 1;
+  if (ms) {
+    for (int i = 0; i < 4; ++i) ms[i] = 0.0f;
+    const int fact = c->factored ? 1 : 0;
+    for (const auto& t : c->tuned)
+      if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N)
+        for (int i = 0; i < 4; ++i) ms[i] = t.ms[i];
+  }
   return ADEF2_OK;
 }
 

@@ -39,6 +39,8 @@ struct Inst {
   int32_t setup_status; // enum adef2_status of the restriction (fallback, ...)
   int32_t kk;           // coarse dimension in use (0: plain Jacobi-PCG)
   int32_t fresh;        // next p update starts a new direction
+  int32_t drift;        // last outer residual > 10x the sweep's recurrence residual
+  int32_t capped;       // the last sweep ended at the segment cap, not at its tolerance
   int32_t n_inactive;
   int32_t k_eff;        // kept restricted modes
   int32_t sweeps;

@@ -88,6 +88,10 @@ struct IterArgs {
   double thresh_floor;     //               thresh_floor * ||b_I||^2)
   int32_t carry_dir;       // keep the previous sweep's search direction
   int32_t seg_maxit;       // a sweep ends after this many iterations (0 = none)
+  // W-free projection: FP64 operator and modes (see k_zproj)
+  const double* dia64;     // [D][N]
+  const double* dia1_64;   // [D1][N]
+  const double* Z64;       // [KP][N] shared, or [B][KP][N] per instance
 };
 
 template <int RPT> struct Rows { static constexpr int PB = IPB * RPT; };
@@ -330,10 +334,9 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V, M> a) {
   if (!stop) rho = adef2_direction<KP>(a.C + (size_t)m * KP * KP, tot, S, defl);
   if (threadIdx.x == 0) {
     S->rr = tot[2 * KP + 1];
-    // residual replacement: continue the previous direction, p = y + beta p
-    // carried only while the FP64 residual keeps decreasing
-    const bool carry = a.carry_dir && S->has_dir && S->rho_end > 0.0 && rho > 0.0 &&
-                       S->rr64 < S->rr64_prev;
+    // residual replacement: continue the previous direction, p = y + beta p,
+    // unless the last sweep drifted from the FP64 residual
+    const bool carry = a.carry_dir && S->has_dir && S->rho_end > 0.0 && rho > 0.0 && !S->drift;
     S->beta = carry ? rho / S->rho_end : 0.0;
     S->fresh = carry ? 0 : 1;
     S->rho = rho;
@@ -440,6 +443,7 @@ __device__ __forceinline__ void update_finish(const double* Cm, const double* to
     int go = 0;
     if (!(rrt > S->thresh2) || (seg_maxit > 0 && S->sweep_iters >= seg_maxit)) {
       S->done = 1;
+      S->capped = (rrt > S->thresh2);
       go = 2;                       // sweep ends: keep r.y for the next sweep
       if (!(rrt < INFINITY)) { S->outer_done = 1; S->status = -5; go = 0; }
     } else if (S->iters >= maxit) {
@@ -529,6 +533,12 @@ __global__ void __launch_bounds__(IPB) k_update(IterArgs<V, M> a) {
 // panel W is not read in the iteration.  k_update_nw streams x, r, z;
 // k_zproj then forms u = S_II z row by row (from t = A z for the factored
 // operator) and reduces [Z^T u | Z^T r | r.z | r.r] with one pass over Z.
+// The preconditioned residual z is rough, so S z is of the size of
+// ||S|| ||z|| while Z^T S z is of the size of the small eigenvalues times
+// ||z||: rounding S, Z or z to FP32 would leave an error of u32 cond(S)
+// relative to it.  This variant therefore needs FP64 vectors and always
+// reads the FP64 operator and FP64 modes (shared by all instances of a batch,
+// so their traffic is paid once per launch, not per instance).
 // ---------------------------------------------------------------------------
 template <typename V, typename M, int KP, int RPT>
 __global__ void __launch_bounds__(IPB) k_update_nw(IterArgs<V, M> a) {
@@ -594,6 +604,7 @@ __global__ void __launch_bounds__(IPB) k_zproj(IterArgs<V, M> a) {
   const uint8_t* mk = a.mask + (size_t)m * N;
   const V* r = a.r + m * a.vs;
   const V* z = a.z + m * a.vs;
+  static_assert(sizeof(V) == 8, "the W-free projection needs FP64 vectors");
   const V* sv = (a.op.D1 ? a.t : a.z) + m * a.vs;
   const bool defl = S->kk > 0;
   const double sa = S->a, sc = S->c;
@@ -609,7 +620,7 @@ __global__ void __launch_bounds__(IPB) k_zproj(IterArgs<V, M> a) {
       rv = (double)r[i];
       rz += rv * zv;
       rr2 += rv * rv;
-      if (defl) uv = sa * stencil_row(a.dia, a.op.offs, a.op.D, a.op.d0, N, i, sv) + sc * zv;
+      if (defl) uv = sa * stencil_row(a.dia64, a.op.offs, a.op.D, a.op.d0, N, i, sv) + sc * zv;
     }
     ul[j] = uv;
     rl[j] = rv;
@@ -623,7 +634,7 @@ __global__ void __launch_bounds__(IPB) k_zproj(IterArgs<V, M> a) {
   const int wid = threadIdx.x >> 6;
   for (int q = wid; q < KP; q += NIWAVE) {
     double su = 0.0, sr = 0.0;
-    if (defl) panel_dot2<M, RPT>(a.Z + (size_t)m * a.zs + (size_t)q * N, base, ul, rl, act, su, sr);
+    if (defl) panel_dot2<double, RPT>(a.Z64 + (size_t)m * a.zs + (size_t)q * N, base, ul, rl, act, su, sr);
     if ((threadIdx.x & 63) == 0) { bv[q] = su; bv[KP + q] = sr; }
   }
   __syncthreads();
@@ -697,10 +708,16 @@ __global__ void __launch_bounds__(IPB) k_resid64(ResidArgs a) {
     if (a.decide) {
       const double bb = S->bb64;
       const double r2 = tot[0];
-      // attainable-accuracy guard: the best FP64 residual has not halved
-      // over the last STALL_STEPS outer steps
+      // Drift: the FP64 residual exceeds the recurrence residual the sweep
+      // ended with by more than 2x (while the iteration is accurate the two
+      // agree to a few per cent); the next sweep then restarts its direction.
+      // Attainable-accuracy guard: the best FP64 residual has not halved over
+      // the last stall_steps sweeps that converged on their own equation (a
+      // sweep stopped by the segment cap is no evidence: CG's residual 2-norm
+      // is not monotone)
+      S->drift = a.first ? 0 : (r2 > 4.0 * S->rr);
       if (a.first || r2 < 0.25 * S->rr64_best) { S->rr64_best = r2; S->stall = 0; }
-      else S->stall += 1;
+      else if (!S->capped) S->stall += 1;
       if (!(bb < INFINITY) || !(r2 < INFINITY)) { S->outer_done = 1; S->status = -1; }
       else if (!(r2 > a.tol2 * bb)) { S->outer_done = 1; }
       else if (S->stall >= a.stall_steps) { S->outer_done = 1; S->status = 3; }

@@ -38,6 +38,7 @@ def test_fullsize_batched_against_xstar(lib, c2full, xstars, prec):
     s = lib.Solver(precision=p)
     s.set_reference_factored(op.A, op.alpha, op.shift, c2full.Z)
     out = s.solve_batched(masks, bs, 1e-10)
+    print(f"   variant (rows/thread, w_mode, trial ms): {s.variant()}", flush=True)
     X = out["x"].cpu().numpy()
     for j, m in enumerate(sel):
         I, xs, F = xstars[m]
