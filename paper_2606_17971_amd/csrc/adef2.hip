@@ -22,10 +22,11 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int round8(int k) { return (k + 7) & ~7; }
 
 enum KernelId { KI_INIT = 0, KI_INIT2, KI_PUPDATE, KI_SPMV, KI_UPDATE, KI_RESID, KI_ACCUM,
-                KI_GRAM, KI_COARSE, KI_COMPACT, KI_UPDATE_NW, KI_ZPROJ, KI_COUNT };
+                KI_GRAM, KI_COARSE, KI_COMPACT, KI_UPDATE_NW, KI_ZPROJ, KI_PUPDATE_BT, KI_ZPROJ_BT,
+                KI_COUNT };
 const char* kKernelNames[KI_COUNT] = {"init", "init2", "pupdate", "spmv", "update", "resid64",
                                       "accumulate", "spmm_gram", "coarse", "compact", "update_nw",
-                                      "zproj"};
+                                      "zproj", "pupdate_bt", "zproj_bt"};
 
 }  // namespace
 
@@ -119,6 +120,8 @@ struct adef2_ctx {
   int wfree = 0;                 // 1: W^T z as Z^T (S z), W not read per iteration
   bool solved = false;           // a solve ran (variant is meaningful)
   int ntiles = 0, ntiles_pad = 0;
+  int bt_ntiles = 0, bt_ntiles_pad = 0;   // tile-major kernels (BT_ROWS-row tiles)
+  RedGeom g_bt{};
   struct Tuned { int B, prec, KP, fact; int64_t N; int rpt, wfree; float ms[4]; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
@@ -269,6 +272,8 @@ struct KTab {
   void (*update)(IterArgs<V, M>);
   void (*update_nw)(IterArgs<V, M>);
   void (*zproj)(IterArgs<V, M>);
+  void (*pupdate_bt)(IterArgs<V, M>);
+  void (*zproj_bt)(IterArgs<V, M>);
 };
 
 template <typename V, typename M, int KP, int RPT>
@@ -276,10 +281,10 @@ KTab<V, M> make_tab() {
   if constexpr (sizeof(V) == 8)
     return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
             k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, k_update_nw<V, M, KP, RPT>,
-            k_zproj<V, M, KP, RPT>};
+            k_zproj<V, M, KP, RPT>, k_pupdate_bt<V, M, KP>, k_zproj_bt<M, KP>};
   else
     return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
-            k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, nullptr, nullptr};
+            k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, nullptr, nullptr, nullptr, nullptr};
 }
 
 template <typename V, typename M, int RPT>
@@ -374,6 +379,9 @@ void set_variant(adef2_ctx* c, int rpt, int wfree) {
   c->ntiles = (int)cdiv(c->N, (int64_t)IPB * rpt);
   c->ntiles_pad = (int)cdiv(c->ntiles, 8) * 8;
   c->g_iter = make_geom(c->ntiles_pad);
+  c->bt_ntiles = (int)cdiv(c->N, (int64_t)BT_ROWS);
+  c->bt_ntiles_pad = (int)cdiv(c->bt_ntiles, 8) * 8;
+  c->g_bt = make_geom(c->bt_ntiles_pad);
 }
 
 int ensure_batch(adef2_ctx* c, int B, int prec) {
@@ -428,11 +436,14 @@ int ensure_batch(adef2_ctx* c, int B, int prec) {
   if ((rc = dalloc(c, &c->Tm, c->factored ? BN * KP : 0))) return rc;
   // reduction scratch: enough for the iteration kernels (NV <= KP+2) and the
   // Gram kernel (NV = 2 KP^2); geometry is recomputed per call from B
-  const size_t pi = (size_t)make_geom((int)cdiv(cdiv(N, IPB), 8) * 8).ptotal * (2 * KP + 2);
+  const size_t pi = (size_t)std::max(make_geom((int)cdiv(cdiv(N, IPB), 8) * 8).ptotal,
+                                     make_geom((int)cdiv(cdiv(N, BT_ROWS), 8) * 8).ptotal) *
+                    (2 * KP + 2);
   const size_t pg = (size_t)make_geom(256).ptotal * 2 * kk;
   c->part_elems = (size_t)B * std::max(pi, pg);
-  c->ctr_elems = (size_t)B * std::max(make_geom((int)cdiv(cdiv(N, IPB), 8) * 8).ctotal,
-                                      make_geom(256).ctotal) + 16;
+  c->ctr_elems = (size_t)B * std::max({make_geom((int)cdiv(cdiv(N, IPB), 8) * 8).ctotal,
+                                       make_geom((int)cdiv(cdiv(N, BT_ROWS), 8) * 8).ctotal,
+                                       make_geom(256).ctotal}) + 16;
   if ((rc = dalloc(c, &c->part, c->part_elems))) return rc;
   if ((rc = dalloc(c, &c->ctr, c->ctr_elems))) return rc;
   HIPCHK(c, hipMemsetAsync(c->ctr, 0, c->ctr_elems * sizeof(unsigned), c->st));
@@ -539,6 +550,10 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.dia64 = c->dia64;
   a.dia1_64 = c->dia1_64;
   a.Z64 = c->Z64;
+  a.B = c->B;
+  a.bt_ntiles = c->bt_ntiles;
+  a.bt_ntiles_pad = c->bt_ntiles_pad;
+  a.gbt = c->g_bt;
   if constexpr (sizeof(M) == 8) {
     a.dia1 = (const M*)c->dia1_64;
     a.dia = (const M*)c->dia64;
@@ -629,6 +644,9 @@ template <typename V, typename M>
 int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale,
               double thresh_floor, int carry_dir, int max_chunks = 0) {
   const bool wfree = c->wfree && c->KP > 0 && sizeof(V) == 8;
+  // tile-major kernels need the basis shared by all instances
+  const bool bt = wfree && c->zs == 0;
+  const dim3 gbt(c->bt_ntiles_pad);
   IterArgs<V, M> a = iter_args<V, M>(c);
   a.src = src;
   a.x0 = x0pad;
@@ -669,7 +687,11 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
     launched += chunk;
     if (c->o.profile) bm = byte_model(c, (double)sizeof(V), (double)sizeof(M), true);
     for (int it = 0; it < chunk; ++it) {
-      timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, c->st, a); });
+      if (bt)
+        timed(c, KI_PUPDATE_BT, bm.pupdate,
+              [&] { hipLaunchKernelGGL(kt.pupdate_bt, gbt, dim3(BT_ROWS), 0, c->st, a); });
+      else
+        timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, c->st, a); });
       timed(c, KI_SPMV, bm.spmv, [&] {
         if (c->factored)
           hipLaunchKernelGGL(st1, grid, blk, 0, c->st, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
@@ -680,11 +702,14 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
       } else {
         timed(c, KI_UPDATE_NW, bm.update_nw,
               [&] { hipLaunchKernelGGL(kt.update_nw, grid, blk, 0, c->st, a); });
-        timed(c, KI_ZPROJ, bm.zproj, [&] {
+        timed(c, bt ? KI_ZPROJ_BT : KI_ZPROJ, bm.zproj, [&] {
           if (c->factored)
             hipLaunchKernelGGL((stencil1_fn<double, V, V>(c->rpt)), grid, blk, 0, c->st, og, c->dia1_64,
                                (const V*)a.z, a.t, c->vs, c->inst, 1);
-          hipLaunchKernelGGL(kt.zproj, grid, blk, 0, c->st, a);
+          if (bt)
+            hipLaunchKernelGGL(kt.zproj_bt, gbt, dim3(BT_ROWS), 0, c->st, a);
+          else
+            hipLaunchKernelGGL(kt.zproj, grid, blk, 0, c->st, a);
         });
       }
     }

@@ -8,7 +8,7 @@ namespace adef2 {
 
 constexpr int TPB = 256;            // threads per block of the setup kernels
 constexpr int NWAVE = TPB / 64;     // wave64
-constexpr int IPB = 1024;           // threads per block of the iteration kernels
+constexpr int IPB = 256;            // threads per block of the iteration kernels
 constexpr int NIWAVE = IPB / 64;
 constexpr int KMAX = 64;            // max deflation rank (padded to a multiple of 8)
 constexpr int RED_FAN = 16;         // fan-in of the reduction tree

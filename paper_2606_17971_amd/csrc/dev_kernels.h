@@ -92,26 +92,63 @@ struct IterArgs {
   const double* dia64;     // [D][N]
   const double* dia1_64;   // [D1][N]
   const double* Z64;       // [KP][N] shared, or [B][KP][N] per instance
+  // tile-major kernels (k_pupdate_bt, k_zproj_bt): BT_ROWS-row tiles
+  int32_t B;               // instances
+  int32_t bt_ntiles, bt_ntiles_pad;
+  RedGeom gbt;             // reduction tree over the bt tiles
 };
 
 template <int RPT> struct Rows { static constexpr int PB = IPB * RPT; };
 
 // Row tile of one iteration block: IPB * RPT consecutive rows starting at
-// base; thread t owns rows base + t + j * IPB.  Panel reductions (M^T v over
-// the k columns of Z or W) are split over the waves: wave w takes columns
-// w, w + NIWAVE, ..., and each lane walks the tile rows lane, lane + 64, ...
-// with the vector read from LDS, so every column load is a coalesced 512-byte
-// wave access and each lane keeps one accumulator.
-template <typename M, int RPT>
-__device__ __forceinline__ double panel_dot(const M* col, int64_t base, const double* vec,
-                                            const uint8_t* act) {
+// base; thread t owns rows base + t + j * IPB.
+
+// Panel products of a whole block: for the NQ columns q = 0..NQ-1 (column q
+// of the panel at col(q), multiplied with the LDS vector vec(q)), wave w
+// sums the columns w, w + NIWAVE, ... over the tile rows and lane 0 stores
+// the totals in out[q].  Rows and columns are fully unrolled so that each
+// lane has all of its column loads in flight at once (with a handful of
+// outstanding loads per lane these reductions are latency bound far below
+// HBM bandwidth).  The LDS vectors are zero on rows that do not take part,
+// so only rows past N need a guard (last tile).
+template <typename M, int RPT, int NQ, typename ColF, typename VecF>
+__device__ __forceinline__ void panel_dots(int64_t base, int64_t N, ColF col, VecF vec, double* out) {
   constexpr int R = Rows<RPT>::PB;
-  const int lane = threadIdx.x & 63;
-  double acc = 0.0;
-#pragma unroll 4
-  for (int j = lane; j < R; j += 64)
-    if (!act[j]) acc += (double)col[base + j] * vec[j];
-  return wave_sum(acc);
+  constexpr int NQW = (NQ + NIWAVE - 1) / NIWAVE;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double acc[NQW > 0 ? NQW : 1];
+#pragma unroll
+  for (int s = 0; s < NQW; ++s) acc[s] = 0.0;
+  if (base + R <= N) {
+#pragma unroll
+    for (int s = 0; s < NQW; ++s) {
+      const int q = wid + s * NIWAVE;
+      if (q < NQ) {
+        const M* c = col(q);
+        const double* v = vec(q);
+#pragma unroll
+        for (int j = lane; j < R; j += 64) acc[s] += (double)c[base + j] * v[j];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < NQW; ++s) {
+      const int q = wid + s * NIWAVE;
+      if (q < NQ) {
+        const M* c = col(q);
+        const double* v = vec(q);
+        for (int j = lane; j < R && base + j < N; j += 64) acc[s] += (double)c[base + j] * v[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NQW; ++s) {
+    const int q = wid + s * NIWAVE;
+    if (q < NQ) {
+      const double t = wave_sum(acc[s]);
+      if (lane == 0) out[q] = t;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -167,10 +204,10 @@ __global__ void __launch_bounds__(IPB) k_init(IterArgs<V, M> a) {
     double v1[1] = {bb};
     block_sum<1, NIWAVE>(v1, red, bv + KP);
   }
-  const int wid = threadIdx.x >> 6;
-  for (int q = wid; q < KP; q += NIWAVE) {
-    const double s = panel_dot<M, RPT>(a.Z + (size_t)m * a.zs + (size_t)q * N, base, vl, act);
-    if ((threadIdx.x & 63) == 0) bv[q] = s;
+  {
+    const M* Zm = a.Z + (size_t)m * a.zs;
+    panel_dots<M, RPT, KP>(base, N, [&](int q) { return Zm + (size_t)q * N; },
+                           [&](int) { return (const double*)vl; }, bv);
   }
   __syncthreads();
   double* part = a.part + (size_t)m * a.g.ptotal * NV;
@@ -242,15 +279,14 @@ __device__ __forceinline__ bool reduce_directions(const IterArgs<V, M>& a, int m
     double v2[2] = {rz, rr2};
     block_sum<2, NIWAVE>(v2, red, bv + 2 * KP);
   }
-  const int wid = threadIdx.x >> 6;
   const int64_t N = a.op.N;
-  for (int q = wid; q < 2 * KP; q += NIWAVE) {
-    double s = 0.0;
-    if (defl) {
-      s = (q < KP) ? panel_dot<M, RPT>(W + (size_t)q * N, base, zl, act)
-                   : panel_dot<M, RPT>(a.Z + (size_t)m * a.zs + (size_t)(q - KP) * N, base, rl, act);
-    }
-    if ((threadIdx.x & 63) == 0) bv[q] = s;
+  if (defl) {
+    const M* Zm = a.Z + (size_t)m * a.zs;
+    panel_dots<M, RPT, 2 * KP>(
+        base, N, [&](int q) { return q < KP ? W + (size_t)q * N : Zm + (size_t)(q - KP) * N; },
+        [&](int q) { return q < KP ? zl : rl; }, bv);
+  } else {
+    for (int q = threadIdx.x; q < 2 * KP; q += blockDim.x) bv[q] = 0.0;
   }
   __syncthreads();
   double* part = a.part + (size_t)m * a.g.ptotal * NV;
@@ -306,9 +342,10 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V, M> a) {
       double xv = (double)x[i];
       rv = (double)r[i];
       if (defl) {
-#pragma unroll 8
+        const M* Zi = a.Z + (size_t)m * a.zs + i;
+#pragma unroll
         for (int q = 0; q < KP; ++q) {
-          xv += (double)a.Z[(size_t)m * a.zs + (size_t)q * N + i] * cf[q];
+          xv += (double)Zi[(size_t)q * N] * cf[q];
           rv -= (double)W[(size_t)q * N + i] * cf[q];
         }
       }
@@ -370,8 +407,9 @@ __global__ void __launch_bounds__(IPB) k_pupdate(IterArgs<V, M> a) {
     if (i < N && mk[i] == 0) {
       double pv = (double)z[i];
       if (defl) {
-#pragma unroll 8
-        for (int q = 0; q < KP; ++q) pv -= (double)a.Z[(size_t)m * a.zs + (size_t)q * N + i] * cf[q];
+        const M* Zi = a.Z + (size_t)m * a.zs + i;
+#pragma unroll
+        for (int q = 0; q < KP; ++q) pv -= (double)Zi[(size_t)q * N] * cf[q];
       }
       if (keep) pv += beta * (double)p[i];
       p[i] = (V)pv;
@@ -568,24 +606,6 @@ __global__ void __launch_bounds__(IPB) k_update_nw(IterArgs<V, M> a) {
   }
 }
 
-// sum over the tile rows of col * u and col * r (one read of the column)
-template <typename M, int RPT>
-__device__ __forceinline__ void panel_dot2(const M* col, int64_t base, const double* u, const double* r,
-                                           const uint8_t* act, double& su, double& sr) {
-  constexpr int R = Rows<RPT>::PB;
-  const int lane = threadIdx.x & 63;
-  double au = 0.0, ar = 0.0;
-#pragma unroll 4
-  for (int j = lane; j < R; j += 64)
-    if (!act[j]) {
-      const double c = (double)col[base + j];
-      au += c * u[j];
-      ar += c * r[j];
-    }
-  su = wave_sum(au);
-  sr = wave_sum(ar);
-}
-
 template <typename V, typename M, int KP, int RPT>
 __global__ void __launch_bounds__(IPB) k_zproj(IterArgs<V, M> a) {
   constexpr int R = Rows<RPT>::PB;
@@ -631,17 +651,176 @@ __global__ void __launch_bounds__(IPB) k_zproj(IterArgs<V, M> a) {
     double v2[2] = {rz, rr2};
     block_sum<2, NIWAVE>(v2, red, bv + 2 * KP);
   }
-  const int wid = threadIdx.x >> 6;
-  for (int q = wid; q < KP; q += NIWAVE) {
-    double su = 0.0, sr = 0.0;
-    if (defl) panel_dot2<double, RPT>(a.Z64 + (size_t)m * a.zs + (size_t)q * N, base, ul, rl, act, su, sr);
-    if ((threadIdx.x & 63) == 0) { bv[q] = su; bv[KP + q] = sr; }
+  if (defl) {
+    const double* Zm = a.Z64 + (size_t)m * a.zs;
+    panel_dots<double, RPT, 2 * KP>(
+        base, N, [&](int q) { return Zm + (size_t)(q < KP ? q : q - KP) * N; },
+        [&](int q) { return q < KP ? (const double*)ul : (const double*)rl; }, bv);
+  } else {
+    for (int q = threadIdx.x; q < 2 * KP; q += blockDim.x) bv[q] = 0.0;
   }
   __syncthreads();
   double* part = a.part + (size_t)m * a.g.ptotal * NV;
   unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
   if (!tree_reduce(a.g, tile, NV, part, ctr, bv, tot)) return;
   update_finish<KP>(a.C + (size_t)m * KP * KP, tot, S, defl, a.maxit, a.seg_maxit);
+}
+
+// ---------------------------------------------------------------------------
+// Tile-major kernels for a basis shared by all instances.  One block owns a
+// tile of BT_ROWS rows for every instance of the batch, so each row of Z is
+// read once per launch instead of once per instance (with B instances the
+// per-instance kernels pull the Z tile B times through L2, which bounds them
+// well below HBM bandwidth).
+//   k_pupdate_bt: p_m = z_m - Z c_m + beta_m p_m; the thread keeps its row of
+//     Z in registers and loops over the instances.
+//   k_zproj_bt: the panel products of the W-free update for all instances
+//     as one FP64 matrix product per tile, [Z^T u_m, Z^T r_m]_m = Z^T V with
+//     V = [u_1 r_1 ... u_G r_G] (BT_ROWS x 2G, staged in LDS), on the matrix
+//     cores (v_mfma_f64_16x16x4): lane l feeds A[l%16][l/16] = Z[row][q] and
+//     B[l/16][l%16] = V[row][c], and holds D[4j + l/16][l%16] in element j.
+//     Then one reduction tree per instance, whose finisher ends the
+//     iteration as k_update does.
+// ---------------------------------------------------------------------------
+constexpr int BT_ROWS = 128;   // rows per tile = threads per block (2 waves)
+constexpr int BT_G = 16;       // instances per MFMA group (2 BT_G = 32 columns)
+
+template <typename V, typename M, int KP>
+__global__ void __launch_bounds__(BT_ROWS) k_pupdate_bt(IterArgs<V, M> a) {
+  constexpr int K1 = KP > 0 ? KP : 1;
+  __shared__ double cf[BT_G][K1];
+  __shared__ double sb[BT_G];
+  __shared__ int sk[BT_G];
+  const int tile = xcd_tile(blockIdx.x, a.bt_ntiles_pad);
+  if (tile >= a.bt_ntiles) return;
+  const int64_t N = a.op.N;
+  const int64_t i = (int64_t)tile * BT_ROWS + threadIdx.x;
+  const bool row = i < N;
+  M zr[K1];
+#pragma unroll
+  for (int q = 0; q < KP; ++q) zr[q] = row ? a.Z[(size_t)q * N + i] : (M)0;
+  for (int g0 = 0; g0 < a.B; g0 += BT_G) {
+    const int G = min(BT_G, a.B - g0);
+    __syncthreads();
+    if (threadIdx.x < G) {
+      const Inst* S = a.inst + g0 + threadIdx.x;
+      sk[threadIdx.x] = S->done ? 0 : (S->kk > 0 ? 2 : 1);
+      sb[threadIdx.x] = S->fresh ? 0.0 : S->beta;
+    }
+    for (int e = threadIdx.x; e < G * KP; e += BT_ROWS) {
+      const int j = e / K1, q = e % K1;
+      cf[j][q] = a.inst[g0 + j].coef[q];
+    }
+    __syncthreads();
+    for (int j = 0; j < G; ++j) {
+      if (!sk[j] || !row) continue;
+      const int m = g0 + j;
+      if (a.mask[(size_t)m * N + i]) continue;
+      const V* z = a.z + m * a.vs;
+      V* p = a.p + m * a.vs;
+      double pv = (double)z[i];
+      if (sk[j] == 2) {
+#pragma unroll
+        for (int q = 0; q < KP; ++q) pv -= (double)zr[q] * cf[j][q];
+      }
+      pv += sb[j] * (double)p[i];
+      p[i] = (V)pv;
+    }
+  }
+}
+
+typedef double bt_d4 __attribute__((ext_vector_type(4)));
+
+template <typename M, int KP>
+__global__ void __launch_bounds__(BT_ROWS) k_zproj_bt(IterArgs<double, M> a) {
+  constexpr int KQ = (KP + 15) / 16 * 16;          // Z columns padded to the MFMA tile
+  constexpr int NC = 2 * BT_G;                     // V columns
+  constexpr int NV = 2 * KP + 2;
+  constexpr int NT = (KQ / 16) * (NC / 16);        // 16 x 16 output tiles
+  __shared__ double vs[BT_ROWS][NC + 1];
+  __shared__ double outb[NC][KQ + 1];
+  __shared__ double red[2][BT_G][2];
+  __shared__ int sk[BT_G];
+  __shared__ double bv[NV];
+  __shared__ double tot[NV];
+  const int tile = xcd_tile(blockIdx.x, a.bt_ntiles_pad);
+  const int64_t N = a.op.N;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int64_t base = (int64_t)tile * BT_ROWS;
+  const int64_t i = base + t;
+  const bool row = (tile < a.bt_ntiles) && i < N;
+  for (int g0 = 0; g0 < a.B; g0 += BT_G) {
+    const int G = min(BT_G, a.B - g0);
+    __syncthreads();
+    if (t < BT_G) {
+      int k = 0;
+      if (t < G) {
+        const Inst* S = a.inst + g0 + t;
+        k = S->done ? 0 : (S->kk > 0 ? 2 : 1);
+      }
+      sk[t] = k;
+    }
+    __syncthreads();
+    // V = [u r] per instance on this tile's rows, and r.z, r.r block sums
+    for (int j = 0; j < BT_G; ++j) {
+      double uv = 0.0, rv = 0.0, rz = 0.0, rr2 = 0.0;
+      if (sk[j]) {
+        const int m = g0 + j;
+        if (row && a.mask[(size_t)m * N + i] == 0) {
+          const Inst* S = a.inst + m;
+          const double* z = a.z + m * a.vs;
+          const double* sv = (a.op.D1 ? a.t : a.z) + m * a.vs;
+          const double zv = z[i];
+          rv = a.r[m * a.vs + i];
+          rz = rv * zv;
+          rr2 = rv * rv;
+          if (sk[j] == 2) uv = S->a * stencil_row(a.dia64, a.op.offs, a.op.D, a.op.d0, N, i, sv) + S->c * zv;
+        }
+        rz = wave_sum(rz);
+        rr2 = wave_sum(rr2);
+        if (lane == 0) { red[wid][j][0] = rz; red[wid][j][1] = rr2; }
+      }
+      vs[t][2 * j] = uv;
+      vs[t][2 * j + 1] = rv;
+    }
+    __syncthreads();
+    // [Z^T u | Z^T r] for the group: NT output tiles over the 2 waves
+    for (int ot = wid; ot < NT; ot += BT_ROWS / 64) {
+      const int q0 = (ot / (NC / 16)) * 16, c0 = (ot % (NC / 16)) * 16;
+      const int qa = q0 + (lane & 15), cb = c0 + (lane & 15), kr = lane >> 4;
+      bt_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < BT_ROWS; k0 += 4) {
+        const int rr = k0 + kr;
+        const int64_t gi = base + rr;
+        const double av = (qa < KP && tile < a.bt_ntiles && gi < N) ? a.Z64[(size_t)qa * N + gi] : 0.0;
+        const double bw = vs[rr][cb];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) outb[cb][q0 + 4 * e + kr] = acc[e];
+    }
+    __syncthreads();
+    // one reduction tree per instance
+    for (int j = 0; j < G; ++j) {
+      if (!sk[j]) continue;
+      const int m = g0 + j;
+      for (int e = t; e < NV; e += BT_ROWS) {
+        double v;
+        if (e < KP) v = outb[2 * j][e];
+        else if (e < 2 * KP) v = outb[2 * j + 1][e - KP];
+        else v = red[0][j][e - 2 * KP] + red[1][j][e - 2 * KP];
+        bv[e] = v;
+      }
+      __syncthreads();
+      double* part = a.part + (size_t)m * a.gbt.ptotal * NV;
+      unsigned* ctr = a.ctr + (size_t)m * a.gbt.ctotal;
+      if (tree_reduce(a.gbt, tile, NV, part, ctr, bv, tot)) {
+        Inst* S = a.inst + m;
+        update_finish<KP>(a.C + (size_t)m * KP * KP, tot, S, S->kk > 0, a.maxit, a.seg_maxit);
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
