@@ -53,8 +53,8 @@ def parse():
     ap.add_argument("--snap-tol", type=float, default=1e-8)
     ap.add_argument("--rpt", type=int, default=0, choices=[0, 1, 2],
                     help="rows per thread of the iteration kernels (0 = tuned)")
-    ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2],
-                    help="1 = read W, 2 = W-free, 0 = tuned")
+    ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="1 = read W, 2 = W-free tile-major, 3 = W-free per instance, 0 = tuned")
     ap.add_argument("--counter-run", action="store_true",
                     help="short run for rocprofv3 counter passes: one headline solve capped at "
                          "--counter-maxit iterations, then a 256 MiB device copy of known size; "

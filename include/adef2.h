@@ -121,14 +121,18 @@ typedef struct {
                            1 = read the stored W; 2 = Z^T (S_II z), one more
                            stencil pass instead of reading W, with the FP64
                            operator and modes (z is rough, so FP32 rounding of
-                           S or Z would be amplified by cond(S)); needs FP64
-                           vectors: E_UNSUPPORTED with FP32_REFINE; 0 = tuned
-                           on the first solve of each configuration.  Tuning runs
-                           every candidate for the first 64 iterations from
-                           the same start, keeps the fastest per context
-                           (batch size, precision, basis width, operator
-                           form, N) and reuses it, so repeated solves in one
-                           context are bitwise reproducible                 */
+                           S or Z would be amplified by cond(S)), in
+                           tile-major kernels that read each row of a shared
+                           Z once for the whole batch (matrix-core panel
+                           products); 3 = as 2 with per-instance kernels;
+                           2 and 3 need FP64 vectors (E_UNSUPPORTED with
+                           FP32_REFINE); 0 = tuned on the first solve of each
+                           configuration.  Tuning runs every candidate for
+                           the first 64 iterations from the same start, keeps
+                           the fastest per context (batch size, precision,
+                           basis width, operator form, N) and reuses it, so
+                           repeated solves in one context are bitwise
+                           reproducible                                     */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;
@@ -277,11 +281,10 @@ int adef2_coarse_info(adef2_ctx *ctx, double *E, int32_t *kept, int32_t *k_eff,
                       double *cond_E);
 
 /* Iteration-kernel variant used by the last solve on ctx: rows per thread
- * (1 or 2) and w_mode (1 = stored W read, 2 = W-free), whether fixed by the
- * options or tuned.  ms (host f32[4], may be NULL) receives the trial times of
- * the tuned candidates in the order (rpt 1, W), (rpt 1, W-free), (rpt 2, W),
- * (rpt 2, W-free) restricted to the candidates tried, 0 when not tuned.
- * E_STATE before the first solve. */
+ * (1 or 2) and w_mode (1, 2 or 3 as in adef2_opts), whether fixed by the
+ * options or tuned.  ms (host f32[6], may be NULL) receives the trial times
+ * of the tuned candidates, rows per thread outer, w_mode inner, restricted to
+ * the candidates tried (0 when not tuned).  E_STATE before the first solve. */
 int adef2_variant(adef2_ctx *ctx, int32_t *rows_per_thread, int32_t *w_mode, float *ms);
 
 typedef struct {

@@ -117,12 +117,13 @@ struct adef2_ctx {
 
   // geometry and variant of the streaming kernels
   int rpt = 2;
-  int wfree = 0;                 // 1: W^T z as Z^T (S z), W not read per iteration
+  int wfree = 0;                 // W^T z as Z^T (S z), W not read: 1 tile-major, 2 per instance
   bool solved = false;           // a solve ran (variant is meaningful)
   int ntiles = 0, ntiles_pad = 0;
   int bt_ntiles = 0, bt_ntiles_pad = 0;   // tile-major kernels (BT_ROWS-row tiles)
+  int bt_nblk_pad = 0;                     // k_zproj_bt blocks (BT_TPB tiles each)
   RedGeom g_bt{};
-  struct Tuned { int B, prec, KP, fact; int64_t N; int rpt, wfree; float ms[4]; };
+  struct Tuned { int B, prec, KP, fact; int64_t N; int rpt, wfree; float ms[6]; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
   int gram_blocks = 0;
@@ -381,13 +382,14 @@ void set_variant(adef2_ctx* c, int rpt, int wfree) {
   c->g_iter = make_geom(c->ntiles_pad);
   c->bt_ntiles = (int)cdiv(c->N, (int64_t)BT_ROWS);
   c->bt_ntiles_pad = (int)cdiv(c->bt_ntiles, 8) * 8;
-  c->g_bt = make_geom(c->bt_ntiles_pad);
+  c->bt_nblk_pad = (int)cdiv(cdiv(c->bt_ntiles, BT_TPB), 8) * 8;
+  c->g_bt = make_geom(c->bt_nblk_pad);
 }
 
 int ensure_batch(adef2_ctx* c, int B, int prec) {
   const int64_t N = c->N;
   const int KP = c->KP;
-  set_variant(c, (c->o.rows_per_thread == 2) ? 2 : 1, c->o.w_mode == 2 ? 1 : 0);
+  set_variant(c, (c->o.rows_per_thread == 2) ? 2 : 1, c->o.w_mode >= 2 ? c->o.w_mode - 1 : 0);
   const int64_t nsub_max = cdiv(N, 32);
   int gb = (int)std::max<int64_t>(8, std::min<int64_t>(256, 2048 / std::max(B, 1)));
   gb = (int)std::min<int64_t>(gb, nsub_max);
@@ -553,6 +555,7 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.B = c->B;
   a.bt_ntiles = c->bt_ntiles;
   a.bt_ntiles_pad = c->bt_ntiles_pad;
+  a.bt_nblk_pad = c->bt_nblk_pad;
   a.gbt = c->g_bt;
   if constexpr (sizeof(M) == 8) {
     a.dia1 = (const M*)c->dia1_64;
@@ -644,8 +647,8 @@ template <typename V, typename M>
 int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale,
               double thresh_floor, int carry_dir, int max_chunks = 0) {
   const bool wfree = c->wfree && c->KP > 0 && sizeof(V) == 8;
-  // tile-major kernels need the basis shared by all instances
-  const bool bt = wfree && c->zs == 0;
+  // tile-major kernels (w_mode 2) need the basis shared by all instances
+  const bool bt = wfree && c->wfree == 1 && c->zs == 0;
   const dim3 gbt(c->bt_ntiles_pad);
   IterArgs<V, M> a = iter_args<V, M>(c);
   a.src = src;
@@ -689,7 +692,7 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
     for (int it = 0; it < chunk; ++it) {
       if (bt)
         timed(c, KI_PUPDATE_BT, bm.pupdate,
-              [&] { hipLaunchKernelGGL(kt.pupdate_bt, gbt, dim3(BT_ROWS), 0, c->st, a); });
+              [&] { hipLaunchKernelGGL(kt.pupdate_bt, gbt, dim3(BT_THREADS), 0, c->st, a); });
       else
         timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, c->st, a); });
       timed(c, KI_SPMV, bm.spmv, [&] {
@@ -707,7 +710,7 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
             hipLaunchKernelGGL((stencil1_fn<double, V, V>(c->rpt)), grid, blk, 0, c->st, og, c->dia1_64,
                                (const V*)a.z, a.t, c->vs, c->inst, 1);
           if (bt)
-            hipLaunchKernelGGL(kt.zproj_bt, gbt, dim3(BT_ROWS), 0, c->st, a);
+            hipLaunchKernelGGL(kt.zproj_bt, dim3(c->bt_nblk_pad), dim3(BT_THREADS), 0, c->st, a);
           else
             hipLaunchKernelGGL(kt.zproj, grid, blk, 0, c->st, a);
         });
@@ -775,11 +778,12 @@ int reset_solve_state(adef2_ctx* c) {
 // one configuration use the same kernels (and give identical results).
 int choose_variant(adef2_ctx* c, const double* b, double tol) {
   const int fr = c->o.rows_per_thread, fw = c->o.w_mode;
-  if (fw == 2 && !vec64(c->prec))
+  if (fw >= 2 && !vec64(c->prec))
     return fail(c, ADEF2_E_UNSUPPORTED, "W-free iterations need FP64 vectors (FP64 or MIXED_REFINE)");
   std::vector<int> rpts = (fr == 1 || fr == 2) ? std::vector<int>{fr} : std::vector<int>{1, 2};
   std::vector<int> wfs = (fw == 1 || c->KP == 0 || !vec64(c->prec)) ? std::vector<int>{0}
-                         : (fw == 2 ? std::vector<int>{1} : std::vector<int>{0, 1});
+                         : (fw == 2 ? std::vector<int>{1}
+                                    : (fw == 3 ? std::vector<int>{2} : std::vector<int>{0, 1, 2}));
   if (rpts.size() * wfs.size() == 1) { set_variant(c, rpts[0], wfs[0]); return ADEF2_OK; }
   const int fact = c->factored ? 1 : 0;
   for (const auto& t : c->tuned)
@@ -792,7 +796,7 @@ int choose_variant(adef2_ctx* c, const double* b, double tol) {
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, c->N, rpts[0], wfs[0], {0, 0, 0, 0}};
+  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0}};
   float best_ms = INFINITY;
   int rc = ADEF2_OK, ci = 0;
   for (int rpt : rpts) {
@@ -916,7 +920,7 @@ bool valid_opts(const adef2_opts* o) {
          (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
          o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0 &&
          o->rows_per_thread >= 0 && o->rows_per_thread <= 2 &&
-         o->w_mode >= 0 && o->w_mode <= 2;
+         o->w_mode >= 0 && o->w_mode <= 3;
 }
 
 }  // namespace
@@ -1384,13 +1388,13 @@ int adef2_variant(adef2_ctx* c, int32_t* rows_per_thread, int32_t* w_mode, float
   if (!c) return ADEF2_E_ARG;
   if (!c->solved) return fail(c, ADEF2_E_STATE, "variant before the first solve");
   if (rows_per_thread) *rows_per_thread = c->rpt;
-  if (w_mode) *w_mode = c->wfree ? 2 : 1;
+  if (w_mode) *w_mode = c->wfree + 1;
   if (ms) {
-    for (int i = 0; i < 4; ++i) ms[i] = 0.0f;
+    for (int i = 0; i < 6; ++i) ms[i] = 0.0f;
     const int fact = c->factored ? 1 : 0;
     for (const auto& t : c->tuned)
       if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N)
-        for (int i = 0; i < 4; ++i) ms[i] = t.ms[i];
+        for (int i = 0; i < 6; ++i) ms[i] = t.ms[i];
   }
   return ADEF2_OK;
 }

@@ -147,6 +147,63 @@ __device__ inline bool tree_reduce(const RedGeom& g, int tile, int nv, double* p
   return true;
 }
 
+// tree_reduce for up to 32 instances at once that share the tile geometry:
+// instance j (active when bit j of act is set) has its block sums in
+// bval[j * nv ..], partials at part + pstride * j and counters at
+// ctr + cstride * j.  The counter updates of all instances are issued
+// together (one thread each), so a block pays one round trip per level
+// instead of one per instance.  Returns the set of instances whose tree this
+// block completed; their totals are in out[j * nv ..].
+__device__ inline unsigned tree_reduce_multi(const RedGeom& g, int tile, int nv, unsigned act, int G,
+                                             double* part, size_t pstride, unsigned* ctr, size_t cstride,
+                                             const double* bval, double* out) {
+  __shared__ unsigned s_last;
+  if (g.nlev == 1) {
+    for (int e = threadIdx.x; e < G * nv; e += blockDim.x) out[e] = bval[e];
+    __syncthreads();
+    return act;
+  }
+  int node = tile;
+  for (int e = threadIdx.x; e < G * nv; e += blockDim.x) {
+    const int j = e / nv, v = e - j * nv;
+    if ((act >> j) & 1u) st_coherent(&part[pstride * j + (size_t)(g.pofs[0] + node) * nv + v], bval[e]);
+  }
+  if (threadIdx.x == 0) s_last = 0u;
+  for (int l = 1; l < g.nlev; ++l) {
+    wait_mem();
+    __syncthreads();
+    const int parent = node / RED_FAN;
+    const int first = parent * RED_FAN;
+    const int cnt = min(RED_FAN, g.n[l - 1] - first);
+    if (threadIdx.x < G && ((act >> threadIdx.x) & 1u)) {
+      unsigned* c = ctr + cstride * threadIdx.x + g.cofs[l] + parent;
+      const unsigned old = __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old == (unsigned)(cnt - 1)) {
+        __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicOr(&s_last, 1u << threadIdx.x);
+      }
+    }
+    __syncthreads();
+    act = s_last;
+    __syncthreads();                  // every thread has read s_last before it is cleared
+    if (threadIdx.x == 0) s_last = 0u;
+    if (!act) return 0u;
+    const bool top = (l == g.nlev - 1);
+    for (int e = threadIdx.x; e < G * nv; e += blockDim.x) {
+      const int j = e / nv, v = e - j * nv;
+      if (!((act >> j) & 1u)) continue;
+      double sum = 0.0;
+      for (int i = 0; i < cnt; ++i)
+        sum += ld_coherent(&part[pstride * j + (size_t)(g.pofs[l - 1] + first + i) * nv + v]);
+      if (top) out[e] = sum;
+      else st_coherent(&part[pstride * j + (size_t)(g.pofs[l] + parent) * nv + v], sum);
+    }
+    node = parent;
+  }
+  __syncthreads();
+  return act;
+}
+
 // Map a workgroup id to a tile so that each XCD (workgroups are dispatched to
 // the 8 XCDs round-robin) owns a contiguous range of tiles: stencil neighbours
 // of a tile then mostly hit the same XCD's L2.  ntiles_pad % 8 == 0.

@@ -95,7 +95,8 @@ struct IterArgs {
   // tile-major kernels (k_pupdate_bt, k_zproj_bt): BT_ROWS-row tiles
   int32_t B;               // instances
   int32_t bt_ntiles, bt_ntiles_pad;
-  RedGeom gbt;             // reduction tree over the bt tiles
+  int32_t bt_nblk_pad;     // k_zproj_bt blocks (BT_TPB tiles each), multiple of 8
+  RedGeom gbt;             // reduction tree over the k_zproj_bt blocks
 };
 
 template <int RPT> struct Rows { static constexpr int PB = IPB * RPT; };
@@ -682,73 +683,97 @@ __global__ void __launch_bounds__(IPB) k_zproj(IterArgs<V, M> a) {
 //     Then one reduction tree per instance, whose finisher ends the
 //     iteration as k_update does.
 // ---------------------------------------------------------------------------
-constexpr int BT_ROWS = 128;   // rows per tile = threads per block (2 waves)
-constexpr int BT_G = 16;       // instances per MFMA group (2 BT_G = 32 columns)
+constexpr int BT_ROWS = 128;   // rows per tile
+constexpr int BT_SL = 4;       // instance slices: threads per row
+constexpr int BT_THREADS = BT_ROWS * BT_SL;   // 8 waves
+constexpr int BT_G = 16;       // instances per group (2 BT_G = 32 MFMA columns)
+constexpr int BT_GS = BT_G / BT_SL;           // instances per slice
 
 template <typename V, typename M, int KP>
-__global__ void __launch_bounds__(BT_ROWS) k_pupdate_bt(IterArgs<V, M> a) {
+__global__ void __launch_bounds__(BT_THREADS) k_pupdate_bt(IterArgs<V, M> a) {
   constexpr int K1 = KP > 0 ? KP : 1;
+  __shared__ M zt[K1][BT_ROWS];
   __shared__ double cf[BT_G][K1];
   __shared__ double sb[BT_G];
   __shared__ int sk[BT_G];
   const int tile = xcd_tile(blockIdx.x, a.bt_ntiles_pad);
   if (tile >= a.bt_ntiles) return;
   const int64_t N = a.op.N;
-  const int64_t i = (int64_t)tile * BT_ROWS + threadIdx.x;
+  const int t = threadIdx.x;
+  const int rl = t % BT_ROWS, sl = t / BT_ROWS;
+  const int64_t i = (int64_t)tile * BT_ROWS + rl;
   const bool row = i < N;
-  M zr[K1];
-#pragma unroll
-  for (int q = 0; q < KP; ++q) zr[q] = row ? a.Z[(size_t)q * N + i] : (M)0;
+  for (int e = t; e < KP * BT_ROWS; e += BT_THREADS) {      // Z tile, coalesced along rows
+    const int q = e / BT_ROWS, r = e % BT_ROWS;
+    const int64_t gi = (int64_t)tile * BT_ROWS + r;
+    zt[q][r] = gi < N ? a.Z[(size_t)q * N + gi] : (M)0;
+  }
   for (int g0 = 0; g0 < a.B; g0 += BT_G) {
     const int G = min(BT_G, a.B - g0);
     __syncthreads();
-    if (threadIdx.x < G) {
-      const Inst* S = a.inst + g0 + threadIdx.x;
-      sk[threadIdx.x] = S->done ? 0 : (S->kk > 0 ? 2 : 1);
-      sb[threadIdx.x] = S->fresh ? 0.0 : S->beta;
+    if (t < BT_G) {
+      int k = 0;
+      double b = 0.0;
+      if (t < G) {
+        const Inst* S = a.inst + g0 + t;
+        k = S->done ? 0 : (S->kk > 0 ? 2 : 1);
+        b = S->fresh ? 0.0 : S->beta;
+      }
+      sk[t] = k;
+      sb[t] = b;
     }
-    for (int e = threadIdx.x; e < G * KP; e += BT_ROWS) {
+    for (int e = t; e < G * KP; e += BT_THREADS) {
       const int j = e / K1, q = e % K1;
       cf[j][q] = a.inst[g0 + j].coef[q];
     }
     __syncthreads();
-    for (int j = 0; j < G; ++j) {
-      if (!sk[j] || !row) continue;
+    if (!row) continue;
+#pragma unroll
+    for (int jj = 0; jj < BT_GS; ++jj) {
+      const int j = sl * BT_GS + jj;
+      if (!sk[j]) continue;
       const int m = g0 + j;
-      if (a.mask[(size_t)m * N + i]) continue;
-      const V* z = a.z + m * a.vs;
+      // loads issued regardless of the mask (all arrays span N rows); the
+      // store is skipped on active rows, where p stays 0
+      const bool on = a.mask[(size_t)m * N + i] == 0;
       V* p = a.p + m * a.vs;
-      double pv = (double)z[i];
+      double pv = (double)a.z[m * a.vs + i] + sb[j] * (double)p[i];
       if (sk[j] == 2) {
 #pragma unroll
-        for (int q = 0; q < KP; ++q) pv -= (double)zr[q] * cf[j][q];
+        for (int q = 0; q < KP; ++q) pv -= (double)zt[q][rl] * cf[j][q];
       }
-      pv += sb[j] * (double)p[i];
-      p[i] = (V)pv;
+      if (on) p[i] = (V)pv;
     }
   }
 }
 
 typedef double bt_d4 __attribute__((ext_vector_type(4)));
 
+// k_zproj_bt: each block walks BT_TPB consecutive tiles and keeps summing into
+// its matrix-core accumulators, so the reduction tree has one leaf per block.
+constexpr int BT_TPB = 4;
+
 template <typename M, int KP>
-__global__ void __launch_bounds__(BT_ROWS) k_zproj_bt(IterArgs<double, M> a) {
+__global__ void __launch_bounds__(BT_THREADS) k_zproj_bt(IterArgs<double, M> a) {
   constexpr int KQ = (KP + 15) / 16 * 16;          // Z columns padded to the MFMA tile
   constexpr int NC = 2 * BT_G;                     // V columns
   constexpr int NV = 2 * KP + 2;
-  constexpr int NT = (KQ / 16) * (NC / 16);        // 16 x 16 output tiles
+  constexpr int NQT = KQ / 16;                     // q tiles (0 when KP = 0: no coarse space)
+  constexpr int NT = NQT * (NC / 16);              // output tiles
+  constexpr int NWV = BT_THREADS / 64;             // waves
+  constexpr int TPW = NT > 0 ? (NT + NWV - 1) / NWV : 1;   // output tiles per wave
+  constexpr int KS = BT_ROWS / 4;                  // MFMA k steps per tile
+  constexpr int DR = 8;                            // stencil diagonals kept in registers
   __shared__ double vs[BT_ROWS][NC + 1];
-  __shared__ double outb[NC][KQ + 1];
-  __shared__ double red[2][BT_G][2];
+  __shared__ double bvs[BT_G * NV];                // block sums, instance-major
+  __shared__ double tots[BT_G * NV];
+  __shared__ double red[NWV][2 * BT_GS];
   __shared__ int sk[BT_G];
-  __shared__ double bv[NV];
-  __shared__ double tot[NV];
-  const int tile = xcd_tile(blockIdx.x, a.bt_ntiles_pad);
+  const int blk = xcd_tile(blockIdx.x, a.bt_nblk_pad);   // leaf of the reduction tree
   const int64_t N = a.op.N;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const int64_t base = (int64_t)tile * BT_ROWS;
-  const int64_t i = base + t;
-  const bool row = (tile < a.bt_ntiles) && i < N;
+  const int rl = t % BT_ROWS, sl = t / BT_ROWS;    // waves 2 sl, 2 sl + 1 hold slice sl
+  const int D = a.op.D;
   for (int g0 = 0; g0 < a.B; g0 += BT_G) {
     const int G = min(BT_G, a.B - g0);
     __syncthreads();
@@ -761,63 +786,110 @@ __global__ void __launch_bounds__(BT_ROWS) k_zproj_bt(IterArgs<double, M> a) {
       sk[t] = k;
     }
     __syncthreads();
-    // V = [u r] per instance on this tile's rows, and r.z, r.r block sums
-    for (int j = 0; j < BT_G; ++j) {
-      double uv = 0.0, rv = 0.0, rz = 0.0, rr2 = 0.0;
-      if (sk[j]) {
-        const int m = g0 + j;
-        if (row && a.mask[(size_t)m * N + i] == 0) {
-          const Inst* S = a.inst + m;
-          const double* z = a.z + m * a.vs;
-          const double* sv = (a.op.D1 ? a.t : a.z) + m * a.vs;
-          const double zv = z[i];
-          rv = a.r[m * a.vs + i];
-          rz = rv * zv;
-          rr2 = rv * rv;
-          if (sk[j] == 2) uv = S->a * stencil_row(a.dia64, a.op.offs, a.op.D, a.op.d0, N, i, sv) + S->c * zv;
-        }
-        rz = wave_sum(rz);
-        rr2 = wave_sum(rr2);
-        if (lane == 0) { red[wid][j][0] = rz; red[wid][j][1] = rr2; }
-      }
-      vs[t][2 * j] = uv;
-      vs[t][2 * j + 1] = rv;
-    }
-    __syncthreads();
-    // [Z^T u | Z^T r] for the group: NT output tiles over the 2 waves
-    for (int ot = wid; ot < NT; ot += BT_ROWS / 64) {
-      const int q0 = (ot / (NC / 16)) * 16, c0 = (ot % (NC / 16)) * 16;
-      const int qa = q0 + (lane & 15), cb = c0 + (lane & 15), kr = lane >> 4;
-      bt_d4 acc = {0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < BT_ROWS; k0 += 4) {
-        const int rr = k0 + kr;
-        const int64_t gi = base + rr;
-        const double av = (qa < KP && tile < a.bt_ntiles && gi < N) ? a.Z64[(size_t)qa * N + gi] : 0.0;
-        const double bw = vs[rr][cb];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bw, acc, 0, 0, 0);
-      }
+    double rzv[BT_GS], rrv[BT_GS];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) outb[cb][q0 + 4 * e + kr] = acc[e];
-    }
-    __syncthreads();
-    // one reduction tree per instance
-    for (int j = 0; j < G; ++j) {
-      if (!sk[j]) continue;
-      const int m = g0 + j;
-      for (int e = t; e < NV; e += BT_ROWS) {
-        double v;
-        if (e < KP) v = outb[2 * j][e];
-        else if (e < 2 * KP) v = outb[2 * j + 1][e - KP];
-        else v = red[0][j][e - 2 * KP] + red[1][j][e - 2 * KP];
-        bv[e] = v;
+    for (int jj = 0; jj < BT_GS; ++jj) { rzv[jj] = 0.0; rrv[jj] = 0.0; }
+    bt_d4 acc[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) acc[s] = bt_d4{0.0, 0.0, 0.0, 0.0};
+    for (int tt = 0; tt < BT_TPB; ++tt) {
+      const int tile = blk * BT_TPB + tt;
+      const int64_t base = (int64_t)tile * BT_ROWS;
+      const int64_t i = base + rl;
+      const bool row = (tile < a.bt_ntiles) && i < N;
+      // V = [u r] for this thread's slice of instances on its row
+      double cw[DR];
+#pragma unroll
+      for (int d = 0; d < DR; ++d) cw[d] = (row && d < D) ? a.dia64[(size_t)d * N + i] : 0.0;
+#pragma unroll
+      for (int jj = 0; jj < BT_GS; ++jj) {
+        const int j = sl * BT_GS + jj;
+        double uv = 0.0, rv = 0.0;
+        if (sk[j] && row) {
+          const int m = g0 + j;
+          const bool on = a.mask[(size_t)m * N + i] == 0;
+          const double zv = a.z[m * a.vs + i];       // zero on active rows
+          rv = a.r[m * a.vs + i];
+          rzv[jj] += rv * zv;
+          rrv[jj] += rv * rv;
+          if (sk[j] == 2 && on) {
+            const double* sv = (a.op.D1 ? a.t : a.z) + m * a.vs;
+            double sacc = 0.0;
+            if (D <= DR) {
+#pragma unroll
+              for (int d = 0; d < DR; ++d)
+                if (d < D) sacc += cw[d] * sv[i + a.op.offs[d]];
+            } else {
+              for (int d = 0; d < D; ++d) sacc += a.dia64[(size_t)d * N + i] * sv[i + a.op.offs[d]];
+            }
+            const Inst* S = a.inst + m;
+            uv = S->a * sacc + S->c * zv;
+          }
+        }
+        vs[rl][2 * j] = uv;
+        vs[rl][2 * j + 1] = rv;
       }
       __syncthreads();
-      double* part = a.part + (size_t)m * a.gbt.ptotal * NV;
-      unsigned* ctr = a.ctr + (size_t)m * a.gbt.ctotal;
-      if (tree_reduce(a.gbt, tile, NV, part, ctr, bv, tot)) {
-        Inst* S = a.inst + m;
-        update_finish<KP>(a.C + (size_t)m * KP * KP, tot, S, S->kk > 0, a.maxit, a.seg_maxit);
+      // [Z^T u | Z^T r] += Z_tile^T V_tile on the matrix cores, one output tile
+      // per wave; the wave's A operands (Z^T, FP64) are loaded first
+#pragma unroll
+      for (int s = 0; s < TPW; ++s) {
+        const int ot = wid + s * NWV;
+        if (ot < NT) {
+          const int qt = ot / (NC / 16), ct = ot % (NC / 16);
+          const int cb = ct * 16 + (lane & 15), kr = lane >> 4;
+          const int qa = qt * 16 + (lane & 15);
+          double av[KS];
+#pragma unroll
+          for (int k = 0; k < KS; ++k) {
+            const int64_t gi = base + 4 * k + kr;
+            av[k] = (qa < KP && tile < a.bt_ntiles && gi < N) ? a.Z64[(size_t)qa * N + gi] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < KS; ++k)
+            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], vs[4 * k + kr][cb], acc[s], 0, 0, 0);
+        }
       }
+      __syncthreads();
+    }
+    // block sums: D[q][c], q = 16 qt + 4 e + kr, c = cb: u (even c) or r (odd c) of instance c / 2
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+      const int ot = wid + s * NWV;
+      if (ot < NT) {
+        const int qt = ot / (NC / 16), ct = ot % (NC / 16);
+        const int cb = ct * 16 + (lane & 15), kr = lane >> 4;
+        const int jj = cb >> 1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int q = qt * 16 + 4 * e + kr;
+          if (q < KP) bvs[jj * NV + (cb & 1) * KP + q] = acc[s][e];
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < BT_GS; ++jj) {
+      const double s1 = wave_sum(rzv[jj]);
+      const double s2 = wave_sum(rrv[jj]);
+      if (lane == 0) { red[wid][2 * jj] = s1; red[wid][2 * jj + 1] = s2; }
+    }
+    __syncthreads();
+    for (int e = t; e < BT_G * 2; e += BT_THREADS) {   // slice j / BT_GS: waves 2 sl, 2 sl + 1
+      const int j = e >> 1, w2 = e & 1;
+      const int s2 = j / BT_GS, jj = j % BT_GS;
+      bvs[j * NV + 2 * KP + w2] = red[2 * s2][2 * jj + w2] + red[2 * s2 + 1][2 * jj + w2];
+    }
+    __syncthreads();
+    unsigned act = 0u;
+    for (int j = 0; j < G; ++j)
+      if (sk[j]) act |= 1u << j;
+    const unsigned fin = tree_reduce_multi(a.gbt, blk, NV, act, G,
+                                           a.part + (size_t)g0 * a.gbt.ptotal * NV, (size_t)a.gbt.ptotal * NV,
+                                           a.ctr + (size_t)g0 * a.gbt.ctotal, (size_t)a.gbt.ctotal, bvs, tots);
+    for (int j = 0; j < G; ++j) {
+      if (!((fin >> j) & 1u)) continue;
+      Inst* S = a.inst + g0 + j;
+      update_finish<KP>(a.C + (size_t)(g0 + j) * KP * KP, tots + j * NV, S, S->kk > 0, a.maxit, a.seg_maxit);
       __syncthreads();
     }
   }
