@@ -194,7 +194,9 @@ def main():
         t_b = time.perf_counter() - t0
         bi = np.asarray(ob["iters"])
         batched = {"solves_per_s": B / t_b, "ms_per_step": t_b * 1e3, "iters_mean": float(bi.mean()),
-                   "iters_max": int(bi.max()), "relres_true_max": float(np.asarray(ob["relres_true"]).max())}
+                   "iters_max": int(bi.max()), "relres_true_max": float(np.asarray(ob["relres_true"]).max()),
+                   "iters_per_instance": bi.tolist(),
+                   "cond_E_max": float(np.max(ob["cond_E"]))}
         print(f"[bench] batched (reference modes only) done ({t_b:.2f}s)", file=sys.stderr, flush=True)
 
     plain = None
@@ -269,6 +271,8 @@ def main():
         "variant": {"rows_per_thread": v_rpt, "w_mode": v_wm, "tuned": args.rpt == 0 or args.w_mode == 0,
                     "trial_ms": [round(float(t), 3) for t in v_ms]},
         "learned_used": (int(np.asarray(out["learned"]).sum()) if learned is not None else 0),
+        "cond_E": {"min": float(np.min(out["cond_E"])), "max": float(np.max(out["cond_E"]))},
+        "iters_per_instance": np.asarray(out["iters"]).tolist(),
         "learned_fit": learned,
         "batched_reference_modes": batched,
         "relres_true_max": float(head_rel.max()),

@@ -90,7 +90,10 @@ typedef struct {
                            (Remark tau_cond)                                 */
   double drop_rel;      /* restricted-basis column dropped when its part
                            orthogonal to earlier columns is <= drop_rel times
-                           its own norm; 1e-6                                 */
+                           its own norm; 1e-6.  With FP32 panels (refinement
+                           modes) at least 1e-3: the independent part of a
+                           column carries the FP32 rounding of the whole
+                           column amplified by the inverse of that ratio     */
   int32_t maxit;        /* iteration cap (total over refinement sweeps);
                            100000 (App. "CG stopping criterion")             */
   int32_t precision;    /* enum adef2_precision                              */
@@ -251,7 +254,9 @@ int adef2_pod(adef2_ctx *ctx, int32_t M, const double *X, int32_t p, double *Phi
 /* Use given POD modes (device f64[n*p], column-major) instead. */
 int adef2_set_pod_modes(adef2_ctx *ctx, int32_t p, const double *Phi);
 /* MLP parameters (host f32[83200]); resets the Adam state.  tau_learned: the
- * cond(E) bound of the enriched basis (>= 1; 1e8 in the learned workload). */
+ * cond(E) bound of the enriched basis (>= 1; 1e8 in the learned workload).
+ * With FP32 panels (refinement modes) the bound used is at most 1.7e4, where
+ * the FP32 coarse solve's error u32 cond(E) reaches 1e-3. */
 int adef2_learned_set_params(adef2_ctx *ctx, const float *params, double tau_learned);
 int adef2_learned_get_params(adef2_ctx *ctx, float *params);
 /* Training samples: masks (device u8[M*n]), right-hand sides b and solutions

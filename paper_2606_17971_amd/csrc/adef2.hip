@@ -20,6 +20,8 @@ std::string g_create_error;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int round8(int k) { return (k + 7) & ~7; }
+constexpr double FP32_DROP = 1e-3;   // column-drop threshold with FP32 panels
+constexpr double FP32_COND = 1e-3 / 5.96e-8;   // learned cond(E) bound with FP32 panels
 
 enum KernelId { KI_INIT = 0, KI_INIT2, KI_PUPDATE, KI_SPMV, KI_UPDATE, KI_RESID, KI_ACCUM,
                 KI_GRAM, KI_COARSE, KI_COMPACT, KI_UPDATE_NW, KI_ZPROJ, KI_PUPDATE_BT, KI_ZPROJ_BT,
@@ -80,6 +82,8 @@ struct adef2_ctx {
   double* Zb64 = nullptr;        // [B][KP][N] per-instance basis
   float* Zb32 = nullptr;
   size_t zb_cap = 0;             // elements allocated in Zb64 / Zb32
+  double* Zsh64 = nullptr;       // shared reference modes while Z points at Zb
+  float* Zsh32 = nullptr;
   double tau_learned = 1e8;
 
   // restriction / batch state
@@ -357,10 +361,15 @@ void launch_coarse(adef2_ctx* c) {
   ca.kept = c->kept;
   ca.inst = c->inst;
   ca.k = c->k;
-  ca.drop_rel = c->o.drop_rel;
+  // with FP32 panels the part of a column orthogonal to the earlier ones
+  // carries the FP32 rounding of the whole column amplified by 1/|R_jj|: keep
+  // only columns whose independent part is at least FP32_DROP of their norm
+  ca.drop_rel = mat64(c->prec) ? c->o.drop_rel : std::max(c->o.drop_rel, FP32_DROP);
   ca.tau_cond = c->o.tau_cond;
   ca.k_base = c->k_base;
-  ca.tau_learned = c->tau_learned;
+  // with FP32 panels the coarse solve errs by ~u32 cond(E): cap the learned
+  // basis' bound so that this stays below 1e-3
+  ca.tau_learned = mat64(c->prec) ? c->tau_learned : std::min(c->tau_learned, FP32_COND);
 #define COARSE_CASE(KPV) \
   case KPV: hipLaunchKernelGGL((k_coarse<KPV>), dim3(c->B), dim3(TPB), 0, c->st, ca); break;
   switch (c->KP) {
@@ -552,6 +561,8 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.dia64 = c->dia64;
   a.dia1_64 = c->dia1_64;
   a.Z64 = c->Z64;
+  a.kb = c->zs ? c->k_base : c->KP;
+  a.Zsh64 = c->zs ? c->Zsh64 : c->Z64;
   a.B = c->B;
   a.bt_ntiles = c->bt_ntiles;
   a.bt_ntiles_pad = c->bt_ntiles_pad;
@@ -562,11 +573,13 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
     a.dia = (const M*)c->dia64;
     a.Z = (const M*)c->Z64;
     a.W = (const M*)c->W64;
+    a.Zsh = (const M*)(c->zs ? c->Zsh64 : c->Z64);
   } else {
     a.dia1 = (const M*)c->dia1_32;
     a.dia = (const M*)c->dia32;
     a.Z = (const M*)c->Z32;
     a.W = (const M*)c->W32;
+    a.Zsh = (const M*)(c->zs ? c->Zsh32 : c->Z32);
   }
   if constexpr (sizeof(V) == 8) {
     a.t = (V*)interior(c, c->t64);
@@ -607,7 +620,9 @@ ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active
   const double N1 = (double)c->N;
   const double Nall = N1 * nact;                     // mask bytes, inner-stencil rows
   const double U = std::min(N1, nI);                 // rows of shared operands used
-  const double zsh = (c->zs ? nI : U) * k * wm;      // Z: shared, or per instance (learned basis)
+  // Z: shared; with a per-instance basis only the columns past k_base are per instance
+  const double kb = c->zs ? (double)c->k_base : k;
+  const double zsh = (U * kb + (c->zs ? nI * (k - kb) : 0.0)) * wm;
   const double D = c->D, D1 = c->D1;
   b.init = nI * (8.0 + 2 * wv) + zsh + Nall;                   // src -> x, r; Z^T r
   b.init2 = nI * (k * wm + 6 * wv) + zsh + Nall;               // W c0, x r z dinv
@@ -992,6 +1007,7 @@ struct BasisSwap {
                        c->N, k, KPe, c->p, c->Z64, c->Phi, c->mout, c->Zb64, c->Zb32);
     HIPCHK(c, hipGetLastError());
     Z64s = c->Z64; Z32s = c->Z32; k0 = c->k; KP0 = c->KP;
+    c->Zsh64 = c->Z64; c->Zsh32 = c->Z32;
     c->Z64 = c->Zb64; c->Z32 = c->Zb32;
     c->k_base = k;
     c->k = k + MLP_NV;
@@ -1003,6 +1019,7 @@ struct BasisSwap {
   ~BasisSwap() {
     if (!active) return;
     c->Z64 = Z64s; c->Z32 = Z32s;
+    c->Zsh64 = nullptr; c->Zsh32 = nullptr;
     c->k = k0; c->KP = KP0;
     c->k_base = 0;
     c->zs = 0;

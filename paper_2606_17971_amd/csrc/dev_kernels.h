@@ -70,6 +70,12 @@ struct IterArgs {
   const V* dinv;           // [B][N]
   const M* Z;              // [KP][N] shared, or [B][KP][N] per instance
   int64_t zs;              // instance stride of Z (0: shared by all instances)
+  // with a per-instance basis whose first kb columns are the shared modes,
+  // those columns are read from the shared copy (one stream through L2 for
+  // the whole batch instead of one per instance)
+  const M* Zsh;            // [kb][N] shared leading columns
+  const double* Zsh64;
+  int32_t kb;              // columns q < kb come from Zsh (KP when zs == 0)
   const M* W;              // [B][KP][N]
   V* x; V* r; V* z; V* p; V* w;   // padded, pointer to instance 0 interior
   int64_t vs;              // padded vector stride
@@ -100,6 +106,16 @@ struct IterArgs {
 };
 
 template <int RPT> struct Rows { static constexpr int PB = IPB * RPT; };
+
+// column q of instance m's basis (FP32/FP64 panel type M, or FP64)
+template <typename V, typename M>
+__device__ __forceinline__ const M* zcol(const IterArgs<V, M>& a, int m, int q) {
+  return q < a.kb ? a.Zsh + (size_t)q * a.op.N : a.Z + (size_t)m * a.zs + (size_t)q * a.op.N;
+}
+template <typename V, typename M>
+__device__ __forceinline__ const double* zcol64(const IterArgs<V, M>& a, int m, int q) {
+  return q < a.kb ? a.Zsh64 + (size_t)q * a.op.N : a.Z64 + (size_t)m * a.zs + (size_t)q * a.op.N;
+}
 
 // Row tile of one iteration block: IPB * RPT consecutive rows starting at
 // base; thread t owns rows base + t + j * IPB.
@@ -206,8 +222,7 @@ __global__ void __launch_bounds__(IPB) k_init(IterArgs<V, M> a) {
     block_sum<1, NIWAVE>(v1, red, bv + KP);
   }
   {
-    const M* Zm = a.Z + (size_t)m * a.zs;
-    panel_dots<M, RPT, KP>(base, N, [&](int q) { return Zm + (size_t)q * N; },
+    panel_dots<M, RPT, KP>(base, N, [&](int q) { return zcol(a, m, q); },
                            [&](int) { return (const double*)vl; }, bv);
   }
   __syncthreads();
@@ -282,9 +297,8 @@ __device__ __forceinline__ bool reduce_directions(const IterArgs<V, M>& a, int m
   }
   const int64_t N = a.op.N;
   if (defl) {
-    const M* Zm = a.Z + (size_t)m * a.zs;
     panel_dots<M, RPT, 2 * KP>(
-        base, N, [&](int q) { return q < KP ? W + (size_t)q * N : Zm + (size_t)(q - KP) * N; },
+        base, N, [&](int q) { return q < KP ? W + (size_t)q * N : zcol(a, m, q - KP); },
         [&](int q) { return q < KP ? zl : rl; }, bv);
   } else {
     for (int q = threadIdx.x; q < 2 * KP; q += blockDim.x) bv[q] = 0.0;
@@ -343,10 +357,9 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V, M> a) {
       double xv = (double)x[i];
       rv = (double)r[i];
       if (defl) {
-        const M* Zi = a.Z + (size_t)m * a.zs + i;
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
-          xv += (double)Zi[(size_t)q * N] * cf[q];
+          xv += (double)zcol(a, m, q)[i] * cf[q];
           rv -= (double)W[(size_t)q * N + i] * cf[q];
         }
       }
@@ -408,9 +421,8 @@ __global__ void __launch_bounds__(IPB) k_pupdate(IterArgs<V, M> a) {
     if (i < N && mk[i] == 0) {
       double pv = (double)z[i];
       if (defl) {
-        const M* Zi = a.Z + (size_t)m * a.zs + i;
 #pragma unroll
-        for (int q = 0; q < KP; ++q) pv -= (double)Zi[(size_t)q * N] * cf[q];
+        for (int q = 0; q < KP; ++q) pv -= (double)zcol(a, m, q)[i] * cf[q];
       }
       if (keep) pv += beta * (double)p[i];
       p[i] = (V)pv;
@@ -653,9 +665,8 @@ __global__ void __launch_bounds__(IPB) k_zproj(IterArgs<V, M> a) {
     block_sum<2, NIWAVE>(v2, red, bv + 2 * KP);
   }
   if (defl) {
-    const double* Zm = a.Z64 + (size_t)m * a.zs;
     panel_dots<double, RPT, 2 * KP>(
-        base, N, [&](int q) { return Zm + (size_t)(q < KP ? q : q - KP) * N; },
+        base, N, [&](int q) { return zcol64(a, m, q < KP ? q : q - KP); },
         [&](int q) { return q < KP ? (const double*)ul : (const double*)rl; }, bv);
   } else {
     for (int q = threadIdx.x; q < 2 * KP; q += blockDim.x) bv[q] = 0.0;
