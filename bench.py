@@ -258,8 +258,10 @@ def main():
         "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(t_head * 1e3, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {lib.MIXED_REFINE: "f32 operator/panels + f64 vectors",
-                  lib.FP32_REFINE: "f32 + f64 refinement", lib.FP64: "f64"}[prec],
+        "dtype": {lib.MIXED_REFINE: "f32+f64", lib.FP32_REFINE: "f32+f64", lib.FP64: "f64"}[prec],
+        "dtype_detail": {lib.MIXED_REFINE: "FP32 operator and Z/W panels, FP64 vectors and residuals",
+                         lib.FP32_REFINE: "FP32 operator, panels and vectors, FP64 refinement",
+                         lib.FP64: "FP64 throughout"}[prec],
         "data": "synthetic",
         "config": {"workload": f"cd2d_upwind_{args.n}x{args.n}_k{args.k}_B{B}", "grid": args.n,
                    "N": op.N, "k": args.k, "instances": B, "tol": args.tol,
