@@ -112,6 +112,8 @@ def fit_enrichment(solver, args, lib):
     print(f"[bench] {args.train} snapshot solves in {t2 - t1:.1f}s", file=sys.stderr, flush=True)
     X = snap["x"]
     Phi, sig = solver.pod(X.T, args.pod)
+    if not sig[0] > 0:
+        raise RuntimeError("snapshot solves returned zero solutions; cannot fit the enrichment")
     solver.learned_set_params(gen.mlp_params(1))
     solver.learned_prepare(m_tr, b_tr, X, th_tr)
     hist = solver.learned_train(args.train_steps, lr=args.lr)
@@ -124,6 +126,30 @@ def fit_enrichment(solver, args, lib):
             "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
             "snapshot_s": round(t2 - t1, 2), "fit_s": round(t3 - t2, 2),
             "inputs_s": round(t1 - t0, 2)}, Phi
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary in
+    profiles/, or None when there is none for it or the kernel sources changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dev_common.h", "dev_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2606_17971_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("#", "|", "`")):
+                key, _, val = line.partition(":")
+                kv[key.strip()] = val.strip()
+        if kv.get("kernel") == kernel and kv.get("kernel-source-sha256") == sha:
+            return {"traffic": float(kv["traffic-bytes-per-launch"]),
+                    "traffic_alg_bytes": float(kv["alg-bytes-per-launch"]),
+                    "traffic_source": os.path.relpath(path, ROOT)}
+    return None
 
 
 def main():
@@ -149,12 +175,12 @@ def main():
     prec = {"mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE, "fp64": lib.FP64}[args.precision]
 
     tune = dict(rows_per_thread=args.rpt, w_mode=args.w_mode)
-    if args.counter_run:
-        tune["maxit"] = args.counter_maxit
     head = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
     head.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     thetas = torch.as_tensor(np.stack([i.theta for i in w.instances]).astype(np.float32), device="cuda")
     learned, Phi = (None, None) if args.no_learned else fit_enrichment(head, args, lib)
+    if args.counter_run:
+        head.set_opts(maxit=args.counter_maxit)
     use_theta = None if args.no_learned else thetas
 
     def head_step():
@@ -242,9 +268,19 @@ def main():
     kernels = {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
                    "alg_GBps": v["alg_bytes"] / (v["ms"] * 1e-3) / 1e9}
                for k, v in st.items() if v["launches"] and v["ms"] > 0}
+    kp = ((args.k + (0 if learned is None else 8)) + 7) // 8 * 8
+    vt, mt = {lib.MIXED_REFINE: ("double", "float"), lib.FP32_REFINE: ("float", "float"),
+              lib.FP64: ("double", "double")}[prec]
+    inst = f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}>"
+    tr = measured_traffic(inst)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["traffic"] if tr else None,
+                "kernel": dom, "instantiation": inst,
+                "alg_bytes_per_launch": round(d["alg_bytes"] / d["launches"]),
                 "avg_us": round(d["ms"] / d["launches"] * 1e3, 2), "kernels": kernels}
+    if tr:
+        roofline["traffic_alg_bytes_same_launches"] = tr["traffic_alg_bytes"]
+        roofline["traffic_source"] = tr["traffic_source"]
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -261,7 +261,9 @@ int adef2_learned_set_params(adef2_ctx *ctx, const float *params, double tau_lea
 int adef2_learned_get_params(adef2_ctx *ctx, float *params);
 /* Training samples: masks (device u8[M*n]), right-hand sides b and solutions
  * xsol (device f64[M*n]), theta (device f32[M*4]), operator scales (host, or
- * NULL).  Computes per sample H (p x p), g (p), b_Z^T G_ZZ^-1 b_Z, b^T x. */
+ * NULL).  Computes per sample H (p x p), g (p), b_Z^T G_ZZ^-1 b_Z, b^T x.
+ * E_ARG when a sample has b_I^T x_I <= 0 (x is not the solution, or b_I = 0);
+ * E_UNSUPPORTED when k*k + k*(p+1) > 8192. */
 int adef2_learned_prepare(adef2_ctx *ctx, int32_t M, const uint8_t *masks, const double *b,
                           const double *xsol, const float *theta, const double *a,
                           const double *c);

@@ -1605,6 +1605,12 @@ int adef2_learned_prepare(adef2_ctx* c, int32_t M, const uint8_t* masks, const d
   hipError_t e = hipStreamSynchronize(c->st);
   cleanup();
   if (e != hipSuccess) return fail(c, ADEF2_E_HIP, std::string("learned_prepare: ") + hipGetErrorString(e));
+  // b^T x* > 0 for an SPD system and b != 0: it normalises the loss
+  HIPCHK(c, hipMemcpy(bxh.data(), c->bxtr, sizeof(double) * M, hipMemcpyDeviceToHost));
+  for (int m = 0; m < M; ++m)
+    if (!(bxh[m] > 0.0) || !std::isfinite(bxh[m]))
+      return fail(c, ADEF2_E_ARG, "learned_prepare: sample " + std::to_string(m) +
+                                      " has b_I^T x_I <= 0 (not a solution, or b_I = 0)");
   c->Mtr = M;
   return ADEF2_OK;
 }
