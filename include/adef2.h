@@ -136,6 +136,17 @@ typedef struct {
                            basis width, operator form, N) and reuses it, so
                            repeated solves in one context are bitwise
                            reproducible                                     */
+  int32_t w_boundary;   /* 1: with FP32 panels, reference modes that are
+                           eigenvectors of the reference operator B
+                           (||B z - mu z|| <= 1e-7 |mu| ||z||, tested at
+                           set_reference) keep W = S_II Z_I as
+                           W - lambda Z, lambda = a mu + c, which vanishes
+                           except on inactive rows coupled to the active set
+                           (up to the eigen-residual, below FP32 rounding);
+                           the iteration then reads W only on those rows and
+                           takes lambda Z^T z from the shared modes.
+                           0 (default): W stored and read whole (faster on
+                           MI355X at 511^2 although it moves more bytes)    */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;

@@ -44,6 +44,7 @@ class Opts(ctypes.Structure):
         ("rows_per_thread", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("w_mode", ctypes.c_int32),
+        ("w_boundary", ctypes.c_int32),
     ]
 
 

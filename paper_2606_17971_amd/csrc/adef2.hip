@@ -21,6 +21,7 @@ std::string g_create_error;
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int round8(int k) { return (k + 7) & ~7; }
 constexpr double FP32_DROP = 1e-3;   // column-drop threshold with FP32 panels
+constexpr double EIG_TOL = 1e-7;     // eigen-residual bound for the boundary form of W
 constexpr double FP32_COND = 1e-3 / 5.96e-8;   // learned cond(E) bound with FP32 panels
 
 enum KernelId { KI_INIT = 0, KI_INIT2, KI_PUPDATE, KI_SPMV, KI_UPDATE, KI_RESID, KI_ACCUM,
@@ -84,6 +85,14 @@ struct adef2_ctx {
   size_t zb_cap = 0;             // elements allocated in Zb64 / Zb32
   double* Zsh64 = nullptr;       // shared reference modes while Z points at Zb
   float* Zsh32 = nullptr;
+  // reference modes as eigenvectors of the base operator (boundary form of W)
+  double* mu64 = nullptr;        // [KP] Rayleigh quotients
+  uint8_t* eigf = nullptr;       // [KP] eigen-residual <= EIG_TOL
+  int n_eig = 0;                 // columns flagged
+  uint8_t* bnd = nullptr;        // [B][N] boundary rows of the current restriction
+  uint8_t* hb = nullptr;         // [B][N] scratch of the boundary test
+  double* zero64 = nullptr;      // 64 zero words (branch-free skipped loads)
+  int ne = 0;                    // columns in boundary form for the current restriction
   double tau_learned = 1e8;
 
   // restriction / batch state
@@ -223,7 +232,7 @@ void free_all(adef2_ctx* c) {
   F(c->part); F(c->ctr);
   F(c->Phi); F(c->mlp); F(c->mlp_bf); F(c->mlp_g); F(c->mlp_m); F(c->mlp_v); F(c->theta_tr);
   F(c->Htr); F(c->gtr); F(c->e0tr); F(c->bxtr); F(c->act); F(c->mout); F(c->dout); F(c->dA1);
-  F(c->dA2); F(c->lossv); F(c->Zb64); F(c->Zb32);
+  F(c->dA2); F(c->lossv); F(c->Zb64); F(c->Zb32); F(c->mu64); F(c->eigf); F(c->bnd); F(c->hb); F(c->zero64);
   if (c->inst_h) hipHostFree(c->inst_h);
   for (auto& e : c->ev_pending) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
   for (auto e : c->ev_pool) hipEventDestroy(e);
@@ -343,7 +352,7 @@ void launch_gram(adef2_ctx* c, const V* dummy_tag, V* W) {
     nsub = (int)cdiv(c->N, GramCfg<KPV>::GR);                                                \
     hipLaunchKernelGGL((k_spmm_gram<V, KPV>), grid, dim3(TPB), 0, c->st, og, c->dia64, c->Z64, \
                        c->zs, c->Tm, (int)c->factored, c->masks, W, c->inst, c->part, c->ctr,        \
-                       c->g_gram, c->gram, nsub);                                            \
+                       c->g_gram, c->gram, nsub, c->mu64, c->eigf, c->ne);                   \
     break;
   switch (c->KP) {
     GRAM_CASE(8) GRAM_CASE(16) GRAM_CASE(24) GRAM_CASE(32) GRAM_CASE(40) GRAM_CASE(48)
@@ -395,6 +404,9 @@ void set_variant(adef2_ctx* c, int rpt, int wfree) {
   c->g_bt = make_geom(c->bt_nblk_pad);
 }
 
+template <typename V>
+void fill(adef2_ctx* c, V* p, size_t n, V v);
+
 int ensure_batch(adef2_ctx* c, int B, int prec) {
   const int64_t N = c->N;
   const int KP = c->KP;
@@ -445,6 +457,9 @@ int ensure_batch(adef2_ctx* c, int B, int prec) {
   if ((rc = dalloc(c, &c->t64, c->factored ? BV : 0))) return rc;
   if ((rc = dalloc(c, &c->t32, (c->factored && !v64) ? BV : 0))) return rc;
   if ((rc = dalloc(c, &c->Tm, c->factored ? BN * KP : 0))) return rc;
+  if ((rc = dalloc(c, &c->bnd, BN)) || (rc = dalloc(c, &c->hb, BN)) || (rc = dalloc(c, &c->zero64, 64)))
+    return rc;
+  fill<double>(c, c->zero64, 64, 0.0);
   // reduction scratch: enough for the iteration kernels (NV <= KP+2) and the
   // Gram kernel (NV = 2 KP^2); geometry is recomputed per call from B
   const size_t pi = (size_t)std::max(make_geom((int)cdiv(cdiv(N, IPB), 8) * 8).ptotal,
@@ -513,6 +528,18 @@ int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
   }
   fill<double>(c, c->x0pad, BV, 0.0);
   fill<double>(c, c->t64, BV, 0.0);
+  // boundary form of W: FP32 panels and reference modes that are eigenvectors
+  c->ne = (c->KP > 0 && c->o.w_boundary == 1 && !mat64(c->prec) && c->n_eig > 0)
+              ? (c->zs ? c->k_base : c->k) : 0;
+  if (c->ne > 0) {
+    OpGeom og = op_geom(c);
+    if (c->factored) {
+      hipLaunchKernelGGL(k_bnd_inner, g1, dim3(256), 0, c->st, og, c->dia1_64, c->masks, c->hb);
+      hipLaunchKernelGGL(k_bnd_outer, g1, dim3(256), 0, c->st, og, c->dia64, c->masks, c->hb, c->bnd);
+    } else {
+      hipLaunchKernelGGL(k_bnd_outer, g1, dim3(256), 0, c->st, og, c->dia64, c->masks, c->masks, c->bnd);
+    }
+  }
   // coarse space
   if (c->KP > 0) {
     const double wbytes = (mat64(c->prec) ? 8.0 : 4.0);
@@ -562,6 +589,11 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.dia1_64 = c->dia1_64;
   a.Z64 = c->Z64;
   a.kb = c->zs ? c->k_base : c->KP;
+  a.mu = c->mu64;
+  a.eig = c->eigf;
+  a.bnd = c->bnd;
+  a.ne = c->ne;
+  a.wzero = (const M*)c->zero64;
   a.Zsh64 = c->zs ? c->Zsh64 : c->Z64;
   a.B = c->B;
   a.bt_ntiles = c->bt_ntiles;
@@ -935,7 +967,7 @@ bool valid_opts(const adef2_opts* o) {
          (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
          o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0 &&
          o->rows_per_thread >= 0 && o->rows_per_thread <= 2 &&
-         o->w_mode >= 0 && o->w_mode <= 3;
+         o->w_mode >= 0 && o->w_mode <= 3 && (o->w_boundary == 0 || o->w_boundary == 1);
 }
 
 }  // namespace
@@ -1046,6 +1078,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->rows_per_thread = 0;
   o->profile = 0;
   o->w_mode = 0;
+  o->w_boundary = 0;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
@@ -1179,15 +1212,51 @@ int load_dia(adef2_ctx* c, int64_t n, const int64_t* row_ptr, const int32_t* col
   return ADEF2_OK;
 }
 
+// Rayleigh quotients of the reference modes for the base operator and the
+// eigen flags (relative eigen-residual <= EIG_TOL), on the full domain.
+int eigen_test(adef2_ctx* c) {
+  const int64_t n = c->N;
+  const int KP = c->KP;
+  int rc;
+  if ((rc = dalloc(c, &c->mu64, (size_t)KP)) || (rc = dalloc(c, &c->eigf, (size_t)KP))) return rc;
+  double *T = nullptr, *BZ = nullptr;
+  if ((rc = dalloc(c, &BZ, (size_t)KP * n)) || (c->factored && (rc = dalloc(c, &T, (size_t)KP * n)))) {
+    if (BZ) hipFree(BZ);
+    return rc;
+  }
+  OpGeom og = op_geom(c);
+  const dim3 g((unsigned)cdiv(n, 256), KP);
+  if (c->factored) {
+    hipLaunchKernelGGL(k_ref_inner, g, dim3(256), 0, c->st, og, c->dia1_64, c->Z64, T);
+    hipLaunchKernelGGL(k_ref_outer, g, dim3(256), 0, c->st, og, c->dia64, T, BZ);
+  } else {
+    hipLaunchKernelGGL(k_ref_outer, g, dim3(256), 0, c->st, og, c->dia64, c->Z64, BZ);
+  }
+  hipLaunchKernelGGL(k_ref_stats, dim3(KP), dim3(TPB), 0, c->st, n, c->k, c->Z64, BZ, EIG_TOL, c->mu64,
+                     c->eigf);
+  std::vector<uint8_t> e(KP);
+  hipError_t err = hipMemcpyAsync(e.data(), c->eigf, KP, hipMemcpyDeviceToHost, c->st);
+  if (err == hipSuccess) err = hipStreamSynchronize(c->st);
+  hipFree(BZ);
+  if (T) hipFree(T);
+  if (err != hipSuccess) return fail(c, ADEF2_E_HIP, std::string("eigen test: ") + hipGetErrorString(err));
+  c->n_eig = 0;
+  for (int q = 0; q < KP; ++q) c->n_eig += e[q];
+  return ADEF2_OK;
+}
+
 int load_modes(adef2_ctx* c, int64_t n, int32_t k, const double* Z) {
   c->k = k;
   c->KP = round8(k);
+  c->n_eig = 0;
   int rc;
   if (c->KP > 0) {
     if ((rc = dalloc(c, &c->Z64, (size_t)c->KP * n)) || (rc = dalloc(c, &c->Z32, (size_t)c->KP * n)))
       return rc;
     hipLaunchKernelGGL(k_copy_modes, dim3((unsigned)cdiv(n, 256), c->KP), dim3(256), 0, c->st, n, k,
                        c->KP, Z, c->Z64, c->Z32);
+    HIPCHK(c, hipGetLastError());
+    if ((rc = eigen_test(c))) return rc;
     HIPCHK(c, hipStreamSynchronize(c->st));
   }
   return ADEF2_OK;

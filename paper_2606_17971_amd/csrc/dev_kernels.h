@@ -76,6 +76,16 @@ struct IterArgs {
   const M* Zsh;            // [kb][N] shared leading columns
   const double* Zsh64;
   int32_t kb;              // columns q < kb come from Zsh (KP when zs == 0)
+  // boundary form of W for reference modes that are eigenvectors of the base
+  // operator B (S = a B + c I): column q < ne with eig[q] stores W - lambda Z,
+  // lambda = a mu[q] + c, which vanishes (to the eigen-residual) except on
+  // rows flagged in bnd; then W^T z = lambda Z^T z + sum over those rows
+  const double* mu;        // [KP] Rayleigh quotients of the reference modes for B
+  const uint8_t* eig;      // [KP]
+  const uint8_t* bnd;      // [B][N]
+  int32_t ne;              // 0: W stored whole
+  const M* wzero;          // a zero in device memory: the W load of a row that
+                           // needs no W reads it (one cached line, no branch)
   const M* W;              // [B][KP][N]
   V* x; V* r; V* z; V* p; V* w;   // padded, pointer to instance 0 interior
   int64_t vs;              // padded vector stride
@@ -282,6 +292,98 @@ __device__ __forceinline__ double adef2_direction(const double* Cm, const double
   return s_rho;
 }
 
+// [W^T z | Z^T r] with the boundary form of W.  The tile's boundary rows are
+// compacted into an LDS list (wave ballots and prefix counts, so the order is
+// fixed); an eigen column then takes one dense pass over Z (serving Z^T z
+// and Z^T r) and a short pass over the listed rows of its stored panel
+// W - lambda Z; a non-eigen column (learned vectors) reads its W whole.
+template <typename V, typename M, int KP, int RPT>
+__device__ __forceinline__ void spectral_dots(const IterArgs<V, M>& a, int m, int64_t base, const M* W,
+                                              const double* zl, const double* rl, double* out) {
+  constexpr int R = Rows<RPT>::PB;
+  constexpr int NQW = (KP + NIWAVE - 1) / NIWAVE;
+  constexpr int NCH = R / 64;                       // 64-row chunks of the tile
+  __shared__ int blist[R];
+  __shared__ int bcnt[NCH + 1];
+  const int64_t N = a.op.N;
+  const uint8_t* bm = a.bnd + (size_t)m * N;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // chunk c = rows 64 c .. 64 c + 63, handled by wave c % NIWAVE
+  for (int c = wid; c < NCH; c += NIWAVE) {
+    const int64_t i = base + 64 * c + lane;
+    const bool f = i < N && bm[i] != 0;
+    const unsigned long long bal = __ballot(f);
+    if (lane == 0) bcnt[c + 1] = __popcll(bal);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bcnt[0] = 0;
+    for (int c = 0; c < NCH; ++c) bcnt[c + 1] += bcnt[c];
+  }
+  __syncthreads();
+  for (int c = wid; c < NCH; c += NIWAVE) {
+    const int64_t i = base + 64 * c + lane;
+    const bool f = i < N && bm[i] != 0;
+    const unsigned long long bal = __ballot(f);
+    if (f) blist[bcnt[c] + __popcll(bal & ((1ull << lane) - 1ull))] = 64 * c + lane;
+  }
+  __syncthreads();
+  const int nb = bcnt[NCH];
+  const Inst* S = a.inst + m;
+  const bool full = base + R <= N;
+#pragma unroll
+  for (int s = 0; s < NQW; ++s) {
+    const int q = wid + s * NIWAVE;
+    if (q < KP) {
+      const M* zc = zcol(a, m, q) + base;
+      const M* wc = W + (size_t)q * N + base;
+      const bool e = q < a.ne && a.eig[q];
+      double aw = 0.0, az = 0.0, ar = 0.0;
+      if (e) {
+        if (full) {
+#pragma unroll
+          for (int j = lane; j < R; j += 64) {
+            const double zv = (double)zc[j];
+            az += zv * zl[j];
+            ar += zv * rl[j];
+          }
+        } else {
+          for (int j = lane; j < R && base + j < N; j += 64) {
+            const double zv = (double)zc[j];
+            az += zv * zl[j];
+            ar += zv * rl[j];
+          }
+        }
+        for (int t = lane; t < nb; t += 64) {
+          const int j = blist[t];
+          aw += (double)wc[j] * zl[j];
+        }
+      } else {
+        if (full) {
+#pragma unroll
+          for (int j = lane; j < R; j += 64) {
+            aw += (double)wc[j] * zl[j];
+            ar += (double)zc[j] * rl[j];
+          }
+        } else {
+          for (int j = lane; j < R && base + j < N; j += 64) {
+            aw += (double)wc[j] * zl[j];
+            ar += (double)zc[j] * rl[j];
+          }
+        }
+      }
+      aw = wave_sum(aw);
+      az = wave_sum(az);
+      ar = wave_sum(ar);
+      if (lane == 0) {
+        const double lam = e ? S->a * a.mu[q] + S->c : 0.0;
+        out[q] = aw + lam * az;
+        out[KP + q] = ar;
+      }
+    }
+  }
+}
+
 // Second half of init2 / update: block sums of [W^T z | Z^T r | r.z | r.r]
 // for the tile (z, r already in LDS), then the reduction tree.
 template <typename V, typename M, int KP, int RPT>
@@ -296,7 +398,9 @@ __device__ __forceinline__ bool reduce_directions(const IterArgs<V, M>& a, int m
     block_sum<2, NIWAVE>(v2, red, bv + 2 * KP);
   }
   const int64_t N = a.op.N;
-  if (defl) {
+  if (defl && a.ne > 0) {
+    spectral_dots<V, M, KP, RPT>(a, m, base, W, zl, rl, bv);
+  } else if (defl) {
     panel_dots<M, RPT, 2 * KP>(
         base, N, [&](int q) { return q < KP ? W + (size_t)q * N : zcol(a, m, q - KP); },
         [&](int q) { return q < KP ? zl : rl; }, bv);
@@ -322,6 +426,7 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V, M> a) {
   __shared__ double bv[NV];
   __shared__ double tot[NV];
   __shared__ double cf[KP > 0 ? KP : 1];
+  __shared__ double lamq[KP > 0 ? KP : 1];
   int tile, m;
   tile_inst(a.op.ntiles_pad, tile, m);
   Inst* S = a.inst + m;
@@ -344,7 +449,10 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V, M> a) {
   const V* dinv = a.dinv + (size_t)m * N;
   const M* W = a.W + (size_t)m * KP * N;
   const bool defl = S->kk > 0;
-  for (int q = threadIdx.x; q < KP; q += blockDim.x) cf[q] = S->coef[q];
+  for (int q = threadIdx.x; q < KP; q += blockDim.x) {
+    cf[q] = S->coef[q];
+    lamq[q] = (q < a.ne && a.eig[q]) ? S->a * a.mu[q] + S->c : 0.0;
+  }
   __syncthreads();
   double rz = 0.0, rr2 = 0.0;
 #pragma unroll
@@ -359,8 +467,9 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V, M> a) {
       if (defl) {
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
-          xv += (double)zcol(a, m, q)[i] * cf[q];
-          rv -= (double)W[(size_t)q * N + i] * cf[q];
+          const double zq = (double)zcol(a, m, q)[i];
+          xv += zq * cf[q];
+          rv -= ((double)W[(size_t)q * N + i] + lamq[q] * zq) * cf[q];
         }
       }
       const V rq = (V)rv;

@@ -208,6 +208,104 @@ __global__ void k_stencil_modes(OpGeom op, const double* A64, const double* Z64,
   T[((size_t)m * KP + q) * N + i] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// Reference modes as eigenvectors of the base operator B (A^T A for the
+// factored form, the assembled stencil otherwise): BZ = B Z on the full
+// domain, then per column the Rayleigh quotient mu_q = z^T B z / z^T z and
+// the flag eig_q = ||B z - mu_q z|| <= tol |mu_q| ||z||.
+// ---------------------------------------------------------------------------
+__global__ void k_ref_inner(OpGeom op, const double* A64, const double* Z64, double* T) {
+  const int q = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = op.N;
+  if (i >= N) return;
+  const double* Zq = Z64 + (size_t)q * N;
+  double acc = 0.0;
+  for (int e = 0; e < op.D1; ++e) {
+    const int64_t j = i + op.offs1[e];
+    if (j >= 0 && j < N) acc += A64[(size_t)e * N + i] * Zq[j];
+  }
+  T[(size_t)q * N + i] = acc;
+}
+
+__global__ void k_ref_outer(OpGeom op, const double* dia64, const double* src, double* BZ) {
+  const int q = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = op.N;
+  if (i >= N) return;
+  const double* sq = src + (size_t)q * N;
+  double acc = 0.0;
+  for (int d = 0; d < op.D; ++d) {
+    const int64_t j = i + op.offs[d];
+    if (j >= 0 && j < N) acc += dia64[(size_t)d * N + i] * sq[j];
+  }
+  BZ[(size_t)q * N + i] = acc;
+}
+
+// one block per column; two passes (mu first, then the residual) so that the
+// residual is not a difference of nearly equal sums
+__global__ void __launch_bounds__(TPB) k_ref_stats(int64_t N, int k, const double* Z64, const double* BZ,
+                                                   double tol, double* mu, uint8_t* eig) {
+  __shared__ double red[TPB / 64 * 2];
+  __shared__ double tot[2];
+  const int q = blockIdx.x;
+  const double* z = Z64 + (size_t)q * N;
+  const double* bz = BZ + (size_t)q * N;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < N; i += TPB) {
+    v[0] += z[i] * bz[i];
+    v[1] += z[i] * z[i];
+  }
+  block_sum<2, TPB / 64>(v, red, tot);
+  const double zz = tot[1];
+  const double m = zz > 0.0 ? tot[0] / zz : 0.0;
+  double r[1] = {0.0};
+  for (int64_t i = threadIdx.x; i < N; i += TPB) {
+    const double e = bz[i] - m * z[i];
+    r[0] += e * e;
+  }
+  __syncthreads();
+  block_sum<1, TPB / 64>(r, red, tot);
+  if (threadIdx.x == 0) {
+    mu[q] = m;
+    eig[q] = (q < k && zz > 0.0 && sqrt(tot[0]) <= tol * fabs(m) * sqrt(zz)) ? 1 : 0;
+  }
+}
+
+// Rows of the inactive set whose row of S couples to the active set: there
+// W = S_II Z_I differs from (S Z)_I = Z_I Lambda.  Factored S: h_l = row l of
+// A touches an active column; boundary_i = row i of A^T touches an l with h_l.
+__global__ void k_bnd_inner(OpGeom op, const double* A64, const uint8_t* masks, uint8_t* h) {
+  const int m = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = op.N;
+  if (i >= N) return;
+  const uint8_t* mk = masks + (size_t)m * N;
+  uint8_t f = 0;
+  for (int e = 0; e < op.D1; ++e) {
+    const int64_t j = i + op.offs1[e];
+    if (j >= 0 && j < N && mk[j] && A64[(size_t)e * N + i] != 0.0) f = 1;
+  }
+  h[(size_t)m * N + i] = f;
+}
+
+__global__ void k_bnd_outer(OpGeom op, const double* dia64, const uint8_t* masks, const uint8_t* src,
+                            uint8_t* bnd) {
+  const int m = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = op.N;
+  if (i >= N) return;
+  const uint8_t* mk = masks + (size_t)m * N;
+  const uint8_t* sm = src + (size_t)m * N;
+  uint8_t f = 0;
+  if (mk[i] == 0)
+    for (int d = 0; d < op.D; ++d) {
+      const int64_t j = i + op.offs[d];
+      if (j >= 0 && j < N && sm[j] && dia64[(size_t)d * N + i] != 0.0) f = 1;
+    }
+  bnd[(size_t)m * N + i] = f;
+}
+
 // Z (column-major n x k, FP64) -> Z64 / Z32 (column-major n x KP, zero padded)
 __global__ void k_copy_modes(int64_t n, int k, int KP, const double* Z, double* Z64, float* Z32) {
   const int q = blockIdx.y;
@@ -241,7 +339,8 @@ __global__ void __launch_bounds__(TPB) k_spmm_gram(OpGeom op, const double* dia6
                                                     int64_t zs, const double* src, int factored,
                                                     const uint8_t* mask, V* W, Inst* inst,
                                                     double* part, unsigned* ctr, RedGeom g,
-                                                    double* gram, int nsub) {
+                                                    double* gram, int nsub, const double* mu,
+                                                    const uint8_t* eig, int ne) {
   using C = GramCfg<KP>;
   __shared__ double lds[C::LDS];
   double* zt = lds;                 // [GR][KP]
@@ -275,7 +374,10 @@ __global__ void __launch_bounds__(TPB) k_spmm_gram(OpGeom op, const double* dia6
           }
           zv = Zq[i];
           wv = sa * s + sc * zv;
-          Wm[(size_t)q * N + i] = (V)wv;
+          // eigen columns are stored as W - lambda Z (zero away from the
+          // active-set boundary up to the eigen-residual); E uses W itself
+          const double lam = (q < ne && eig[q]) ? sa * mu[q] + sc : 0.0;
+          Wm[(size_t)q * N + i] = (V)(wv - lam * zv);
         } else if (i < N) {
           Wm[(size_t)q * N + i] = (V)0;
         }

@@ -377,3 +377,27 @@ def test_autotuned_variant_is_reused(lib):
     b = s.solve_batched(masks, bs, 1e-10)
     np.testing.assert_array_equal(a["iters"], b["iters"])
     np.testing.assert_array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
+
+
+@pytest.mark.parametrize("form", ["assembled", "factored"])
+@pytest.mark.parametrize("w_boundary", [0, 1])
+def test_boundary_form_of_w(lib, form, w_boundary):
+    """Mixed precision with W kept whole (0) or in the boundary form (1: the
+    reference modes of these operators are eigenvectors to ~1e-9)."""
+    w = gen.c2_workload(n=127, k=24, B=3)
+    S = spec(w.op, form)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case(f"boundary-form W={w_boundary} {form} cd2d n=127 k=24 B=3")
+    s = solver(lib, w.op, w.Z, form, precision=lib.MIXED_REFINE, rows_per_thread=1, w_mode=1,
+               w_boundary=w_boundary)
+    out = s.solve_batched(masks, bs, 1e-10)
+    X = out["x"].cpu().numpy()
+    for m, inst in enumerate(w.instances):
+        ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
+        I, xs = _xstar(S, inst.mask, inst.b)
+        e = oracle.rel_err(X[m, I], xs)
+        assert out["status"][m] == 0
+        assert out["relres_true"][m] <= 1e-10
+        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), (m, e)
+        assert int(out["iters"][m]) <= 1.5 * ref.iters + 50
