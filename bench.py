@@ -55,6 +55,8 @@ def parse():
                     help="rows per thread of the iteration kernels (0 = tuned)")
     ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2, 3],
                     help="1 = read W, 2 = W-free tile-major, 3 = W-free per instance, 0 = tuned")
+    ap.add_argument("--w-boundary", type=int, default=0, choices=[0, 1],
+                    help="1 = boundary form of W for eigen reference modes")
     ap.add_argument("--counter-run", action="store_true",
                     help="short run for rocprofv3 counter passes: one headline solve capped at "
                          "--counter-maxit iterations, then a 256 MiB device copy of known size; "
@@ -174,7 +176,7 @@ def main():
     B = args.batch
     prec = {"mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE, "fp64": lib.FP64}[args.precision]
 
-    tune = dict(rows_per_thread=args.rpt, w_mode=args.w_mode)
+    tune = dict(rows_per_thread=args.rpt, w_mode=args.w_mode, w_boundary=args.w_boundary)
     head = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
     head.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     thetas = torch.as_tensor(np.stack([i.theta for i in w.instances]).astype(np.float32), device="cuda")
@@ -255,7 +257,7 @@ def main():
 
     # roofline: one instrumented headline step, HIP events around every launch
     prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1,
-                      rows_per_thread=v_rpt, w_mode=v_wm)
+                      rows_per_thread=v_rpt, w_mode=v_wm, w_boundary=args.w_boundary)
     prof.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     if learned is not None:
         prof.set_pod_modes(Phi)
