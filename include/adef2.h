@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define ADEF2_MAX_DIAGS 64   /* distinct diagonals of S                  */
+#define ADEF2_MAX_DIAGS 32   /* distinct diagonals of S (A: 16)           */
 #define ADEF2_MAX_K     64   /* deflation rank (shared + per-instance)   */
 
 enum adef2_status {

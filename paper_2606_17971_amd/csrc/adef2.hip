@@ -288,6 +288,7 @@ struct KTab {
   void (*zproj)(IterArgs<V, M>);
   void (*pupdate_bt)(IterArgs<V, M>);
   void (*zproj_bt)(IterArgs<V, M>);
+  void (*update_spec)(IterArgs<V, M>);
 };
 
 template <typename V, typename M, int KP, int RPT>
@@ -295,10 +296,12 @@ KTab<V, M> make_tab() {
   if constexpr (sizeof(V) == 8)
     return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
             k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, k_update_nw<V, M, KP, RPT>,
-            k_zproj<V, M, KP, RPT>, k_pupdate_bt<V, M, KP>, k_zproj_bt<M, KP>};
+            k_zproj<V, M, KP, RPT>, k_pupdate_bt<V, M, KP>, k_zproj_bt<M, KP>,
+            k_update<V, M, KP, RPT, true>};
   else
     return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
-            k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, nullptr, nullptr, nullptr, nullptr};
+            k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, nullptr, nullptr, nullptr, nullptr,
+            k_update<V, M, KP, RPT, true>};
 }
 
 template <typename V, typename M, int RPT>
@@ -748,7 +751,9 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
         hipLaunchKernelGGL(kt.spmv, grid, blk, 0, c->st, a);
       });
       if (!wfree) {
-        timed(c, KI_UPDATE, bm.update, [&] { hipLaunchKernelGGL(kt.update, grid, blk, 0, c->st, a); });
+        timed(c, KI_UPDATE, bm.update, [&] {
+          hipLaunchKernelGGL((c->ne > 0 ? kt.update_spec : kt.update), grid, blk, 0, c->st, a);
+        });
       } else {
         timed(c, KI_UPDATE_NW, bm.update_nw,
               [&] { hipLaunchKernelGGL(kt.update_nw, grid, blk, 0, c->st, a); });

@@ -17,8 +17,8 @@
 
 namespace adef2 {
 
-constexpr int MAXD = 64;
-constexpr int MAXD1 = 32;
+constexpr int MAXD = ADEF2_MAX_DIAGS;   // diagonals of S, or of A^T (factored)
+constexpr int MAXD1 = 16;               // diagonals of A (factored)
 
 struct OpGeom {
   int64_t N;
@@ -141,39 +141,44 @@ __device__ __forceinline__ const double* zcol64(const IterArgs<V, M>& a, int m, 
 template <typename M, int RPT, int NQ, typename ColF, typename VecF>
 __device__ __forceinline__ void panel_dots(int64_t base, int64_t N, ColF col, VecF vec, double* out) {
   constexpr int R = Rows<RPT>::PB;
-  constexpr int NQW = (NQ + NIWAVE - 1) / NIWAVE;
+  constexpr int NQW = (NQ + NIWAVE - 1) / NIWAVE;   // columns per wave
+  constexpr int PG = 4;                              // columns per group (loads in flight)
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double acc[NQW > 0 ? NQW : 1];
+  const bool full = base + R <= N;
+#pragma unroll 1
+  for (int s0 = 0; s0 < NQW; s0 += PG) {
+    double acc[PG];
 #pragma unroll
-  for (int s = 0; s < NQW; ++s) acc[s] = 0.0;
-  if (base + R <= N) {
+    for (int g = 0; g < PG; ++g) acc[g] = 0.0;
+    if (full) {
 #pragma unroll
-    for (int s = 0; s < NQW; ++s) {
-      const int q = wid + s * NIWAVE;
-      if (q < NQ) {
-        const M* c = col(q);
-        const double* v = vec(q);
+      for (int g = 0; g < PG; ++g) {
+        const int q = wid + (s0 + g) * NIWAVE;
+        if (s0 + g < NQW && q < NQ) {
+          const M* c = col(q);
+          const double* v = vec(q);
 #pragma unroll
-        for (int j = lane; j < R; j += 64) acc[s] += (double)c[base + j] * v[j];
+          for (int j = lane; j < R; j += 64) acc[g] += (double)c[base + j] * v[j];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < PG; ++g) {
+        const int q = wid + (s0 + g) * NIWAVE;
+        if (s0 + g < NQW && q < NQ) {
+          const M* c = col(q);
+          const double* v = vec(q);
+          for (int j = lane; j < R && base + j < N; j += 64) acc[g] += (double)c[base + j] * v[j];
+        }
       }
     }
-  } else {
 #pragma unroll
-    for (int s = 0; s < NQW; ++s) {
-      const int q = wid + s * NIWAVE;
-      if (q < NQ) {
-        const M* c = col(q);
-        const double* v = vec(q);
-        for (int j = lane; j < R && base + j < N; j += 64) acc[s] += (double)c[base + j] * v[j];
+    for (int g = 0; g < PG; ++g) {
+      const int q = wid + (s0 + g) * NIWAVE;
+      if (s0 + g < NQW && q < NQ) {
+        const double t = wave_sum(acc[g]);
+        if (lane == 0) out[q] = t;
       }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < NQW; ++s) {
-    const int q = wid + s * NIWAVE;
-    if (q < NQ) {
-      const double t = wave_sum(acc[s]);
-      if (lane == 0) out[q] = t;
     }
   }
 }
@@ -232,7 +237,10 @@ __global__ void __launch_bounds__(IPB) k_init(IterArgs<V, M> a) {
     block_sum<1, NIWAVE>(v1, red, bv + KP);
   }
   {
-    panel_dots<M, RPT, KP>(base, N, [&](int q) { return zcol(a, m, q); },
+    __shared__ const M* colp[KP > 0 ? KP : 1];
+    for (int q = threadIdx.x; q < KP; q += blockDim.x) colp[q] = zcol(a, m, q);
+    __syncthreads();
+    panel_dots<M, RPT, KP>(base, N, [&](int q) { return colp[q]; },
                            [&](int) { return (const double*)vl; }, bv);
   }
   __syncthreads();
@@ -386,7 +394,7 @@ __device__ __forceinline__ void spectral_dots(const IterArgs<V, M>& a, int m, in
 
 // Second half of init2 / update: block sums of [W^T z | Z^T r | r.z | r.r]
 // for the tile (z, r already in LDS), then the reduction tree.
-template <typename V, typename M, int KP, int RPT>
+template <typename V, typename M, int KP, int RPT, bool SPEC = false>
 __device__ __forceinline__ bool reduce_directions(const IterArgs<V, M>& a, int m, int tile, int64_t base,
                                                   const M* W, bool defl, double rz, double rr2,
                                                   const double* zl, const double* rl,
@@ -398,12 +406,19 @@ __device__ __forceinline__ bool reduce_directions(const IterArgs<V, M>& a, int m
     block_sum<2, NIWAVE>(v2, red, bv + 2 * KP);
   }
   const int64_t N = a.op.N;
-  if (defl && a.ne > 0) {
-    spectral_dots<V, M, KP, RPT>(a, m, base, W, zl, rl, bv);
+  if constexpr (SPEC) {
+    if (defl) spectral_dots<V, M, KP, RPT>(a, m, base, W, zl, rl, bv);
+    else
+      for (int q = threadIdx.x; q < 2 * KP; q += blockDim.x) bv[q] = 0.0;
   } else if (defl) {
+    // column base pointers computed once per block (the shared/per-instance
+    // choice of zcol inside the unrolled loop costs ~2x the registers)
+    __shared__ const M* colp[KP > 0 ? 2 * KP : 1];
+    for (int q = threadIdx.x; q < 2 * KP; q += blockDim.x)
+      colp[q] = q < KP ? W + (size_t)q * N : zcol(a, m, q - KP);
+    __syncthreads();
     panel_dots<M, RPT, 2 * KP>(
-        base, N, [&](int q) { return q < KP ? W + (size_t)q * N : zcol(a, m, q - KP); },
-        [&](int q) { return q < KP ? zl : rl; }, bv);
+        base, N, [&](int q) { return colp[q]; }, [&](int q) { return q < KP ? zl : rl; }, bv);
   } else {
     for (int q = threadIdx.x; q < 2 * KP; q += blockDim.x) bv[q] = 0.0;
   }
@@ -634,7 +649,9 @@ __device__ __forceinline__ void update_finish(const double* Cm, const double* to
 // x += alpha p, r -= alpha w, z = K r;  W^T z, Z^T r, r.z, ||r||^2
 // finisher: stopping test on ||r||, beta = r.y / rho, coarse coordinates
 // ---------------------------------------------------------------------------
-template <typename V, typename M, int KP, int RPT>
+// SPEC: W in the boundary form (a.ne > 0), a separate instantiation so that
+// the default kernel carries neither its code nor its LDS
+template <typename V, typename M, int KP, int RPT, bool SPEC = false>
 __global__ void __launch_bounds__(IPB) k_update(IterArgs<V, M> a) {
   constexpr int R = Rows<RPT>::PB;
   constexpr int NV = 2 * KP + 2;
@@ -683,7 +700,7 @@ __global__ void __launch_bounds__(IPB) k_update(IterArgs<V, M> a) {
     act[j] = !on;
   }
   __syncthreads();
-  if (!reduce_directions<V, M, KP, RPT>(a, m, tile, base, W, defl, rz, rr2, zl, rl, act, red, bv, tot))
+  if (!reduce_directions<V, M, KP, RPT, SPEC>(a, m, tile, base, W, defl, rz, rr2, zl, rl, act, red, bv, tot))
     return;
   update_finish<KP>(a.C + (size_t)m * KP * KP, tot, S, defl, a.maxit, a.seg_maxit);
 }
@@ -774,8 +791,11 @@ __global__ void __launch_bounds__(IPB) k_zproj(IterArgs<V, M> a) {
     block_sum<2, NIWAVE>(v2, red, bv + 2 * KP);
   }
   if (defl) {
+    __shared__ const double* colp[KP > 0 ? KP : 1];
+    for (int q = threadIdx.x; q < KP; q += blockDim.x) colp[q] = zcol64(a, m, q);
+    __syncthreads();
     panel_dots<double, RPT, 2 * KP>(
-        base, N, [&](int q) { return zcol64(a, m, q < KP ? q : q - KP); },
+        base, N, [&](int q) { return colp[q < KP ? q : q - KP]; },
         [&](int q) { return q < KP ? (const double*)ul : (const double*)rl; }, bv);
   } else {
     for (int q = threadIdx.x; q < 2 * KP; q += blockDim.x) bv[q] = 0.0;
