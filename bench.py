@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--snap-tol", type=float, default=1e-8)
-    ap.add_argument("--rpt", type=int, default=0, choices=[0, 1, 2],
+    ap.add_argument("--rpt", type=int, default=0, choices=[0, 1, 2, 4],
                     help="rows per thread of the iteration kernels (0 = tuned)")
     ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2, 3],
                     help="1 = read W, 2 = W-free tile-major, 3 = W-free per instance, 0 = tuned")

@@ -117,8 +117,8 @@ typedef struct {
                            segment restarts; 0                              */
   int32_t check_every;  /* iterations between host polls of convergence; 32 */
   int32_t rows_per_thread; /* rows per thread of the iteration kernels (tile
-                           height 1024 or 2048 rows): 1 or 2, or 0 = tuned on
-                           the first solve of each configuration            */
+                           height 256, 512 or 1024 rows): 1, 2 or 4, or 0 =
+                           tuned on the first solve of each configuration   */
   int32_t profile;      /* 1 = time kernels with HIP events (adef2_get_stats) */
   int32_t w_mode;       /* how the iteration forms W^T z (W = S_II Z_I):
                            1 = read the stored W; 2 = Z^T (S_II z), one more
@@ -147,6 +147,12 @@ typedef struct {
                            takes lambda Z^T z from the shared modes.
                            0 (default): W stored and read whole (faster on
                            MI355X at 511^2 although it moves more bytes)    */
+  int32_t graph;        /* 1 (default): each chunk of check_every iterations
+                           is captured once into a HIP graph (per kernel
+                           arguments) and replayed on a private stream of the
+                           context, ordered against its stream by events;
+                           0: kernels launched one by one.  profile = 1
+                           launches one by one                             */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;
@@ -300,7 +306,7 @@ int adef2_coarse_info(adef2_ctx *ctx, double *E, int32_t *kept, int32_t *k_eff,
 
 /* Iteration-kernel variant used by the last solve on ctx: rows per thread
  * (1 or 2) and w_mode (1, 2 or 3 as in adef2_opts), whether fixed by the
- * options or tuned.  ms (host f32[6], may be NULL) receives the trial times
+ * options or tuned.  ms (host f32[9], may be NULL) receives the trial times
  * of the tuned candidates, rows per thread outer, w_mode inner, restricted to
  * the candidates tried (0 when not tuned).  E_STATE before the first solve. */
 int adef2_variant(adef2_ctx *ctx, int32_t *rows_per_thread, int32_t *w_mode, float *ms);

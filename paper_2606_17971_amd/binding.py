@@ -45,6 +45,7 @@ class Opts(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("w_mode", ctypes.c_int32),
         ("w_boundary", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
     ]
 
 
@@ -335,7 +336,7 @@ class Solver:
     def variant(self):
         """(rows_per_thread, w_mode, trial ms) of the last solve."""
         r, wm = _i32(0), _i32(0)
-        ms = np.zeros(6, np.float32)
+        ms = np.zeros(9, np.float32)
         self._check(_lib.adef2_variant(self._ctx, ctypes.byref(r), ctypes.byref(wm), ms.ctypes.data),
                     allow=(OK,))
         return r.value, wm.value, ms

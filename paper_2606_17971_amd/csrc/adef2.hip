@@ -36,6 +36,12 @@ const char* kKernelNames[KI_COUNT] = {"init", "init2", "pupdate", "spmv", "updat
 struct adef2_ctx {
   adef2_opts o{};
   hipStream_t st = nullptr;
+  // captured chunks of iterations (HIP graphs), replayed on a private stream
+  // ordered against st by events
+  hipStream_t gst = nullptr;
+  hipEvent_t gev_in = nullptr, gev_out = nullptr;
+  struct GraphEntry { std::vector<char> key; hipGraphExec_t exec; };
+  std::vector<GraphEntry> graphs;
   int dev = 0;
   std::string err;
 
@@ -136,7 +142,7 @@ struct adef2_ctx {
   int bt_ntiles = 0, bt_ntiles_pad = 0;   // tile-major kernels (BT_ROWS-row tiles)
   int bt_nblk_pad = 0;                     // k_zproj_bt blocks (BT_TPB tiles each)
   RedGeom g_bt{};
-  struct Tuned { int B, prec, KP, fact; int64_t N; int rpt, wfree; float ms[6]; };
+  struct Tuned { int B, prec, KP, fact; int64_t N; int rpt, wfree; float ms[9]; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
   int gram_blocks = 0;
@@ -221,7 +227,16 @@ OpGeom op_geom(const adef2_ctx* c) {
   return g;
 }
 
+void drop_graphs(adef2_ctx* c) {
+  for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
 void free_all(adef2_ctx* c) {
+  drop_graphs(c);
+  if (c->gev_in) { hipEventDestroy(c->gev_in); c->gev_in = nullptr; }
+  if (c->gev_out) { hipEventDestroy(c->gev_out); c->gev_out = nullptr; }
+  if (c->gst) { hipStreamDestroy(c->gst); c->gst = nullptr; }
   auto F = [](void* p) { if (p) hipFree(p); };
   F(c->dia64); F(c->dia32); F(c->diag); F(c->Z64); F(c->Z32);
   F(c->masks); F(c->I); F(c->g2l); F(c->ccount); F(c->cofs); F(c->ntot); F(c->inst);
@@ -321,6 +336,7 @@ KTab<V, M> pick_kp(int KP) {
 
 template <typename V, typename M>
 KTab<V, M> pick(int KP, int rpt) {
+  if (rpt == 4) return pick_kp<V, M, 4>(KP);
   if (rpt == 2) return pick_kp<V, M, 2>(KP);
   return pick_kp<V, M, 1>(KP);
 }
@@ -329,17 +345,20 @@ template <int RPT>
 void (*pick_resid(void))(ResidArgs) { return k_resid64<RPT>; }
 
 void (*resid_fn(int rpt))(ResidArgs) {
+  if (rpt == 4) return k_resid64<4>;
   if (rpt == 2) return k_resid64<2>;
   return k_resid64<1>;
 }
 template <typename VM, typename VI, typename VO>
 void (*stencil1_fn(int rpt))(OpGeom, const VM*, const VI*, VO*, int64_t, const Inst*, int) {
+  if (rpt == 4) return k_stencil1<VM, VI, VO, 4>;
   if (rpt == 2) return k_stencil1<VM, VI, VO, 2>;
   return k_stencil1<VM, VI, VO, 1>;
 }
 
 template <typename V>
 void (*accum_fn(int rpt))(OpGeom, const uint8_t*, const V*, double*, int64_t, Inst*) {
+  if (rpt == 4) return k_accumulate<V, 4>;
   if (rpt == 2) return k_accumulate<V, 2>;
   return k_accumulate<V, 1>;
 }
@@ -413,7 +432,7 @@ void fill(adef2_ctx* c, V* p, size_t n, V v);
 int ensure_batch(adef2_ctx* c, int B, int prec) {
   const int64_t N = c->N;
   const int KP = c->KP;
-  set_variant(c, (c->o.rows_per_thread == 2) ? 2 : 1, c->o.w_mode >= 2 ? c->o.w_mode - 1 : 0);
+  set_variant(c, (c->o.rows_per_thread >= 2) ? c->o.rows_per_thread : 1, c->o.w_mode >= 2 ? c->o.w_mode - 1 : 0);
   const int64_t nsub_max = cdiv(N, 32);
   int gb = (int)std::max<int64_t>(8, std::min<int64_t>(256, 2048 / std::max(B, 1)));
   gb = (int)std::min<int64_t>(gb, nsub_max);
@@ -692,6 +711,42 @@ int poll(adef2_ctx* c, bool outer, bool* all_done) {
 
 // run one A-DEF2 sweep in precision V for all instances: init, init2, then
 // chunks of iterations until every instance's sweep is done
+// Instantiated graph of one chunk of iterations for these kernel arguments:
+// captured on the private stream the first time, then reused while the
+// arguments (buffers, geometry, variant) are unchanged.  A handful of
+// configurations are kept per context.
+template <typename V, typename M, typename F>
+int chunk_graph(adef2_ctx* c, const IterArgs<V, M>& a, int chunk, int variant, F&& launch_chunk,
+                hipGraphExec_t* out) {
+  std::vector<char> key(sizeof(a) + 4 * sizeof(int));
+  std::memcpy(key.data(), &a, sizeof(a));
+  const int extra[4] = {(int)sizeof(V), (int)sizeof(M), chunk, variant * 16 + c->rpt};
+  std::memcpy(key.data() + sizeof(a), extra, sizeof(extra));
+  for (auto& g : c->graphs)
+    if (g.key == key) { *out = g.exec; return ADEF2_OK; }
+  if (!c->gst) {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&c->gev_in, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->gev_out, hipEventDisableTiming));
+  }
+  hipGraph_t graph = nullptr;
+  HIPCHK(c, hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
+  launch_chunk(c->gst);
+  const hipError_t ce = hipStreamEndCapture(c->gst, &graph);
+  if (ce != hipSuccess) return fail(c, ADEF2_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(c, ADEF2_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+  if (c->graphs.size() >= 8) {
+    hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({key, exec});
+  *out = exec;
+  return ADEF2_OK;
+}
+
 // max_chunks > 0 stops after that many chunks (tuning trials).
 template <typename V, typename M>
 int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale,
@@ -728,6 +783,45 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   timed(c, KI_INIT2, bm.init2, [&] { hipLaunchKernelGGL(kt.init2, grid, blk, 0, c->st, a); });
   HIPCHK(c, hipGetLastError());
   const int chunk = std::max(1, c->o.check_every);
+  // one chunk of iterations on stream s (kernel arguments are the same for
+  // every iteration: all per-iteration state lives in device memory)
+  auto launch_chunk = [&](hipStream_t s) {
+    for (int it = 0; it < chunk; ++it) {
+      if (bt)
+        timed(c, KI_PUPDATE_BT, bm.pupdate,
+              [&] { hipLaunchKernelGGL(kt.pupdate_bt, gbt, dim3(BT_THREADS), 0, s, a); });
+      else
+        timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, s, a); });
+      timed(c, KI_SPMV, bm.spmv, [&] {
+        if (c->factored)
+          hipLaunchKernelGGL(st1, grid, blk, 0, s, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
+        hipLaunchKernelGGL(kt.spmv, grid, blk, 0, s, a);
+      });
+      if (!wfree) {
+        timed(c, KI_UPDATE, bm.update, [&] {
+          hipLaunchKernelGGL((c->ne > 0 ? kt.update_spec : kt.update), grid, blk, 0, s, a);
+        });
+      } else {
+        timed(c, KI_UPDATE_NW, bm.update_nw,
+              [&] { hipLaunchKernelGGL(kt.update_nw, grid, blk, 0, s, a); });
+        timed(c, bt ? KI_ZPROJ_BT : KI_ZPROJ, bm.zproj, [&] {
+          if (c->factored)
+            hipLaunchKernelGGL((stencil1_fn<double, V, V>(c->rpt)), grid, blk, 0, s, og, c->dia1_64,
+                               (const V*)a.z, a.t, c->vs, c->inst, 1);
+          if (bt)
+            hipLaunchKernelGGL(kt.zproj_bt, dim3(c->bt_nblk_pad), dim3(BT_THREADS), 0, s, a);
+          else
+            hipLaunchKernelGGL(kt.zproj, grid, blk, 0, s, a);
+        });
+      }
+    }
+  };
+  hipGraphExec_t gexec = nullptr;
+  if (c->o.graph && !c->o.profile) {
+    int rc = chunk_graph<V, M>(c, a, chunk, (int)bt * 4 + (int)wfree * 2 + (c->ne > 0 ? 1 : 0),
+                               launch_chunk, &gexec);
+    if (rc) return rc;
+  }
   int64_t launched = 0;
   for (;;) {
     bool ad = false;
@@ -739,34 +833,14 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
       return fail(c, ADEF2_E_HIP, "iteration kernels made no progress");
     launched += chunk;
     if (c->o.profile) bm = byte_model(c, (double)sizeof(V), (double)sizeof(M), true);
-    for (int it = 0; it < chunk; ++it) {
-      if (bt)
-        timed(c, KI_PUPDATE_BT, bm.pupdate,
-              [&] { hipLaunchKernelGGL(kt.pupdate_bt, gbt, dim3(BT_THREADS), 0, c->st, a); });
-      else
-        timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, c->st, a); });
-      timed(c, KI_SPMV, bm.spmv, [&] {
-        if (c->factored)
-          hipLaunchKernelGGL(st1, grid, blk, 0, c->st, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
-        hipLaunchKernelGGL(kt.spmv, grid, blk, 0, c->st, a);
-      });
-      if (!wfree) {
-        timed(c, KI_UPDATE, bm.update, [&] {
-          hipLaunchKernelGGL((c->ne > 0 ? kt.update_spec : kt.update), grid, blk, 0, c->st, a);
-        });
-      } else {
-        timed(c, KI_UPDATE_NW, bm.update_nw,
-              [&] { hipLaunchKernelGGL(kt.update_nw, grid, blk, 0, c->st, a); });
-        timed(c, bt ? KI_ZPROJ_BT : KI_ZPROJ, bm.zproj, [&] {
-          if (c->factored)
-            hipLaunchKernelGGL((stencil1_fn<double, V, V>(c->rpt)), grid, blk, 0, c->st, og, c->dia1_64,
-                               (const V*)a.z, a.t, c->vs, c->inst, 1);
-          if (bt)
-            hipLaunchKernelGGL(kt.zproj_bt, dim3(c->bt_nblk_pad), dim3(BT_THREADS), 0, c->st, a);
-          else
-            hipLaunchKernelGGL(kt.zproj, grid, blk, 0, c->st, a);
-        });
-      }
+    if (gexec) {
+      HIPCHK(c, hipEventRecord(c->gev_in, c->st));
+      HIPCHK(c, hipStreamWaitEvent(c->gst, c->gev_in, 0));
+      HIPCHK(c, hipGraphLaunch(gexec, c->gst));
+      HIPCHK(c, hipEventRecord(c->gev_out, c->gst));
+      HIPCHK(c, hipStreamWaitEvent(c->st, c->gev_out, 0));
+    } else {
+      launch_chunk(c->st);
     }
     HIPCHK(c, hipGetLastError());
     if (max_chunks > 0 && launched >= (int64_t)max_chunks * chunk) break;
@@ -832,7 +906,7 @@ int choose_variant(adef2_ctx* c, const double* b, double tol) {
   const int fr = c->o.rows_per_thread, fw = c->o.w_mode;
   if (fw >= 2 && !vec64(c->prec))
     return fail(c, ADEF2_E_UNSUPPORTED, "W-free iterations need FP64 vectors (FP64 or MIXED_REFINE)");
-  std::vector<int> rpts = (fr == 1 || fr == 2) ? std::vector<int>{fr} : std::vector<int>{1, 2};
+  std::vector<int> rpts = (fr == 1 || fr == 2 || fr == 4) ? std::vector<int>{fr} : std::vector<int>{1, 2, 4};
   std::vector<int> wfs = (fw == 1 || c->KP == 0 || !vec64(c->prec)) ? std::vector<int>{0}
                          : (fw == 2 ? std::vector<int>{1}
                                     : (fw == 3 ? std::vector<int>{2} : std::vector<int>{0, 1, 2}));
@@ -848,7 +922,7 @@ int choose_variant(adef2_ctx* c, const double* b, double tol) {
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0}};
+  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0}};
   float best_ms = INFINITY;
   int rc = ADEF2_OK, ci = 0;
   for (int rpt : rpts) {
@@ -971,8 +1045,10 @@ bool valid_opts(const adef2_opts* o) {
           o->precision == ADEF2_MIXED_REFINE) &&
          (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
          o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0 &&
-         o->rows_per_thread >= 0 && o->rows_per_thread <= 2 &&
-         o->w_mode >= 0 && o->w_mode <= 3 && (o->w_boundary == 0 || o->w_boundary == 1);
+         (o->rows_per_thread == 0 || o->rows_per_thread == 1 || o->rows_per_thread == 2 ||
+          o->rows_per_thread == 4) &&
+         o->w_mode >= 0 && o->w_mode <= 3 && (o->w_boundary == 0 || o->w_boundary == 1) &&
+         (o->graph == 0 || o->graph == 1);
 }
 
 }  // namespace
@@ -1084,6 +1160,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->profile = 0;
   o->w_mode = 0;
   o->w_boundary = 0;
+  o->graph = 1;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
@@ -1481,11 +1558,11 @@ int adef2_variant(adef2_ctx* c, int32_t* rows_per_thread, int32_t* w_mode, float
   if (rows_per_thread) *rows_per_thread = c->rpt;
   if (w_mode) *w_mode = c->wfree + 1;
   if (ms) {
-    for (int i = 0; i < 6; ++i) ms[i] = 0.0f;
+    for (int i = 0; i < 9; ++i) ms[i] = 0.0f;
     const int fact = c->factored ? 1 : 0;
     for (const auto& t : c->tuned)
       if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N)
-        for (int i = 0; i < 6; ++i) ms[i] = t.ms[i];
+        for (int i = 0; i < 9; ++i) ms[i] = t.ms[i];
   }
   return ADEF2_OK;
 }

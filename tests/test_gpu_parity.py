@@ -344,7 +344,7 @@ def test_error_paths(lib, c1):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("form", ["assembled", "factored"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("rpt,w_mode", [(1, 1), (1, 2), (2, 1), (2, 2)])
+@pytest.mark.parametrize("rpt,w_mode", [(1, 1), (1, 2), (2, 1), (2, 2), (4, 1), (4, 3)])
 def test_kernel_variants_match_oracle(lib, rpt, w_mode, prec, form):
     w = gen.c2_workload(n=95, k=16, B=3)
     S = spec(w.op, form)
@@ -401,3 +401,23 @@ def test_boundary_form_of_w(lib, form, w_boundary):
         assert out["relres_true"][m] <= 1e-10
         assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), (m, e)
         assert int(out["iters"][m]) <= 1.5 * ref.iters + 50
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replays_match_eager(lib, prec):
+    """Iteration chunks replayed from captured HIP graphs give the eager
+    result on every replay (three solves in a row, each preceded by the
+    context's own eager restriction work and synchronisation)."""
+    w = gen.c2_workload(n=95, k=16, B=4)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    p = lib.FP64 if prec == "fp64" else lib.MIXED_REFINE
+    case(f"graph replays vs eager {prec} cd2d n=95 B=4")
+    eager = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=2, w_mode=1, graph=0)
+    ref = eager.solve_batched(masks, bs, 1e-10)
+    g = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=2, w_mode=1, graph=1)
+    for rep in range(3):
+        out = g.solve_batched(masks, bs, 1e-10)
+        np.testing.assert_array_equal(out["iters"], ref["iters"])
+        np.testing.assert_array_equal(out["status"], ref["status"])
+        np.testing.assert_array_equal(out["x"].cpu().numpy(), ref["x"].cpu().numpy())
