@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--inner-rtol", type=float, default=1e-2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--force-learned", action="store_true",
+                    help="apply the enrichment even when its gain test fails")
     ap.add_argument("--no-batched-compare", action="store_true")
     ap.add_argument("--train", type=int, default=40, help="snapshot solves for the enrichment")
     ap.add_argument("--pod", type=int, default=32, help="POD modes the MLP combines")
@@ -123,11 +125,34 @@ def fit_enrichment(solver, args, lib):
     t3 = time.perf_counter()
     print(f"[bench] POD + {args.train_steps} training steps in {t3 - t2:.1f}s "
           f"(loss {hist[0]:.4f} -> {hist[-1]:.4f})", file=sys.stderr, flush=True)
+    # gain test: batched solves of 16 training members (tolerance of the
+    # timed solves) with and without the enrichment; it is kept only if it
+    # saves time (enrichment adds 8 columns to every panel pass)
+    sel = slice(0, min(16, args.train))
+
+    def timed_solve(theta, tol):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        o = solver.solve_batched(m_tr[sel], b_tr[sel], tol, theta=theta)
+        torch.cuda.synchronize()
+        return time.perf_counter() - ta, o
+
+    timed_solve(None, 1e-6)                # kernel variants are tuned on the first solve
+    timed_solve(th_tr[sel], 1e-6)
+    t_plain, o_plain = timed_solve(None, args.tol)
+    t_lrn, o_lrn = timed_solve(th_tr[sel], args.tol)
+    keep = t_lrn < 0.98 * t_plain
+    print(f"[bench] gain test on 16 training members: plain basis {t_plain:.2f}s, learned {t_lrn:.2f}s "
+          f"-> enrichment {'kept' if keep else 'not used'}", file=sys.stderr, flush=True)
     return {"snapshots": args.train, "snapshot_tol": args.snap_tol, "pod_modes": args.pod,
             "sigma_ratio_last": float(sig[-1] / sig[0]), "train_steps": args.train_steps,
             "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
             "snapshot_s": round(t2 - t1, 2), "fit_s": round(t3 - t2, 2),
-            "inputs_s": round(t1 - t0, 2)}, Phi
+            "inputs_s": round(t1 - t0, 2),
+            "gain_test": {"instances": 16, "plain_s": round(t_plain, 3), "learned_s": round(t_lrn, 3),
+                          "plain_iters_mean": float(np.mean(o_plain["iters"])),
+                          "learned_iters_mean": float(np.mean(o_lrn["iters"])),
+                          "learned_used": int(np.sum(o_lrn["learned"])), "kept": bool(keep)}}, Phi
 
 
 def measured_traffic(kernel: str):
@@ -181,9 +206,11 @@ def main():
     head.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     thetas = torch.as_tensor(np.stack([i.theta for i in w.instances]).astype(np.float32), device="cuda")
     learned, Phi = (None, None) if args.no_learned else fit_enrichment(head, args, lib)
+    # the enrichment is applied only when its gain test passed
+    apply_learned = learned is not None and (args.force_learned or learned["gain_test"]["kept"])
     if args.counter_run:
         head.set_opts(maxit=args.counter_maxit)
-    use_theta = None if args.no_learned else thetas
+    use_theta = thetas if apply_learned else None
 
     def head_step():
         return head.solve_batched(masks, bs, args.tol, theta=use_theta)
@@ -214,7 +241,7 @@ def main():
     X_head = out["x"].clone()
 
     batched = None
-    if learned is not None and not args.no_batched_compare:
+    if apply_learned and not args.no_batched_compare:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ob = head.solve_batched(masks, bs, args.tol)
@@ -259,7 +286,7 @@ def main():
     prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1,
                       rows_per_thread=v_rpt, w_mode=v_wm, w_boundary=args.w_boundary)
     prof.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
-    if learned is not None:
+    if apply_learned:
         prof.set_pod_modes(Phi)
         prof.learned_set_params(head.learned_get_params())
     prof.solve_batched(masks, bs, args.tol, theta=use_theta)
@@ -270,10 +297,11 @@ def main():
     kernels = {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
                    "alg_GBps": v["alg_bytes"] / (v["ms"] * 1e-3) / 1e9}
                for k, v in st.items() if v["launches"] and v["ms"] > 0}
-    kp = ((args.k + (0 if learned is None else 8)) + 7) // 8 * 8
+    kp = ((args.k + (8 if apply_learned else 0)) + 7) // 8 * 8
     vt, mt = {lib.MIXED_REFINE: ("double", "float"), lib.FP32_REFINE: ("float", "float"),
               lib.FP64: ("double", "double")}[prec]
-    inst = f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}>"
+    inst = (f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}, {'true' if args.w_boundary else 'false'}>" if dom == "update"
+            else f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}>")
     tr = measured_traffic(inst)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["traffic"] if tr else None,
@@ -303,14 +331,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"cd2d_upwind_{args.n}x{args.n}_k{args.k}_B{B}", "grid": args.n,
                    "N": op.N, "k": args.k, "instances": B, "tol": args.tol,
-                   "mode": "batched" if args.no_learned else "batched+learned",
+                   "mode": "batched+learned" if learned is not None else "batched",
+                   "learned_applied": bool(apply_learned),
                    "precision": args.precision,
                    "operator": "S = alpha A^T A + shift I (A: 5-point upwind, factored)"},
         "iters": {"mean": float(head_iters.mean()), "min": int(head_iters.min()),
                   "max": int(head_iters.max())},
         "variant": {"rows_per_thread": v_rpt, "w_mode": v_wm, "tuned": args.rpt == 0 or args.w_mode == 0,
                     "trial_ms": [round(float(t), 3) for t in v_ms]},
-        "learned_used": (int(np.asarray(out["learned"]).sum()) if learned is not None else 0),
+        "learned_used": (int(np.asarray(out["learned"]).sum()) if apply_learned else 0),
         "cond_E": {"min": float(np.min(out["cond_E"])), "max": float(np.max(out["cond_E"]))},
         "iters_per_instance": np.asarray(out["iters"]).tolist(),
         "learned_fit": learned,
