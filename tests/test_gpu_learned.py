@@ -149,4 +149,10 @@ def test_training_enriched_solves_safeguard_and_gain(lib, setup):
     s.learned_set_params(params, tau_learned=1.0)
     fb = s.solve_batched(masks, bs, 1e-10, theta=th[test])
     assert np.all(fb["learned"] == 0)
-    np.testing.assert_array_equal(fb["iters"], plain["iters"])
+    # same basis as the plain solve; the wider buffers of the enriched basis may
+    # tune to another tile height, so the reduction order (rounding) can differ
+    assert np.all(np.abs(fb["iters"].astype(int) - plain["iters"].astype(int)) <= 2)
+    Xf = fb["x"].cpu().numpy()
+    for j, m in enumerate(test):
+        I, _, _ = oracle.compact(insts[m].mask)
+        assert oracle.rel_err(Xf[j, I], xs[m][I]) <= 1e-8
