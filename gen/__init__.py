@@ -36,7 +36,8 @@ __all__ = [
     "laplacian_2d", "upwind_2d", "diffusion_2d", "diffusion_3d",
     "sinusoid_field", "gaussian_field_2d", "inclusion_field_3d",
     "mask_top_fraction", "gaussian_bump", "sine_modes_2d",
-    "c1_workload", "c2_workload", "c2_family_instance", "c2_thetas", "mlp_params", "c3_workload", "c5_workload",
+    "c1_workload", "c2_workload", "c2_family_instance", "c2_thetas", "mlp_params",
+    "OCPWorkload", "ocp_2d_sym", "c3_workload", "c5_workload",
     "cache_dir",
 ]
 
@@ -464,6 +465,44 @@ def c2_workload(n: int = 511, k: int = 32, B: int = 16, theta: float = math.pi /
     insts = [c2_family_instance(n, th) for th in c2_thetas(B, seed0, spread_rho=True)]
     return Workload(name=f"c2_cd2d_n{n}_k{k}_B{B}", op=op, Z=Z, instances=insts, tol=1e-10,
                     meta={"theta": theta, "peclet": peclet})
+
+
+# ---------------------------------------------------------------------------
+# State-constrained optimal control, 2D Laplacian "2d_sym" family (App.
+# "2D Laplacian problems"): y_d = a sin(pi x1) sin(pi x2), a in [0.8, 1.2];
+# M = alpha L^T L + I with L = -Laplacian (5-point FD, Dirichlet) =
+# K / h^2 in terms of the (4, -1) stencil K, so M = (alpha / h^4) K^T K + I.
+# sin(pi x1) sin(pi x2) sampled on the grid is an eigenvector of K with
+# eigenvalue mu = 8 sin^2(pi h / 2), so the unconstrained solution is
+# y_unc = a / (1 + alpha mu^2 / h^4) sin sin exactly; psi is the
+# (1 - active) quantile of y_unc at a = 1 (target active fraction at the
+# mid parameter).
+# ---------------------------------------------------------------------------
+@dataclass
+class OCPWorkload:
+    name: str
+    op: "Operator"
+    y_d: np.ndarray           # [B][N]
+    psi: np.ndarray           # [B][N]
+    params: np.ndarray        # [B]
+    tau: float = 1e-10
+
+
+def ocp_2d_sym(n: int = 127, B: int = 4, alpha: float = 1e-3, active: float = 0.2) -> OCPWorkload:
+    h = 1.0 / (n + 1)
+    K = canonical_csr(laplacian_2d(n))
+    N = n * n
+    op = Operator(n=n, dim=2, B=canonical_csr((alpha / h ** 4) * (K.T @ K)), shift=1.0,
+                  name=f"ocp2dsym_n{n}", A=K, alpha=alpha / h ** 4)
+    x1, x2 = _coords(n, 2)
+    base = np.sin(np.pi * x1) * np.sin(np.pi * x2)
+    mu = 8.0 * np.sin(np.pi * h / 2.0) ** 2
+    y_unc_mid = base / (1.0 + alpha * mu * mu / h ** 4)
+    psi_val = float(np.quantile(y_unc_mid, 1.0 - active))
+    amps = np.linspace(0.8, 1.2, B) if B > 1 else np.array([1.0])
+    y_d = np.stack([a * base for a in amps])
+    psi = np.full((B, N), psi_val)
+    return OCPWorkload(name=f"ocp_2d_sym_n{n}_B{B}", op=op, y_d=y_d, psi=psi, params=amps)
 
 
 MLP_DIMS = (4, 128, 128, 512)

@@ -451,3 +451,46 @@ def test_factored_exact_solution_is_the_factored_operators():
         res.append(float(Fraction(b[i]) - fa * u - fs * xf[i]))
     Mx = np.abs(F.toarray()) @ np.abs(x)
     assert np.all(np.abs(res) <= 8 * 2.2e-16 * Mx)
+
+
+# ---------------------------------------------------------------------------
+# primal active-set outer loop
+# ---------------------------------------------------------------------------
+def _sym_unconstrained(w):
+    n = w.op.n
+    h = 1.0 / (n + 1)
+    x1, x2 = gen._coords(n, 2)
+    mu = 8.0 * np.sin(np.pi * h / 2.0) ** 2
+    return np.sin(np.pi * x1) * np.sin(np.pi * x2) / (1.0 + w.op.alpha * mu * mu)
+
+
+def test_active_set_unconstrained_closed_form():
+    """psi above the unconstrained solution: one outer step, empty active set,
+    y = M^-1 y_d, which for y_d = a sin sin is a / (1 + alpha mu^2) sin sin."""
+    from oracle.active_set import active_set
+    w = gen.ocp_2d_sym(n=31, B=3)
+    spec = ("factored", w.op.A, w.op.alpha, w.op.shift)
+    base = _sym_unconstrained(w)
+    for m in range(3):
+        y, act, k, conv = active_set(spec, w.y_d[m], np.full(w.op.N, 10.0))
+        assert conv and k == 1 and act.sum() == 0
+        np.testing.assert_allclose(y, w.params[m] * base, rtol=1e-12, atol=1e-15)
+
+
+def test_active_set_fixed_point_and_iterations():
+    """At return: y_A = psi_A, y_I solves M_II y_I = (y_d)_I - M_IA psi_A, the
+    active set equals {y > psi - tau}, and the loop took 2-4 outer steps (the
+    paper's range for its benchmark families)."""
+    from oracle.active_set import active_set, apply_full
+    w = gen.ocp_2d_sym(n=31, B=3)
+    spec = ("factored", w.op.A, w.op.alpha, w.op.shift)
+    for m in range(3):
+        y, act, k, conv = active_set(spec, w.y_d[m], w.psi[m])
+        assert conv and 2 <= k <= 4, k
+        A = act != 0
+        np.testing.assert_array_equal(y[A], w.psi[m][A])
+        r = w.y_d[m] - apply_full(spec, y)
+        assert np.linalg.norm(r[~A]) <= 1e-10 * np.linalg.norm(w.y_d[m][~A])
+        np.testing.assert_array_equal((y > w.psi[m] - 1e-10).astype(np.uint8), act)
+        # the constraint holds up to tau on the inactive set after convergence
+        assert np.all(y[~A] <= w.psi[m][~A] - 1e-10 + 1e-12)
