@@ -304,6 +304,26 @@ int adef2_apply_restricted(adef2_ctx *ctx, const double *x, double *y);
 int adef2_coarse_info(adef2_ctx *ctx, double *E, int32_t *kept, int32_t *k_eff,
                       double *cond_E);
 
+/* Primal active-set iteration of the state-constrained problem (the
+ * appendix algorithm on active-set identification, around eq. (reduced)) for
+ * B instances on the reference operator M (a = 1, c = 0): cold start
+ * y = 0, A = {}; each outer step fixes y_A = psi_A, solves
+ * M_II y_I = (y_d)_I - M_IA psi_A with adef2_solve_batched (the instances
+ * still iterating form the batch) and predicts A = {i : y_i > psi_i - tau};
+ * an instance stops when the prediction repeats its active set.
+ *   y_d, psi : device f64[B*n] desired state and bound, global order.
+ *   tau      : active-set tolerance (1e-10 in the paper); tol: inner CG tolerance.
+ *   y        : device f64[B*n] out, the state (psi on the active set).
+ *   masks_out: device u8[B*n] out (1 = active), may be NULL.
+ *   outer, inner_iters, status: host int32[B] (may be NULL): outer steps,
+ *   CG iterations summed over them, and the worst inner status, raised to
+ *   W_MAXIT when max_outer steps end without a repeat.
+ * Returns the most severe per-instance status (negative = error). */
+int adef2_active_set_batched(adef2_ctx *ctx, int32_t B, const double *y_d, const double *psi,
+                             double tau, double tol, int32_t max_outer, double *y,
+                             uint8_t *masks_out, int32_t *outer, int32_t *inner_iters,
+                             int32_t *status);
+
 /* Iteration-kernel variant used by the last solve on ctx: rows per thread
  * (1 or 2) and w_mode (1, 2 or 3 as in adef2_opts), whether fixed by the
  * options or tuned.  ms (host f32[9], may be NULL) receives the trial times

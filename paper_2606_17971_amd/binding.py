@@ -86,6 +86,7 @@ _sig = {
     "adef2_apply_restricted": (ctypes.c_int, [_P, _P, _P]),
     "adef2_coarse_info": (ctypes.c_int, [_P, _P, _P, _Pi32, _Pf64]),
     "adef2_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _P]),
+    "adef2_active_set_batched": (ctypes.c_int, [_P, _i32, _P, _P, _f64, _f64, _i32, _P, _P, _P, _P, _P]),
     "adef2_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "adef2_reset_stats": (ctypes.c_int, [_P]),
     "adef2_last_error": (ctypes.c_char_p, [_P]),
@@ -332,6 +333,22 @@ class Solver:
         y = torch.empty_like(xt)
         self._check(_lib.adef2_apply_restricted(self._ctx, _ptr(xt), _ptr(y)), allow=(OK,))
         return y
+
+    def active_set_batched(self, y_d, psi, tau: float = 1e-10, tol: float = 1e-10, max_outer: int = 20):
+        """Primal active-set loop for B instances (y_d, psi: B x N)."""
+        Yd = _dev(y_d, torch.float64)
+        Ps = _dev(psi, torch.float64)
+        B = int(Yd.shape[0])
+        y = torch.empty_like(Yd)
+        masks = torch.empty(Yd.shape, dtype=torch.uint8, device="cuda")
+        outer = np.zeros(B, np.int32)
+        inner = np.zeros(B, np.int32)
+        status = np.zeros(B, np.int32)
+        rc = _lib.adef2_active_set_batched(self._ctx, B, _ptr(Yd), _ptr(Ps), float(tau), float(tol),
+                                           int(max_outer), _ptr(y), _ptr(masks), outer.ctypes.data,
+                                           inner.ctypes.data, status.ctypes.data)
+        self._check(rc)
+        return dict(y=y, masks=masks, outer=outer, inner_iters=inner, status=status)
 
     def variant(self):
         """(rows_per_thread, w_mode, trial ms) of the last solve."""

@@ -1552,6 +1552,87 @@ int adef2_apply_restricted(adef2_ctx* c, const double* x, double* y) {
   return ADEF2_OK;
 }
 
+int adef2_active_set_batched(adef2_ctx* c, int32_t B, const double* y_d, const double* psi, double tau,
+                             double tol, int32_t max_outer, double* y, uint8_t* masks_out, int32_t* outer,
+                             int32_t* inner_iters, int32_t* status) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_ref) return fail(c, ADEF2_E_STATE, "active_set_batched before set_reference");
+  if (B <= 0 || !y_d || !psi || !y || max_outer <= 0 || !(tau >= 0.0) || !(tol > 0.0))
+    return fail(c, ADEF2_E_ARG, "invalid active-set arguments");
+  const int64_t N = c->N;
+  const int64_t vs = N + 2 * c->H;
+  uint8_t *mk = nullptr, *msub = nullptr;
+  double *bsub = nullptr, *xsub = nullptr, *ps = nullptr, *t = nullptr;
+  int *idx = nullptr, *chg = nullptr;
+  auto cleanup = [&] {
+    for (void* q : {(void*)mk, (void*)msub, (void*)bsub, (void*)xsub, (void*)ps, (void*)t, (void*)idx,
+                    (void*)chg})
+      if (q) hipFree(q);
+  };
+  int rc;
+  if ((rc = dalloc(c, &mk, (size_t)B * N)) || (rc = dalloc(c, &msub, (size_t)B * N)) ||
+      (rc = dalloc(c, &bsub, (size_t)B * N)) || (rc = dalloc(c, &xsub, (size_t)B * N)) ||
+      (rc = dalloc(c, &ps, (size_t)B * vs)) || (c->factored && (rc = dalloc(c, &t, (size_t)B * vs))) ||
+      (rc = dalloc(c, &idx, (size_t)B)) || (rc = dalloc(c, &chg, (size_t)B))) {
+    cleanup();
+    return rc;
+  }
+  HIPCHK(c, hipMemsetAsync(mk, 0, (size_t)B * N, c->st));               // cold start: A = {}
+  fill<double>(c, ps, (size_t)B * vs, 0.0);                               // zero halos
+  if (t) fill<double>(c, t, (size_t)B * vs, 0.0);
+  std::vector<int> conv(B, 0), outer_h(B, 0), inner_h(B, 0), st_h(B, 0);
+  std::vector<int32_t> it_b(B), st_b(B);
+  std::vector<int> act, chg_h(B);
+  OpGeom og = op_geom(c);
+  int worst = ADEF2_OK;
+  for (int k = 0; k < max_outer; ++k) {
+    act.clear();
+    for (int m = 0; m < B; ++m)
+      if (!conv[m]) act.push_back(m);
+    if (act.empty()) break;
+    const int Bs = (int)act.size();
+    HIPCHK(c, hipMemcpyAsync(idx, act.data(), sizeof(int) * Bs, hipMemcpyHostToDevice, c->st));
+    const dim3 g((unsigned)cdiv(N, 256), Bs);
+    double* psi_i = ps + c->H;                 // interior of slot 0 (stride vs)
+    hipLaunchKernelGGL(k_ocp_psi, g, dim3(256), 0, c->st, N, idx, mk, psi, vs, psi_i);
+    const double* src = psi_i;
+    if (c->factored) {
+      hipLaunchKernelGGL(k_ocp_inner, g, dim3(256), 0, c->st, og, c->dia1_64, psi_i, vs, t + c->H);
+      src = t + c->H;
+    }
+    hipLaunchKernelGGL(k_ocp_rhs, g, dim3(256), 0, c->st, og, c->dia64, (int)c->factored,
+                       c->factored ? c->alpha_ref : 1.0, idx, mk, y_d, src, vs, bsub, msub);
+    HIPCHK(c, hipGetLastError());
+    rc = adef2_solve_batched(c, Bs, msub, bsub, nullptr, nullptr, nullptr, tol, xsub, it_b.data(),
+                             st_b.data(), nullptr, nullptr, nullptr, nullptr);
+    if (rc < 0) { cleanup(); return rc; }
+    HIPCHK(c, hipMemsetAsync(chg, 0, sizeof(int) * Bs, c->st));
+    hipLaunchKernelGGL(k_ocp_update, g, dim3(256), 0, c->st, N, idx, mk, xsub, psi, tau, y, chg);
+    HIPCHK(c, hipMemcpyAsync(chg_h.data(), chg, sizeof(int) * Bs, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (int j = 0; j < Bs; ++j) {
+      const int m = act[j];
+      outer_h[m] = k + 1;
+      inner_h[m] += it_b[j];
+      if (st_b[j] < 0 || st_h[m] < 0) st_h[m] = std::min(st_h[m], (int)st_b[j]);
+      else st_h[m] = std::max(st_h[m], (int)st_b[j]);
+      if (!chg_h[j]) conv[m] = 1;
+    }
+  }
+  for (int m = 0; m < B; ++m) {
+    if (!conv[m] && st_h[m] >= 0) st_h[m] = std::max(st_h[m], (int)ADEF2_W_MAXIT);
+    if (st_h[m] < 0) worst = std::min(worst, st_h[m]);
+    else if (worst >= 0) worst = std::max(worst, st_h[m]);
+    if (outer) outer[m] = outer_h[m];
+    if (inner_iters) inner_iters[m] = inner_h[m];
+    if (status) status[m] = st_h[m];
+  }
+  if (masks_out) HIPCHK(c, hipMemcpyAsync(masks_out, mk, (size_t)B * N, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  cleanup();
+  return worst;
+}
+
 int adef2_variant(adef2_ctx* c, int32_t* rows_per_thread, int32_t* w_mode, float* ms) {
   if (!c) return ADEF2_E_ARG;
   if (!c->solved) return fail(c, ADEF2_E_STATE, "variant before the first solve");

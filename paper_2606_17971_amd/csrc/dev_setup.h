@@ -306,6 +306,73 @@ __global__ void k_bnd_outer(OpGeom op, const double* dia64, const uint8_t* masks
   bnd[(size_t)m * N + i] = f;
 }
 
+// ---------------------------------------------------------------------------
+// Primal active-set outer loop (state-constrained problems): the instances
+// still iterating are addressed through idx (instance of batch slot j).
+// ---------------------------------------------------------------------------
+// psi restricted to the active set, padded layout: ps[j][i] = mask ? psi : 0
+__global__ void k_ocp_psi(int64_t N, const int* idx, const uint8_t* mk, const double* psi, int64_t vs,
+                          double* ps) {
+  const int j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int m = idx[j];
+  ps[(size_t)j * vs + i] = mk[(size_t)m * N + i] ? psi[(size_t)m * N + i] : 0.0;
+}
+
+// t = A ps on all rows (factored operator; ps padded, zero halo)
+__global__ void k_ocp_inner(OpGeom op, const double* A64, const double* ps, int64_t vs, double* t) {
+  const int j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = op.N;
+  if (i >= N) return;
+  const double* pj = ps + (size_t)j * vs;
+  double acc = 0.0;
+  for (int e = 0; e < op.D1; ++e) acc += A64[(size_t)e * N + i] * pj[i + op.offs1[e]];
+  t[(size_t)j * vs + i] = acc;
+}
+
+// right-hand side of eq. (reduced): b = (y_d)_I - M_IA psi_A, with M_IA psi_A
+// = (M ps)_I (ps vanishes on I); M = alpha A^T A + shift I (factored: src = t)
+// or the assembled stencil (src = ps); also the batch slot's mask
+__global__ void k_ocp_rhs(OpGeom op, const double* dia64, int factored, double alpha, const int* idx,
+                          const uint8_t* mk, const double* yd, const double* src, int64_t vs, double* b,
+                          uint8_t* msub) {
+  const int j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = op.N;
+  if (i >= N) return;
+  const int m = idx[j];
+  const uint8_t a = mk[(size_t)m * N + i];
+  msub[(size_t)j * N + i] = a;
+  double v = 0.0;
+  if (!a) {
+    const double* sj = src + (size_t)j * vs;
+    double acc = 0.0;
+    for (int d = 0; d < op.D; ++d) acc += dia64[(size_t)d * N + i] * sj[i + op.offs[d]];
+    v = yd[(size_t)m * N + i] - (factored ? alpha * acc : acc);
+  }
+  b[(size_t)j * N + i] = v;
+}
+
+// y = psi on the active set, the solve elsewhere; next active set
+// {y > psi - tau}; changed[j] = 1 when it differs from the current one
+__global__ void k_ocp_update(int64_t N, const int* idx, uint8_t* mk, const double* x, const double* psi,
+                             double tau, double* y, int* changed) {
+  const int j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int m = idx[j];
+  const size_t gi = (size_t)m * N + i;
+  const uint8_t old = mk[gi];
+  const double pv = psi[gi];
+  const double yv = old ? pv : x[(size_t)j * N + i];
+  y[gi] = yv;
+  const uint8_t nw = (yv > pv - tau) ? 1 : 0;
+  mk[gi] = nw;
+  if (nw != old) changed[j] = 1;
+}
+
 // Z (column-major n x k, FP64) -> Z64 / Z32 (column-major n x KP, zero padded)
 __global__ void k_copy_modes(int64_t n, int k, int KP, const double* Z, double* Z64, float* Z32) {
   const int q = blockIdx.y;
