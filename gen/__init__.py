@@ -468,15 +468,20 @@ def c2_workload(n: int = 511, k: int = 32, B: int = 16, theta: float = math.pi /
 
 
 # ---------------------------------------------------------------------------
-# State-constrained optimal control, 2D Laplacian "2d_sym" family (App.
-# "2D Laplacian problems"): y_d = a sin(pi x1) sin(pi x2), a in [0.8, 1.2];
-# M = alpha L^T L + I with L = -Laplacian (5-point FD, Dirichlet) =
-# K / h^2 in terms of the (4, -1) stencil K, so M = (alpha / h^4) K^T K + I.
-# sin(pi x1) sin(pi x2) sampled on the grid is an eigenvector of K with
-# eigenvalue mu = 8 sin^2(pi h / 2), so the unconstrained solution is
-# y_unc = a / (1 + alpha mu^2 / h^4) sin sin exactly; psi is the
-# (1 - active) quantile of y_unc at a = 1 (target active fraction at the
-# mid parameter).
+# State-constrained optimal control, the 2D Laplacian suite (App. "2D
+# Laplacian problems"): M = alpha L^T L + I with L = -Laplacian (5-point FD,
+# Dirichlet, h = 1/(n+1)) = K / h^2 in terms of the (4, -1) stencil K, so
+# M = (alpha / h^4) K^T K + I, alpha = 1e-3.  Desired states:
+#   2d_asym   : sum of 4 Gaussians (sigma 0.1) at radius sqrt(0.08) about
+#               (0.5, 0.5), angles 5 pi/4 + (k-1) pi/2 + theta, theta in [0, pi/2]
+#   2d_sym    : a sin(pi x1) sin(pi x2), a in [0.8, 1.2]
+#   2d_nonsep : a sin(2 pi x1 x2),      a in [0.8, 1.2]
+# The bound psi is constant: the (1 - active) quantile of the unconstrained
+# state M^-1 y_d at the mid parameter (App. "Mesh sizes and active-set
+# details", percentile protocol).  The grid sine modes diagonalise K, hence
+# M, so M^-1 y_d is computed exactly by an orthonormal 2D DST-I: eigenvalue
+# 1 + alpha ((s_i + s_j) / h^2)^2, s_q = 4 sin^2(q pi h / 2).  Parameters are
+# uniformly spaced over their range (the paper uses 30 instances).
 # ---------------------------------------------------------------------------
 @dataclass
 class OCPWorkload:
@@ -488,21 +493,54 @@ class OCPWorkload:
     tau: float = 1e-10
 
 
-def ocp_2d_sym(n: int = 127, B: int = 4, alpha: float = 1e-3, active: float = 0.2) -> OCPWorkload:
+OCP_2D = ("2d_asym", "2d_sym", "2d_nonsep")
+OCP_RANGES = {"2d_asym": (0.0, math.pi / 2), "2d_sym": (0.8, 1.2), "2d_nonsep": (0.8, 1.2)}
+
+
+def ocp_desired_state(name: str, n: int, p: float) -> np.ndarray:
+    x1, x2 = _coords(n, 2)
+    if name == "2d_sym":
+        return p * np.sin(np.pi * x1) * np.sin(np.pi * x2)
+    if name == "2d_nonsep":
+        return p * np.sin(2.0 * np.pi * x1 * x2)
+    if name == "2d_asym":
+        r, sig = math.sqrt(0.08), 0.1
+        out = np.zeros_like(x1)
+        for k in range(4):
+            ang = 5.0 * math.pi / 4.0 + k * math.pi / 2.0 + p
+            c1, c2 = 0.5 + r * math.cos(ang), 0.5 + r * math.sin(ang)
+            out += np.exp(-((x1 - c1) ** 2 + (x2 - c2) ** 2) / (2.0 * sig * sig))
+        return out
+    raise ValueError(name)
+
+
+def ocp_unconstrained(n: int, y_d: np.ndarray, alpha: float = 1e-3) -> np.ndarray:
+    """M^-1 y_d for M = (alpha / h^4) K^T K + I on the n x n grid (exact, DST-I)."""
+    from scipy.fft import dstn, idstn
+    h = 1.0 / (n + 1)
+    s = 4.0 * np.sin(np.arange(1, n + 1) * np.pi * h / 2.0) ** 2
+    lam = 1.0 + alpha * ((s[:, None] + s[None, :]) / h ** 2) ** 2
+    c = dstn(y_d.reshape(n, n), type=1, norm="ortho")
+    return idstn(c / lam, type=1, norm="ortho").ravel()
+
+
+def ocp_2d(name: str, n: int = 127, B: int = 4, alpha: float = 1e-3, active: float = 0.2) -> OCPWorkload:
     h = 1.0 / (n + 1)
     K = canonical_csr(laplacian_2d(n))
     N = n * n
     op = Operator(n=n, dim=2, B=canonical_csr((alpha / h ** 4) * (K.T @ K)), shift=1.0,
-                  name=f"ocp2dsym_n{n}", A=K, alpha=alpha / h ** 4)
-    x1, x2 = _coords(n, 2)
-    base = np.sin(np.pi * x1) * np.sin(np.pi * x2)
-    mu = 8.0 * np.sin(np.pi * h / 2.0) ** 2
-    y_unc_mid = base / (1.0 + alpha * mu * mu / h ** 4)
+                  name=f"ocp{name.replace('_', '')}_n{n}", A=K, alpha=alpha / h ** 4)
+    lo, hi = OCP_RANGES[name]
+    y_unc_mid = ocp_unconstrained(n, ocp_desired_state(name, n, 0.5 * (lo + hi)), alpha)
     psi_val = float(np.quantile(y_unc_mid, 1.0 - active))
-    amps = np.linspace(0.8, 1.2, B) if B > 1 else np.array([1.0])
-    y_d = np.stack([a * base for a in amps])
+    params = np.linspace(lo, hi, B) if B > 1 else np.array([0.5 * (lo + hi)])
+    y_d = np.stack([ocp_desired_state(name, n, p) for p in params])
     psi = np.full((B, N), psi_val)
-    return OCPWorkload(name=f"ocp_2d_sym_n{n}_B{B}", op=op, y_d=y_d, psi=psi, params=amps)
+    return OCPWorkload(name=f"ocp_{name}_n{n}_B{B}", op=op, y_d=y_d, psi=psi, params=params)
+
+
+def ocp_2d_sym(n: int = 127, B: int = 4, alpha: float = 1e-3, active: float = 0.2) -> OCPWorkload:
+    return ocp_2d("2d_sym", n, B, alpha, active)
 
 
 MLP_DIMS = (4, 128, 128, 512)

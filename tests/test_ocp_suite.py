@@ -1,0 +1,74 @@
+"""The 2D optimal-control inputs and the oracle's active-set loop and cold
+Jacobi-PCG against the numbers the paper prints for this suite
+(tests/golden/ocp_2d_suite.txt): the percentile-calibrated bound at 500^2,
+the active-fraction range over the sweep, and the mean cold-CG iteration
+count over 30 instances at 100^2.  The iteration count is a pin of the
+whole chain (operator scaling, desired state, bound, active-set rule,
+Jacobi preconditioner, stopping rule): a wrong factor anywhere moves it by
+far more than the 1 % bar."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import gen
+from oracle.active_set import active_set, apply_full, coupled_rhs
+from oracle.solver import compact, jacobi_pcg, restricted_operator
+
+HERE = os.path.dirname(__file__)
+
+
+def printed():
+    rows = {}
+    with open(os.path.join(HERE, "golden", "ocp_2d_suite.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            rows[t[0]] = dict(cold=[int(v) for v in t[1:6]], psi=float(t[6]), a_mean=float(t[7]),
+                              a_min=float(t[8]), a_max=float(t[9]), red40=float(t[10]))
+    return rows
+
+
+@pytest.mark.parametrize("name", gen.OCP_2D)
+def test_psi_calibration_at_500(name):
+    w = gen.ocp_2d(name, n=500, B=1)
+    assert round(float(w.psi[0, 0]), 3) == printed()[name]["psi"]
+
+
+def test_unconstrained_state_is_exact():
+    n = 40
+    for name in gen.OCP_2D:
+        w = gen.ocp_2d(name, n=n, B=3)
+        spec = ("factored", w.op.A, w.op.alpha, w.op.shift)
+        for m in range(3):
+            y = gen.ocp_unconstrained(n, w.y_d[m])
+            r = apply_full(spec, y) - w.y_d[m]
+            # rounding leaves ~u ||M|| ||y|| (||M|| ~ 2e5 here); a wrong
+            # eigenvalue or scaling leaves an O(1) residual
+            assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(w.y_d[m])
+
+
+@pytest.mark.parametrize("name", gen.OCP_2D)
+def test_cold_cg_and_active_fractions_at_100(name):
+    ref = printed()[name]
+    w = gen.ocp_2d(name, n=100, B=30)
+    spec = ("factored", w.op.A, w.op.alpha, w.op.shift)
+    iters, frac = [], []
+    for m in range(30):
+        y, act, k, conv = active_set(spec, w.y_d[m], w.psi[m], tau=w.tau)
+        assert conv and 2 <= k <= 4
+        I, _, _ = compact(act)
+        S_II, _ = restricted_operator(spec, I)
+        b = coupled_rhs(spec, w.y_d[m], w.psi[m], act)[I]
+        iters.append(jacobi_pcg(S_II, b, 1e-10).iters)
+        frac.append(act.mean())
+    mean_it = float(np.mean(iters))
+    print(f"{name}: cold mean {mean_it:.1f} (printed {ref['cold'][0]}), active "
+          f"{np.mean(frac):.3f} [{min(frac):.3f}, {max(frac):.3f}]")
+    assert abs(mean_it - ref["cold"][0]) <= 0.01 * ref["cold"][0]
+    # the printed fractions are at 500^2; the active set is grid-converged to ~0.5 %
+    assert abs(np.mean(frac) - ref["a_mean"]) <= 0.01
+    assert abs(min(frac) - ref["a_min"]) <= 0.01
+    assert abs(max(frac) - ref["a_max"]) <= 0.01
