@@ -182,9 +182,9 @@ def measured_traffic(kernel: str):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not "
-                                   "part of this build (instances shard across GPUs with no "
-                                   "communication, see DESIGN.md)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; a batch of instances would "
+                                   "shard across GPUs with no communication, which is not "
+                                   "implemented"}))
         sys.exit(2)
     import torch
 

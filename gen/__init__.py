@@ -18,8 +18,8 @@ paper allows for finite-element-style scalings:
 
 with K the (FE-scaled) state operator; a and c per workload.
 
-Readings taken here where the configuration text is silent are listed in
-the design doc (input recipe).
+Where the paper leaves a detail open, the reading taken is stated next to
+the generator that uses it.
 """
 from __future__ import annotations
 

@@ -6,8 +6,7 @@ SVD) merged under a conditioning guard (Alg. 2, Sec. "Conditioning-based safe
 merge").  The learned variant built here replaces the fixed choice of POD
 modes by 8 combinations V = Phi C^T of the first p POD modes, with C (8 x p)
 produced from the problem parameters theta by a small MLP.  The paper has no
-learned component; the objective below is this build's reading (listed in
-the design doc): the fraction of the solution's energy norm that the A-DEF2 coarse
+learned component; the objective below is a reading of ours: the fraction of the solution's energy norm that the A-DEF2 coarse
 correction with the basis [Z_I, V_I] leaves unresolved.
 
 Only the tests and the smoke check use this module.

@@ -14,6 +14,7 @@ Spectral Deflation for State Constrained Optimal Control Problems"):
                                            restriction"
 * restricted reference basis + QR ........ Sec. "Core idea: reference eigenmode
                                            basis" (simple restriction)
+* Ritz reselection from a pool .......... Sec. "Ritz re-selection"
 * coarse Gram E, fallback ................ Sec. "Online deflated solve (A-DEF2)",
                                            Alg. 3 (online workflow), Remark
                                            tau_cond; App. "GPU implementation"
@@ -24,7 +25,7 @@ Spectral Deflation for State Constrained Optimal Control Problems"):
 * exact solution for parity .............. eq. (accuracy_rel_err): the direct
                                            solution of eq. (reduced)
 
-Reading of Alg. 1 (listed in the design doc): as printed, the loop advances x along
+Reading of Alg. 1: as printed, the loop advances x along
 the *unprojected* preconditioned residual while the step length uses the
 projected operator, so x drifts inside range(Z) and the unprojected residual
 used by the stopping test stops decreasing.  The oracle uses the A-DEF2
@@ -49,7 +50,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 __all__ = [
-    "compact", "restrict", "restricted_basis", "CoarseSpace", "coarse_setup",
+    "compact", "restrict", "restricted_basis", "ritz_reselect", "CoarseSpace", "coarse_setup",
     "apply_projector", "adef2", "jacobi_pcg", "SolveResult", "solve_instance",
     "two_sum", "two_prod", "dd_residual", "exact_solution", "rel_err",
     "FactoredOp", "restrict_factored", "restricted_operator",
@@ -157,6 +158,20 @@ def restricted_basis(Z: np.ndarray, I: np.ndarray, drop_rel: float = 1e-6):
         # dropped directions exactly
         Q, R = np.linalg.qr(ZI[:, keep], mode="reduced")
     return Q, np.asarray(keep, dtype=np.int64)
+
+
+def ritz_reselect(S_II, Zo: np.ndarray, r: int):
+    """Sec. "Ritz re-selection": the orthonormal restricted pool Zo
+    (n_I x r_pool) defines the projected eigenproblem
+    Zo^T M_II Zo c_j = mu_j c_j; the r eigenvectors with the smallest Ritz
+    values give the basis Zo [c_1 .. c_r].  Returns (basis, Ritz values of
+    the kept vectors); r <= 0 or r >= r_pool returns the pool unchanged."""
+    if r <= 0 or r >= Zo.shape[1]:
+        return Zo, None
+    F = Zo.T @ np.asarray(S_II @ Zo)
+    F = 0.5 * (F + F.T)
+    mu, C = np.linalg.eigh(F)            # ascending
+    return Zo @ C[:, :r], mu[:r]
 
 
 # ---------------------------------------------------------------------------
@@ -322,17 +337,21 @@ class SolveResult:
 
 
 def solve_instance(S, Z, mask, b, tol: float, tau_cond: float = 1e10,
-                   maxit: int = 100000, x0=None, precond: str = "jacobi") -> SolveResult:
+                   maxit: int = 100000, x0=None, precond: str = "jacobi",
+                   ritz_keep: int = 0) -> SolveResult:
     """Restrict, build the coarse space, solve and scatter one instance.
 
     S is an assembled sparse matrix or ("factored", A, alpha, shift).  b and x
     are global (length N); b on the active set is ignored and x there is
     returned as zero.  ``x0`` (global) is an optional warm start.
+    ``ritz_keep`` > 0 reselects that many Ritz vectors from the restricted
+    pool (Sec. "Ritz re-selection").
     """
     I, _, n_I = compact(mask)
     S_II, d_I = restricted_operator(S, I)
     b_I = np.asarray(b, dtype=np.float64)[I]
     Zo, kept = restricted_basis(Z, I)
+    Zo, _ = ritz_reselect(S_II, Zo, ritz_keep)
     cs, fallback = coarse_setup(S_II, Zo, tau_cond)
     cs.kept = kept
     status = STATUS_OK

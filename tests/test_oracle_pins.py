@@ -494,3 +494,61 @@ def test_active_set_fixed_point_and_iterations():
         np.testing.assert_array_equal((y > w.psi[m] - 1e-10).astype(np.uint8), act)
         # the constraint holds up to tau on the inactive set after convergence
         assert np.all(y[~A] <= w.psi[m][~A] - 1e-10 + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Ritz reselection (Sec. "Ritz re-selection")
+# ---------------------------------------------------------------------------
+def _sym_op(n):
+    w = gen.ocp_2d_sym(n=n, B=1)
+    return w.op, ("factored", w.op.A, w.op.alpha, w.op.shift)
+
+
+def test_ritz_recovers_lowest_modes_closed_form():
+    """Empty active set: M_II = M, whose eigenvectors are the sine modes with
+    eigenvalues 1 + alpha' (s_i + s_j)^2.  A pool of the 16 lowest modes mixed
+    by a random rotation must give back the 4 lowest (a gap follows the 4th:
+    (1,1), (1,2), (2,1), (2,2), then (1,3)) with their closed-form values."""
+    from oracle.solver import restricted_basis, restricted_operator, ritz_reselect
+    n = 31
+    op, spec = _sym_op(n)
+    Z, pairs, _ = gen.sine_modes_2d(n, 16)
+    Qr, _ = np.linalg.qr(np.random.default_rng(5).standard_normal((16, 16)))
+    I = np.arange(op.N)
+    S_II, _ = restricted_operator(spec, I)
+    Zo, _ = restricted_basis(Z @ Qr, I)
+    Zs, mu = ritz_reselect(S_II, Zo, 4)
+    h = 1.0 / (n + 1)
+    s = lambda q: 4.0 * np.sin(q * np.pi * h / 2.0) ** 2
+    lam = sorted(1.0 + op.alpha * (s(i) + s(j)) ** 2 for i, j in pairs)[:4]
+    assert np.allclose(mu, lam, rtol=1e-12)
+    low = Z[:, :4]
+    assert np.linalg.norm(Zs - low @ (low.T @ Zs)) <= 1e-10
+    assert np.allclose(Zs.T @ Zs, np.eye(4), atol=1e-12)
+
+
+def test_ritz_values_interlace_and_diagonalise():
+    """With a real active set the kept Ritz values bound the lowest eigenvalues
+    of M_II from above (Courant-Fischer), the kept basis is orthonormal and
+    diagonalises the projected operator, and r >= pool returns the pool."""
+    from oracle.solver import compact, restricted_basis, restricted_operator, ritz_reselect
+    n = 15
+    op, spec = _sym_op(n)
+    rng = np.random.default_rng(9)
+    mask = (rng.random(op.N) < 0.25).astype(np.uint8)
+    I, _, _ = compact(mask)
+    S_II, _ = restricted_operator(spec, I)
+    Z = gen.sine_modes_2d(n, 12)[0]
+    Zo, _ = restricted_basis(Z, I)
+    Zs, mu = ritz_reselect(S_II, Zo, 5)
+    ev = np.linalg.eigvalsh(S_II.toarray())
+    assert np.all(mu >= ev[:5] * (1 - 1e-12))
+    assert np.all(np.diff(mu) >= 0)
+    F = Zs.T @ (S_II @ Zs)
+    assert np.allclose(F, np.diag(mu), atol=1e-9 * mu[-1])
+    assert np.allclose(Zs.T @ Zs, np.eye(5), atol=1e-12)
+    same, none = ritz_reselect(S_II, Zo, Zo.shape[1])
+    assert none is None and same is Zo
+    # a smaller pool never gives smaller Ritz values (the pool spans less)
+    _, mu8 = ritz_reselect(S_II, restricted_basis(Z[:, :8], I)[0], 5)
+    assert np.all(mu8 >= mu * (1 - 1e-12))
