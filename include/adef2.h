@@ -153,6 +153,17 @@ typedef struct {
                            context, ordered against its stream by events;
                            0: kernels launched one by one.  profile = 1
                            launches one by one                             */
+  int32_t ritz_keep;    /* Rayleigh-Ritz reselection (Sec. "Ritz
+                           re-selection"): 0 (default) off; 0 < r: after
+                           restriction and orthonormalisation the kept
+                           columns form a candidate pool, and the r
+                           eigenvectors of the pool's projected operator
+                           with the smallest Ritz values become the
+                           deflation basis (no effect when r >= the kept
+                           columns).  cond(E) is then the ratio of the
+                           largest to the smallest kept Ritz value, and
+                           the deflation rank min(r, k_eff).  The iteration
+                           kernels still read the whole pool.              */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;

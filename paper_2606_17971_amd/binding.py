@@ -46,6 +46,7 @@ class Opts(ctypes.Structure):
         ("w_mode", ctypes.c_int32),
         ("w_boundary", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("ritz_keep", ctypes.c_int32),
     ]
 
 

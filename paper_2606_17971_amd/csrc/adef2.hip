@@ -398,6 +398,7 @@ void launch_coarse(adef2_ctx* c) {
   ca.drop_rel = mat64(c->prec) ? c->o.drop_rel : std::max(c->o.drop_rel, FP32_DROP);
   ca.tau_cond = c->o.tau_cond;
   ca.k_base = c->k_base;
+  ca.ritz_keep = c->o.ritz_keep;
   // with FP32 panels the coarse solve errs by ~u32 cond(E): cap the learned
   // basis' bound so that this stays below 1e-3
   ca.tau_learned = mat64(c->prec) ? c->tau_learned : std::min(c->tau_learned, FP32_COND);
@@ -1048,7 +1049,7 @@ bool valid_opts(const adef2_opts* o) {
          (o->rows_per_thread == 0 || o->rows_per_thread == 1 || o->rows_per_thread == 2 ||
           o->rows_per_thread == 4) &&
          o->w_mode >= 0 && o->w_mode <= 3 && (o->w_boundary == 0 || o->w_boundary == 1) &&
-         (o->graph == 0 || o->graph == 1);
+         (o->graph == 0 || o->graph == 1) && o->ritz_keep >= 0 && o->ritz_keep <= ADEF2_MAX_K;
 }
 
 }  // namespace
@@ -1161,6 +1162,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->w_mode = 0;
   o->w_boundary = 0;
   o->graph = 1;
+  o->ritz_keep = 0;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
@@ -1194,7 +1196,8 @@ int adef2_set_opts(adef2_ctx* c, const adef2_opts* o) {
   const bool prec_changed = o->precision != c->o.precision;
   const bool rpt_changed = o->rows_per_thread != c->o.rows_per_thread;
   const bool precond_changed = o->precond != c->o.precond;
-  const bool coarse_changed = o->tau_cond != c->o.tau_cond || o->drop_rel != c->o.drop_rel;
+  const bool coarse_changed = o->tau_cond != c->o.tau_cond || o->drop_rel != c->o.drop_rel ||
+                              o->ritz_keep != c->o.ritz_keep;
   c->o = *o;
   if (prec_changed || rpt_changed || precond_changed || coarse_changed) c->restricted = false;
   return ADEF2_OK;

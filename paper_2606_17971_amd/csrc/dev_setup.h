@@ -499,6 +499,8 @@ struct CoarseArgs {
   int k_base;            // > 0: columns k_base.. are learned enrichment vectors;
   double tau_learned;    //   if cond(E) exceeds tau_learned (or the setup fails)
                          //   the instance retries with the first k_base columns
+  int ritz_keep;         // 0 < r < kept columns: Rayleigh-Ritz reselection of
+                         //   the r smallest Ritz vectors of the restricted pool
 };
 
 template <int KP>
@@ -513,7 +515,8 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
   __shared__ double rc[K / 2 + 1], rs[K / 2 + 1];
   __shared__ int rp_[K / 2 + 1], rq_[K / 2 + 1];
   __shared__ double red[NWAVE];
-  __shared__ double gdiag[K];
+  __shared__ double gdiag[K];    // diag(G), later the selected Ritz values
+  __shared__ int ord[K];
   const int m = blockIdx.x;
   const int tid = threadIdx.x;
   Inst* S = ca.inst + m;
@@ -601,7 +604,14 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
     ca.Finfo[(size_t)m * KP * KP + bb * KP + aa] = v;
   }
   __syncthreads();
-  for (int e = tid; e < kp * kp; e += TPB) A2[(e / kp) * KP + e % kp] = A0[(e / kp) * KP + e % kp];
+  // Ritz reselection (Sec. "Ritz re-selection"): the eigenvectors of F are
+  // accumulated in A2 (the Cholesky of F is not needed on that path)
+  const bool ritz = ca.ritz_keep > 0 && ca.ritz_keep < kp;
+  const int nx = ritz ? ca.ritz_keep : kp;
+  for (int e = tid; e < kp * kp; e += TPB) {
+    const int aa = e / kp, bb = e % kp;
+    A2[aa * KP + bb] = ritz ? (aa == bb ? 1.0 : 0.0) : A0[aa * KP + bb];
+  }
   for (int j = tid; j < KP; j += TPB) {
     int f = 0;
     for (int a2 = 0; a2 < kp; ++a2) f |= (kidx[a2] == j);
@@ -663,6 +673,11 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
             const double aip = A0[i * KP + p], aiq = A0[i * KP + q];
             A0[i * KP + p] = c * aip - s * aiq;
             A0[i * KP + q] = s * aip + c * aiq;
+            if (ritz) {                                     // V <- V J
+              const double vip = A2[i * KP + p], viq = A2[i * KP + q];
+              A2[i * KP + p] = c * vip - s * viq;
+              A2[i * KP + q] = s * vip + c * viq;
+            }
           }
         }
         __syncthreads();
@@ -687,11 +702,26 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
     cond = (lmin > 0.0) ? lmax / lmin : INFINITY;
   }
   __syncthreads();
+  if (ritz) {
+    // ascending Ritz values; keep the ritz_keep smallest
+    if (tid == 0) {
+      for (int i = 0; i < kp; ++i) ord[i] = i;
+      for (int i = 0; i < nx; ++i) {
+        int best = i;
+        for (int j = i + 1; j < kp; ++j)
+          if (A0[ord[j] * KP + ord[j]] < A0[ord[best] * KP + ord[best]]) best = j;
+        const int t = ord[i]; ord[i] = ord[best]; ord[best] = t;
+      }
+      for (int i = 0; i < nx; ++i) gdiag[i] = A0[ord[i] * KP + ord[i]];
+    }
+    __syncthreads();
+    cond = (gdiag[0] > 0.0) ? gdiag[nx - 1] / gdiag[0] : INFINITY;
+  }
 
   // --- Cholesky F = L L^T (lower, in A2) ---
-  if (tid == 0) s_fail = 0;
+  if (tid == 0) s_fail = ritz ? !(gdiag[0] > 0.0) : 0;
   __syncthreads();
-  for (int j = 0; j < kp; ++j) {
+  for (int j = 0; j < (ritz ? 0 : kp); ++j) {
     if (tid == 0) {
       const double d = A2[j * KP + j];
       if (!(d > 0.0) || !(d < INFINITY)) s_fail = 1;
@@ -716,8 +746,18 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
   if (tid == 0) s_retry = enriched && fallback;
   __syncthreads();
   if (s_retry) continue;     // plain reference basis as fallback (uniform)
-  // --- X = L^{-1} T^T (A0), one column per thread ---
-  if (!fallback) {
+  // --- X = L^{-1} T^T (A0), one column per thread; with Ritz reselection
+  //     X = Lambda_r^{-1/2} Y_r^T T^T (r rows), so C = X^T X is the coarse
+  //     inverse of the selected basis Z T Y_r in pool coordinates ---
+  if (!fallback && ritz) {
+    for (int e = tid; e < nx * kp; e += TPB) {
+      const int i = e / kp, c = e % kp;
+      const int col = ord[i];
+      double s = 0.0;
+      for (int mm = c; mm < kp; ++mm) s += A2[mm * KP + col] * A1[c * KP + mm];
+      A0[i * KP + c] = s / sqrt(gdiag[i]);
+    }
+  } else if (!fallback) {
     for (int c = tid; c < kp; c += TPB) {
       for (int i = 0; i < kp; ++i) {
         double s = A1[c * KP + i];                 // (T^T)[i][c] = T[c][i]
@@ -735,7 +775,7 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
     for (int e = tid; e < kp * kp; e += TPB) {
       const int aa = e / kp, bb = e % kp;
       double s = 0.0;
-      for (int i = 0; i < kp; ++i) s += A0[i * KP + aa] * A0[i * KP + bb];
+      for (int i = 0; i < nx; ++i) s += A0[i * KP + aa] * A0[i * KP + bb];
       Cm[kidx[aa] * KP + kidx[bb]] = s;
     }
   }
