@@ -15,6 +15,9 @@ Spectral Deflation for State Constrained Optimal Control Problems"):
 * restricted reference basis + QR ........ Sec. "Core idea: reference eigenmode
                                            basis" (simple restriction)
 * Ritz reselection from a pool .......... Sec. "Ritz re-selection"
+* POD candidates, safe merge ............. Sec. "Online POD enrichment",
+                                           Sec. "Conditioning-based safe
+                                           merge", Alg. 2
 * coarse Gram E, fallback ................ Sec. "Online deflated solve (A-DEF2)",
                                            Alg. 3 (online workflow), Remark
                                            tau_cond; App. "GPU implementation"
@@ -50,7 +53,8 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 __all__ = [
-    "compact", "restrict", "restricted_basis", "ritz_reselect", "CoarseSpace", "coarse_setup",
+    "compact", "restrict", "restricted_basis", "ritz_reselect", "safe_merge", "CoarseSpace",
+    "coarse_setup",
     "apply_projector", "adef2", "jacobi_pcg", "SolveResult", "solve_instance",
     "two_sum", "two_prod", "dd_residual", "exact_solution", "rel_err",
     "FactoredOp", "restrict_factored", "restricted_operator",
@@ -172,6 +176,30 @@ def ritz_reselect(S_II, Zo: np.ndarray, r: int):
     F = 0.5 * (F + F.T)
     mu, C = np.linalg.eigh(F)            # ascending
     return Zo @ C[:, :r], mu[:r]
+
+
+def safe_merge(S_II, Phi_eig: np.ndarray, Phi_pod: np.ndarray, tau_safe: float = 1e4,
+               tau_dep: float = 1e-10) -> np.ndarray:
+    """Alg. 2: start from the orthonormal eigenmode basis; take the POD
+    candidates in order, orthogonalise each against the current basis (two
+    passes of Gram-Schmidt), skip it when what remains is shorter than
+    tau_dep, otherwise normalise it and accept the trial basis unless
+    cond(Z_trial^T M_II Z_trial) exceeds tau_safe, which ends the merge."""
+    Z = np.asarray(Phi_eig, dtype=np.float64)
+    for j in range(Phi_pod.shape[1]):
+        z = np.array(Phi_pod[:, j], dtype=np.float64)
+        for _ in range(2):
+            z = z - Z @ (Z.T @ z)
+        nz = float(np.linalg.norm(z))
+        if nz < tau_dep:
+            continue
+        trial = np.column_stack([Z, z / nz])
+        Et = trial.T @ np.asarray(S_II @ trial)
+        ev = np.linalg.eigvalsh(0.5 * (Et + Et.T))
+        if not (ev[0] > 0 and ev[-1] / ev[0] <= tau_safe):
+            break
+        Z = trial
+    return Z
 
 
 # ---------------------------------------------------------------------------
@@ -338,19 +366,23 @@ class SolveResult:
 
 def solve_instance(S, Z, mask, b, tol: float, tau_cond: float = 1e10,
                    maxit: int = 100000, x0=None, precond: str = "jacobi",
-                   ritz_keep: int = 0) -> SolveResult:
+                   ritz_keep: int = 0, Phi=None, tau_safe: float = 1e4,
+                   tau_dep: float = 1e-10) -> SolveResult:
     """Restrict, build the coarse space, solve and scatter one instance.
 
     S is an assembled sparse matrix or ("factored", A, alpha, shift).  b and x
     are global (length N); b on the active set is ignored and x there is
     returned as zero.  ``x0`` (global) is an optional warm start.
     ``ritz_keep`` > 0 reselects that many Ritz vectors from the restricted
-    pool (Sec. "Ritz re-selection").
+    pool (Sec. "Ritz re-selection").  ``Phi`` (N x p POD modes) enriches the
+    restricted eigenmodes by the safe merge (Alg. 2) before the coarse setup.
     """
     I, _, n_I = compact(mask)
     S_II, d_I = restricted_operator(S, I)
     b_I = np.asarray(b, dtype=np.float64)[I]
     Zo, kept = restricted_basis(Z, I)
+    if Phi is not None and Phi.shape[1] > 0:
+        Zo = safe_merge(S_II, Zo, restricted_basis(Phi, I)[0], tau_safe, tau_dep)
     Zo, _ = ritz_reselect(S_II, Zo, ritz_keep)
     cs, fallback = coarse_setup(S_II, Zo, tau_cond)
     cs.kept = kept

@@ -552,3 +552,47 @@ def test_ritz_values_interlace_and_diagonalise():
     # a smaller pool never gives smaller Ritz values (the pool spans less)
     _, mu8 = ritz_reselect(S_II, restricted_basis(Z[:, :8], I)[0], 5)
     assert np.all(mu8 >= mu * (1 - 1e-12))
+
+
+# ---------------------------------------------------------------------------
+# safe merge of POD candidates (Alg. 2)
+# ---------------------------------------------------------------------------
+def test_safe_merge_skip_and_break_rules():
+    """Diagonal M with unit-vector candidates, so every cond is known:
+    Phi_eig = [e0] (eigenvalue 1); candidates e1 (2), a vector inside
+    span(e0, e1) (dependent: skipped, merge continues), e2 (1e5: cond 1e5 >
+    tau_safe = 1e4, merge stops), e3 (3: never reached)."""
+    from oracle.solver import safe_merge
+    n = 8
+    d = np.array([1.0, 2.0, 1e5, 3.0, 5.0, 6.0, 7.0, 8.0])
+    M = sp.diags(d).tocsr()
+    e = np.eye(n)
+    Phi_eig = e[:, :1]
+    dep = (e[:, 0] + e[:, 1]) / np.sqrt(2.0)
+    Phi_pod = np.column_stack([e[:, 1], dep, e[:, 2], e[:, 3]])
+    Z = safe_merge(M, Phi_eig, Phi_pod, tau_safe=1e4)
+    assert Z.shape == (n, 2)
+    assert np.allclose(np.abs(Z), e[:, :2])
+    # without the conditioning stop the later candidates are taken
+    Z2 = safe_merge(M, Phi_eig, Phi_pod, tau_safe=1e6)
+    assert Z2.shape == (n, 4)
+    assert np.allclose(Z2.T @ Z2, np.eye(4), atol=1e-14)
+    assert np.allclose(np.abs(Z2[:, 3]), e[:, 3])
+
+
+def test_safe_merge_spans_union_and_keeps_eigen_prefix():
+    from oracle.solver import compact, restricted_basis, restricted_operator, safe_merge
+    n = 15
+    op, spec = _sym_op(n)
+    rng = np.random.default_rng(3)
+    mask = (rng.random(op.N) < 0.2).astype(np.uint8)
+    I, _, _ = compact(mask)
+    S_II, _ = restricted_operator(spec, I)
+    Phi_eig = restricted_basis(gen.sine_modes_2d(n, 6)[0], I)[0]
+    Phi_pod = restricted_basis(rng.standard_normal((op.N, 4)), I)[0]
+    Z = safe_merge(S_II, Phi_eig, Phi_pod, tau_safe=np.inf)
+    assert Z.shape[1] == 10
+    assert np.array_equal(Z[:, :6], Phi_eig)
+    assert np.allclose(Z.T @ Z, np.eye(10), atol=1e-12)
+    U = np.column_stack([Phi_eig, Phi_pod])
+    assert np.linalg.norm(U - Z @ (Z.T @ U)) <= 1e-10
