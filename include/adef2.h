@@ -315,6 +315,22 @@ int adef2_apply_restricted(adef2_ctx *ctx, const double *x, double *y);
 int adef2_coarse_info(adef2_ctx *ctx, double *E, int32_t *kept, int32_t *k_eff,
                       double *cond_E);
 
+/* Online POD enrichment with the conditioning-based safe merge (Sec.
+ * "Online POD enrichment", Sec. "Conditioning-based safe merge", Alg. 2):
+ * the first p POD modes held by ctx (adef2_pod or adef2_set_pod_modes)
+ * become candidate columns after the k reference modes.  At every later
+ * restriction each instance appends them in order (by decreasing singular
+ * value): a candidate numerically inside the span of the columns before it
+ * is skipped, and the first candidate whose trial basis gives
+ * cond(Z^T S_II Z) > tau_safe ends the merge (1e4 in the paper).  For the
+ * causal use the caller keeps the archive of past full-state solutions and
+ * calls adef2_pod + adef2_pod_enrich between batches.  p = 0 restores the
+ * reference modes alone.  Exclusive with the learned enrichment (a solve
+ * with theta ignores the candidates' merge rule).
+ * Returns E_ARG for p < 0, k + p > ADEF2_MAX_K or tau_safe < 1; E_STATE
+ * before set_reference or when fewer than p POD modes are held. */
+int adef2_pod_enrich(adef2_ctx *ctx, int32_t p, double tau_safe);
+
 /* Primal active-set iteration of the state-constrained problem (the
  * appendix algorithm on active-set identification, around eq. (reduced)) for
  * B instances on the reference operator M (a = 1, c = 0): cold start

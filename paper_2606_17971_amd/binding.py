@@ -88,6 +88,7 @@ _sig = {
     "adef2_coarse_info": (ctypes.c_int, [_P, _P, _P, _Pi32, _Pf64]),
     "adef2_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _P]),
     "adef2_active_set_batched": (ctypes.c_int, [_P, _i32, _P, _P, _f64, _f64, _i32, _P, _P, _P, _P, _P]),
+    "adef2_pod_enrich": (ctypes.c_int, [_P, _i32, _f64]),
     "adef2_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "adef2_reset_stats": (ctypes.c_int, [_P]),
     "adef2_last_error": (ctypes.c_char_p, [_P]),
@@ -350,6 +351,10 @@ class Solver:
                                            inner.ctypes.data, status.ctypes.data)
         self._check(rc)
         return dict(y=y, masks=masks, outer=outer, inner_iters=inner, status=status)
+
+    def pod_enrich(self, p: int, tau_safe: float = 1e4):
+        """Append the first p held POD modes as safe-merge candidates (p = 0: none)."""
+        self._check(_lib.adef2_pod_enrich(self._ctx, int(p), float(tau_safe)), allow=(OK,))
 
     def variant(self):
         """(rows_per_thread, w_mode, trial ms) of the last solve."""

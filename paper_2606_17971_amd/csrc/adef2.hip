@@ -64,6 +64,10 @@ struct adef2_ctx {
   double* dia1_64 = nullptr;
   float* dia1_32 = nullptr;
   double alpha_ref = 1.0, shift_ref = 0.0;
+  // POD enrichment: the first k_ref columns of Z are the reference modes;
+  // columns k_safe.. (k_safe > 0) are POD candidates for the safe merge
+  int k_ref = 0, k_safe = 0;
+  double tau_safe = 1e4;
   // current coarse basis: shared reference modes (zs = 0) or a per-instance
   // basis [Z | V_m] of the learned enrichment (zs = KP * N, k_base = k of Z)
   int64_t zs = 0;
@@ -399,6 +403,8 @@ void launch_coarse(adef2_ctx* c) {
   ca.tau_cond = c->o.tau_cond;
   ca.k_base = c->k_base;
   ca.ritz_keep = c->o.ritz_keep;
+  ca.k_safe = c->k_safe;
+  ca.tau_safe = c->tau_safe;
   // with FP32 panels the coarse solve errs by ~u32 cond(E): cap the learned
   // basis' bound so that this stays below 1e-3
   ca.tau_learned = mat64(c->prec) ? c->tau_learned : std::min(c->tau_learned, FP32_COND);
@@ -1376,6 +1382,8 @@ int adef2_set_reference(adef2_ctx* c, int64_t n, const int64_t* row_ptr, const i
   for (int o : c->offs) maxoff = std::max(maxoff, std::abs(o));
   c->H = ((maxoff + 63) / 64) * 64;
   if ((rc = load_modes(c, n, k, Z))) return rc;
+  c->k_ref = k;
+  c->k_safe = 0;
   c->have_ref = true;
   return ADEF2_OK;
 }
@@ -1414,6 +1422,8 @@ int adef2_set_reference_factored(adef2_ctx* c, int64_t n, const int64_t* row_ptr
   c->alpha_ref = alpha;
   c->shift_ref = shift;
   if ((rc = load_modes(c, n, k, Z))) return rc;
+  c->k_ref = k;
+  c->k_safe = 0;
   c->have_ref = true;
   return ADEF2_OK;
 }
@@ -1744,6 +1754,38 @@ int adef2_set_pod_modes(adef2_ctx* c, int32_t p, const double* Phi) {
   HIPCHK(c, hipMemcpyAsync(c->Phi, Phi, sizeof(double) * c->N * p, hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->p = p;
+  return ADEF2_OK;
+}
+
+int adef2_pod_enrich(adef2_ctx* c, int32_t p, double tau_safe) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_ref) return fail(c, ADEF2_E_STATE, "pod_enrich before set_reference");
+  if (p < 0 || (p > 0 && !(tau_safe >= 1.0)) || c->k_ref + p > ADEF2_MAX_K)
+    return fail(c, ADEF2_E_ARG, "pod_enrich: need 0 <= p, k + p <= ADEF2_MAX_K and tau_safe >= 1");
+  if (p > 0 && (!c->Phi || p > c->p)) return fail(c, ADEF2_E_STATE, "pod_enrich: fewer POD modes held than p");
+  const int64_t N = c->N;
+  const int kn = c->k_ref + p;
+  double* Zt = nullptr;
+  int rc;
+  if (kn > 0) {
+    if ((rc = dalloc(c, &Zt, (size_t)N * kn))) return rc;
+    if (c->k_ref > 0)
+      HIPCHK(c, hipMemcpyAsync(Zt, c->Z64, sizeof(double) * N * c->k_ref, hipMemcpyDeviceToDevice, c->st));
+    if (p > 0)
+      HIPCHK(c, hipMemcpyAsync(Zt + (size_t)N * c->k_ref, c->Phi, sizeof(double) * N * p,
+                               hipMemcpyDeviceToDevice, c->st));
+  }
+  drop_graphs(c);
+  HIPCHK(c, hipStreamSynchronize(c->st));     // Zt is read from the old Z64
+  rc = load_modes(c, N, kn, Zt);
+  if (Zt) {
+    hipStreamSynchronize(c->st);
+    hipFree(Zt);
+  }
+  if (rc) return rc;
+  c->k_safe = p > 0 ? c->k_ref : 0;
+  c->tau_safe = tau_safe;
+  c->restricted = false;
   return ADEF2_OK;
 }
 

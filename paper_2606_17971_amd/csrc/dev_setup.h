@@ -501,7 +501,102 @@ struct CoarseArgs {
                          //   the instance retries with the first k_base columns
   int ritz_keep;         // 0 < r < kept columns: Rayleigh-Ritz reselection of
                          //   the r smallest Ritz vectors of the restricted pool
+  int k_safe;            // > 0: columns k_safe.. are POD candidates merged by the
+  double tau_safe;       //   conditioning rule (cond <= tau_safe) of the safe merge
 };
+
+// Cyclic Jacobi on the leading n x n block of the symmetric matrix A (LDS,
+// row stride KP) in parallel round-robin order; V (LDS, may be null)
+// accumulates the rotations (V <- V J).  On return diag(A) holds the
+// eigenvalues.  Every thread of the block calls it with the same n.
+template <int KP>
+__device__ void jacobi_eig(double* A, double* V, int n, double* rc, double* rs, int* rp_, int* rq_,
+                           double* red) {
+  const int tid = threadIdx.x;
+  const int M = (n + 1) & ~1;
+  const int npair = M / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    // off-diagonal mass
+    double off = 0.0, dia = 0.0;
+    for (int e = tid; e < n * n; e += TPB) {
+      const int aa = e / n, bb = e % n;
+      const double v = A[aa * KP + bb];
+      if (aa != bb) off += v * v; else dia += v * v;
+    }
+    off = wave_sum(off);
+    dia = wave_sum(dia);
+    if ((tid & 63) == 0) red[tid >> 6] = off;
+    __syncthreads();
+    double offt = 0.0;
+    for (int w = 0; w < NWAVE; ++w) offt += red[w];
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = dia;
+    __syncthreads();
+    double diat = 0.0;
+    for (int w = 0; w < NWAVE; ++w) diat += red[w];
+    __syncthreads();
+    if (!(offt > 1e-30 * diat)) break;
+    for (int rnd = 0; rnd < M - 1; ++rnd) {
+      for (int t = tid; t < npair; t += TPB) {
+        int p, q;
+        if (t == 0) { p = rnd; q = M - 1; }
+        else { p = (rnd + t) % (M - 1); q = (rnd - t + (M - 1)) % (M - 1); }
+        if (p > q) { const int tt = p; p = q; q = tt; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p * KP + q];
+          if (fabs(apq) > 1e-300) {
+            const double app = A[p * KP + p], aqq = A[q * KP + q];
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        rp_[t] = p; rq_[t] = q; rc[t] = c; rs[t] = s;
+      }
+      __syncthreads();
+      for (int e = tid; e < npair * n; e += TPB) {      // A <- A J (columns)
+        const int t = e / n, i = e % n;
+        const int p = rp_[t], q = rq_[t];
+        if (q < n) {
+          const double c = rc[t], s = rs[t];
+          const double aip = A[i * KP + p], aiq = A[i * KP + q];
+          A[i * KP + p] = c * aip - s * aiq;
+          A[i * KP + q] = s * aip + c * aiq;
+          if (V) {                                        // V <- V J
+            const double vip = V[i * KP + p], viq = V[i * KP + q];
+            V[i * KP + p] = c * vip - s * viq;
+            V[i * KP + q] = s * vip + c * viq;
+          }
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < npair * n; e += TPB) {      // A <- J^T A (rows)
+        const int t = e / n, j = e % n;
+        const int p = rp_[t], q = rq_[t];
+        if (q < n) {
+          const double c = rc[t], s = rs[t];
+          const double apj = A[p * KP + j], aqj = A[q * KP + j];
+          A[p * KP + j] = c * apj - s * aqj;
+          A[q * KP + j] = s * apj + c * aqj;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Largest and smallest diagonal entries of the leading n x n block of A.
+template <int KP>
+__device__ __forceinline__ double diag_cond(const double* A, int n) {
+  double lmin = INFINITY, lmax = -INFINITY;
+  for (int i = 0; i < n; ++i) {
+    lmin = fmin(lmin, A[i * KP + i]);
+    lmax = fmax(lmax, A[i * KP + i]);
+  }
+  return (lmin > 0.0) ? lmax / lmin : INFINITY;
+}
 
 template <int KP>
 __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
@@ -604,6 +699,35 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
     ca.Finfo[(size_t)m * KP * KP + bb * KP + aa] = v;
   }
   __syncthreads();
+  // Safe merge of POD candidates (Sec. "Conditioning-based safe merge",
+  // Alg. 2).  The Cholesky above already orthogonalised every candidate
+  // against the kept columns before it and skipped dependent ones; the
+  // leading q x q block of F is E of the first q kept columns in an
+  // orthonormal basis, and by Cauchy interlacing its condition number
+  // grows with q.  Stopping at the first candidate whose trial basis
+  // exceeds tau_safe is therefore keeping the longest prefix within it,
+  // found by bisection over the candidates.
+  if (ca.k_safe > 0 && ca.k_base == 0 && ca.k_safe < k && kp > 0) {
+    int ne = 0;
+    while (ne < kp && kidx[ne] < ca.k_safe) ++ne;      // kept eigenmode columns
+    if (kp > ne) {
+      for (int e = tid; e < kp * kp; e += TPB) A2[(e / kp) * KP + e % kp] = A0[(e / kp) * KP + e % kp];
+      int lo = ne, hi = kp;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        __syncthreads();
+        for (int e = tid; e < mid * mid; e += TPB) A0[(e / mid) * KP + e % mid] = A2[(e / mid) * KP + e % mid];
+        __syncthreads();
+        jacobi_eig<KP>(A0, nullptr, mid, rc, rs, rp_, rq_, red);
+        const double cm = diag_cond<KP>(A0, mid);
+        if (cm <= ca.tau_safe) lo = mid; else hi = mid - 1;
+      }
+      __syncthreads();
+      kp = lo;
+      for (int e = tid; e < kp * kp; e += TPB) A0[(e / kp) * KP + e % kp] = A2[(e / kp) * KP + e % kp];
+      __syncthreads();
+    }
+  }
   // Ritz reselection (Sec. "Ritz re-selection"): the eigenvectors of F are
   // accumulated in A2 (the Cholesky of F is not needed on that path)
   const bool ritz = ca.ritz_keep > 0 && ca.ritz_keep < kp;
@@ -619,81 +743,10 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
   }
   __syncthreads();
 
-  // --- cyclic Jacobi eigenvalues of F (A0), parallel round-robin ordering ---
+  // --- cyclic Jacobi eigenvalues of F (A0) ---
   double cond = 1.0;
   if (kp > 0) {
-    const int M = (kp + 1) & ~1;
-    const int npair = M / 2;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-      // off-diagonal mass
-      double off = 0.0, dia = 0.0;
-      for (int e = tid; e < kp * kp; e += TPB) {
-        const int aa = e / kp, bb = e % kp;
-        const double v = A0[aa * KP + bb];
-        if (aa != bb) off += v * v; else dia += v * v;
-      }
-      off = wave_sum(off);
-      dia = wave_sum(dia);
-      if ((tid & 63) == 0) red[tid >> 6] = off;
-      __syncthreads();
-      double offt = 0.0;
-      for (int w = 0; w < NWAVE; ++w) offt += red[w];
-      __syncthreads();
-      if ((tid & 63) == 0) red[tid >> 6] = dia;
-      __syncthreads();
-      double diat = 0.0;
-      for (int w = 0; w < NWAVE; ++w) diat += red[w];
-      __syncthreads();
-      if (!(offt > 1e-30 * diat)) break;
-      for (int rnd = 0; rnd < M - 1; ++rnd) {
-        for (int t = tid; t < npair; t += TPB) {
-          int p, q;
-          if (t == 0) { p = rnd; q = M - 1; }
-          else { p = (rnd + t) % (M - 1); q = (rnd - t + (M - 1)) % (M - 1); }
-          if (p > q) { const int tt = p; p = q; q = tt; }
-          double c = 1.0, s = 0.0;
-          if (q < kp) {
-            const double apq = A0[p * KP + q];
-            if (fabs(apq) > 1e-300) {
-              const double app = A0[p * KP + p], aqq = A0[q * KP + q];
-              const double tau = (aqq - app) / (2.0 * apq);
-              const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-              c = 1.0 / sqrt(1.0 + tt * tt);
-              s = tt * c;
-            }
-          }
-          rp_[t] = p; rq_[t] = q; rc[t] = c; rs[t] = s;
-        }
-        __syncthreads();
-        for (int e = tid; e < npair * kp; e += TPB) {      // A <- A J (columns)
-          const int t = e / kp, i = e % kp;
-          const int p = rp_[t], q = rq_[t];
-          if (q < kp) {
-            const double c = rc[t], s = rs[t];
-            const double aip = A0[i * KP + p], aiq = A0[i * KP + q];
-            A0[i * KP + p] = c * aip - s * aiq;
-            A0[i * KP + q] = s * aip + c * aiq;
-            if (ritz) {                                     // V <- V J
-              const double vip = A2[i * KP + p], viq = A2[i * KP + q];
-              A2[i * KP + p] = c * vip - s * viq;
-              A2[i * KP + q] = s * vip + c * viq;
-            }
-          }
-        }
-        __syncthreads();
-        for (int e = tid; e < npair * kp; e += TPB) {      // A <- J^T A (rows)
-          const int t = e / kp, j = e % kp;
-          const int p = rp_[t], q = rq_[t];
-          if (q < kp) {
-            const double c = rc[t], s = rs[t];
-            const double apj = A0[p * KP + j], aqj = A0[q * KP + j];
-            A0[p * KP + j] = c * apj - s * aqj;
-            A0[q * KP + j] = s * apj + c * aqj;
-          }
-        }
-        __syncthreads();
-      }
-    }
+    jacobi_eig<KP>(A0, ritz ? A2 : nullptr, kp, rc, rs, rp_, rq_, red);
     double lmin = INFINITY, lmax = -INFINITY;
     for (int i = 0; i < kp; ++i) {
       lmin = fmin(lmin, A0[i * KP + i]);
