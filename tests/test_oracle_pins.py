@@ -596,3 +596,56 @@ def test_safe_merge_spans_union_and_keeps_eigen_prefix():
     assert np.allclose(Z.T @ Z, np.eye(10), atol=1e-12)
     U = np.column_stack([Phi_eig, Phi_pod])
     assert np.linalg.norm(U - Z @ (Z.T @ U)) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# coarse-grid prolongation (Alg. 4)
+# ---------------------------------------------------------------------------
+def test_prolongation_1d_hat_functions():
+    """Column j of P1D is the coarse hat function sampled at the fine nodes;
+    for n = 2 n_c + 1 it copies coarse values and averages at midpoints."""
+    from oracle.basis import prolongation_1d
+    n, nc = 20, 7
+    P = prolongation_1d(n, nc).toarray()
+    x = np.arange(1, n + 1) / (n + 1)
+    X = np.arange(1, nc + 1) / (nc + 1)
+    H = 1.0 / (nc + 1)
+    hat = np.maximum(0.0, 1.0 - np.abs(x[:, None] - X[None, :]) / H)
+    assert np.allclose(P, hat, atol=1e-14)
+    P2 = prolongation_1d(2 * nc + 1, nc).toarray()
+    for j in range(nc):
+        assert P2[2 * j + 1, j] == 1.0
+    assert np.allclose(P2[0], 0.5 * np.eye(nc)[0])
+    assert np.allclose(P2[2], 0.5 * (np.eye(nc)[0] + np.eye(nc)[1]))
+
+
+def test_prolongation_kron_order_and_accuracy():
+    """2D: P applied to a separable coarse field is the outer product of the
+    1D interpolants (x fastest); prolonged coarse sine modes are within the
+    linear-interpolation error bound of the fine sine modes."""
+    from oracle.basis import coarse_basis, prolongation, prolongation_1d
+    n, nc = 63, 31
+    P1 = prolongation_1d(n, nc)
+    g = np.random.default_rng(2).standard_normal(nc)
+    hh = np.random.default_rng(3).standard_normal(nc)
+    field = np.outer(hh, g).ravel()                     # [y][x], x fastest
+    out = prolongation(n, nc, 2) @ field
+    assert np.allclose(out, np.outer(P1 @ hh, P1 @ g).ravel(), atol=1e-13)
+    Zc = gen.sine_modes_2d(nc, 3)[0]
+    Q, keep = coarse_basis(Zc, n, nc, 2)
+    assert keep.size == 3 and np.allclose(Q.T @ Q, np.eye(3), atol=1e-13)
+    Zf = gen.sine_modes_2d(n, 3)[0]
+    # interpolation error of sin(q pi x) on a grid of width H: (H q pi)^2 / 8
+    H = 1.0 / (nc + 1)
+    bound = 2 * (H * 2 * np.pi) ** 2 / 8
+    assert np.linalg.norm(Zf - Q @ (Q.T @ Zf), 2) <= bound
+
+
+def test_coarse_basis_drops_dependent_column():
+    from oracle.basis import coarse_basis
+    nc, n = 9, 19
+    Zc = gen.sine_modes_2d(nc, 4)[0]
+    Zc = np.column_stack([Zc[:, :2], Zc[:, 0] + 2 * Zc[:, 1], Zc[:, 2:]])
+    Q, keep = coarse_basis(Zc, n, nc, 2)
+    assert list(keep) == [0, 1, 3, 4]
+    assert np.allclose(Q.T @ Q, np.eye(4), atol=1e-13)
