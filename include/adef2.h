@@ -315,6 +315,22 @@ int adef2_apply_restricted(adef2_ctx *ctx, const double *x, double *y);
 int adef2_coarse_info(adef2_ctx *ctx, double *E, int32_t *kept, int32_t *k_eff,
                       double *cond_E);
 
+/* Offline coarse-grid reference basis (Sec. "Coarse-grid eigenmode
+ * prolongation", eq. (prolong), Alg. 4): r coarse-grid modes on the
+ * nc^dim interior grid are interpolated linearly to the n^dim fine grid
+ * (tensor product of the 1D interpolation with zero Dirichlet values,
+ * coarse nodes at (j+1)/(nc+1)) and orthonormalised by two passes of
+ * Cholesky QR; a column whose part orthogonal to the kept columns before it
+ * is at most tau_sv times its own norm is dropped (the paper leaves tau_sv's
+ * value open; 1e-10 is a sensible default).  Needs no reference operator.
+ *   dim 2 or 3; Zc: device f64[r * nc^dim], column-major, lexicographic
+ *   with x fastest; Z_out: device f64[r * n^dim], column-major: the first
+ *   *r_out (host int32, may be NULL) columns are orthonormal, the rest 0.
+ *   1 <= r <= ADEF2_MAX_K, 1 <= nc <= n, n^dim <= 2^31.
+ * Returns E_ARG on bad sizes, E_NOT_SPD if every column is dropped. */
+int adef2_prolong_basis(adef2_ctx *ctx, int32_t dim, int64_t n, int64_t nc, int32_t r,
+                        const double *Zc, double tau_sv, double *Z_out, int32_t *r_out);
+
 /* Online POD enrichment with the conditioning-based safe merge (Sec.
  * "Online POD enrichment", Sec. "Conditioning-based safe merge", Alg. 2):
  * the first p POD modes held by ctx (adef2_pod or adef2_set_pod_modes)

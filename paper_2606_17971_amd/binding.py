@@ -89,6 +89,7 @@ _sig = {
     "adef2_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _P]),
     "adef2_active_set_batched": (ctypes.c_int, [_P, _i32, _P, _P, _f64, _f64, _i32, _P, _P, _P, _P, _P]),
     "adef2_pod_enrich": (ctypes.c_int, [_P, _i32, _f64]),
+    "adef2_prolong_basis": (ctypes.c_int, [_P, _i32, _i64, _i64, _i32, _P, _f64, _P, _Pi32]),
     "adef2_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "adef2_reset_stats": (ctypes.c_int, [_P]),
     "adef2_last_error": (ctypes.c_char_p, [_P]),
@@ -355,6 +356,17 @@ class Solver:
     def pod_enrich(self, p: int, tau_safe: float = 1e4):
         """Append the first p held POD modes as safe-merge candidates (p = 0: none)."""
         self._check(_lib.adef2_pod_enrich(self._ctx, int(p), float(tau_safe)), allow=(OK,))
+
+    def prolong_basis(self, Zc, dim: int, n: int, nc: int, tau_sv: float = 1e-10):
+        """Coarse modes Zc (nc^dim x r) -> orthonormal fine-grid basis (n^dim x r')."""
+        r = int(Zc.shape[1])
+        Zt = _dev(np.asfortranarray(Zc, dtype=np.float64).ravel(order="F"), torch.float64)
+        Nf = n ** dim
+        out = torch.empty(Nf * r, dtype=torch.float64, device="cuda")
+        ro = _i32(0)
+        self._check(_lib.adef2_prolong_basis(self._ctx, int(dim), int(n), int(nc), r, _ptr(Zt), float(tau_sv),
+                                             _ptr(out), ctypes.byref(ro)), allow=(OK,))
+        return out.reshape(r, Nf).T[:, :ro.value]
 
     def variant(self):
         """(rows_per_thread, w_mode, trial ms) of the last solve."""

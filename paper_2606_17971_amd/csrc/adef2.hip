@@ -1565,6 +1565,67 @@ int adef2_apply_restricted(adef2_ctx* c, const double* x, double* y) {
   return ADEF2_OK;
 }
 
+int adef2_prolong_basis(adef2_ctx* c, int32_t dim, int64_t n, int64_t nc, int32_t r, const double* Zc,
+                        double tau_sv, double* Z_out, int32_t* r_out) {
+  if (!c) return ADEF2_E_ARG;
+  if ((dim != 2 && dim != 3) || nc < 1 || n < nc || r < 1 || r > ADEF2_MAX_K || !(tau_sv >= 0.0) || !Zc ||
+      !Z_out)
+    return fail(c, ADEF2_E_ARG, "prolong_basis: need dim 2 or 3, 1 <= nc <= n, 1 <= r <= ADEF2_MAX_K");
+  const double nf_d = std::pow((double)n, dim);
+  if (nf_d > (double)((int64_t)1 << 31)) return fail(c, ADEF2_E_ARG, "prolong_basis: fine grid too large");
+  const int64_t Nf = dim == 2 ? n * n : n * n * n;
+  const int rpb = 4096;
+  const int nrb = (int)cdiv(Nf, rpb);
+  const int nt = (int)cdiv(r, GT);
+  double *Pt = nullptr, *Q1 = nullptr, *part = nullptr, *G = nullptr, *T = nullptr;
+  int *kidx = nullptr, *kpd = nullptr;
+  auto cleanup = [&] {
+    for (void* q : {(void*)Pt, (void*)Q1, (void*)part, (void*)G, (void*)T, (void*)kidx, (void*)kpd})
+      if (q) hipFree(q);
+  };
+  int rc;
+  if ((rc = dalloc(c, &Pt, (size_t)Nf * r)) || (rc = dalloc(c, &Q1, (size_t)Nf * r)) ||
+      (rc = dalloc(c, &part, (size_t)nrb * r * r)) || (rc = dalloc(c, &G, (size_t)r * r)) ||
+      (rc = dalloc(c, &T, (size_t)r * r)) || (rc = dalloc(c, &kidx, (size_t)r)) || (rc = dalloc(c, &kpd, 1))) {
+    cleanup();
+    return rc;
+  }
+  hipLaunchKernelGGL(k_prolong, dim3((unsigned)cdiv(Nf, 256), r), dim3(256), 0, c->st, dim, n, nc, Zc, Pt);
+  // two passes of Cholesky QR; the first drops dependent columns
+  const double* X = Pt;
+  int ncol = r, kp = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_gram_ts, dim3(nrb, nt * nt, 1), dim3(TPB), 0, c->st, Nf, ncol, ncol, X, (int64_t)0, X,
+                       (int64_t)0, (const uint8_t*)nullptr, (int64_t)0, rpb, part);
+    hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)cdiv(ncol * ncol, 256), 1), dim3(256), 0, c->st, nrb, ncol,
+                       ncol, part, G);
+    hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(64), 0, c->st, ncol, G, pass == 0 ? tau_sv : 0.0, T, kidx,
+                       kpd);
+    int kph = 0;
+    if (hipMemcpyAsync(&kph, kpd, sizeof(int), hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess) {
+      cleanup();
+      return fail(c, ADEF2_E_HIP, "prolong_basis: device error");
+    }
+    if (kph == 0 || (pass == 1 && kph != ncol)) {
+      cleanup();
+      return fail(c, ADEF2_E_NOT_SPD, "prolong_basis: prolonged modes are numerically dependent");
+    }
+    double* Y = pass == 0 ? Q1 : Z_out;
+    hipLaunchKernelGGL(k_apply_tri, dim3((unsigned)cdiv(Nf, 256), kph), dim3(256), 0, c->st, Nf, ncol, kidx, T,
+                       X, Y);
+    X = Q1;
+    ncol = kph;
+    kp = kph;
+  }
+  if (kp < r) HIPCHK(c, hipMemsetAsync(Z_out + (size_t)kp * Nf, 0, sizeof(double) * Nf * (r - kp), c->st));
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  cleanup();
+  if (r_out) *r_out = kp;
+  return ADEF2_OK;
+}
+
 int adef2_active_set_batched(adef2_ctx* c, int32_t B, const double* y_d, const double* psi, double tau,
                              double tol, int32_t max_outer, double* y, uint8_t* masks_out, int32_t* outer,
                              int32_t* inner_iters, int32_t* status) {

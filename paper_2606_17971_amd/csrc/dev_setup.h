@@ -307,6 +307,112 @@ __global__ void k_bnd_outer(OpGeom op, const double* dia64, const uint8_t* masks
 }
 
 // ---------------------------------------------------------------------------
+// Offline coarse-grid reference basis (Sec. "Coarse-grid eigenmode
+// prolongation", eq. (prolong), Alg. 4)
+// ---------------------------------------------------------------------------
+// 1D linear interpolation weights of fine node i: coarse nodes at positions
+// (j+1)/(nc+1), zero values at 0 and 1.  Integer arithmetic locates the
+// interval exactly.  lo/hi are coarse indices (-1: boundary, weight unused).
+__device__ __forceinline__ void hat_weights(int64_t i, int64_t n, int64_t nc, int64_t* lo, double* wlo,
+                                            int64_t* hi, double* whi) {
+  const int64_t num = (i + 1) * (nc + 1);
+  const int64_t j = num / (n + 1);                 // left node, 0 = boundary
+  const double w = (double)(num - j * (n + 1)) / (double)(n + 1);
+  *lo = (j >= 1 && j <= nc) ? j - 1 : -1;
+  *wlo = 1.0 - w;
+  *hi = (j + 1 >= 1 && j + 1 <= nc && w != 0.0) ? j : -1;
+  *whi = w;
+}
+
+// Pt[q][i] = (P Zc[q])(i) with P the tensor product of the 1D operator
+// (lexicographic, x fastest); dim 2 or 3
+__global__ void k_prolong(int dim, int64_t n, int64_t nc, const double* Zc, double* Pt) {
+  const int q = blockIdx.y;
+  const int64_t Nf = dim == 2 ? n * n : n * n * n;
+  const int64_t Nc = dim == 2 ? nc * nc : nc * nc * nc;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Nf) return;
+  int64_t lo[3], hi[3];
+  double wl[3], wh[3];
+  int64_t rem = i;
+  for (int d = 0; d < dim; ++d) {
+    hat_weights(rem % n, n, nc, &lo[d], &wl[d], &hi[d], &wh[d]);
+    rem /= n;
+  }
+  const double* z = Zc + (size_t)q * Nc;
+  double acc = 0.0;
+  const int ncorner = 1 << dim;
+  for (int cidx = 0; cidx < ncorner; ++cidx) {
+    int64_t off = 0, stride = 1;
+    double wt = 1.0;
+    bool ok = true;
+    for (int d = 0; d < dim; ++d) {
+      const bool up = (cidx >> d) & 1;
+      const int64_t node = up ? hi[d] : lo[d];
+      ok = ok && node >= 0;
+      wt *= up ? wh[d] : wl[d];
+      off += (node >= 0 ? node : 0) * stride;
+      stride *= nc;
+    }
+    if (ok) acc += wt * z[off];
+  }
+  Pt[(size_t)q * Nf + i] = acc;
+}
+
+// Cholesky of the Gram G (r x r, row-major, r <= 64) with column dropping:
+// column j is kept when its part orthogonal to the kept columns before it
+// exceeds tau times its own norm.  T = R^-1 of the kept columns (row-major,
+// stride r), their indices kidx and count kp.  One thread does the O(r^3)
+// work in LDS (an offline step).
+__global__ void k_chol_drop(int r, const double* G, double tau, double* T, int* kidx, int* kp_out) {
+  __shared__ double A[64 * 64];
+  __shared__ double Ti[64 * 64];
+  __shared__ int kid[64];
+  if (threadIdx.x != 0) return;
+  for (int e = 0; e < r * r; ++e) A[e] = G[e];
+  int kp = 0;
+  for (int j = 0; j < r; ++j) {
+    const double g0 = G[j * r + j];
+    const double d = A[j * r + j];
+    if (g0 > 0.0 && d > tau * tau * g0 && d == d) {
+      const double rjj = sqrt(d);
+      for (int l = j + 1; l < r; ++l) A[j * r + l] /= rjj;
+      A[j * r + j] = rjj;
+      for (int l = j + 1; l < r; ++l)
+        for (int mm = l; mm < r; ++mm) A[l * r + mm] -= A[j * r + l] * A[j * r + mm];
+      kid[kp++] = j;
+    } else {
+      for (int l = 0; l < r; ++l) A[j * r + l] = 0.0;
+    }
+  }
+  // R of the kept columns (upper) and its inverse by back substitution
+  for (int c = 0; c < kp; ++c) {
+    for (int i = 0; i < kp; ++i) Ti[i * 64 + c] = 0.0;
+    Ti[c * 64 + c] = 1.0 / A[kid[c] * r + kid[c]];
+    for (int i = c - 1; i >= 0; --i) {
+      double sum = 0.0;
+      for (int mm = i + 1; mm <= c; ++mm) sum += A[kid[i] * r + kid[mm]] * Ti[mm * 64 + c];
+      Ti[i * 64 + c] = -sum / A[kid[i] * r + kid[i]];
+    }
+  }
+  for (int a = 0; a < kp; ++a)
+    for (int b = 0; b < kp; ++b) T[a * r + b] = Ti[a * 64 + b];
+  for (int a = 0; a < kp; ++a) kidx[a] = kid[a];
+  *kp_out = kp;
+}
+
+// Y[a] = sum_{b <= a} X[kidx[b]] T[b][a]  (columns of length Nf, T stride r)
+__global__ void k_apply_tri(int64_t Nf, int r, const int* kidx, const double* T, const double* X,
+                            double* Y) {
+  const int a = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Nf) return;
+  double acc = 0.0;
+  for (int b = 0; b <= a; ++b) acc += X[(size_t)kidx[b] * Nf + i] * T[b * r + a];
+  Y[(size_t)a * Nf + i] = acc;
+}
+
+// ---------------------------------------------------------------------------
 // Primal active-set outer loop (state-constrained problems): the instances
 // still iterating are addressed through idx (instance of batch slot j).
 // ---------------------------------------------------------------------------
