@@ -331,6 +331,25 @@ int adef2_coarse_info(adef2_ctx *ctx, double *E, int32_t *kept, int32_t *k_eff,
 int adef2_prolong_basis(adef2_ctx *ctx, int32_t dim, int64_t n, int64_t nc, int32_t r,
                         const double *Zc, double tau_sv, double *Z_out, int32_t *r_out);
 
+/* Reference eigenmodes on the GPU (the offline eigensolve of Sec. "Core
+ * idea: reference eigenmode basis" and of the coarse grid in Alg. 4, which
+ * the paper runs with ARPACK): the r smallest eigenpairs of the reference
+ * operator by block inverse iteration with Rayleigh-Ritz.  Each step solves
+ * S Y = X for the r columns with adef2_solve_batched (empty active sets, the
+ * context's options and reference modes as deflation, tolerance inner_tol),
+ * projects on span(Y) (E = Y^T X = Y^T S Y, G = Y^T Y) and takes the Ritz
+ * vectors as the next block, until every relative residual
+ * ||S z_j - lambda_j z_j|| / lambda_j (with S z_j from the solve) is <= tol.
+ *   X0: device f64[r*n] start block (column-major, full rank);
+ *   Z_out: device f64[r*n] orthonormal Ritz vectors, ascending Ritz values;
+ *   lambda_out, resid_out: host f64[r] (may be NULL); iters_out: host int32.
+ * The Ritz values of a block of r converge at the rate lambda_j /
+ * lambda_{r+1}: take a few more columns than needed.  Returns W_MAXIT when
+ * max_iter steps end first, E_NOT_SPD if the block loses rank. */
+int adef2_reference_eigs(adef2_ctx *ctx, int32_t r, const double *X0, int32_t max_iter, double tol,
+                         double inner_tol, double *Z_out, double *lambda_out, double *resid_out,
+                         int32_t *iters_out);
+
 /* Online POD enrichment with the conditioning-based safe merge (Sec.
  * "Online POD enrichment", Sec. "Conditioning-based safe merge", Alg. 2):
  * the first p POD modes held by ctx (adef2_pod or adef2_set_pod_modes)

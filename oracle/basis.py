@@ -21,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-__all__ = ["prolongation_1d", "prolongation", "coarse_basis"]
+__all__ = ["prolongation_1d", "prolongation", "coarse_basis", "reference_eigs"]
 
 
 def prolongation_1d(n: int, nc: int) -> sp.csr_matrix:
@@ -58,3 +58,16 @@ def coarse_basis(Zc: np.ndarray, n: int, nc: int, dim: int, tau_sv: float = 1e-1
     if len(keep) < Pt.shape[1]:
         Q, _ = np.linalg.qr(Pt[:, keep], mode="reduced")
     return Q, np.asarray(keep, dtype=np.int64)
+
+
+def reference_eigs(spec, r: int):
+    """The r smallest eigenpairs of the full reference operator by its plain
+    definition (dense symmetric eigensolver; small grids only).  spec is an
+    assembled matrix or ("factored", A, alpha, shift)."""
+    if isinstance(spec, tuple) and spec and spec[0] == "factored":
+        _, A, alpha, shift = spec
+        S = (alpha * (A.T @ A) + shift * sp.identity(A.shape[0])).toarray()
+    else:
+        S = spec.toarray()
+    lam, U = np.linalg.eigh(0.5 * (S + S.T))
+    return lam[:r], U[:, :r]

@@ -90,6 +90,7 @@ _sig = {
     "adef2_active_set_batched": (ctypes.c_int, [_P, _i32, _P, _P, _f64, _f64, _i32, _P, _P, _P, _P, _P]),
     "adef2_pod_enrich": (ctypes.c_int, [_P, _i32, _f64]),
     "adef2_prolong_basis": (ctypes.c_int, [_P, _i32, _i64, _i64, _i32, _P, _f64, _P, _Pi32]),
+    "adef2_reference_eigs": (ctypes.c_int, [_P, _i32, _P, _i32, _f64, _f64, _P, _P, _P, _Pi32]),
     "adef2_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "adef2_reset_stats": (ctypes.c_int, [_P]),
     "adef2_last_error": (ctypes.c_char_p, [_P]),
@@ -367,6 +368,19 @@ class Solver:
         self._check(_lib.adef2_prolong_basis(self._ctx, int(dim), int(n), int(nc), r, _ptr(Zt), float(tau_sv),
                                              _ptr(out), ctypes.byref(ro)), allow=(OK,))
         return out.reshape(r, Nf).T[:, :ro.value]
+
+    def reference_eigs(self, X0, max_iter: int = 100, tol: float = 1e-8, inner_tol: float = 1e-12):
+        """Smallest eigenpairs of the reference operator from the start block X0 (n x r)."""
+        r = int(X0.shape[1])
+        Xt = _dev(np.asfortranarray(X0, dtype=np.float64).ravel(order="F"), torch.float64)
+        Z = torch.empty(self.n * r, dtype=torch.float64, device="cuda")
+        lam = np.zeros(r)
+        res = np.zeros(r)
+        it = _i32(0)
+        rc = _lib.adef2_reference_eigs(self._ctx, r, _ptr(Xt), int(max_iter), float(tol), float(inner_tol),
+                                       _ptr(Z), lam.ctypes.data, res.ctypes.data, ctypes.byref(it))
+        self._check(rc, allow=(OK, W_MAXIT))
+        return dict(Z=Z.reshape(r, self.n).T, lam=lam, resid=res, iters=it.value, status=rc)
 
     def variant(self):
         """(rows_per_thread, w_mode, trial ms) of the last solve."""

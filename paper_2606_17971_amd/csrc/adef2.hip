@@ -1626,6 +1626,82 @@ int adef2_prolong_basis(adef2_ctx* c, int32_t dim, int64_t n, int64_t nc, int32_
   return ADEF2_OK;
 }
 
+int adef2_reference_eigs(adef2_ctx* c, int32_t r, const double* X0, int32_t max_iter, double tol,
+                         double inner_tol, double* Z_out, double* lambda_out, double* resid_out,
+                         int32_t* iters_out) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_ref) return fail(c, ADEF2_E_STATE, "reference_eigs before set_reference");
+  if (r < 1 || r > ADEF2_MAX_K || !X0 || !Z_out || max_iter < 1 || !(tol > 0.0) || !(inner_tol > 0.0))
+    return fail(c, ADEF2_E_ARG, "reference_eigs: need 1 <= r <= ADEF2_MAX_K, max_iter >= 1, tol > 0");
+  const int64_t N = c->N;
+  const int rpb = 4096;
+  const int nrb = (int)cdiv(N, rpb);
+  double *X = nullptr, *Y = nullptr, *Zb = nullptr, *D = nullptr, *part = nullptr, *G = nullptr, *E = nullptr;
+  double *T1 = nullptr, *F = nullptr, *V = nullptr, *ev = nullptr, *T = nullptr, *lam = nullptr, *Gd = nullptr;
+  uint8_t* mk = nullptr;
+  int* fl = nullptr;
+  auto cleanup = [&] {
+    for (void* q : {(void*)X, (void*)Y, (void*)Zb, (void*)D, (void*)part, (void*)G, (void*)E, (void*)T1, (void*)F,
+                    (void*)V, (void*)ev, (void*)T, (void*)lam, (void*)Gd, (void*)mk, (void*)fl})
+      if (q) hipFree(q);
+  };
+  const size_t NR = (size_t)N * r, RR = (size_t)r * r;
+  int rc;
+  if ((rc = dalloc(c, &X, NR)) || (rc = dalloc(c, &Y, NR)) || (rc = dalloc(c, &Zb, NR)) || (rc = dalloc(c, &D, NR)) ||
+      (rc = dalloc(c, &part, (size_t)nrb * RR)) || (rc = dalloc(c, &G, RR)) || (rc = dalloc(c, &E, RR)) ||
+      (rc = dalloc(c, &T1, RR)) || (rc = dalloc(c, &F, RR)) || (rc = dalloc(c, &V, RR)) ||
+      (rc = dalloc(c, &ev, (size_t)r)) || (rc = dalloc(c, &T, RR)) || (rc = dalloc(c, &lam, (size_t)r)) ||
+      (rc = dalloc(c, &Gd, RR)) || (rc = dalloc(c, &mk, NR)) || (rc = dalloc(c, &fl, 1))) {
+    cleanup();
+    return rc;
+  }
+  HIPCHK(c, hipMemcpyAsync(X, X0, sizeof(double) * NR, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipMemsetAsync(mk, 0, NR, c->st));        // no active points: the full operator
+  auto gram = [&](const double* A, const double* Bm, double* out) {
+    hipLaunchKernelGGL(k_gram_ts, dim3(nrb, 1, 1), dim3(TPB), 0, c->st, N, r, r, A, (int64_t)0, Bm, (int64_t)0,
+                       (const uint8_t*)nullptr, (int64_t)0, rpb, part);
+    hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)cdiv(RR, 256), 1), dim3(256), 0, c->st, nrb, r, r, part, out);
+  };
+  std::vector<int32_t> st(r), its(r);
+  std::vector<double> gd(RR), lh(r), res(r, INFINITY);
+  int it = 0;
+  const dim3 gv((unsigned)cdiv(N, 256), r);
+  for (it = 1; it <= max_iter; ++it) {
+    rc = adef2_solve_batched(c, r, mk, X, nullptr, nullptr, nullptr, inner_tol, Y, its.data(), st.data(), nullptr,
+                             nullptr, nullptr, nullptr);
+    if (rc < 0) { cleanup(); return rc; }
+    gram(Y, Y, G);
+    gram(Y, X, E);
+    hipLaunchKernelGGL(k_rr_reduce, dim3(1), dim3(64), 0, c->st, r, G, E, T1, F, fl);
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(1024), 0, c->st, r, F, V, ev);
+    hipLaunchKernelGGL(k_rr_finish, dim3(1), dim3(64), 0, c->st, r, T1, V, ev, T, lam);
+    hipLaunchKernelGGL(k_ritz_vectors, gv, dim3(256), 0, c->st, N, r, T, lam, X, Y, Zb, D);
+    gram(D, D, Gd);
+    int flh = 0;
+    HIPCHK(c, hipMemcpyAsync(&flh, fl, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(gd.data(), Gd, sizeof(double) * RR, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(lh.data(), lam, sizeof(double) * r, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (flh) { cleanup(); return fail(c, ADEF2_E_NOT_SPD, "reference_eigs: the iterated block lost rank"); }
+    double worst = 0.0;
+    for (int j = 0; j < r; ++j) {
+      res[j] = std::sqrt(std::max(gd[(size_t)j * r + j], 0.0)) / std::fabs(lh[j]);
+      worst = std::max(worst, res[j]);
+    }
+    std::swap(X, Zb);
+    if (worst <= tol) break;
+  }
+  const bool conv = it <= max_iter;
+  if (!conv) it = max_iter;
+  HIPCHK(c, hipMemcpyAsync(Z_out, X, sizeof(double) * NR, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (lambda_out) for (int j = 0; j < r; ++j) lambda_out[j] = lh[j];
+  if (resid_out) for (int j = 0; j < r; ++j) resid_out[j] = res[j];
+  if (iters_out) *iters_out = it;
+  cleanup();
+  return conv ? ADEF2_OK : ADEF2_W_MAXIT;
+}
+
 int adef2_active_set_batched(adef2_ctx* c, int32_t B, const double* y_d, const double* psi, double tau,
                              double tol, int32_t max_outer, double* y, uint8_t* masks_out, int32_t* outer,
                              int32_t* inner_iters, int32_t* status) {

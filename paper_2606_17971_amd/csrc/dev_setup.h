@@ -413,6 +413,94 @@ __global__ void k_apply_tri(int64_t Nf, int r, const int* kidx, const double* T,
 }
 
 // ---------------------------------------------------------------------------
+// Reference eigenmodes by block inverse iteration with Rayleigh-Ritz: with
+// S Y = X (one batched solve per step) the projected pair is E = Y^T X,
+// G = Y^T Y, and S Z = X T for the Ritz vectors Z = Y T.
+// ---------------------------------------------------------------------------
+// Cholesky G = R^T R, T1 = R^-1 (upper) and F = T1^T sym(E) T1, all r x r
+// row-major (r <= 64).  One thread in LDS (r^3 work per step); *fail = 1
+// when G is not numerically positive definite.
+__global__ void k_rr_reduce(int r, const double* G, const double* E, double* T1g, double* F, int* fail) {
+  __shared__ double A[64 * 64];
+  __shared__ double Ti[64 * 64];
+  if (threadIdx.x != 0) return;
+  for (int e = 0; e < r * r; ++e) A[e] = G[e];
+  int bad = 0;
+  for (int j = 0; j < r && !bad; ++j) {
+    const double d = A[j * r + j];
+    if (!(d > 0.0) || !(d < INFINITY)) { bad = 1; break; }
+    const double rjj = sqrt(d);
+    for (int l = j + 1; l < r; ++l) A[j * r + l] /= rjj;
+    A[j * r + j] = rjj;
+    for (int l = j + 1; l < r; ++l)
+      for (int mm = l; mm < r; ++mm) A[l * r + mm] -= A[j * r + l] * A[j * r + mm];
+  }
+  *fail = bad;
+  if (bad) return;
+  for (int c = 0; c < r; ++c) {
+    for (int i = 0; i < r; ++i) Ti[i * 64 + c] = 0.0;
+    Ti[c * 64 + c] = 1.0 / A[c * r + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double sum = 0.0;
+      for (int mm = i + 1; mm <= c; ++mm) sum += A[i * r + mm] * Ti[mm * 64 + c];
+      Ti[i * 64 + c] = -sum / A[i * r + i];
+    }
+  }
+  // A <- sym(E) T1, then F = T1^T A
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) {
+      double sum = 0.0;
+      for (int mm = 0; mm <= b; ++mm) sum += 0.5 * (E[a * r + mm] + E[mm * r + a]) * Ti[mm * 64 + b];
+      A[a * 64 + b] = sum;
+    }
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) {
+      double sum = 0.0;
+      for (int mm = 0; mm <= a; ++mm) sum += Ti[mm * 64 + a] * A[mm * 64 + b];
+      F[a * r + b] = sum;
+    }
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) T1g[a * r + b] = Ti[a * 64 + b];
+}
+
+// Ritz values in ascending order and T = T1 V with the columns permuted alike
+__global__ void k_rr_finish(int r, const double* T1, const double* V, const double* ev, double* T, double* lam) {
+  __shared__ int ord[64];
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < r; ++i) ord[i] = i;
+  for (int i = 0; i < r; ++i) {
+    int best = i;
+    for (int j = i + 1; j < r; ++j)
+      if (ev[ord[j]] < ev[ord[best]]) best = j;
+    const int t = ord[i]; ord[i] = ord[best]; ord[best] = t;
+  }
+  for (int j = 0; j < r; ++j) {
+    lam[j] = ev[ord[j]];
+    for (int a = 0; a < r; ++a) {
+      double sum = 0.0;
+      for (int b = a; b < r; ++b) sum += T1[a * r + b] * V[b * r + ord[j]];
+      T[a * r + j] = sum;
+    }
+  }
+}
+
+// Z = Y T (Ritz vectors) and D = X T - Z diag(lam) = S Z - Z diag(lam)
+__global__ void k_ritz_vectors(int64_t N, int r, const double* T, const double* lam, const double* X,
+                               const double* Y, double* Z, double* D) {
+  const int j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double z = 0.0, sx = 0.0;
+  for (int b = 0; b < r; ++b) {
+    const double t = T[b * r + j];
+    z += Y[(size_t)b * N + i] * t;
+    sx += X[(size_t)b * N + i] * t;
+  }
+  Z[(size_t)j * N + i] = z;
+  D[(size_t)j * N + i] = sx - lam[j] * z;
+}
+
+// ---------------------------------------------------------------------------
 // Primal active-set outer loop (state-constrained problems): the instances
 // still iterating are addressed through idx (instance of batch slot j).
 // ---------------------------------------------------------------------------

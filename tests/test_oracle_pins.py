@@ -649,3 +649,19 @@ def test_coarse_basis_drops_dependent_column():
     Q, keep = coarse_basis(Zc, n, nc, 2)
     assert list(keep) == [0, 1, 3, 4]
     assert np.allclose(Q.T @ Q, np.eye(4), atol=1e-13)
+
+
+def test_reference_eigs_closed_form():
+    """2d_sym operator: eigenvalues 1 + alpha' (s_i + s_j)^2 with the sine
+    modes as eigenvectors (Sec. "Analytical eigenmodes on tensor-product
+    grids")."""
+    from oracle.basis import reference_eigs
+    n = 15
+    op, spec = _sym_op(n)
+    lam, U = reference_eigs(spec, 6)
+    Z, pairs, _ = gen.sine_modes_2d(n, 6)
+    h = 1.0 / (n + 1)
+    s = lambda q: 4.0 * np.sin(q * np.pi * h / 2.0) ** 2
+    ref = np.array(sorted(1.0 + op.alpha * (s(i) + s(j)) ** 2 for i, j in pairs))
+    assert np.allclose(lam, ref, rtol=1e-12)
+    assert np.linalg.norm(Z - U @ (U.T @ Z)) <= 1e-10
