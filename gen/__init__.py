@@ -543,6 +543,66 @@ def ocp_2d_sym(n: int = 127, B: int = 4, alpha: float = 1e-3, active: float = 0.
     return ocp_2d("2d_sym", n, B, alpha, active)
 
 
+# ---------------------------------------------------------------------------
+# Space-time extension (App. "Space-time extension"): implicit Euler in all
+# at once form.  F is block lower bidiagonal with diagonal blocks
+# D = I/dt + L and subdiagonal blocks -I/dt (y^0 = 0), M_st = alpha F^T F + I
+# is block tridiagonal; unknowns ordered time-major (step n holds entries
+# n N_s .. (n+1) N_s - 1).  The desired state follows the paper's space-time
+# recipe in 2D: a temporal ramp (1 - exp(-t/0.2)) times four Gaussians
+# (sigma 0.12) rotating with theta about the centre as in 2d_asym, t_n = n dt,
+# T = 1.  The bound is fixed at 0.7 max y_unc at the mid parameter (the
+# space-time protocol; not target-calibrated), y_unc by a sparse direct solve.
+# ---------------------------------------------------------------------------
+def spacetime_forward(L: sp.spmatrix, n_t: int, T: float = 1.0) -> sp.csr_matrix:
+    dt = T / n_t
+    Ns = L.shape[0]
+    I = sp.identity(Ns, format="csr")
+    sub = sp.diags([np.ones(n_t - 1)], [-1], shape=(n_t, n_t))
+    F = sp.kron(sp.identity(n_t), I / dt + L) - sp.kron(sub, I / dt)
+    return canonical_csr(F)
+
+
+def kron_basis(Z_s: np.ndarray, n_t: int) -> np.ndarray:
+    """Z_st = I_nt (x) Z_s (eq. kron_basis), dense N_s n_t x r n_t."""
+    return np.kron(np.eye(n_t), Z_s)
+
+
+def const_time_basis(Z_s: np.ndarray, n_t: int) -> np.ndarray:
+    """The constant-in-time lift 1_nt (x) Z_s."""
+    return np.kron(np.ones((n_t, 1)), Z_s)
+
+
+def spacetime_2d(n: int = 15, n_t: int = 10, B: int = 2, alpha: float = 1e-3, T: float = 1.0) -> OCPWorkload:
+    h = 1.0 / (n + 1)
+    L = canonical_csr(laplacian_2d(n) / (h * h))
+    F = spacetime_forward(L, n_t, T)
+    Ns = n * n
+    N = Ns * n_t
+    op = Operator(n=n, dim=2, B=canonical_csr(alpha * (F.T @ F)), shift=1.0, name=f"st2d_n{n}_t{n_t}",
+                  A=F, alpha=alpha)
+    dt = T / n_t
+    x1, x2 = _coords(n, 2)
+    r, sig = math.sqrt(0.08), 0.12
+
+    def y_d(theta):
+        g = np.zeros(Ns)
+        for k in range(4):
+            ang = 5.0 * math.pi / 4.0 + k * math.pi / 2.0 + theta
+            c1, c2 = 0.5 + r * math.cos(ang), 0.5 + r * math.sin(ang)
+            g += np.exp(-((x1 - c1) ** 2 + (x2 - c2) ** 2) / (2.0 * sig * sig))
+        ramp = 1.0 - np.exp(-dt * np.arange(1, n_t + 1) / 0.2)
+        return np.kron(ramp, g)
+
+    M = (alpha * (F.T @ F) + sp.identity(N)).tocsc()
+    y_unc = spla.spsolve(M, y_d(math.pi / 4))
+    psi_val = 0.7 * float(np.max(y_unc))
+    # the four Gaussians repeat under a rotation by pi/2: sample [0, pi/2)
+    params = np.linspace(0.0, math.pi / 2, B, endpoint=False) if B > 1 else np.array([math.pi / 4])
+    return OCPWorkload(name=f"st2d_n{n}_t{n_t}_B{B}", op=op, y_d=np.stack([y_d(t) for t in params]),
+                       psi=np.full((B, N), psi_val), params=params)
+
+
 MLP_DIMS = (4, 128, 128, 512)
 
 

@@ -665,3 +665,53 @@ def test_reference_eigs_closed_form():
     ref = np.array(sorted(1.0 + op.alpha * (s(i) + s(j)) ** 2 for i, j in pairs))
     assert np.allclose(lam, ref, rtol=1e-12)
     assert np.linalg.norm(Z - U @ (U.T @ Z)) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# space-time extension (App. "Space-time extension", eq. kron_basis)
+# ---------------------------------------------------------------------------
+def test_spacetime_forward_is_implicit_euler_and_blocks_match():
+    """F y = u for y marched by implicit Euler from y^0 = 0; M_st = alpha
+    F^T F + I has the block structure of the paper's figure: diagonal
+    blocks alpha (D^T D + B^T B) + I except the last (alpha D^T D + I),
+    off-diagonal blocks -alpha D^T B / -alpha B^T D, zero beyond."""
+    import scipy.sparse.linalg as spla
+    n, n_t, T, alpha = 6, 5, 1.0, 1e-3
+    h = 1.0 / (n + 1)
+    L = gen.laplacian_2d(n) / (h * h)
+    F = gen.spacetime_forward(L, n_t, T)
+    Ns, dt = n * n, T / n_t
+    u = np.random.default_rng(4).standard_normal(Ns * n_t)
+    D = (sp.identity(Ns) / dt + L).tocsc()
+    y = np.zeros(Ns * n_t)
+    prev = np.zeros(Ns)
+    for k in range(n_t):
+        prev = spla.spsolve(D, u[k * Ns:(k + 1) * Ns] + prev / dt)
+        y[k * Ns:(k + 1) * Ns] = prev
+    assert np.linalg.norm(F @ y - u) <= 1e-10 * np.linalg.norm(u)
+    M = (alpha * (F.T @ F) + sp.identity(Ns * n_t)).toarray()
+    Dd = D.toarray()
+    Bb = np.eye(Ns) / dt
+    blk = lambda i, j: M[i * Ns:(i + 1) * Ns, j * Ns:(j + 1) * Ns]
+    for i in range(n_t):
+        diag = alpha * (Dd.T @ Dd + (Bb.T @ Bb if i < n_t - 1 else 0)) + np.eye(Ns)
+        assert np.allclose(blk(i, i), diag, rtol=1e-12, atol=1e-12 * np.abs(diag).max())
+        if i + 1 < n_t:
+            assert np.allclose(blk(i, i + 1), -alpha * Dd.T @ Bb, atol=1e-9)
+            assert np.allclose(blk(i + 1, i), -alpha * Bb.T @ Dd, atol=1e-9)
+        for j in range(i + 2, n_t):
+            assert not blk(i, j).any() and not blk(j, i).any()
+
+
+def test_kron_basis_structure():
+    n, n_t, r = 5, 4, 3
+    Zs = gen.sine_modes_2d(n, r)[0]
+    Zst = gen.kron_basis(Zs, n_t)
+    assert Zst.shape == (n * n * n_t, r * n_t)
+    assert np.allclose(Zst.T @ Zst, np.eye(r * n_t), atol=1e-14)
+    # column k r + j is mode j at time step k only
+    Ns = n * n
+    assert np.array_equal(Zst[2 * Ns:3 * Ns, 2 * r + 1], Zs[:, 1])
+    assert not Zst[:2 * Ns, 2 * r + 1].any() and not Zst[3 * Ns:, 2 * r + 1].any()
+    C = gen.const_time_basis(Zs, n_t)
+    assert np.allclose(C, Zst @ np.kron(np.ones((n_t, 1)), np.eye(r)))
