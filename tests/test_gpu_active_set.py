@@ -83,3 +83,38 @@ def test_active_set_outer_cap_and_arguments(lib, ocp):
     with pytest.raises(lib.Adef2Error):
         s.active_set_batched(w.y_d, w.psi, tau=-1.0)
     s.close()
+
+
+def test_active_set_unconstrained_closed_form(lib):
+    """psi far above the state: one outer step, empty active set, and y equal
+    to the discrete closed form a / (1 + alpha' mu^2) sin(pi x1) sin(pi x2)."""
+    n = 63
+    w = gen.ocp_2d_sym(n=n, B=3)
+    case("active set with an inactive bound: closed form, FP64 and FP32_REFINE")
+    h = 1.0 / (n + 1)
+    mu = 8.0 * np.sin(np.pi * h / 2.0) ** 2
+    base = w.y_d[0] / w.params[0]
+    for prec in (lib.FP64, lib.FP32_REFINE):
+        s = lib.Solver(precision=prec)
+        s.set_reference_factored(w.op.A, w.op.alpha, w.op.shift, gen.sine_modes_2d(n, K)[0])
+        out = s.active_set_batched(w.y_d, np.full_like(w.psi, 10.0), tau=TAU, tol=TOL)
+        Y = out["y"].cpu().numpy()
+        assert np.all(out["outer"] == 1) and not out["masks"].cpu().numpy().any()
+        for m, a in enumerate(w.params):
+            ref = a / (1.0 + w.op.alpha * mu * mu) * base
+            e = oracle.rel_err(Y[m], ref)
+            print(f"   prec={prec} a={a:.3f} e_rel={e:.2e} status={out['status'][m]}", flush=True)
+            assert e <= 1e-8
+        s.close()
+
+
+def test_active_set_single_instance_fp32_refine(lib, ocp):
+    w, Z, ref = ocp
+    case("active set, one instance, FP32_REFINE")
+    s = _solver(lib, w, Z, lib.FP32_REFINE, "factored")
+    out = s.active_set_batched(w.y_d[2:3], w.psi[2:3], tau=TAU, tol=TOL)
+    y_ref, a_ref, k_ref, _ = ref[2]
+    assert out["outer"][0] == k_ref
+    assert np.array_equal(out["masks"].cpu().numpy()[0], a_ref)
+    assert oracle.rel_err(out["y"].cpu().numpy()[0], y_ref) <= 1e-8
+    s.close()
