@@ -72,3 +72,26 @@ def test_cold_cg_and_active_fractions_at_100(name):
     assert abs(np.mean(frac) - ref["a_mean"]) <= 0.01
     assert abs(min(frac) - ref["a_min"]) <= 0.01
     assert abs(max(frac) - ref["a_max"]) <= 0.01
+
+
+def test_3d_inputs_exact_modes_and_unconstrained_state():
+    """3D: the grid sine modes are orthonormal eigenvectors of the 7-point
+    stencil with eigenvalues s_i + s_j + s_l, and the DST solve satisfies
+    M y_unc = y_d."""
+    n = 9
+    K = gen.laplacian_3d(n)
+    Z, trip = gen.sine_modes_3d(n, 10)
+    h = 1.0 / (n + 1)
+    s = lambda q: 4.0 * np.sin(q * np.pi * h / 2.0) ** 2
+    lam = np.array([s(i) + s(j) + s(l) for i, j, l in trip])
+    assert np.allclose(K @ Z, Z * lam, atol=1e-12)
+    assert np.allclose(Z.T @ Z, np.eye(10), atol=1e-13)
+    assert np.all(np.diff(lam) >= -1e-15)
+    w = gen.ocp_3d_obstacle(n=n, B=3)
+    spec = ("factored", w.op.A, w.op.alpha, w.op.shift)
+    for m in range(3):
+        y = gen.ocp_unconstrained_3d(n, w.y_d[m])
+        r = apply_full(spec, y) - w.y_d[m]
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(w.y_d[m])
+    # theta = 0 and pi/2 give the same source set (the square maps onto itself)
+    assert np.allclose(w.y_d[0], w.y_d[2], atol=1e-12)
