@@ -65,6 +65,10 @@ def parse():
                          "prints no benchmark line")
     ap.add_argument("--counter-maxit", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pod-merge", action="store_true",
+                    help="skip the POD safe-merge comparator arm (reported, never the headline)")
+    ap.add_argument("--pod-merge-p", type=int, default=8, help="POD candidates of the comparator arm")
+    ap.add_argument("--tau-safe", type=float, default=1e4)
     ap.add_argument("--cpu-iters", type=int, default=200,
                     help="oracle iterations timed for the CPU baseline sample")
     return ap.parse_args()
@@ -153,6 +157,34 @@ def fit_enrichment(solver, args, lib):
                           "plain_iters_mean": float(np.mean(o_plain["iters"])),
                           "learned_iters_mean": float(np.mean(o_lrn["iters"])),
                           "learned_used": int(np.sum(o_lrn["learned"])), "kept": bool(keep)}}, Phi
+
+
+def pod_merge_arm(args, lib, op, Z, Phi, masks, bs, prec, tune, t_head, head_iters):
+    """The paper's non-learned enrichment as a comparator: the first p POD
+    modes of the same snapshots appended after the reference modes and
+    merged per instance by the conditioning rule (tau_safe), solving the
+    timed instances on a solver of its own."""
+    import torch
+    s = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
+    s.set_reference_factored(op.A, op.alpha, op.shift, Z)
+    s.set_pod_modes(Phi[:, :args.pod_merge_p])
+    s.pod_enrich(args.pod_merge_p, args.tau_safe)
+    s.solve_batched(masks, bs, 1e-6)                 # kernel variants are tuned on the first solve
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    o = s.solve_batched(masks, bs, args.tol)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s.close()
+    it = np.asarray(o["iters"])
+    B = masks.shape[0]
+    print(f"[bench] POD safe-merge arm: {t:.2f}s ({B / t:.3f} solves/s), iterations {it.mean():.0f} "
+          f"vs {head_iters.mean():.0f}", file=sys.stderr, flush=True)
+    return {"candidates": args.pod_merge_p, "tau_safe": args.tau_safe, "solves_per_s": round(B / t, 4),
+            "vs_headline": round(t_head / t, 3), "iters_mean": float(it.mean()),
+            "headline_iters_mean": float(head_iters.mean()),
+            "cond_E_max": float(np.max(o["cond_E"])),
+            "relres_true_max": float(np.asarray(o["relres_true"]).max())}
 
 
 def measured_traffic(kernel: str):
@@ -254,6 +286,13 @@ def main():
                    "cond_E_max": float(np.max(ob["cond_E"]))}
         print(f"[bench] batched (reference modes only) done ({t_b:.2f}s)", file=sys.stderr, flush=True)
 
+    pod_arm = None
+    if Phi is not None and not args.no_pod_merge:
+        try:
+            pod_arm = pod_merge_arm(args, lib, op, w.Z, Phi, masks, bs, prec, tune, t_head, head_iters)
+        except Exception as e:            # reported, never fatal for the headline
+            pod_arm = {"error": str(e)}
+
     plain = None
     if not args.no_plain:
         ps = lib.Solver(precision=lib.FP64)
@@ -344,6 +383,7 @@ def main():
         "iters_per_instance": np.asarray(out["iters"]).tolist(),
         "learned_fit": learned,
         "batched_reference_modes": batched,
+        "pod_merge": pod_arm,
         "relres_true_max": float(head_rel.max()),
         "plain": plain,
         "speedup_vs_plain": (round(value / plain["solves_per_s"], 3) if plain else None),
