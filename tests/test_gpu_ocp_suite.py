@@ -41,7 +41,7 @@ def printed():
             if line.startswith("#") or not line.strip():
                 continue
             t = line.split()
-            rows[t[0]] = dict(cold300=int(t[3]), red40=float(t[10]))
+            rows[t[0]] = dict(cold300=int(t[3]), cold500=int(t[5]), red40=float(t[10]))
     return rows
 
 
@@ -114,3 +114,36 @@ def test_suite_300_replicates_printed_counts(lib, name):
           f"{red:.1f} % (per-instance mean {red_inst:.1f} %; printed {ref['red40']:.0f} %)", flush=True)
     assert abs(mc - ref["cold300"]) <= 0.02 * ref["cold300"]
     assert abs(red - ref["red40"]) <= 10.0
+
+
+@pytest.mark.parametrize("name", gen.OCP_2D)
+def test_suite_500_cold_counts(lib, name):
+    """The paper's largest 2D grid: mean cold Jacobi-PCG iterations over 30
+    instances on the final inactive sets, within 2 % of the printed counts.
+    The iteration cap is the paper's 1e5 (App. "CG stopping criterion"); on
+    2d_nonsep the instance with the smallest active set reaches it, and the
+    printed mean is matched (to 0.01 %) only with that capped count in it,
+    so a cold solve may end at the cap, with exactly 1e5 iterations."""
+    n, B = 500, 30
+    ref = printed()[name]
+    case(f"{name} {n}^2 x {B}: cold iteration counts vs the printed table")
+    w = gen.ocp_2d(name, n=n, B=B)
+    s = lib.Solver(precision=lib.FP64)
+    s.set_reference_factored(w.op.A, w.op.alpha, w.op.shift, gen.sine_modes_2d(n, 40)[0])
+    out = s.active_set_batched(w.y_d, w.psi, tau=w.tau, tol=TOL, max_outer=20)
+    s.close()
+    masks = out["masks"].cpu().numpy()
+    b = _rhs(w, masks)
+    c = lib.Solver(precision=lib.FP64)
+    c.set_reference_factored(w.op.A, w.op.alpha, w.op.shift, None)
+    cold = c.solve_batched(masks, b, TOL)
+    c.close()
+    mc = float(np.mean(cold["iters"]))
+    frac = masks.mean(axis=1)
+    print(f"   outer {sorted(set(out['outer'].tolist()))}, active {frac.mean():.3f} "
+          f"[{frac.min():.3f}, {frac.max():.3f}], cold mean {mc:.1f} (printed {ref['cold500']})", flush=True)
+    assert np.all(out["status"] == 0)
+    capped = cold["status"] == lib.W_MAXIT
+    assert np.all((cold["status"] == 0) | capped)
+    assert np.all(cold["iters"][capped] == 100000)
+    assert abs(mc - ref["cold500"]) <= 0.02 * ref["cold500"]
