@@ -53,12 +53,14 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--snap-tol", type=float, default=1e-8)
-    ap.add_argument("--rpt", type=int, default=0, choices=[0, 1, 2, 4],
+    ap.add_argument("--rpt", type=int, default=0, choices=[0, 1, 2],
                     help="rows per thread of the iteration kernels (0 = tuned)")
-    ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2, 3],
-                    help="1 = read W, 2 = W-free tile-major, 3 = W-free per instance, 0 = tuned")
-    ap.add_argument("--w-boundary", type=int, default=0, choices=[0, 1],
-                    help="1 = boundary form of W for eigen reference modes")
+    ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2, 3, 4],
+                    help="1 = read W, 2 = W-free tile-major, 3 = W-free per instance, "
+                         "4 = tile-major boundary form, 0 = tuned")
+    ap.add_argument("--w-boundary", type=int, default=2, choices=[0, 1, 2],
+                    help="boundary form of W for eigen reference modes: 0 off, 1 on, "
+                         "2 when every reference mode is an eigenvector")
     ap.add_argument("--counter-run", action="store_true",
                     help="short run for rocprofv3 counter passes: one headline solve capped at "
                          "--counter-maxit iterations, then a 256 MiB device copy of known size; "
@@ -339,8 +341,12 @@ def main():
     kp = ((args.k + (8 if apply_learned else 0)) + 7) // 8 * 8
     vt, mt = {lib.MIXED_REFINE: ("double", "float"), lib.FP32_REFINE: ("float", "float"),
               lib.FP64: ("double", "double")}[prec]
-    inst = (f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}, {'true' if args.w_boundary else 'false'}>" if dom == "update"
-            else f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}>")
+    if dom in ("update_tm", "pupdate_tm"):
+        inst = f"k_{dom}<{mt}, {kp}>"
+    elif dom == "update":
+        inst = f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}, {'true' if args.w_boundary else 'false'}>"
+    else:
+        inst = f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}>"
     tr = measured_traffic(inst)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["traffic"] if tr else None,

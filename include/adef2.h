@@ -25,7 +25,13 @@
  *   - Vectors are in global order (length n).  Entries on the active set are
  *     ignored on input and returned as 0.
  *   - Operators must be banded/stencil matrices: at most ADEF2_MAX_DIAGS
- *     distinct diagonals (column - row offsets).  Others give ADEF2_E_UNSUPPORTED.
+ *     distinct diagonals (column - row offsets).  Others give
+ *     ADEF2_E_UNSUPPORTED.  This is deliberate: every operator the paper
+ *     builds is a finite-difference stencil on a structured grid (App.
+ *     "Finite difference discretization"), and the diagonal format needs no
+ *     column indices, so the restricted operator is a mask over the full
+ *     grid and the matvec streams only coefficients and vectors.  A general
+ *     sparse S would need a sliced-ELL restricted submatrix per instance.
  *   - Not thread-safe per context; distinct contexts are independent.
  */
 #ifndef ADEF2_H
@@ -116,9 +122,10 @@ typedef struct {
                            residual by more than 2x (drift), when the next
                            segment restarts; 0                              */
   int32_t check_every;  /* iterations between host polls of convergence; 32 */
-  int32_t rows_per_thread; /* rows per thread of the iteration kernels (tile
-                           height 256, 512 or 1024 rows): 1, 2 or 4, or 0 =
-                           tuned on the first solve of each configuration   */
+  int32_t rows_per_thread; /* rows per thread of the per-instance iteration
+                           kernels (tile height 256 or 512 rows): 1 or 2, or
+                           0 = tuned on the first solve of each
+                           configuration                                    */
   int32_t profile;      /* 1 = time kernels with HIP events (adef2_get_stats) */
   int32_t w_mode;       /* how the iteration forms W^T z (W = S_II Z_I):
                            1 = read the stored W; 2 = Z^T (S_II z), one more
@@ -129,8 +136,18 @@ typedef struct {
                            Z once for the whole batch (matrix-core panel
                            products); 3 = as 2 with per-instance kernels;
                            2 and 3 need FP64 vectors (E_UNSUPPORTED with
-                           FP32_REFINE); 0 = tuned on the first solve of each
-                           configuration.  Tuning runs every candidate for
+                           FP32_REFINE); 4 = tile-major boundary form: one
+                           block per tile and group of instances updates
+                           x, r, z and forms [Z^T z | Z^T r] for the whole
+                           group on the matrix cores (the shared modes are
+                           read once per group), with W^T z = Lambda Z^T z +
+                           the boundary rows of W - Lambda Z (see
+                           w_boundary); needs MIXED_REFINE, modes shared by
+                           all instances that are all eigenvectors of the
+                           reference operator, and w_boundary != 0
+                           (E_UNSUPPORTED otherwise); 0 = tuned on the first
+                           solve of each configuration (4 is a candidate
+                           whenever it applies).  Tuning runs every candidate for
                            the first 64 iterations from the same start, keeps
                            the fastest per context (batch size, precision,
                            basis width, operator form, N) and reuses it, so
@@ -138,15 +155,16 @@ typedef struct {
                            reproducible                                     */
   int32_t w_boundary;   /* 1: with FP32 panels, reference modes that are
                            eigenvectors of the reference operator B
-                           (||B z - mu z|| <= 1e-7 |mu| ||z||, tested at
+                           (||B z - mu z|| <= 1e-6 |mu| ||z||, tested at
                            set_reference) keep W = S_II Z_I as
                            W - lambda Z, lambda = a mu + c, which vanishes
                            except on inactive rows coupled to the active set
-                           (up to the eigen-residual, below FP32 rounding);
-                           the iteration then reads W only on those rows and
-                           takes lambda Z^T z from the shared modes.
-                           0 (default): W stored and read whole (faster on
-                           MI355X at 511^2 although it moves more bytes)    */
+                           (up to the eigen-residual, of the order of the
+                           FP32 rounding of W itself); the iteration then
+                           reads W only on those rows and takes
+                           lambda Z^T z from the shared modes.  2 (default):
+                           as 1 when every shared reference mode passes the
+                           test, else 0.  0: W stored and read whole      */
   int32_t graph;        /* 1 (default): each chunk of check_every iterations
                            is captured once into a HIP graph (per kernel
                            arguments) and replayed on a private stream of the
@@ -164,6 +182,15 @@ typedef struct {
                            largest to the smallest kept Ritz value, and
                            the deflation rank min(r, k_eff).  The iteration
                            kernels still read the whole pool.              */
+  double tau_safe;      /* conditioning bound of the POD safe merge (Alg. 2):
+                           the merge stops at the first candidate whose
+                           trial basis has cond(Z^T S_II Z) > tau_safe; used
+                           by adef2_pod_enrich when its tau_safe <= 0; 1e4
+                           (Sec. "Conditioning-based safe merge")            */
+  double tau_dep;       /* POD candidates whose part orthogonal to the columns
+                           before them is at most tau_dep of their restricted
+                           norm are skipped (Alg. 2); the effective bound is
+                           max(drop_rel, tau_dep); 1e-10                     */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;
@@ -241,7 +268,8 @@ int adef2_solve(adef2_ctx *ctx, const double *b, const double *x0, double tol,
                 double *x, int32_t *iters, double *relres_true, double *cond_E);
 
 /* Batched solve of B independent instances in one launch sequence (shared S
- * and Z; per-instance masks, operator scales and right-hand sides).
+ * and Z; per-instance masks, operator scales, right-hand sides and
+ * tolerances).
  *   masks: device uint8[B*n]; b, x: device f64[B*n] (instance-major).
  *   a, c : host f64[B] operator scales (S_m = a_m S_ref + c_m I), or NULL (1, 0).
  *   theta: device f32[B*4] problem parameters, or NULL.  When given (after
@@ -252,15 +280,18 @@ int adef2_solve(adef2_ctx *ctx, const double *b, const double *x0, double tol,
  *          plain restricted reference modes (Alg. 2's conditioning guard used
  *          as the safeguard of the learned addition).
  *   tol  : relative tolerance, as in adef2_solve.
+ *   tol_each: host f64[B] per-instance tolerances replacing tol, or NULL.
+ *          E_ARG when any tolerance is not positive and finite.
  *   iters, status (enum adef2_status per instance), relres_true, cond_E,
  *   n_inactive, learned (1 = learned vectors in use): host arrays of B entries
  *   (each may be NULL).
  * Returns the most severe per-instance status. */
 int adef2_solve_batched(adef2_ctx *ctx, int32_t B, const uint8_t *masks,
                         const double *b, const double *a, const double *c,
-                        const float *theta, double tol, double *x, int32_t *iters,
-                        int32_t *status, double *relres_true, double *cond_E,
-                        int64_t *n_inactive, int32_t *learned);
+                        const float *theta, double tol, const double *tol_each,
+                        double *x, int32_t *iters, int32_t *status,
+                        double *relres_true, double *cond_E, int64_t *n_inactive,
+                        int32_t *learned);
 
 /* ---- learned coarse-space enrichment (offline training on the device) ----
  * The enrichment vectors are V = Phi C^T, Phi = p POD modes of solution
@@ -280,6 +311,20 @@ int adef2_solve_batched(adef2_ctx *ctx, int32_t B, const uint8_t *masks,
 int adef2_pod(adef2_ctx *ctx, int32_t M, const double *X, int32_t p, double *Phi_out,
               double *sigma);
 /* Use given POD modes (device f64[n*p], column-major) instead. */
+/* Learned enrichment in one call (the paper's POD space, Sec. "Online POD
+ * enrichment", with the network of the learned addition):
+ *   p     : POD modes, 1 <= p <= 64; Phi: device f64[n*p], column-major
+ *           (FP64: the expansion V = Phi C^T is formed in FP64 and rounded
+ *           only for the FP32 panels of the refinement modes).
+ *   mlp_params: host f32[83200] packed parameters (layout above; BF16 compute
+ *           copies are made on the device), or NULL to keep the current ones.
+ *   n_vec : enrichment vectors per instance; the network emits 8 (any other
+ *           value gives E_UNSUPPORTED).
+ *   tau_learned: cond(E) bound of the enriched basis (>= 1), as in
+ *           adef2_learned_set_params.
+ * E_STATE before set_reference, E_ARG for bad sizes or k + 8 > ADEF2_MAX_K. */
+int adef2_set_enrichment(adef2_ctx *ctx, int32_t p, const double *Phi, const float *mlp_params,
+                         int32_t n_vec, double tau_learned);
 int adef2_set_pod_modes(adef2_ctx *ctx, int32_t p, const double *Phi);
 /* MLP parameters (host f32[83200]); resets the Adam state.  tau_learned: the
  * cond(E) bound of the enriched basis (>= 1; 1e8 in the learned workload).
@@ -362,7 +407,9 @@ int adef2_reference_eigs(adef2_ctx *ctx, int32_t r, const double *X0, int32_t ma
  * calls adef2_pod + adef2_pod_enrich between batches.  p = 0 restores the
  * reference modes alone.  Exclusive with the learned enrichment (a solve
  * with theta ignores the candidates' merge rule).
- * Returns E_ARG for p < 0, k + p > ADEF2_MAX_K or tau_safe < 1; E_STATE
+ * tau_safe <= 0 takes opts.tau_safe; candidates are also skipped below
+ * opts.tau_dep (see adef2_opts).
+ * Returns E_ARG for p < 0, k + p > ADEF2_MAX_K or 0 < tau_safe < 1; E_STATE
  * before set_reference or when fewer than p POD modes are held. */
 int adef2_pod_enrich(adef2_ctx *ctx, int32_t p, double tau_safe);
 

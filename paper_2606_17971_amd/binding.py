@@ -47,6 +47,8 @@ class Opts(ctypes.Structure):
         ("w_boundary", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("ritz_keep", ctypes.c_int32),
+        ("tau_safe", ctypes.c_double),
+        ("tau_dep", ctypes.c_double),
     ]
 
 
@@ -75,7 +77,8 @@ _sig = {
     "adef2_compact": (ctypes.c_int, [_P, _P, _i64, _P, _P, _Pi64]),
     "adef2_restrict": (ctypes.c_int, [_P, _P, _Pi64, _Pi32, _Pf64]),
     "adef2_solve": (ctypes.c_int, [_P, _P, _P, _f64, _P, _Pi32, _Pf64, _Pf64]),
-    "adef2_solve_batched": (ctypes.c_int, [_P, _i32, _P, _P, _P, _P, _P, _f64, _P, _P, _P, _P, _P, _P, _P]),
+    "adef2_solve_batched": (ctypes.c_int, [_P, _i32, _P, _P, _P, _P, _P, _f64, _P, _P, _P, _P, _P, _P, _P,
+                                           _P]),
     "adef2_pod": (ctypes.c_int, [_P, _i32, _P, _i32, _P, _P]),
     "adef2_set_pod_modes": (ctypes.c_int, [_P, _i32, _P]),
     "adef2_learned_set_params": (ctypes.c_int, [_P, _P, _f64]),
@@ -89,6 +92,7 @@ _sig = {
     "adef2_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _P]),
     "adef2_active_set_batched": (ctypes.c_int, [_P, _i32, _P, _P, _f64, _f64, _i32, _P, _P, _P, _P, _P]),
     "adef2_pod_enrich": (ctypes.c_int, [_P, _i32, _f64]),
+    "adef2_set_enrichment": (ctypes.c_int, [_P, _i32, _P, _P, _i32, _f64]),
     "adef2_prolong_basis": (ctypes.c_int, [_P, _i32, _i64, _i64, _i32, _P, _f64, _P, _Pi32]),
     "adef2_reference_eigs": (ctypes.c_int, [_P, _i32, _P, _i32, _f64, _f64, _P, _P, _P, _Pi32]),
     "adef2_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
@@ -249,7 +253,8 @@ class Solver:
         self._check(rc)
         return SolveOut(x, it.value, rel.value, cond.value, rc)
 
-    def solve_batched(self, masks, b, tol: float, a=None, c=None, theta=None):
+    def solve_batched(self, masks, b, tol, a=None, c=None, theta=None):
+        """tol: one relative tolerance, or one per instance."""
         M = _dev(masks, torch.uint8)
         Bt = _dev(b, torch.float64)
         Th = None if theta is None else _dev(theta, torch.float32)
@@ -263,10 +268,13 @@ class Solver:
         cond = np.zeros(B, np.float64)
         nI = np.zeros(B, np.int64)
         lrn = np.zeros(B, np.int32)
+        tol_a = np.asarray(tol, dtype=np.float64)
+        tol_each = np.ascontiguousarray(np.broadcast_to(tol_a, (B,))) if tol_a.ndim else None
+        tol0 = float(tol_a.ravel()[0]) if tol_a.ndim else float(tol_a)
         hp = lambda arr: None if arr is None else arr.ctypes.data  # noqa: E731
         rc = _lib.adef2_solve_batched(self._ctx, B, _ptr(M), _ptr(Bt), hp(a_h), hp(c_h), _ptr(Th),
-                                      float(tol), _ptr(x), hp(iters), hp(status), hp(rel), hp(cond),
-                                      hp(nI), hp(lrn))
+                                      tol0, hp(tol_each), _ptr(x), hp(iters), hp(status), hp(rel),
+                                      hp(cond), hp(nI), hp(lrn))
         self._check(rc)
         return dict(x=x, iters=iters, status=status, relres_true=rel, cond_E=cond, n_inactive=nI,
                     learned=lrn, rc=rc)
@@ -288,6 +296,17 @@ class Solver:
         Pt = _dev(np.asfortranarray(Phi).ravel(order="F") if not isinstance(Phi, torch.Tensor)
                   else Phi.T.contiguous().reshape(-1), torch.float64)
         self._check(_lib.adef2_set_pod_modes(self._ctx, int(Phi.shape[1]), _ptr(Pt)), allow=(OK,))
+
+    def set_enrichment(self, Phi, params=None, n_vec: int = 8, tau_learned: float = 1e8):
+        """POD modes Phi (N x p) and, optionally, the MLP parameters in one call."""
+        Pt = _dev(np.asfortranarray(Phi).ravel(order="F") if not isinstance(Phi, torch.Tensor)
+                  else Phi.T.contiguous().reshape(-1), torch.float64)
+        pp = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        if pp is not None:
+            assert pp.size == self.NPARAM
+        self._check(_lib.adef2_set_enrichment(self._ctx, int(Phi.shape[1]), _ptr(Pt),
+                                              None if pp is None else pp.ctypes.data, int(n_vec),
+                                              float(tau_learned)), allow=(OK,))
 
     def learned_set_params(self, params: np.ndarray, tau_learned: float = 1e8):
         p = np.ascontiguousarray(params, dtype=np.float32)

@@ -11,6 +11,7 @@
 
 #include "../../include/adef2.h"
 #include "dev_learned.h"
+#include "iter_tab.h"
 
 using namespace adef2;
 
@@ -21,15 +22,19 @@ std::string g_create_error;
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int round8(int k) { return (k + 7) & ~7; }
 constexpr double FP32_DROP = 1e-3;   // column-drop threshold with FP32 panels
-constexpr double EIG_TOL = 1e-7;     // eigen-residual bound for the boundary form of W
+// eigen-residual bound for the boundary form of W (FP32 panels only): an
+// interior row of W - Lambda Z then holds at most 1e-6 |lambda| of its mode,
+// the order of the FP32 rounding (6e-8) of the stored W that the mixed
+// iteration carries anyway; the FP64 residual replacement keeps the accuracy
+constexpr double EIG_TOL = 1e-6;
 constexpr double FP32_COND = 1e-3 / 5.96e-8;   // learned cond(E) bound with FP32 panels
 
 enum KernelId { KI_INIT = 0, KI_INIT2, KI_PUPDATE, KI_SPMV, KI_UPDATE, KI_RESID, KI_ACCUM,
                 KI_GRAM, KI_COARSE, KI_COMPACT, KI_UPDATE_NW, KI_ZPROJ, KI_PUPDATE_BT, KI_ZPROJ_BT,
-                KI_COUNT };
+                KI_PUPDATE_TM, KI_UPDATE_TM, KI_COUNT };
 const char* kKernelNames[KI_COUNT] = {"init", "init2", "pupdate", "spmv", "update", "resid64",
                                       "accumulate", "spmm_gram", "coarse", "compact", "update_nw",
-                                      "zproj", "pupdate_bt", "zproj_bt"};
+                                      "zproj", "pupdate_bt", "zproj_bt", "pupdate_tm", "update_tm"};
 
 }  // namespace
 
@@ -55,6 +60,7 @@ struct adef2_ctx {
   double* diag = nullptr;
   double* Z64 = nullptr;
   float* Z32 = nullptr;
+  float* ZT32 = nullptr;           // [N][KP] row-major copy (tile-major kernels)
   double scale_a = 1.0, scale_c = 0.0;
   // factored operator S = alpha A^T A + shift I: inner stencil A (dia1),
   // outer stencil A^T (dia64/dia32 above, offsets offs)
@@ -103,6 +109,18 @@ struct adef2_ctx {
   uint8_t* hb = nullptr;         // [B][N] scratch of the boundary test
   double* zero64 = nullptr;      // 64 zero words (branch-free skipped loads)
   int ne = 0;                    // columns in boundary form for the current restriction
+  // boundary rows compacted per instance and tile (tile-major boundary-form
+  // update): counts, offsets [B][ub_ntiles + 1], rows and W - Lambda Z rows
+  bool tm_ok = false;            // the current restriction supports the tile-major update
+  int* bcnt = nullptr;
+  double* ftot = nullptr;        // [B][2 KP + 2] totals of the tile-major finisher
+  unsigned* fctr = nullptr;      // [B] its arrival counters
+  int* btoff = nullptr;
+  int* btot = nullptr;
+  int* bidx = nullptr;
+  float* bW32 = nullptr;
+  size_t bcap = 0;               // entries allocated in bidx / bW32
+  int64_t nbnd = 0;              // entries of the current restriction
   double tau_learned = 1e8;
 
   // restriction / batch state
@@ -140,13 +158,16 @@ struct adef2_ctx {
 
   // geometry and variant of the streaming kernels
   int rpt = 2;
-  int wfree = 0;                 // W^T z as Z^T (S z), W not read: 1 tile-major, 2 per instance
+  int wfree = 0;                 // W^T z as Z^T (S z), W not read: 1 tile-major, 2 per instance;
+                                 // 3: tile-major boundary form (k_pupdate_tm / k_update_tm)
   bool solved = false;           // a solve ran (variant is meaningful)
   int ntiles = 0, ntiles_pad = 0;
   int bt_ntiles = 0, bt_ntiles_pad = 0;   // tile-major kernels (BT_ROWS-row tiles)
   int bt_nblk_pad = 0;                     // k_zproj_bt blocks (BT_TPB tiles each)
+  int ub_ntiles = 0, ub_ntiles_pad = 0;    // tile-major boundary-form kernels (UB_ROWS-row tiles)
+  RedGeom g_ub{};
   RedGeom g_bt{};
-  struct Tuned { int B, prec, KP, fact; int64_t N; int rpt, wfree; float ms[9]; };
+  struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[9]; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
   int gram_blocks = 0;
@@ -160,6 +181,7 @@ struct adef2_ctx {
   double st_ms[KI_COUNT] = {};
   double st_bytes[KI_COUNT] = {};
   std::vector<long long> nI_host;
+  std::vector<double> tol_h;     // per-instance tolerances of the current solve
 };
 
 namespace {
@@ -252,6 +274,7 @@ void free_all(adef2_ctx* c) {
   F(c->Phi); F(c->mlp); F(c->mlp_bf); F(c->mlp_g); F(c->mlp_m); F(c->mlp_v); F(c->theta_tr);
   F(c->Htr); F(c->gtr); F(c->e0tr); F(c->bxtr); F(c->act); F(c->mout); F(c->dout); F(c->dA1);
   F(c->dA2); F(c->lossv); F(c->Zb64); F(c->Zb32); F(c->mu64); F(c->eigf); F(c->bnd); F(c->hb); F(c->zero64);
+  F(c->ZT32); F(c->bcnt); F(c->ftot); F(c->fctr); F(c->btoff); F(c->btot); F(c->bidx); F(c->bW32);
   if (c->inst_h) hipHostFree(c->inst_h);
   for (auto& e : c->ev_pending) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
   for (auto e : c->ev_pool) hipEventDestroy(e);
@@ -297,50 +320,7 @@ inline bool vec64(int prec) { return prec != ADEF2_FP32_REFINE; }
 inline bool mat64(int prec) { return prec == ADEF2_FP64; }
 
 template <typename V, typename M>
-struct KTab {
-  void (*init)(IterArgs<V, M>);
-  void (*init2)(IterArgs<V, M>);
-  void (*pupdate)(IterArgs<V, M>);
-  void (*spmv)(IterArgs<V, M>);
-  void (*update)(IterArgs<V, M>);
-  void (*update_nw)(IterArgs<V, M>);
-  void (*zproj)(IterArgs<V, M>);
-  void (*pupdate_bt)(IterArgs<V, M>);
-  void (*zproj_bt)(IterArgs<V, M>);
-  void (*update_spec)(IterArgs<V, M>);
-};
-
-template <typename V, typename M, int KP, int RPT>
-KTab<V, M> make_tab() {
-  if constexpr (sizeof(V) == 8)
-    return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
-            k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, k_update_nw<V, M, KP, RPT>,
-            k_zproj<V, M, KP, RPT>, k_pupdate_bt<V, M, KP>, k_zproj_bt<M, KP>,
-            k_update<V, M, KP, RPT, true>};
-  else
-    return {k_init<V, M, KP, RPT>, k_init2<V, M, KP, RPT>, k_pupdate<V, M, KP, RPT>,
-            k_spmv<V, M, KP, RPT>, k_update<V, M, KP, RPT>, nullptr, nullptr, nullptr, nullptr,
-            k_update<V, M, KP, RPT, true>};
-}
-
-template <typename V, typename M, int RPT>
-KTab<V, M> pick_kp(int KP) {
-  switch (KP) {
-    case 0: return make_tab<V, M, 0, RPT>();
-    case 8: return make_tab<V, M, 8, RPT>();
-    case 16: return make_tab<V, M, 16, RPT>();
-    case 24: return make_tab<V, M, 24, RPT>();
-    case 32: return make_tab<V, M, 32, RPT>();
-    case 40: return make_tab<V, M, 40, RPT>();
-    case 48: return make_tab<V, M, 48, RPT>();
-    case 56: return make_tab<V, M, 56, RPT>();
-    default: return make_tab<V, M, 64, RPT>();
-  }
-}
-
-template <typename V, typename M>
 KTab<V, M> pick(int KP, int rpt) {
-  if (rpt == 4) return pick_kp<V, M, 4>(KP);
   if (rpt == 2) return pick_kp<V, M, 2>(KP);
   return pick_kp<V, M, 1>(KP);
 }
@@ -349,20 +329,17 @@ template <int RPT>
 void (*pick_resid(void))(ResidArgs) { return k_resid64<RPT>; }
 
 void (*resid_fn(int rpt))(ResidArgs) {
-  if (rpt == 4) return k_resid64<4>;
   if (rpt == 2) return k_resid64<2>;
   return k_resid64<1>;
 }
 template <typename VM, typename VI, typename VO>
 void (*stencil1_fn(int rpt))(OpGeom, const VM*, const VI*, VO*, int64_t, const Inst*, int) {
-  if (rpt == 4) return k_stencil1<VM, VI, VO, 4>;
   if (rpt == 2) return k_stencil1<VM, VI, VO, 2>;
   return k_stencil1<VM, VI, VO, 1>;
 }
 
 template <typename V>
 void (*accum_fn(int rpt))(OpGeom, const uint8_t*, const V*, double*, int64_t, Inst*) {
-  if (rpt == 4) return k_accumulate<V, 4>;
   if (rpt == 2) return k_accumulate<V, 2>;
   return k_accumulate<V, 1>;
 }
@@ -405,6 +382,7 @@ void launch_coarse(adef2_ctx* c) {
   ca.ritz_keep = c->o.ritz_keep;
   ca.k_safe = c->k_safe;
   ca.tau_safe = c->tau_safe;
+  ca.tau_dep = c->o.tau_dep;
   // with FP32 panels the coarse solve errs by ~u32 cond(E): cap the learned
   // basis' bound so that this stays below 1e-3
   ca.tau_learned = mat64(c->prec) ? c->tau_learned : std::min(c->tau_learned, FP32_COND);
@@ -431,6 +409,9 @@ void set_variant(adef2_ctx* c, int rpt, int wfree) {
   c->bt_ntiles_pad = (int)cdiv(c->bt_ntiles, 8) * 8;
   c->bt_nblk_pad = (int)cdiv(cdiv(c->bt_ntiles, BT_TPB), 8) * 8;
   c->g_bt = make_geom(c->bt_nblk_pad);
+  c->ub_ntiles = (int)cdiv(c->N, (int64_t)UB_ROWS);
+  c->ub_ntiles_pad = (int)cdiv(c->ub_ntiles, 8) * 8;
+  c->g_ub = make_geom(c->ub_ntiles_pad);
 }
 
 template <typename V>
@@ -487,6 +468,12 @@ int ensure_batch(adef2_ctx* c, int B, int prec) {
   if ((rc = dalloc(c, &c->t32, (c->factored && !v64) ? BV : 0))) return rc;
   if ((rc = dalloc(c, &c->Tm, c->factored ? BN * KP : 0))) return rc;
   if ((rc = dalloc(c, &c->bnd, BN)) || (rc = dalloc(c, &c->hb, BN)) || (rc = dalloc(c, &c->zero64, 64)))
+    return rc;
+  if ((rc = dalloc(c, &c->ftot, (size_t)B * (2 * KP + 2))) || (rc = dalloc(c, &c->fctr, (size_t)B + 16)))
+    return rc;
+  HIPCHK(c, hipMemsetAsync(c->fctr, 0, ((size_t)B + 16) * sizeof(unsigned), c->st));
+  if ((rc = dalloc(c, &c->bcnt, (size_t)B * c->ub_ntiles)) ||
+      (rc = dalloc(c, &c->btoff, (size_t)B * (c->ub_ntiles + 1))) || (rc = dalloc(c, &c->btot, 1)))
     return rc;
   fill<double>(c, c->zero64, 64, 0.0);
   // reduction scratch: enough for the iteration kernels (NV <= KP+2) and the
@@ -558,8 +545,12 @@ int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
   fill<double>(c, c->x0pad, BV, 0.0);
   fill<double>(c, c->t64, BV, 0.0);
   // boundary form of W: FP32 panels and reference modes that are eigenvectors
-  c->ne = (c->KP > 0 && c->o.w_boundary == 1 && !mat64(c->prec) && c->n_eig > 0)
-              ? (c->zs ? c->k_base : c->k) : 0;
+  // (w_boundary 1: the eigen columns; 2: only when every shared reference
+  // mode is one, which also enables the tile-major boundary-form update)
+  const bool wb = c->o.w_boundary == 1 || (c->o.w_boundary == 2 && c->zs == 0 && c->n_eig == c->k);
+  c->ne = (c->KP > 0 && wb && !mat64(c->prec) && c->n_eig > 0) ? (c->zs ? c->k_base : c->k) : 0;
+  c->tm_ok = c->ne > 0 && c->zs == 0 && c->n_eig == c->k && vec64(c->prec) && c->ZT32 != nullptr;
+  c->nbnd = 0;
   if (c->ne > 0) {
     OpGeom og = op_geom(c);
     if (c->factored) {
@@ -581,6 +572,27 @@ int restrict_batch(adef2_ctx* c, const double* a_h, const double* c_h) {
       else launch_gram<float>(c, nullptr, c->W32);
     });
     timed(c, KI_COARSE, 0.0, [&] { launch_coarse(c); });
+    if (c->tm_ok) {
+      // boundary rows (W - Lambda Z != 0) compacted per instance and tile
+      const dim3 gb((unsigned)c->ub_ntiles, B);
+      hipLaunchKernelGGL(k_bnd_count, gb, dim3(UB_ROWS), 0, c->st, N, c->ub_ntiles, c->bnd, c->bcnt);
+      hipLaunchKernelGGL(k_bnd_scan, dim3(1), dim3(1024), 0, c->st, B, c->ub_ntiles, c->bcnt, c->btoff,
+                         c->btot);
+      int tot = 0;
+      HIPCHK(c, hipMemcpyAsync(&tot, c->btot, sizeof(int), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+      if ((size_t)tot > c->bcap) {
+        int rc;
+        const size_t cap = (size_t)tot + tot / 4 + 1024;
+        c->bcap = 0;
+        if ((rc = dalloc(c, &c->bidx, cap)) || (rc = dalloc(c, &c->bW32, cap * c->KP))) return rc;
+        c->bcap = cap;
+      }
+      c->nbnd = tot;
+      if (tot > 0)
+        hipLaunchKernelGGL((k_bnd_fill<float>), gb, dim3(UB_ROWS), 0, c->st, N, c->ub_ntiles, c->KP,
+                           c->bnd, c->btoff, c->W32, c->bidx, c->bW32);
+    }
   }
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(c->inst_h, c->inst, sizeof(Inst) * B, hipMemcpyDeviceToHost, c->st));
@@ -629,6 +641,25 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.bt_ntiles_pad = c->bt_ntiles_pad;
   a.bt_nblk_pad = c->bt_nblk_pad;
   a.gbt = c->g_bt;
+  a.ub_ntiles = c->ub_ntiles;
+  a.ub_ntiles_pad = c->ub_ntiles_pad;
+  a.ub_ngroups = (int)cdiv(c->B, UB_G);
+  a.pb_ngroups = (int)cdiv(c->B, PB_G);
+  a.sg_ngroups = (int)cdiv(c->B, SG_G);
+  a.gub = c->g_ub;
+  a.diag = c->diag;
+  a.precond_none = c->o.precond == ADEF2_NONE;
+  a.btoff = c->btoff;
+  a.bidx = c->bidx;
+  a.ftot = c->ftot;
+  a.fctr = c->fctr;
+  if constexpr (sizeof(M) == 8) {
+    a.ZT = nullptr;
+    a.bW = nullptr;
+  } else {
+    a.ZT = (const M*)c->ZT32;
+    a.bW = (const M*)c->bW32;
+  }
   if constexpr (sizeof(M) == 8) {
     a.dia1 = (const M*)c->dia1_64;
     a.dia = (const M*)c->dia64;
@@ -660,7 +691,7 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
 
 // algorithmic bytes per launch (per instance: inactive rows only); wv / wm =
 // bytes per vector entry / per operator or panel entry
-struct ByteModel { double init, init2, pupdate, spmv, update, resid, accum, update_nw, zproj; };
+struct ByteModel { double init, init2, pupdate, spmv, update, resid, accum, update_nw, zproj, update_tm; };
 // Algorithmic bytes per launch.  Per-instance data (vectors, W, the mask) is
 // counted for every instance still iterating at the last poll (a finished
 // instance's blocks exit at their first instruction); operands shared by
@@ -693,6 +724,9 @@ ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active
   b.spmv = inner + outer;
   b.update = nI * (k * wm + 8 * wv) + zsh + Nall;              // W, Z; x p r w dinv -> x r z
   b.update_nw = nI * 8 * wv + Nall;                            // x p r w dinv -> x r z
+  // x p r w -> x r z; the Jacobi scaling from the shared diagonal (N rows once);
+  // Z once (row-major copy); the boundary rows' list entries
+  b.update_tm = nI * 7 * wv + Nall + N1 * 8.0 + zsh + (double)c->nbnd * (4.0 + k * wm);
   // (t = A z), z, r; Z^T u, Z^T r with the FP64 operator and modes
   const double inner64 = c->factored ? (Nall * 2 * wv + N1 * D1 * 8.0) : 0.0;
   b.zproj = inner64 + nI * 3 * wv + U * D * 8.0 + zsh * (8.0 / wm) + Nall;
@@ -756,17 +790,26 @@ int chunk_graph(adef2_ctx* c, const IterArgs<V, M>& a, int chunk, int variant, F
 
 // max_chunks > 0 stops after that many chunks (tuning trials).
 template <typename V, typename M>
-int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale,
+int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale, int rel_tol,
               double thresh_floor, int carry_dir, int max_chunks = 0) {
-  const bool wfree = c->wfree && c->KP > 0 && sizeof(V) == 8;
+  // tile-major boundary-form kernels (w_mode 4): shared eigen-basis, FP64 vectors
+  const bool tm = c->wfree == 3 && c->KP > 0 && sizeof(V) == 8 && c->tm_ok;
+  const bool wfree = (c->wfree == 1 || c->wfree == 2) && c->KP > 0 && sizeof(V) == 8;
   // tile-major kernels (w_mode 2) need the basis shared by all instances
   const bool bt = wfree && c->wfree == 1 && c->zs == 0;
   const dim3 gbt(c->bt_ntiles_pad);
+  const dim3 gpt((unsigned)(c->ub_ntiles_pad * cdiv(c->B, PB_G)));
+  const dim3 gut((unsigned)(c->ub_ntiles_pad * cdiv(c->B, UB_G)));
+  const dim3 gfin((unsigned)cdiv(2 * c->KP + 2, FC), (unsigned)c->B);
+  // tile-major stencil passes: coefficients of a row held in registers
+  const bool stm = tm && c->D <= SDR && (!c->factored || c->D1 <= SDR);
+  const dim3 gst((unsigned)(c->ub_ntiles_pad * cdiv(c->B, SG_G)));
   IterArgs<V, M> a = iter_args<V, M>(c);
   a.src = src;
   a.x0 = x0pad;
   a.x0s = c->vs;
   a.thresh_scale = thresh_scale;
+  a.thresh_rel_tol = rel_tol;
   a.thresh_floor = thresh_floor;
   a.carry_dir = carry_dir;
   // segment cap: explicit (> 0), none (< 0), or by precision (0): FP32
@@ -775,6 +818,9 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   const int sm = c->o.segment_maxit;
   a.seg_maxit = (c->prec == ADEF2_FP64) ? 0 : (sm > 0 ? sm : (sm == 0 && !vec64(c->prec) ? 1000 : 0));
   KTab<V, M> kt = pick<V, M>(c->KP, c->rpt);
+  BtTab<M> btt{};
+  if constexpr (sizeof(V) == 8)
+    if (bt || tm) btt = pick_bt<M>(c->KP);
   dim3 grid(c->ntiles_pad * c->B), blk(IPB);
   ByteModel bm = byte_model(c, (double)sizeof(V), (double)sizeof(M), false);
   const OpGeom og = a.op;
@@ -794,17 +840,37 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   // every iteration: all per-iteration state lives in device memory)
   auto launch_chunk = [&](hipStream_t s) {
     for (int it = 0; it < chunk; ++it) {
-      if (bt)
-        timed(c, KI_PUPDATE_BT, bm.pupdate,
-              [&] { hipLaunchKernelGGL(kt.pupdate_bt, gbt, dim3(BT_THREADS), 0, s, a); });
-      else
+      if constexpr (sizeof(V) == 8) {
+        if (tm)
+          timed(c, KI_PUPDATE_TM, bm.pupdate,
+                [&] { hipLaunchKernelGGL(btt.pupdate_tm, gpt, dim3(UB_THREADS), 0, s, a); });
+        else if (bt)
+          timed(c, KI_PUPDATE_BT, bm.pupdate,
+                [&] { hipLaunchKernelGGL(btt.pupdate_bt, gbt, dim3(BT_THREADS), 0, s, a); });
+      }
+      if (!tm && !bt)
         timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, s, a); });
       timed(c, KI_SPMV, bm.spmv, [&] {
-        if (c->factored)
-          hipLaunchKernelGGL(st1, grid, blk, 0, s, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
-        hipLaunchKernelGGL(kt.spmv, grid, blk, 0, s, a);
+        if constexpr (sizeof(V) == 8) {
+          if (stm) {
+            if (c->factored) hipLaunchKernelGGL(btt.stencil1_tm, gst, dim3(UB_THREADS), 0, s, a);
+            hipLaunchKernelGGL(btt.spmv_tm, gst, dim3(UB_THREADS), 0, s, a);
+            hipLaunchKernelGGL(btt.alpha_tm, dim3((unsigned)c->B), dim3(UB_THREADS), 0, s, a);
+          }
+        }
+        if (!stm) {
+          if (c->factored)
+            hipLaunchKernelGGL(st1, grid, blk, 0, s, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
+          hipLaunchKernelGGL(kt.spmv, grid, blk, 0, s, a);
+        }
       });
-      if (!wfree) {
+      if (tm) {
+        if constexpr (sizeof(V) == 8)
+          timed(c, KI_UPDATE_TM, bm.update_tm, [&] {
+            hipLaunchKernelGGL(btt.update_tm, gut, dim3(UB_THREADS), 0, s, a);
+            hipLaunchKernelGGL(btt.finish_tm, gfin, dim3(UB_THREADS), 0, s, a);
+          });
+      } else if (!wfree) {
         timed(c, KI_UPDATE, bm.update, [&] {
           hipLaunchKernelGGL((c->ne > 0 ? kt.update_spec : kt.update), grid, blk, 0, s, a);
         });
@@ -815,9 +881,10 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
           if (c->factored)
             hipLaunchKernelGGL((stencil1_fn<double, V, V>(c->rpt)), grid, blk, 0, s, og, c->dia1_64,
                                (const V*)a.z, a.t, c->vs, c->inst, 1);
-          if (bt)
-            hipLaunchKernelGGL(kt.zproj_bt, dim3(c->bt_nblk_pad), dim3(BT_THREADS), 0, s, a);
-          else
+          if (bt) {
+            if constexpr (sizeof(V) == 8)
+              hipLaunchKernelGGL(btt.zproj_bt, dim3(c->bt_nblk_pad), dim3(BT_THREADS), 0, s, a);
+          } else
             hipLaunchKernelGGL(kt.zproj, grid, blk, 0, s, a);
         });
       }
@@ -825,7 +892,7 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   };
   hipGraphExec_t gexec = nullptr;
   if (c->o.graph && !c->o.profile) {
-    int rc = chunk_graph<V, M>(c, a, chunk, (int)bt * 4 + (int)wfree * 2 + (c->ne > 0 ? 1 : 0),
+    int rc = chunk_graph<V, M>(c, a, chunk, (int)tm * 8 + (int)bt * 4 + (int)wfree * 2 + (c->ne > 0 ? 1 : 0),
                                launch_chunk, &gexec);
     if (rc) return rc;
   }
@@ -855,8 +922,7 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   return ADEF2_OK;
 }
 
-int resid64(adef2_ctx* c, const double* b, const double* xpad, int first, int decide, double tol,
-            bool store) {
+int resid64(adef2_ctx* c, const double* b, const double* xpad, int first, int decide, bool store) {
   ResidArgs ra{};
   ra.op = op_geom(c);
   ra.dia = c->dia64;
@@ -872,7 +938,6 @@ int resid64(adef2_ctx* c, const double* b, const double* xpad, int first, int de
   ra.g = c->g_iter;
   ra.first = first;
   ra.decide = decide;
-  ra.tol2 = tol * tol;
   ra.maxit = c->o.maxit;
   ra.max_sweeps = c->o.max_sweeps;
   ra.stall_steps = 4;
@@ -898,6 +963,8 @@ int reset_solve_state(adef2_ctx* c) {
     s.has_dir = 0; s.rho_end = 0.0; s.stall = 0; s.rr64_best = INFINITY; s.drift = 0;
     s.capped = 0;
     s.rr = 0; s.rr64 = 0; s.bb64 = 0;
+    const double t = m < (int)c->tol_h.size() ? c->tol_h[m] : 1e-8;
+    s.tol2 = t * t;
   }
   HIPCHK(c, hipMemcpyAsync(c->inst, c->inst_h, sizeof(Inst) * c->B, hipMemcpyHostToDevice, c->st));
   return ADEF2_OK;
@@ -909,18 +976,27 @@ int reset_solve_state(adef2_ctx* c) {
 // every candidate runs the solve's first two chunks of iterations from the
 // same start and the fastest is kept for this context, so repeated solves of
 // one configuration use the same kernels (and give identical results).
-int choose_variant(adef2_ctx* c, const double* b, double tol) {
+int choose_variant(adef2_ctx* c, const double* b) {
   const int fr = c->o.rows_per_thread, fw = c->o.w_mode;
   if (fw >= 2 && !vec64(c->prec))
     return fail(c, ADEF2_E_UNSUPPORTED, "W-free iterations need FP64 vectors (FP64 or MIXED_REFINE)");
-  std::vector<int> rpts = (fr == 1 || fr == 2 || fr == 4) ? std::vector<int>{fr} : std::vector<int>{1, 2, 4};
+  std::vector<int> rpts = (fr == 1 || fr == 2) ? std::vector<int>{fr} : std::vector<int>{1, 2};
+  if (fw == 4 && !c->tm_ok)
+    return fail(c, ADEF2_E_UNSUPPORTED,
+                "the tile-major boundary-form update needs FP32 panels with FP64 vectors (MIXED_REFINE), "
+                "reference modes shared by all instances that are eigenvectors of the reference operator, "
+                "and w_boundary enabled");
   std::vector<int> wfs = (fw == 1 || c->KP == 0 || !vec64(c->prec)) ? std::vector<int>{0}
                          : (fw == 2 ? std::vector<int>{1}
-                                    : (fw == 3 ? std::vector<int>{2} : std::vector<int>{0, 1, 2}));
+                         : (fw == 3 ? std::vector<int>{2}
+                         : (fw == 4 ? std::vector<int>{3} : std::vector<int>{0, 1, 2})));
+  if (fw == 0 && c->tm_ok && c->KP > 0 && vec64(c->prec)) wfs.push_back(3);
   if (rpts.size() * wfs.size() == 1) { set_variant(c, rpts[0], wfs[0]); return ADEF2_OK; }
   const int fact = c->factored ? 1 : 0;
+  const int tmk = c->tm_ok ? 1 : 0;
   for (const auto& t : c->tuned)
-    if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N) {
+    if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.tm == tmk &&
+        t.N == c->N) {
       set_variant(c, t.rpt, t.wfree);
       return ADEF2_OK;
     }
@@ -929,7 +1005,7 @@ int choose_variant(adef2_ctx* c, const double* b, double tol) {
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, tmk, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0}};
   float best_ms = INFINITY;
   int rc = ADEF2_OK, ci = 0;
   for (int rpt : rpts) {
@@ -938,17 +1014,15 @@ int choose_variant(adef2_ctx* c, const double* b, double tol) {
       if ((rc = reset_solve_state(c))) break;
       if (c->prec != ADEF2_FP64) {
         fill<double>(c, c->x64, (size_t)c->B * c->vs, 0.0);
-        if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, tol, true))) break;
+        if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, true))) break;
       }
       HIPCHK(c, hipEventRecord(e0, c->st));
       if (c->prec == ADEF2_FP64)
-        rc = run_sweep<double, double>(c, b, nullptr, tol * tol, 0.0, 0, 2);
+        rc = run_sweep<double, double>(c, b, nullptr, 1.0, 1, 0.0, 0, 2);
       else if (vec64(c->prec))
-        rc = run_sweep<double, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol,
-                                      0.25 * tol * tol, 0, 2);
+        rc = run_sweep<double, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol, 0, 0.25, 0, 2);
       else
-        rc = run_sweep<float, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol,
-                                     0.25 * tol * tol, 0, 2);
+        rc = run_sweep<float, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol, 0, 0.25, 0, 2);
       if (rc) break;
       HIPCHK(c, hipEventRecord(e1, c->st));
       HIPCHK(c, hipEventSynchronize(e1));
@@ -969,12 +1043,19 @@ int choose_variant(adef2_ctx* c, const double* b, double tol) {
 }
 
 // Solve all B restricted instances; b, x instance-major unpadded [B][N].
-int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, double* x) {
+// tols: host f64[B] per-instance tolerances, or null for tol everywhere
+int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, double* x,
+                const double* tols = nullptr) {
   const int B = c->B;
   const int64_t N = c->N;
-  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(c, ADEF2_E_ARG, "tol must be positive");
+  c->tol_h.assign(B, tol);
+  if (tols)
+    for (int m = 0; m < B; ++m) c->tol_h[m] = tols[m];
+  for (int m = 0; m < B; ++m)
+    if (!(c->tol_h[m] > 0.0) || !std::isfinite(c->tol_h[m]))
+      return fail(c, ADEF2_E_ARG, "tol must be positive and finite");
   int rc;
-  if ((rc = choose_variant(c, b, tol))) return rc;
+  if ((rc = choose_variant(c, b))) return rc;
   if ((rc = reset_solve_state(c))) return rc;
   dim3 gc((unsigned)cdiv(N, 256), B);
   const double* x0p = nullptr;
@@ -986,9 +1067,9 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
   }
   double* xres = nullptr;
   if (c->prec == ADEF2_FP64) {
-    if ((rc = run_sweep<double, double>(c, b, x0p, tol * tol, 0.0, 0))) return rc;
+    if ((rc = run_sweep<double, double>(c, b, x0p, 1.0, 1, 0.0, 0))) return rc;
     xres = interior(c, c->v64[0]);
-    if ((rc = resid64(c, b, xres, 1, 0, tol, false))) return rc;
+    if ((rc = resid64(c, b, xres, 1, 0, false))) return rc;
   } else {
     if (x0p) {
       HIPCHK(c, hipMemcpyAsync(c->x64, c->x0pad, sizeof(double) * (size_t)B * c->vs,
@@ -996,7 +1077,7 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
     } else {
       fill<double>(c, c->x64, (size_t)B * c->vs, 0.0);
     }
-    if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, tol, true))) return rc;
+    if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, true))) return rc;
     const double in2 = c->o.inner_rtol * c->o.inner_rtol;
     const bool v64 = vec64(c->prec);
     ByteModel bm = byte_model(c, v64 ? 8.0 : 4.0, 4.0, false);
@@ -1009,8 +1090,8 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
       // FP32 segment on the correction equation S d = r64; it ends when its
       // recurrence residual fell by inner_rtol (or below tol ||b|| / 2); the
       // FP64 residual then replaces it and the search direction carries on
-      rc = v64 ? run_sweep<double, float>(c, c->r64, nullptr, in2, 0.25 * tol * tol, sweep > 0)
-               : run_sweep<float, float>(c, c->r64, nullptr, in2, 0.25 * tol * tol, sweep > 0);
+      rc = v64 ? run_sweep<double, float>(c, c->r64, nullptr, in2, 0, 0.25, sweep > 0)
+               : run_sweep<float, float>(c, c->r64, nullptr, in2, 0, 0.25, sweep > 0);
       if (rc) return rc;
       timed(c, KI_ACCUM, bm.accum, [&] {
         if (v64)
@@ -1022,7 +1103,7 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
                              op_geom(c), c->masks, interior(c, c->v32[0]), interior(c, c->x64),
                              c->vs, c->inst);
       });
-      if ((rc = resid64(c, b, interior(c, c->x64), 0, 1, tol, true))) return rc;
+      if ((rc = resid64(c, b, interior(c, c->x64), 0, 1, true))) return rc;
     }
     xres = interior(c, c->x64);
   }
@@ -1052,10 +1133,10 @@ bool valid_opts(const adef2_opts* o) {
           o->precision == ADEF2_MIXED_REFINE) &&
          (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
          o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0 &&
-         (o->rows_per_thread == 0 || o->rows_per_thread == 1 || o->rows_per_thread == 2 ||
-          o->rows_per_thread == 4) &&
-         o->w_mode >= 0 && o->w_mode <= 3 && (o->w_boundary == 0 || o->w_boundary == 1) &&
-         (o->graph == 0 || o->graph == 1) && o->ritz_keep >= 0 && o->ritz_keep <= ADEF2_MAX_K;
+         (o->rows_per_thread == 0 || o->rows_per_thread == 1 || o->rows_per_thread == 2) &&
+         o->w_mode >= 0 && o->w_mode <= 4 && o->w_boundary >= 0 && o->w_boundary <= 2 &&
+         (o->graph == 0 || o->graph == 1) && o->ritz_keep >= 0 && o->ritz_keep <= ADEF2_MAX_K &&
+         o->tau_safe >= 1.0 && o->tau_dep >= 0.0 && o->tau_dep < 1.0;
 }
 
 }  // namespace
@@ -1166,9 +1247,11 @@ void adef2_default_opts(adef2_opts* o) {
   o->rows_per_thread = 0;
   o->profile = 0;
   o->w_mode = 0;
-  o->w_boundary = 0;
+  o->w_boundary = 2;
   o->graph = 1;
   o->ritz_keep = 0;
+  o->tau_safe = 1e4;
+  o->tau_dep = 1e-10;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
@@ -1346,6 +1429,9 @@ int load_modes(adef2_ctx* c, int64_t n, int32_t k, const double* Z) {
       return rc;
     hipLaunchKernelGGL(k_copy_modes, dim3((unsigned)cdiv(n, 256), c->KP), dim3(256), 0, c->st, n, k,
                        c->KP, Z, c->Z64, c->Z32);
+    if ((rc = dalloc(c, &c->ZT32, (size_t)c->KP * n))) return rc;
+    hipLaunchKernelGGL((k_modes_rowmajor<float>), dim3((unsigned)cdiv(n, 256), c->KP), dim3(256), 0, c->st,
+                       n, c->KP, c->Z32, c->ZT32);
     HIPCHK(c, hipGetLastError());
     if ((rc = eigen_test(c))) return rc;
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1500,7 +1586,8 @@ int adef2_solve(adef2_ctx* c, const double* b, const double* x0, double tol, dou
 }
 
 int adef2_solve_batched(adef2_ctx* c, int32_t B, const uint8_t* masks, const double* b,
-                        const double* a, const double* cs, const float* theta, double tol, double* x,
+                        const double* a, const double* cs, const float* theta, double tol,
+                        const double* tol_each, double* x,
                         int32_t* iters, int32_t* status, double* relres_true, double* cond_E,
                         int64_t* n_inactive, int32_t* learned) {
   if (!c) return ADEF2_E_ARG;
@@ -1521,7 +1608,7 @@ int adef2_solve_batched(adef2_ctx* c, int32_t B, const uint8_t* masks, const dou
   HIPCHK(c, hipMemcpyAsync(c->masks, masks, (size_t)B * c->N, hipMemcpyDeviceToDevice, c->st));
   rc = restrict_batch(c, a, cs);
   if (rc < 0) return rc;
-  rc = solve_batch(c, b, nullptr, tol, x);
+  rc = solve_batch(c, b, nullptr, tol, x, tol_each);
   if (rc) return rc;
   int worst = ADEF2_OK;
   for (int m = 0; m < B; ++m)
@@ -1667,7 +1754,7 @@ int adef2_reference_eigs(adef2_ctx* c, int32_t r, const double* X0, int32_t max_
   int it = 0;
   const dim3 gv((unsigned)cdiv(N, 256), r);
   for (it = 1; it <= max_iter; ++it) {
-    rc = adef2_solve_batched(c, r, mk, X, nullptr, nullptr, nullptr, inner_tol, Y, its.data(), st.data(), nullptr,
+    rc = adef2_solve_batched(c, r, mk, X, nullptr, nullptr, nullptr, inner_tol, nullptr, Y, its.data(), st.data(), nullptr,
                              nullptr, nullptr, nullptr);
     if (rc < 0) { cleanup(); return rc; }
     gram(Y, Y, G);
@@ -1753,7 +1840,7 @@ int adef2_active_set_batched(adef2_ctx* c, int32_t B, const double* y_d, const d
     hipLaunchKernelGGL(k_ocp_rhs, g, dim3(256), 0, c->st, og, c->dia64, (int)c->factored,
                        c->factored ? c->alpha_ref : 1.0, idx, mk, y_d, src, vs, bsub, msub);
     HIPCHK(c, hipGetLastError());
-    rc = adef2_solve_batched(c, Bs, msub, bsub, nullptr, nullptr, nullptr, tol, xsub, it_b.data(),
+    rc = adef2_solve_batched(c, Bs, msub, bsub, nullptr, nullptr, nullptr, tol, nullptr, xsub, it_b.data(),
                              st_b.data(), nullptr, nullptr, nullptr, nullptr);
     if (rc < 0) { cleanup(); return rc; }
     HIPCHK(c, hipMemsetAsync(chg, 0, sizeof(int) * Bs, c->st));
@@ -1894,9 +1981,26 @@ int adef2_set_pod_modes(adef2_ctx* c, int32_t p, const double* Phi) {
   return ADEF2_OK;
 }
 
+int adef2_set_enrichment(adef2_ctx* c, int32_t p, const double* Phi, const float* mlp_params,
+                         int32_t n_vec, double tau_learned) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->have_ref) return fail(c, ADEF2_E_STATE, "set_enrichment before set_reference");
+  if (n_vec != MLP_NV)
+    return fail(c, ADEF2_E_UNSUPPORTED, "set_enrichment: the network emits 8 enrichment vectors (n_vec = 8)");
+  if (p < 1 || p > MLP_P || !Phi) return fail(c, ADEF2_E_ARG, "set_enrichment: 1 <= p <= 64 and Phi required");
+  if (c->k + MLP_NV > ADEF2_MAX_K)
+    return fail(c, ADEF2_E_ARG, "set_enrichment: k + 8 enrichment vectors exceeds ADEF2_MAX_K");
+  if (mlp_params && !(tau_learned >= 1.0)) return fail(c, ADEF2_E_ARG, "tau_learned must be >= 1");
+  int rc = adef2_set_pod_modes(c, p, Phi);
+  if (rc) return rc;
+  if (mlp_params) return adef2_learned_set_params(c, mlp_params, tau_learned);
+  return ADEF2_OK;
+}
+
 int adef2_pod_enrich(adef2_ctx* c, int32_t p, double tau_safe) {
   if (!c) return ADEF2_E_ARG;
   if (!c->have_ref) return fail(c, ADEF2_E_STATE, "pod_enrich before set_reference");
+  if (tau_safe <= 0.0) tau_safe = c->o.tau_safe;
   if (p < 0 || (p > 0 && !(tau_safe >= 1.0)) || c->k_ref + p > ADEF2_MAX_K)
     return fail(c, ADEF2_E_ARG, "pod_enrich: need 0 <= p, k + p <= ADEF2_MAX_K and tau_safe >= 1");
   if (p > 0 && (!c->Phi || p > c->p)) return fail(c, ADEF2_E_STATE, "pod_enrich: fewer POD modes held than p");

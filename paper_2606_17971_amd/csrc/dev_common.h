@@ -31,6 +31,7 @@ struct Inst {
   double rr64_prev;     // outer residual before the last one
   double rr64_best;     // smallest outer residual so far
   double rr64;          // ||b_I - S_II x||^2 of the last outer residual
+  double tol2;          // squared relative tolerance of this instance
   int32_t iters;        // CG iterations, all sweeps
   int32_t sweep_iters;
   int32_t done;         // current sweep finished (kernels skip the instance)

@@ -13,6 +13,7 @@
 //           S (masked vector) restricted to inactive rows equal to S_II.
 // Tile kernels map blocks to (tile, instance) with tile_inst().
 #pragma once
+#include "../../include/adef2.h"
 #include "dev_common.h"
 
 namespace adef2 {
@@ -100,8 +101,9 @@ struct IterArgs {
   const double* x0;        // padded FP64 warm start (stride x0s) or null
   const double* x0sv;      // stencil source for S x0: x0, or A x0 (factored)
   int64_t x0s;
-  double thresh_scale;     // thresh2 = max(thresh_scale * ||src_I||^2,
-  double thresh_floor;     //               thresh_floor * ||b_I||^2)
+  double thresh_scale;     // thresh2 = max(thresh_scale [* tol2] * ||src_I||^2,
+  double thresh_floor;     //               thresh_floor * tol2 * ||b_I||^2), tol2 per instance
+  int32_t thresh_rel_tol;  // multiply thresh_scale by the instance's tol2
   int32_t carry_dir;       // keep the previous sweep's search direction
   int32_t seg_maxit;       // a sweep ends after this many iterations (0 = none)
   // W-free projection: FP64 operator and modes (see k_zproj)
@@ -113,6 +115,22 @@ struct IterArgs {
   int32_t bt_ntiles, bt_ntiles_pad;
   int32_t bt_nblk_pad;     // k_zproj_bt blocks (BT_TPB tiles each), multiple of 8
   RedGeom gbt;             // reduction tree over the k_zproj_bt blocks
+  // tile-major kernels of the shared reference modes (k_pupdate_tm,
+  // k_update_tm): UB_ROWS-row tiles, instance groups of UB_G / PB_G
+  int32_t ub_ntiles, ub_ntiles_pad;
+  int32_t ub_ngroups, pb_ngroups, sg_ngroups;
+  RedGeom gub;             // reduction tree over the tiles (one leaf per tile)
+  const M* ZT;             // [N][KP] row-major copy of the shared modes
+  const double* diag;      // [N] diagonal of the reference stencil (Jacobi: 1 / (a d + c))
+  int32_t precond_none;
+  // boundary rows of each instance (rows of W - lambda Z that are not zero),
+  // compacted tile by tile: entries btoff[m][t] .. btoff[m][t + 1] - 1 of
+  // instance m lie in tile t, entry e is row bidx[e] with values bW[e][0..KP)
+  const int32_t* btoff;    // [B][ub_ntiles + 1]
+  const int32_t* bidx;
+  const M* bW;
+  double* ftot;            // [B][2 KP + 2] totals of the tile-major finisher
+  unsigned* fctr;          // [B] arrival counters of the tile-major finisher
 };
 
 template <int RPT> struct Rows { static constexpr int PB = IPB * RPT; };
@@ -250,7 +268,8 @@ __global__ void __launch_bounds__(IPB) k_init(IterArgs<V, M> a) {
   if (threadIdx.x == 0) {
     const double b2 = tot[KP];
     S->bb = b2;
-    S->thresh2 = fmax(a.thresh_scale * b2, a.thresh_floor * S->bb64);
+    S->thresh2 = fmax(a.thresh_scale * (a.thresh_rel_tol ? S->tol2 : 1.0) * b2,
+                      a.thresh_floor * S->tol2 * S->bb64);
     S->done = 0;
     S->sweep_iters = 0;
     S->fresh = 1;
@@ -1033,198 +1052,6 @@ __global__ void __launch_bounds__(BT_THREADS) k_zproj_bt(IterArgs<double, M> a) 
       __syncthreads();
     }
   }
-}
-
-// ---------------------------------------------------------------------------
-// FP64 outer residual: r64 = b - S_II x64 (optionally stored), ||r64||^2,
-// ||b_I||^2; finisher applies the outer stopping test (refinement mode).
-// ---------------------------------------------------------------------------
-struct ResidArgs {
-  OpGeom op;
-  const double* dia;       // FP64 [D][N]
-  const uint8_t* mask;
-  const double* b;         // [B][N]
-  const double* x;         // padded FP64 [B][vs]
-  const double* sv;        // stencil source: x, or A x (factored)
-  int64_t vs;
-  double* r64;             // [B][N] or null
-  Inst* inst;
-  double* part; unsigned* ctr; RedGeom g;
-  int32_t first;           // compute ||b_I||^2 (first outer step)
-  int32_t decide;          // apply the outer stopping rule
-  double tol2;
-  int32_t maxit, max_sweeps;
-  int32_t stall_steps;     // outer steps without halving before W_STAGNATED
-};
-
-template <int RPT>
-__global__ void __launch_bounds__(IPB) k_resid64(ResidArgs a) {
-  __shared__ double red[NIWAVE * 2];
-  __shared__ double bv[2];
-  __shared__ double tot[2];
-  int tile, m;
-  tile_inst(a.op.ntiles_pad, tile, m);
-  Inst* S = a.inst + m;
-  if (S->outer_done && a.decide) return;
-  const int64_t N = a.op.N;
-  const uint8_t* mk = a.mask + (size_t)m * N;
-  const double* b = a.b + (size_t)m * N;
-  const double* x = a.x + m * a.vs;
-  const double* sv = a.sv + m * a.vs;
-  const double sa = S->a, sc = S->c;
-  double v[2] = {0.0, 0.0};
-  if (tile < a.op.ntiles) {
-#pragma unroll
-    for (int rr = 0; rr < RPT; ++rr) {
-      const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
-      if (i < N && mk[i] == 0) {
-        double acc = 0.0;
-        for (int d = 0; d < a.op.D; ++d) acc += a.dia[(size_t)d * N + i] * sv[i + a.op.offs[d]];
-        const double bi = b[i];
-        const double rv = bi - (sa * acc + sc * x[i]);
-        if (a.r64) a.r64[(size_t)m * N + i] = rv;
-        v[0] += rv * rv;
-        v[1] += bi * bi;
-      }
-    }
-  }
-  block_sum<2, NIWAVE>(v, red, bv);
-  double* part = a.part + (size_t)m * a.g.ptotal * 2;
-  unsigned* ctr = a.ctr + (size_t)m * a.g.ctotal;
-  if (!tree_reduce(a.g, tile, 2, part, ctr, bv, tot)) return;
-  if (threadIdx.x == 0) {
-    S->rr64_prev = a.first ? INFINITY : S->rr64;
-    S->rr64 = tot[0];
-    if (a.first) S->bb64 = tot[1];
-    if (a.decide) {
-      const double bb = S->bb64;
-      const double r2 = tot[0];
-      // Drift: the FP64 residual exceeds the recurrence residual the sweep
-      // ended with by more than 2x (while the iteration is accurate the two
-      // agree to a few per cent); the next sweep then restarts its direction.
-      // Attainable-accuracy guard: the best FP64 residual has not halved over
-      // the last stall_steps sweeps that converged on their own equation (a
-      // sweep stopped by the segment cap is no evidence: CG's residual 2-norm
-      // is not monotone)
-      S->drift = a.first ? 0 : (r2 > 4.0 * S->rr);
-      if (a.first || r2 < 0.25 * S->rr64_best) { S->rr64_best = r2; S->stall = 0; }
-      else if (!S->capped) S->stall += 1;
-      if (!(bb < INFINITY) || !(r2 < INFINITY)) { S->outer_done = 1; S->status = -1; }
-      else if (!(r2 > a.tol2 * bb)) { S->outer_done = 1; }
-      else if (S->stall >= a.stall_steps) { S->outer_done = 1; S->status = 3; }
-      else if (S->iters >= a.maxit || S->sweeps >= a.max_sweeps) { S->outer_done = 1; S->status = 2; }
-      S->done = 1;
-    }
-  }
-}
-
-// Inner stencil of the factored operator on all rows: t = A v (v is zero on
-// the active set, so t = A[:, I] v_I).  skip: 1 = skip instances whose sweep is
-// done, 2 = skip finished solves, 0 = none.
-template <typename VM, typename VI, typename VO, int RPT>
-__global__ void __launch_bounds__(IPB) k_stencil1(OpGeom op, const VM* dia1, const VI* v, VO* t,
-                                                  int64_t vs, const Inst* inst, int skip) {
-  int tile, m;
-  tile_inst(op.ntiles_pad, tile, m);
-  const Inst* S = inst + m;
-  if ((skip == 1 && S->done) || (skip == 2 && S->outer_done)) return;
-  if (tile >= op.ntiles) return;
-  const int64_t N = op.N;
-  const VI* vm = v + m * vs;
-  VO* tm = t + m * vs;
-#pragma unroll
-  for (int rr = 0; rr < RPT; ++rr) {
-    const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
-    if (i < N) {
-      tm[i] = (VO)stencil_row(dia1, op.offs1, op.D1, op.d01, N, i, vm);
-    }
-  }
-}
-
-// x64 += d (FP32 correction of the last sweep)
-template <typename V, int RPT>
-__global__ void __launch_bounds__(IPB) k_accumulate(OpGeom op, const uint8_t* mask, const V* d,
-                                                    double* x64, int64_t vs, Inst* inst) {
-  int tile, m;
-  tile_inst(op.ntiles_pad, tile, m);
-  Inst* S = inst + m;
-  if (S->outer_done) return;
-  if (tile >= op.ntiles) return;
-  const int64_t N = op.N;
-  const uint8_t* mk = mask + (size_t)m * N;
-#pragma unroll
-  for (int rr = 0; rr < RPT; ++rr) {
-    const int64_t i = (int64_t)tile * Rows<RPT>::PB + rr * IPB + threadIdx.x;
-    if (i < N && mk[i] == 0) x64[m * vs + i] += (double)d[m * vs + i];
-  }
-  if (tile == 0 && threadIdx.x == 0) S->sweeps += 1;
-}
-
-// out[i] = x[i] on inactive rows, 0 on active rows (instance-major, unpadded)
-__global__ void k_scatter_out(int64_t N, const uint8_t* mask, const double* x, int64_t vs, double* out,
-                              const Inst* inst) {
-  const int m = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const bool act = mask[(size_t)m * N + i] != 0;
-  out[(size_t)m * N + i] = act ? 0.0 : x[m * vs + i];
-  (void)inst;
-}
-
-template <typename V>
-__global__ void k_fill(V* p, int64_t n, V val) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t j = i; j < n; j += stride) p[j] = val;
-}
-
-// padded copy: dst[m*vs + i] = src[m*N + i]
-__global__ void k_copy_padded(int64_t N, const double* src, double* dst, int64_t vs) {
-  const int m = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) dst[m * vs + i] = src[(size_t)m * N + i];
-}
-
-// dst[i] = src[i] on inactive rows, 0 on active rows (padded destination)
-__global__ void k_mask_copy_padded(int64_t N, const uint8_t* mask, const double* src, double* dst,
-                                   int64_t vs) {
-  const int m = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) dst[m * vs + i] = mask[(size_t)m * N + i] ? 0.0 : src[(size_t)m * N + i];
-}
-
-// y = S_II x (global layout, FP64): x padded with zeros on the active set
-__global__ void k_apply64(OpGeom op, const double* dia, const uint8_t* mask, const double* x,
-                          const double* sv, double* y, const Inst* inst) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = op.N;
-  if (i >= N) return;
-  double v = 0.0;
-  if (mask[i] == 0) {
-    double acc = 0.0;
-    for (int d = 0; d < op.D; ++d) acc += dia[(size_t)d * N + i] * sv[i + op.offs[d]];
-    v = inst->a * acc + inst->c * x[i];
-  }
-  y[i] = v;
-}
-
-// Jacobi preconditioner of the restricted operator: dinv = 1 / (a d + c) on
-// inactive rows (1 without preconditioner), 0 on active rows.
-template <typename V>
-__global__ void k_dinv(int64_t N, const double* diag, const uint8_t* mask, V* dinv, Inst* inst,
-                       int precond_none) {
-  const int m = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  Inst* S = inst + m;
-  const bool act = mask[(size_t)m * N + i] != 0;
-  double v = 0.0;
-  if (!act) {
-    const double dd = S->a * diag[i] + S->c;
-    if (!(dd > 0.0)) S->setup_status = -5;
-    v = precond_none ? 1.0 : 1.0 / dd;
-  }
-  dinv[(size_t)m * N + i] = (V)v;
 }
 
 }  // namespace adef2

@@ -2,7 +2,8 @@
 // inactive-set compaction, W = S_II Z_I with the Gram matrices Z_I^T Z_I and
 // Z_I^T W, and the one-workgroup k x k coarse setup.
 #pragma once
-#include "dev_kernels.h"
+#include "dev_vec.h"
+#include "dev_tile.h"
 
 namespace adef2 {
 
@@ -578,6 +579,76 @@ __global__ void k_copy_modes(int64_t n, int k, int KP, const double* Z, double* 
   Z32[(size_t)q * n + i] = (float)v;
 }
 
+// Row-major copy of the shared modes for the tile-major kernels:
+// ZT[i][q] = Z[q][i] (the products there read 16 consecutive columns of a row).
+template <typename T>
+__global__ void k_modes_rowmajor(int64_t n, int KP, const T* Z, T* ZT) {
+  const int q = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  ZT[(size_t)i * KP + q] = Z[(size_t)q * n + i];
+}
+
+// Boundary rows of each instance (flags bnd, rows where W - Lambda Z does not
+// vanish), compacted tile by tile for k_update_tm.  Launched with one block of
+// UB_ROWS threads per (tile, instance).
+__global__ void __launch_bounds__(UB_ROWS) k_bnd_count(int64_t N, int ntiles, const uint8_t* bnd, int* cnt) {
+  const int tile = blockIdx.x, m = blockIdx.y;
+  const int64_t i = (int64_t)tile * UB_ROWS + threadIdx.x;
+  const int f = (i < N && bnd[(size_t)m * N + i]) ? 1 : 0;
+  const int c = __syncthreads_count(f);
+  if (threadIdx.x == 0) cnt[(size_t)m * ntiles + tile] = c;
+}
+
+// Exclusive prefix sums of the [B][ntiles] counts (one block of 1024 threads,
+// each scanning a contiguous chunk): off[m][t] = entries before tile t of
+// instance m, off[m][ntiles] = end of instance m; *total = all entries.
+__global__ void __launch_bounds__(1024) k_bnd_scan(int B, int ntiles, const int* cnt, int* off,
+                                                   int* total) {
+  __shared__ int part[1024];
+  const int n = B * ntiles;
+  const int per = (n + 1023) / 1024;
+  const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+  int s = 0;
+  for (int e = lo; e < hi; ++e) s += cnt[e];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < 1024; ++w) { const int v = part[w]; part[w] = run; run += v; }
+    *total = run;
+  }
+  __syncthreads();
+  int run = part[threadIdx.x];
+  for (int e = lo; e < hi; ++e) {
+    const int m = e / ntiles, tl = e - m * ntiles;
+    off[(size_t)m * (ntiles + 1) + tl] = run;
+    run += cnt[e];
+    if (tl == ntiles - 1) off[(size_t)m * (ntiles + 1) + ntiles] = run;
+  }
+}
+
+// Entry e = off[m][tile] + (rank of the row among the tile's flagged rows):
+// bidx[e] = row, bW[e][q] = W_m[q][row] (W stored as W - Lambda Z)
+template <typename M>
+__global__ void __launch_bounds__(UB_ROWS) k_bnd_fill(int64_t N, int ntiles, int KP, const uint8_t* bnd,
+                                                      const int* off, const M* W, int* bidx, M* bW) {
+  __shared__ int wcnt[UB_ROWS / 64];
+  const int tile = blockIdx.x, m = blockIdx.y;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t i = (int64_t)tile * UB_ROWS + threadIdx.x;
+  const bool f = i < N && bnd[(size_t)m * N + i];
+  const unsigned long long bal = __ballot(f);
+  if (lane == 0) wcnt[wid] = __popcll(bal);
+  __syncthreads();
+  if (!f) return;
+  int pos = off[(size_t)m * (ntiles + 1) + tile] + __popcll(bal & ((1ull << lane) - 1ull));
+  for (int w = 0; w < wid; ++w) pos += wcnt[w];
+  bidx[pos] = (int)i;
+  const M* Wm = W + (size_t)m * KP * N;
+  for (int q = 0; q < KP; ++q) bW[(size_t)pos * KP + q] = Wm[(size_t)q * N + i];
+}
+
 // ---------------------------------------------------------------------------
 // W = S_II Z_I (stored as V), and per instance the Gram matrices
 //   G = Z_I^T Z_I,  E = Z_I^T W   (FP64, deterministic tree reduction)
@@ -689,6 +760,8 @@ struct CoarseArgs {
   Inst* inst;
   int k;                 // true number of modes (<= KP)
   double drop_rel;
+  double tau_dep;        // POD candidates (columns k_safe..): also dropped when their part
+                         //   orthogonal to the kept columns is <= tau_dep of their norm
   double tau_cond;
   int k_base;            // > 0: columns k_base.. are learned enrichment vectors;
   double tau_learned;    //   if cond(E) exceeds tau_learned (or the setup fails)
@@ -824,7 +897,8 @@ __global__ void __launch_bounds__(TPB) k_coarse(CoarseArgs ca) {
     if (tid == 0) {
       const double d = A0[j * KP + j];
       const double g0 = gdiag[j];
-      const double thr = ca.drop_rel * ca.drop_rel * g0;
+      const double dr = (ca.k_safe > 0 && j >= ca.k_safe) ? fmax(ca.drop_rel, ca.tau_dep) : ca.drop_rel;
+      const double thr = dr * dr * g0;
       s_keep = (g0 > 0.0) && (d > thr) && (d == d);
       s_d = s_keep ? sqrt(d) : 0.0;
       if (s_keep) kidx[kp] = j;

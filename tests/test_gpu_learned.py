@@ -106,14 +106,23 @@ def test_forward_loss_and_gradient_match_oracle(lib, setup):
         assert np.linalg.norm(gg - go) <= 2e-2 * np.linalg.norm(go) + 1e-12, k
 
 
-def test_training_enriched_solves_safeguard_and_gain(lib, setup):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_training_enriched_solves_safeguard_and_gain(lib, setup, prec):
+    """FP64: the paper's precision.  Mixed (FP32 operator and panels, FP64
+    vectors and residual replacement): the learned vectors enter the FP32
+    per-instance panels, the shared leading columns come from the shared
+    modes and cond(E) is capped for FP32 panels; the solution must still
+    reach x* to 1e-8 and the safeguard must behave as in FP64."""
     w, op, thetas, insts, xs, X, Phi, sig = setup
-    case("train on 48 samples, enriched batched solves on 12 held-out instances")
+    case(f"train on 48 samples, enriched batched solves on 12 held-out instances ({prec})")
     prm, flat = _params(4)
-    s = lib.Solver()
+    s = lib.Solver(precision=lib.FP64 if prec == "fp64" else lib.MIXED_REFINE)
     s.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
-    s.set_pod_modes(Phi)
-    s.learned_set_params(flat)
+    if prec == "fp64":
+        s.set_pod_modes(Phi)
+        s.learned_set_params(flat)
+    else:
+        s.set_enrichment(Phi, flat)
     th = thetas.astype(np.float32)
     s.learned_prepare(np.stack([i.mask for i in insts[:MTR]]), np.stack([i.b for i in insts[:MTR]]),
                       xs[:MTR], th[:MTR])
@@ -139,19 +148,29 @@ def test_training_enriched_solves_safeguard_and_gain(lib, setup):
                                     tau_cond=1e8)
         e = oracle.rel_err(Xl[j, I], xs[m][I])
         assert lrn["status"][j] == 0
-        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs[m][I]))
-        if lrn["learned"][j] and ref.status == 0:
-            assert abs(int(lrn["iters"][j]) - ref.iters) <= max(3, ref.iters // 20)
+        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs[m][I])), (m, e)
+        if prec == "fp64":
+            if lrn["learned"][j] and ref.status == 0:
+                assert abs(int(lrn["iters"][j]) - ref.iters) <= max(3, ref.iters // 20)
+        else:
+            assert lrn["relres_true"][j] <= 1e-10
+            if lrn["learned"][j] and ref.status == 0:
+                assert int(lrn["iters"][j]) <= 1.5 * ref.iters + 50
     print(f"   iterations plain {plain['iters'].tolist()} learned {lrn['iters'].tolist()} "
-          f"learned-used {lrn['learned'].tolist()}", flush=True)
-    assert lrn["iters"].mean() <= plain["iters"].mean()
+          f"learned-used {lrn['learned'].tolist()} cond(E) {np.round(lrn['cond_E'], 1).tolist()}", flush=True)
+    assert lrn["learned"].sum() > 0
+    if prec == "fp64":
+        assert lrn["iters"].mean() <= plain["iters"].mean()
     # safeguard: an unattainable conditioning bound falls back to the plain basis
     s.learned_set_params(params, tau_learned=1.0)
     fb = s.solve_batched(masks, bs, 1e-10, theta=th[test])
     assert np.all(fb["learned"] == 0)
     # same basis as the plain solve; the wider buffers of the enriched basis may
-    # tune to another tile height, so the reduction order (rounding) can differ
-    assert np.all(np.abs(fb["iters"].astype(int) - plain["iters"].astype(int)) <= 2)
+    # tune to another kernel variant (tile height; in mixed precision the
+    # plain basis may run the tile-major boundary form), so the reduction
+    # order (rounding) can differ
+    tol_it = 2 if prec == "fp64" else np.maximum(2, plain["iters"] // 20)
+    assert np.all(np.abs(fb["iters"].astype(int) - plain["iters"].astype(int)) <= tol_it)
     Xf = fb["x"].cpu().numpy()
     for j, m in enumerate(test):
         I, _, _ = oracle.compact(insts[m].mask)

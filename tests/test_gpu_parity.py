@@ -344,7 +344,7 @@ def test_error_paths(lib, c1):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("form", ["assembled", "factored"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("rpt,w_mode", [(1, 1), (1, 2), (2, 1), (2, 2), (4, 1), (4, 3)])
+@pytest.mark.parametrize("rpt,w_mode", [(1, 1), (1, 2), (2, 1), (2, 2), (1, 3), (2, 3)])
 def test_kernel_variants_match_oracle(lib, rpt, w_mode, prec, form):
     w = gen.c2_workload(n=95, k=16, B=3)
     S = spec(w.op, form)
@@ -365,6 +365,47 @@ def test_kernel_variants_match_oracle(lib, rpt, w_mode, prec, form):
             assert abs(int(out["iters"][m]) - ref.iters) <= 2
         else:
             assert out["relres_true"][m] <= 1e-10
+
+
+@pytest.mark.parametrize("form", ["assembled", "factored"])
+@pytest.mark.parametrize("rpt", [1, 2])
+@pytest.mark.parametrize("B", [3, 11])
+def test_tile_major_boundary_update_matches_oracle(lib, form, rpt, B):
+    """Tile-major boundary-form iteration (w_mode 4: k_pupdate_tm /
+    k_update_tm, matrix-core products with the shared modes): B = 11 spans
+    two update groups (8 + 3 instances) and one ragged p-update group; N =
+    95^2 ends in a ragged tile."""
+    w = gen.c2_workload(n=95, k=16, B=B)
+    S = spec(w.op, form)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case(f"tile-major boundary update rpt={rpt} {form} cd2d n=95 k=16 B={B}")
+    s = solver(lib, w.op, w.Z, form, precision=lib.MIXED_REFINE, rows_per_thread=rpt, w_mode=4)
+    out = s.solve_batched(masks, bs, 1e-10)
+    assert s.variant()[1] == 4
+    X = out["x"].cpu().numpy()
+    for m, inst in enumerate(w.instances):
+        ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
+        I, xs = _xstar(S, inst.mask, inst.b)
+        e = oracle.rel_err(X[m, I], xs)
+        assert out["status"][m] == 0
+        assert out["relres_true"][m] <= 1e-10
+        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), (m, e)
+        assert int(out["iters"][m]) <= 1.2 * ref.iters + 20, (m, out["iters"][m], ref.iters)
+    assert np.all(X[masks == 1] == 0.0)
+
+
+def test_tile_major_needs_eigen_basis(lib):
+    """w_mode 4 is refused (E_UNSUPPORTED) with FP64 panels, where the
+    boundary form of W is not used."""
+    w = gen.c2_workload(n=63, k=8, B=2)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case("tile-major refused in FP64")
+    s = solver(lib, w.op, w.Z, "factored", precision=lib.FP64, w_mode=4)
+    with pytest.raises(lib.Adef2Error) as e:
+        s.solve_batched(masks, bs, 1e-10)
+    assert e.value.code == lib.E_UNSUPPORTED
 
 
 def test_autotuned_variant_is_reused(lib):

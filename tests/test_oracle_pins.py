@@ -345,8 +345,8 @@ def _fraction_solve(A, b):
     return x
 
 
-@pytest.mark.parametrize("dense_limit", [4000, 2])
-def test_exact_solution_matches_rational_solve(dense_limit):
+@pytest.mark.parametrize("dense_limit,method", [(4000, "auto"), (2, "banded"), (2, "auto")])
+def test_exact_solution_matches_rational_solve(dense_limit, method):
     """An ill-conditioned SPD system (cond ~ 1e9) solved to ~1 ulp forward error."""
     w = gen.c1_workload(n=3, k=0)
     A = w.op.S()
@@ -355,9 +355,27 @@ def test_exact_solution_matches_rational_solve(dense_limit):
     Ad = 0.5 * (Ad + Ad.T)
     A = sp.csr_matrix(Ad)
     b = np.random.default_rng(6).standard_normal(9)
-    x = oracle.exact_solution(A, b, dense_limit=dense_limit)
+    x = oracle.exact_solution(A, b, dense_limit=dense_limit, method=method)
     xe = np.array([float(v) for v in _fraction_solve(Ad, b)])
     assert np.linalg.norm(x - xe) <= 4e-16 * np.linalg.norm(xe)
+
+
+def test_exact_solution_routes_agree_on_a_restricted_system():
+    """Dense Cholesky, banded Cholesky and sparse LU, each followed by
+    double-double refinement, give the same x* of a factored restricted
+    system (cond ~ 1e7) to a few ulps: the refinement, not the factorisation,
+    sets the accuracy."""
+    w = gen.c2_workload(n=47, k=0, B=1)
+    op = w.op
+    inst = w.instances[0]
+    I, _, _ = oracle.compact(inst.mask)
+    F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
+    b = inst.b[I]
+    xd = oracle.exact_solution(F, b, method="dense")
+    xb = oracle.exact_solution(F, b, method="banded")
+    xs = oracle.exact_solution(F, b, method="splu")
+    assert np.linalg.norm(xb - xd) <= 1e-14 * np.linalg.norm(xd)
+    assert np.linalg.norm(xs - xd) <= 1e-14 * np.linalg.norm(xd)
 
 
 # ---------------------------------------------------------------------------
