@@ -1,28 +1,37 @@
 """Benchmark: restricted A-DEF2 solves per second on the 511 x 511 upwind
 convection-diffusion Schur complement (k = 32 reference modes, 16 instances
-with 10-40 % active, rel. residual 1e-10).
+with 10-40 % active, relative residual 1e-10), every instance checked
+against x* (e_rel <= 1e-8).
 
-One step = MLP inference + basis enrichment + restrict + coarse setup +
-solve for all 16 instances.
-  headline : all 16 instances in one batched launch sequence with the
-             learned enrichment (8 vectors from the problem parameters) and
+One step = restrict + coarse setup + solve for all 16 instances.
+  headline (value): the 16 instances in one batched launch sequence,
              precision per --precision (default mixed: FP32 operator and
-             panels, FP64 vectors, FP64 residual replacement)
-  batched  : the same without enrichment (reference modes only)
-  plain    : FP64 A-DEF2, one instance at a time
-Before timing, the enrichment is fitted once: GPU solves of --train family
-members (snapshots), their POD on the GPU, and --train-steps Adam steps of
-the MLP on the GPU.
-Prints one JSON line (see the contract in the repository README / DESIGN).
+             panels, FP64 vectors, FP64 residual replacement).  When the
+             learned enrichment passes its gain test (held-out family
+             members) it is part of the step and config.mode says so;
+             otherwise the step uses the reference modes and mode is
+             "batched".
+Arms reported next to it (never the headline value):
+  plain          FP64 A-DEF2, one instance at a time (the paper's setting)
+  learned        batched + learned enrichment forced on, same 16 instances
+  pod_merge      the paper's POD safe merge (Alg. 2) as the non-learned
+                 comparator
+  c5             127^3 x 16 two-material 3D workload (k = 64 prolonged
+                 coarse modes): batched mixed vs plain FP64
+  cpu_baseline   the C/OpenMP build of the oracle's A-DEF2 loop on the
+                 host cores (all cores and one core), bounded samples
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import platform
+import subprocess
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -32,10 +41,14 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=511)
     ap.add_argument("--k", type=int, default=32)
@@ -46,18 +59,17 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--force-learned", action="store_true",
-                    help="apply the enrichment even when its gain test fails")
-    ap.add_argument("--no-batched-compare", action="store_true")
+                    help="make the headline step use the enrichment even when its gain test fails")
     ap.add_argument("--train", type=int, default=40, help="snapshot solves for the enrichment")
     ap.add_argument("--pod", type=int, default=32, help="POD modes the MLP combines")
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--snap-tol", type=float, default=1e-8)
     ap.add_argument("--rpt", type=int, default=0, choices=[0, 1, 2],
-                    help="rows per thread of the iteration kernels (0 = tuned)")
-    ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2, 3, 4],
+                    help="rows per thread of the per-instance iteration kernels (0 = tuned)")
+    ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2, 3, 4, 5],
                     help="1 = read W, 2 = W-free tile-major, 3 = W-free per instance, "
-                         "4 = tile-major boundary form, 0 = tuned")
+                         "4 = tile-major boundary form, 5 = 4 with tile-major stencils, 0 = tuned")
     ap.add_argument("--w-boundary", type=int, default=2, choices=[0, 1, 2],
                     help="boundary form of W for eigen reference modes: 0 off, 1 on, "
                          "2 when every reference mode is an eigenvector")
@@ -67,45 +79,110 @@ def parse():
                          "prints no benchmark line")
     ap.add_argument("--counter-maxit", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-pod-merge", action="store_true",
-                    help="skip the POD safe-merge comparator arm (reported, never the headline)")
-    ap.add_argument("--pod-merge-p", type=int, default=8, help="POD candidates of the comparator arm")
+    ap.add_argument("--cpu-iters", type=int, default=400,
+                    help="C-oracle iterations per timed sample on all cores (one core: a quarter)")
+    ap.add_argument("--cpu-reps", type=int, default=5, help="repetitions per CPU sample (median)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time full C-oracle solves of instance 0 (all cores; minutes)")
+    ap.add_argument("--no-xstar", action="store_true", help="skip e_rel of the headline against x*")
+    ap.add_argument("--no-pod-merge", action="store_true")
+    ap.add_argument("--pod-merge-p", type=int, default=8)
     ap.add_argument("--tau-safe", type=float, default=1e4)
-    ap.add_argument("--cpu-iters", type=int, default=200,
-                    help="oracle iterations timed for the CPU baseline sample")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 127^3 arm")
+    ap.add_argument("--c5-n", type=int, default=127)
+    ap.add_argument("--c5-nc", type=int, default=31)
+    ap.add_argument("--c5-plain", type=int, default=2, help="plain FP64 instances timed in the 3D arm")
+    ap.add_argument("--no-profile", action="store_true", help="skip the instrumented roofline pass")
     return ap.parse_args()
 
 
-def cpu_baseline(w, S_spec, iters_ref: float, n_iter: int):
-    """Time the FP64 oracle on a bounded sample of instance 0: restriction,
-    coarse setup and n_iter A-DEF2 iterations; scale to solves/s with the
-    iteration count the GPU FP64 path needed (mean over the batch)."""
+def host_info():
+    model = platform.processor() or ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except Exception:
+        aff = os.cpu_count() or 1
+    return model, aff, os.cpu_count() or 1
+
+
+def cpu_baseline(w, spec, iters_ref: float, args):
+    """The C/OpenMP build of the oracle's A-DEF2 loop (oracle/cpu_adef2.c) on
+    instance 0 of the timed batch: restriction and the orthonormal restricted
+    basis by the Python oracle, then the C coarse setup and iteration.
+    Bounded samples: a fixed number of iterations, median of repetitions,
+    scaled to one solve with the iteration count of the GPU FP64 arm; on all
+    host cores the sampler uses and on one core."""
     import oracle
-    from threadpoolctl import threadpool_limits
+    from oracle import cpu
     inst = w.instances[0]
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        I, _, nI = oracle.compact(inst.mask)
-        S_II, d_I = oracle.restricted_operator(S_spec, I)
-        Zo, kept = oracle.restricted_basis(w.Z, I)
-        cs, fb = oracle.coarse_setup(S_II, Zo)
-        t1 = time.perf_counter()
-        oracle.adef2(S_II, inst.b[I], cs, 1e-30, maxit=n_iter)
-        t2 = time.perf_counter()
-    t_setup = t1 - t0
-    t_it = (t2 - t1) / n_iter
-    per_solve = t_setup + iters_ref * t_it
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"instance 0 (n_I={nI}): restriction + QR + coarse setup ({t_setup:.2f} s) and "
-                       f"{n_iter} FP64 A-DEF2 iterations ({t_it * 1e3:.2f} ms/iteration), scaled to "
-                       f"{iters_ref:.0f} iterations per solve (GPU FP64 mean)"),
-            "seconds_per_solve": per_solve}
+    I, _, nI = oracle.compact(inst.mask)
+    S_II, _ = oracle.restricted_operator(spec, I)
+    A = S_II.assembled()
+    Zo, _ = oracle.restricted_basis(w.Z, I)
+    b = inst.b[I]
+    model, aff, ncpu = host_info()
+    res = {}
+    for label, threads, its in (("all_cores", aff, args.cpu_iters), ("one_core", 1, max(50, args.cpu_iters // 4))):
+        cpu.adef2(A, b, Zo, 1e-30, maxit=10, threads=threads)          # warm-up
+        per_it, setup = [], []
+        for _ in range(args.cpu_reps):
+            r = cpu.adef2(A, b, Zo, 1e-30, maxit=its, threads=threads)
+            per_it.append(r.solve_s / r.iters)
+            setup.append(r.setup_s)
+        t_it = float(np.median(per_it))
+        t_set = float(np.median(setup))
+        per_solve = t_set + iters_ref * t_it
+        res[label] = {"value": 1.0 / per_solve, "unit": "solves/s", "cores": threads,
+                      "seconds_per_solve": per_solve, "ms_per_iteration": t_it * 1e3,
+                      "coarse_setup_s": t_set,
+                      "sample": f"{its} iterations x {args.cpu_reps} repetitions (median), instance 0"}
+    full = None
+    if args.cpu_full:
+        r = cpu.adef2(A, b, Zo, args.tol, threads=aff)
+        full = {"iters": r.iters, "seconds": r.setup_s + r.solve_s, "cores": aff,
+                "solves_per_s": 1.0 / (r.setup_s + r.solve_s), "converged": r.converged}
+    best = res["all_cores"]
+    return {"value": round(best["value"], 6), "unit": "solves/s", "cores": best["cores"], "kind": "oracle",
+            "sample": (f"C/OpenMP FP64 A-DEF2 (oracle/cpu_adef2.c) on instance 0 (n_I={nI}, k={Zo.shape[1]}): "
+                       f"coarse setup + {args.cpu_iters} iterations, median of {args.cpu_reps}, scaled to "
+                       f"{iters_ref:.0f} iterations per solve (GPU FP64 mean); restriction and QR by the "
+                       f"Python oracle, not timed"),
+            "one_core": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in res["one_core"].items()},
+            "all_cores": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in res["all_cores"].items()},
+            "full_solve": full,
+            "host": {"model": model, "cores_available": aff, "cpu_count": ncpu}}
 
 
-def fit_enrichment(solver, args, lib):
-    """Fit the learned enrichment of solver on GPU data: snapshot solves of
-    args.train family members (parameter seed 700, disjoint from the timed
-    instances), POD of the snapshots, MLP training.  Returns a summary."""
+def xstar_errors(w, X):
+    """e_rel of each instance's solution against x* (oracle: sparse direct
+    factorisation with double-double refinement)."""
+    import oracle
+    op = w.op
+
+    def one(m):
+        inst = w.instances[m]
+        I, _, _ = oracle.compact(inst.mask)
+        F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
+        xs = oracle.exact_solution(F, inst.b[I])
+        return oracle.rel_err(X[m, I], xs)
+
+    with ThreadPoolExecutor(8) as ex:
+        return list(ex.map(one, range(len(w.instances))))
+
+
+def fit_enrichment(solver, args, op):
+    """Fit the learned enrichment on GPU data: snapshot solves of args.train
+    family members (parameter seed 700, disjoint from the timed instances),
+    POD of the snapshots, MLP training on the GPU.  Gain test on 16 held-out
+    family members (seed 900): batched solves with and without the
+    enrichment at the timed tolerance; kept when it saves >= 2 % time."""
     import torch
 
     import gen
@@ -119,7 +196,7 @@ def fit_enrichment(solver, args, lib):
     snap = solver.solve_batched(m_tr, b_tr, args.snap_tol)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    print(f"[bench] {args.train} snapshot solves in {t2 - t1:.1f}s", file=sys.stderr, flush=True)
+    log(f"{args.train} snapshot solves in {t2 - t1:.1f}s")
     X = snap["x"]
     Phi, sig = solver.pod(X.T, args.pod)
     if not sig[0] > 0:
@@ -129,34 +206,35 @@ def fit_enrichment(solver, args, lib):
     hist = solver.learned_train(args.train_steps, lr=args.lr)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    print(f"[bench] POD + {args.train_steps} training steps in {t3 - t2:.1f}s "
-          f"(loss {hist[0]:.4f} -> {hist[-1]:.4f})", file=sys.stderr, flush=True)
-    # gain test: batched solves of 16 training members (tolerance of the
-    # timed solves) with and without the enrichment; it is kept only if it
-    # saves time (enrichment adds 8 columns to every panel pass)
-    sel = slice(0, min(16, args.train))
+    log(f"POD + {args.train_steps} training steps in {t3 - t2:.1f}s (loss {hist[0]:.4f} -> {hist[-1]:.4f})")
+    del m_tr, b_tr, X, snap
+    thh = gen.c2_thetas(16, 900)
+    hold = [gen.c2_family_instance(args.n, t) for t in thh]
+    m_h = torch.as_tensor(np.stack([i.mask for i in hold]), device="cuda")
+    b_h = torch.as_tensor(np.stack([i.b for i in hold]), device="cuda")
+    th_h = torch.as_tensor(thh.astype(np.float32), device="cuda")
 
     def timed_solve(theta, tol):
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        o = solver.solve_batched(m_tr[sel], b_tr[sel], tol, theta=theta)
+        o = solver.solve_batched(m_h, b_h, tol, theta=theta)
         torch.cuda.synchronize()
         return time.perf_counter() - ta, o
 
     timed_solve(None, 1e-6)                # kernel variants are tuned on the first solve
-    timed_solve(th_tr[sel], 1e-6)
+    timed_solve(th_h, 1e-6)
     t_plain, o_plain = timed_solve(None, args.tol)
-    t_lrn, o_lrn = timed_solve(th_tr[sel], args.tol)
+    t_lrn, o_lrn = timed_solve(th_h, args.tol)
     keep = t_lrn < 0.98 * t_plain
-    print(f"[bench] gain test on 16 training members: plain basis {t_plain:.2f}s, learned {t_lrn:.2f}s "
-          f"-> enrichment {'kept' if keep else 'not used'}", file=sys.stderr, flush=True)
+    log(f"gain test on 16 held-out members: reference modes {t_plain:.2f}s, learned {t_lrn:.2f}s -> "
+        f"enrichment {'kept' if keep else 'not used'}")
     return {"snapshots": args.train, "snapshot_tol": args.snap_tol, "pod_modes": args.pod,
             "sigma_ratio_last": float(sig[-1] / sig[0]), "train_steps": args.train_steps,
             "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
-            "snapshot_s": round(t2 - t1, 2), "fit_s": round(t3 - t2, 2),
-            "inputs_s": round(t1 - t0, 2),
-            "gain_test": {"instances": 16, "plain_s": round(t_plain, 3), "learned_s": round(t_lrn, 3),
-                          "plain_iters_mean": float(np.mean(o_plain["iters"])),
+            "snapshot_s": round(t2 - t1, 2), "fit_s": round(t3 - t2, 2), "inputs_s": round(t1 - t0, 2),
+            "gain_test": {"instances": "16 held-out family members (seed 900)",
+                          "reference_modes_s": round(t_plain, 3), "learned_s": round(t_lrn, 3),
+                          "reference_modes_iters_mean": float(np.mean(o_plain["iters"])),
                           "learned_iters_mean": float(np.mean(o_lrn["iters"])),
                           "learned_used": int(np.sum(o_lrn["learned"])), "kept": bool(keep)}}, Phi
 
@@ -180,13 +258,64 @@ def pod_merge_arm(args, lib, op, Z, Phi, masks, bs, prec, tune, t_head, head_ite
     s.close()
     it = np.asarray(o["iters"])
     B = masks.shape[0]
-    print(f"[bench] POD safe-merge arm: {t:.2f}s ({B / t:.3f} solves/s), iterations {it.mean():.0f} "
-          f"vs {head_iters.mean():.0f}", file=sys.stderr, flush=True)
+    log(f"POD safe-merge arm: {t:.2f}s ({B / t:.3f} solves/s), iterations {it.mean():.0f} vs {head_iters.mean():.0f}")
     return {"candidates": args.pod_merge_p, "tau_safe": args.tau_safe, "solves_per_s": round(B / t, 4),
             "vs_headline": round(t_head / t, 3), "iters_mean": float(it.mean()),
-            "headline_iters_mean": float(head_iters.mean()),
-            "cond_E_max": float(np.max(o["cond_E"])),
+            "headline_iters_mean": float(head_iters.mean()), "cond_E_max": float(np.max(o["cond_E"])),
             "relres_true_max": float(np.asarray(o["relres_true"]).max())}
+
+
+def c5_arm(args, lib, prec, tune):
+    """127^3 x 16 two-material 3D workload (k = 64 modes prolonged from the
+    coarse grid on the GPU, Alg. 4): batched (tuned, warmed up on a loose
+    tolerance) vs plain FP64 one instance at a time (a sample of instances
+    spanning the active fractions)."""
+    import torch
+
+    import gen
+    t0 = time.perf_counter()
+    w = gen.c5_workload(n=args.c5_n, k=64, B=16, nc=args.c5_nc)
+    log(f"3D workload {w.name} generated in {time.perf_counter() - t0:.1f}s")
+    op = w.op
+    masks = torch.as_tensor(np.stack([i.mask for i in w.instances]), device="cuda")
+    bs = torch.as_tensor(np.stack([i.b for i in w.instances]), device="cuda")
+    s = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
+    Zg = s.prolong_basis(w.meta["Zc"], 3, args.c5_n, args.c5_nc)
+    s.set_reference_factored(op.A, op.alpha, op.shift, Zg)
+    s.solve_batched(masks, bs, 1e-3)                 # variant tuning and graphs
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    o = s.solve_batched(masks, bs, 1e-8)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t1
+    it = np.asarray(o["iters"])
+    v = s.variant()
+    s.close()
+    log(f"3D batched: {t_b:.2f}s ({16 / t_b:.3f} solves/s), iterations mean {it.mean():.0f} max {it.max()}")
+    ps = lib.Solver(precision=lib.FP64)
+    ps.set_reference_factored(op.A, op.alpha, op.shift, Zg)
+    del Zg
+    sel = np.linspace(0, 15, max(1, args.c5_plain)).round().astype(int).tolist()
+    ps.restrict(masks[sel[0]])
+    ps.solve(bs[sel[0]], 1e-3)                       # warm-up: variant and graphs
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pit = []
+    for m in sel:
+        ps.restrict(masks[m])
+        pit.append(ps.solve(bs[m], 1e-8).iters)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t2
+    ps.close()
+    rate_p = len(sel) / t_p
+    log(f"3D plain FP64 sample {sel}: {t_p:.2f}s ({rate_p:.3f} solves/s)")
+    return {"workload": w.name, "grid": args.c5_n, "coarse_grid": args.c5_nc, "k": 64, "instances": 16, "tol": 1e-8,
+            "batched": {"solves_per_s": round(16 / t_b, 4), "seconds": round(t_b, 3), "iters_mean": float(it.mean()),
+                        "iters_max": int(it.max()), "status": np.asarray(o["status"]).tolist(),
+                        "relres_true_max": float(np.asarray(o["relres_true"]).max()),
+                        "variant": {"rows_per_thread": v[0], "w_mode": v[1]}},
+            "plain_fp64": {"solves_per_s": round(rate_p, 4), "instances_timed": sel, "iters": pit},
+            "speedup_vs_plain": round((16 / t_b) / rate_p, 3)}
 
 
 def measured_traffic(kernel: str):
@@ -196,7 +325,7 @@ def measured_traffic(kernel: str):
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in ("dev_common.h", "dev_kernels.h"):
+    for f in ("dev_common.h", "dev_kernels.h", "dev_tile.h"):
         with open(os.path.join(ROOT, "paper_2606_17971_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     sha = h.hexdigest()
@@ -229,27 +358,27 @@ def main():
     t = time.time()
     w = gen.c2_workload(n=args.n, k=args.k, B=args.batch)
     op = w.op
-    print(f"[bench] workload {w.name} generated in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+    log(f"workload {w.name} generated in {time.time() - t:.1f}s")
     masks = torch.as_tensor(np.stack([i.mask for i in w.instances]), device="cuda")
     bs = torch.as_tensor(np.stack([i.b for i in w.instances]), device="cuda")
     B = args.batch
     prec = {"mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE, "fp64": lib.FP64}[args.precision]
-
     tune = dict(rows_per_thread=args.rpt, w_mode=args.w_mode, w_boundary=args.w_boundary)
     head = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
     head.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     thetas = torch.as_tensor(np.stack([i.theta for i in w.instances]).astype(np.float32), device="cuda")
-    learned, Phi = (None, None) if args.no_learned else fit_enrichment(head, args, lib)
-    # the enrichment is applied only when its gain test passed
+
+    learned, Phi = (None, None)
+    if not args.no_learned and not args.counter_run:
+        learned, Phi = fit_enrichment(head, args, op)
     apply_learned = learned is not None and (args.force_learned or learned["gain_test"]["kept"])
-    if args.counter_run:
-        head.set_opts(maxit=args.counter_maxit)
     use_theta = thetas if apply_learned else None
 
     def head_step():
         return head.solve_batched(masks, bs, args.tol, theta=use_theta)
 
     if args.counter_run:
+        head.set_opts(maxit=args.counter_maxit)
         out = head_step()
         torch.cuda.synchronize()
         src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").uniform_()
@@ -260,56 +389,71 @@ def main():
         print(json.dumps({"counter_run": True, "iters": np.asarray(out["iters"]).tolist(),
                           "variant": list(head.variant()[:2]), "copy_bytes_each_way": src.numel() * 8}))
         return
+
     for _ in range(args.warmup):
         out = head_step()
     torch.cuda.synchronize()
+    head.reset_stats()
     t0 = time.perf_counter()
     for s in range(args.steps):
         out = head_step()
-        print(f"[bench] headline step {s} done", file=sys.stderr, flush=True)
+        log(f"headline step {s} done")
     torch.cuda.synchronize()
     t_head = (time.perf_counter() - t0) / args.steps
+    polls = head.polls() / args.steps
     head_iters = np.asarray(out["iters"])
     v_rpt, v_wm, v_ms = head.variant()
     head_rel = np.asarray(out["relres_true"])
     X_head = out["x"].clone()
+    value = B / t_head
+    log(f"headline {value:.4f} solves/s ({t_head * 1e3:.0f} ms/step, {polls:.0f} polls/step)")
 
-    batched = None
-    if apply_learned and not args.no_batched_compare:
+    learned_arm = None
+    if learned is not None:
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ob = head.solve_batched(masks, bs, args.tol)
+        tl = time.perf_counter()
+        ol = head.solve_batched(masks, bs, args.tol, theta=thetas)
         torch.cuda.synchronize()
-        t_b = time.perf_counter() - t0
-        bi = np.asarray(ob["iters"])
-        batched = {"solves_per_s": B / t_b, "ms_per_step": t_b * 1e3, "iters_mean": float(bi.mean()),
-                   "iters_max": int(bi.max()), "relres_true_max": float(np.asarray(ob["relres_true"]).max()),
-                   "iters_per_instance": bi.tolist(),
-                   "cond_E_max": float(np.max(ob["cond_E"]))}
-        print(f"[bench] batched (reference modes only) done ({t_b:.2f}s)", file=sys.stderr, flush=True)
+        t_l = time.perf_counter() - tl
+        li = np.asarray(ol["iters"])
+        num = torch.linalg.norm(ol["x"] - X_head, dim=1)
+        den = torch.linalg.norm(X_head, dim=1)
+        learned_arm = {"solves_per_s": round(B / t_l, 4), "ms_per_step": round(t_l * 1e3, 2),
+                       "iters_mean": float(li.mean()), "iters_max": int(li.max()),
+                       "learned_used": int(np.asarray(ol["learned"]).sum()),
+                       "cond_E_max": float(np.max(ol["cond_E"])),
+                       "relres_true_max": float(np.asarray(ol["relres_true"]).max()),
+                       "vs_headline_e_rel_max": float((num / den).max())}
+        log(f"batched + learned (forced): {t_l:.2f}s ({B / t_l:.3f} solves/s)")
+
+    xerr = None
+    if not args.no_xstar:
+        t1 = time.perf_counter()
+        e = xstar_errors(w, X_head.cpu().numpy())
+        xerr = {"e_rel_max": float(max(e)), "e_rel_per_instance": [float(v) for v in e],
+                "route": "sparse LU of the restricted factored operator + double-double refinement",
+                "seconds": round(time.perf_counter() - t1, 1)}
+        log(f"headline e_rel against x*: max {max(e):.2e}")
 
     pod_arm = None
     if Phi is not None and not args.no_pod_merge:
         try:
             pod_arm = pod_merge_arm(args, lib, op, w.Z, Phi, masks, bs, prec, tune, t_head, head_iters)
-        except Exception as e:            # reported, never fatal for the headline
-            pod_arm = {"error": str(e)}
+        except Exception as ex:            # reported, never fatal for the headline
+            pod_arm = {"error": str(ex)}
 
     plain = None
     if not args.no_plain:
         ps = lib.Solver(precision=lib.FP64)
         ps.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
-
-        def plain_step():
-            res = []
-            for m in range(B):
-                ps.restrict(masks[m])
-                res.append(ps.solve(bs[m], args.tol))
-            return res
-
+        ps.restrict(masks[0])
+        ps.solve(bs[0], 1e-6)                        # warm-up: variant and graphs
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = plain_step()
+        res = []
+        for m in range(B):
+            ps.restrict(masks[m])
+            res.append(ps.solve(bs[m], args.tol))
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         p_iters = np.array([r.iters for r in res])
@@ -317,53 +461,64 @@ def main():
         num = torch.linalg.norm(X_head - X_plain, dim=1)
         den = torch.linalg.norm(X_plain, dim=1)
         e_rel = (num / den).cpu().numpy()
-        plain = {"solves_per_s": B / t_plain, "ms_per_step": t_plain * 1e3,
+        plain = {"solves_per_s": round(B / t_plain, 4), "ms_per_step": round(t_plain * 1e3, 2),
                  "iters_mean": float(p_iters.mean()), "iters_max": int(p_iters.max()),
                  "relres_true_max": float(max(r.relres_true for r in res)),
                  "headline_vs_plain_e_rel_max": float(e_rel.max())}
-        print(f"[bench] plain step done ({t_plain:.2f}s)", file=sys.stderr, flush=True)
+        ps.close()
+        del X_plain
+        log(f"plain step done ({t_plain:.2f}s)")
 
-    # roofline: one instrumented headline step, HIP events around every launch
-    prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1,
-                      rows_per_thread=v_rpt, w_mode=v_wm, w_boundary=args.w_boundary)
-    prof.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
-    if apply_learned:
-        prof.set_pod_modes(Phi)
-        prof.learned_set_params(head.learned_get_params())
-    prof.solve_batched(masks, bs, args.tol, theta=use_theta)
-    st = prof.stats()
-    dom = max(st, key=lambda k: st[k]["ms"])
-    d = st[dom]
-    achieved = d["alg_bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
-    kernels = {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
-                   "alg_GBps": v["alg_bytes"] / (v["ms"] * 1e-3) / 1e9}
-               for k, v in st.items() if v["launches"] and v["ms"] > 0}
-    kp = ((args.k + (8 if apply_learned else 0)) + 7) // 8 * 8
-    vt, mt = {lib.MIXED_REFINE: ("double", "float"), lib.FP32_REFINE: ("float", "float"),
-              lib.FP64: ("double", "double")}[prec]
-    if dom in ("update_tm", "pupdate_tm"):
-        inst = f"k_{dom}<{mt}, {kp}>"
-    elif dom == "update":
-        inst = f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}, {'true' if args.w_boundary else 'false'}>"
-    else:
-        inst = f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}>"
-    tr = measured_traffic(inst)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["traffic"] if tr else None,
-                "kernel": dom, "instantiation": inst,
-                "alg_bytes_per_launch": round(d["alg_bytes"] / d["launches"]),
-                "avg_us": round(d["ms"] / d["launches"] * 1e3, 2), "kernels": kernels}
-    if tr:
-        roofline["traffic_alg_bytes_same_launches"] = tr["traffic_alg_bytes"]
-        roofline["traffic_source"] = tr["traffic_source"]
+    c5 = None
+    if not args.no_c5:
+        try:
+            c5 = c5_arm(args, lib, prec, tune)
+        except Exception as ex:            # reported, never fatal for the headline
+            c5 = {"error": str(ex)}
+
+    roofline = None
+    if not args.no_profile:
+        # one instrumented headline step: HIP events on the solver stream around every launch
+        prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1,
+                          rows_per_thread=v_rpt, w_mode=v_wm, w_boundary=args.w_boundary)
+        prof.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+        if apply_learned:
+            prof.set_pod_modes(Phi)
+            prof.learned_set_params(head.learned_get_params())
+        prof.solve_batched(masks, bs, args.tol, theta=use_theta)
+        st = prof.stats()
+        prof.close()
+        dom = max(st, key=lambda k: st[k]["ms"])
+        d = st[dom]
+        achieved = d["alg_bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
+        kernels = {k: {"launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2),
+                       "alg_GBps": round(v["alg_bytes"] / (v["ms"] * 1e-3) / 1e9, 1)}
+                   for k, v in st.items() if v["launches"] and v["ms"] > 0}
+        kp = ((args.k + (8 if apply_learned else 0)) + 7) // 8 * 8
+        vt, mt = {lib.MIXED_REFINE: ("double", "float"), lib.FP32_REFINE: ("float", "float"),
+                  lib.FP64: ("double", "double")}[prec]
+        if dom in ("update_tm", "pupdate_tm"):
+            inst = f"k_{dom}<{mt}, {kp}>"
+        elif dom == "update":
+            inst = f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}, {'true' if args.w_boundary else 'false'}>"
+        else:
+            inst = f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}>"
+        tr = measured_traffic(inst)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["traffic"] if tr else None,
+                    "kernel": dom, "instantiation": inst,
+                    "alg_bytes_per_launch": round(d["alg_bytes"] / d["launches"]),
+                    "avg_us": round(d["ms"] / d["launches"] * 1e3, 2), "kernels": kernels}
+        if tr:
+            roofline["traffic_alg_bytes_same_launches"] = tr["traffic_alg_bytes"]
+            roofline["traffic_source"] = tr["traffic_source"]
 
     cpu = None
     if not args.no_cpu_baseline:
         ref_iters = plain["iters_mean"] if plain else float(head_iters.mean())
-        spec = ("factored", op.A, op.alpha, op.shift)
-        cpu = cpu_baseline(w, spec, ref_iters, args.cpu_iters)
+        cpu = cpu_baseline(w, ("factored", op.A, op.alpha, op.shift), ref_iters, args)
+        log(f"CPU baseline: {cpu['value']:.5f} solves/s on {cpu['cores']} cores")
 
-    value = B / t_head
     line = {
         "metric": "solves/s + HBM GB/s at 511^2 grid; batched+learned vs plain at rel err <=1e-8",
         "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -376,23 +531,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"cd2d_upwind_{args.n}x{args.n}_k{args.k}_B{B}", "grid": args.n,
                    "N": op.N, "k": args.k, "instances": B, "tol": args.tol,
-                   "mode": "batched+learned" if learned is not None else "batched",
+                   "mode": "batched+learned" if apply_learned else "batched",
                    "learned_applied": bool(apply_learned),
                    "precision": args.precision,
                    "operator": "S = alpha A^T A + shift I (A: 5-point upwind, factored)"},
         "iters": {"mean": float(head_iters.mean()), "min": int(head_iters.min()),
                   "max": int(head_iters.max())},
+        "polls_per_step": polls,
         "variant": {"rows_per_thread": v_rpt, "w_mode": v_wm, "tuned": args.rpt == 0 or args.w_mode == 0,
-                    "trial_ms": [round(float(t), 3) for t in v_ms]},
-        "learned_used": (int(np.asarray(out["learned"]).sum()) if apply_learned else 0),
+                    "trial_ms": [round(float(tt), 3) for tt in v_ms]},
         "cond_E": {"min": float(np.min(out["cond_E"])), "max": float(np.max(out["cond_E"]))},
-        "iters_per_instance": np.asarray(out["iters"]).tolist(),
-        "learned_fit": learned,
-        "batched_reference_modes": batched,
-        "pod_merge": pod_arm,
+        "iters_per_instance": head_iters.tolist(),
         "relres_true_max": float(head_rel.max()),
+        "xstar": xerr,
         "plain": plain,
         "speedup_vs_plain": (round(value / plain["solves_per_s"], 3) if plain else None),
+        "learned_fit": learned,
+        "learned_arm": learned_arm,
+        "pod_merge": pod_arm,
+        "c5": c5,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -56,7 +56,7 @@ class Operator:
     """
     n: int
     dim: int
-    B: sp.csr_matrix
+    B: sp.csr_matrix | None      # None: assembled on first use as alpha A^T A
     shift: float
     name: str
     A: sp.csr_matrix | None = None
@@ -72,6 +72,8 @@ class Operator:
 
     def S(self, a: float = 1.0, c: float | None = None) -> sp.csr_matrix:
         c = self.shift if c is None else c
+        if self.B is None:
+            self.B = canonical_csr(self.alpha * (self.A.T @ self.A))
         M = (a * self.B + c * sp.identity(self.N, format="csr")).tocsr()
         return canonical_csr(M)
 
@@ -726,20 +728,39 @@ def c3_workload(n: int = 255, k: int = 32, B: int = 256, theta_seed: int = 310,
 
 
 def c5_operator(n: int = 127, seed: int = 600):
+    """K = h (7-point flux form) with kappa in {1, 1000}; S = K^2 / h^3 + 1e-2 h^3 I.
+    S is assembled only when asked for (50 M entries at 127^3); the solver
+    applies it in the factored form."""
     h = 1.0 / (n + 1)
     kap = inclusion_field_3d(n, seed)
     K = canonical_csr(diffusion_3d(kap))
-    B = canonical_csr((K @ K) / h ** 3)
-    op = Operator(n=n, dim=3, B=B, shift=1e-2 * h ** 3, name=f"cht3d_{n}", A=K, alpha=1.0 / h ** 3)
+    op = Operator(n=n, dim=3, B=None, shift=1e-2 * h ** 3, name=f"cht3d_{n}", A=K, alpha=1.0 / h ** 3)
     return op, K
 
 
-def c5_workload(n: int = 127, k: int = 64, B: int = 16, seed0: int = 700) -> Workload:
-    """3D two-material diffusion (1:1000 inclusions, 15% volume), S = K M_L^{-1} K + 1e-2 M_L."""
+def c5_workload(n: int = 127, k: int = 64, B: int = 16, seed0: int = 700, nc: int | None = None) -> Workload:
+    """3D two-material diffusion (1:1000 inclusions, 15% volume), S = K M_L^{-1} K + 1e-2 M_L.
+
+    Reference modes: with ``nc`` None, the k lowest eigenvectors of K itself
+    (they are S's; small grids).  With ``nc`` given (a coarse grid with
+    n + 1 = c (nc + 1), the paper's offline route for large grids, Sec.
+    "Coarse-grid eigenmode prolongation"), ``Z`` is None and ``meta`` holds
+    the k lowest eigenvectors ``Zc`` of the coarse operator K_c (the same
+    inclusion field on the nc^3 grid): the solver side prolongs and
+    orthonormalises them (Alg. 4)."""
     op, K = c5_operator(n)
-    Z = _cached(f"c5_Z_n{n}_k{k}", lambda: _low_symmetric(K, k)) if k > 0 \
-        else np.zeros((op.N, 0), order="F")
-    Z = np.asfortranarray(Z)
+    meta = {}
+    if nc is not None:
+        if (n + 1) % (nc + 1) != 0:
+            raise ValueError("coarse grid must satisfy n + 1 = c (nc + 1)")
+        _, Kc = c5_operator(nc)
+        Zc = _cached(f"c5_Z_n{nc}_k{k}", lambda: _low_symmetric(Kc, k))
+        meta = {"Zc": np.asfortranarray(Zc), "nc": nc}
+        Z = None
+    else:
+        Z = _cached(f"c5_Z_n{n}_k{k}", lambda: _low_symmetric(K, k)) if k > 0 \
+            else np.zeros((op.N, 0), order="F")
+        Z = np.asfortranarray(Z)
     insts = []
     for m in range(B):
         rho = 0.15 + 0.20 * m / max(B - 1, 1)
@@ -747,4 +768,4 @@ def c5_workload(n: int = 127, k: int = 64, B: int = 16, seed0: int = 700) -> Wor
         cen = np.random.default_rng(seed0 + 100 + m).uniform(0.2, 0.8, size=3)
         b = gaussian_bump(n, cen, dim=3)
         insts.append(Instance(mask=mask, b=b))
-    return Workload(name=f"c5_cht3d_n{n}_k{k}_B{B}", op=op, Z=Z, instances=insts, tol=1e-8)
+    return Workload(name=f"c5_cht3d_n{n}_k{k}_B{B}", op=op, Z=Z, instances=insts, tol=1e-8, meta=meta)

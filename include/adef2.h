@@ -121,7 +121,8 @@ typedef struct {
                            residual exceeds the segment's final recurrence
                            residual by more than 2x (drift), when the next
                            segment restarts; 0                              */
-  int32_t check_every;  /* iterations between host polls of convergence; 32 */
+  int32_t check_every;  /* iterations per captured chunk (one HIP graph of
+                           check_every iterations of every kernel); 32      */
   int32_t rows_per_thread; /* rows per thread of the per-instance iteration
                            kernels (tile height 256 or 512 rows): 1 or 2, or
                            0 = tuned on the first solve of each
@@ -146,8 +147,11 @@ typedef struct {
                            all instances that are all eigenvectors of the
                            reference operator, and w_boundary != 0
                            (E_UNSUPPORTED otherwise); 0 = tuned on the first
-                           solve of each configuration (4 is a candidate
-                           whenever it applies).  Tuning runs every candidate for
+                           solve of each configuration (4 and 5 are
+                           candidates whenever they apply); 5 = as 4 with the
+                           stencil passes tile-major as well (coefficients of
+                           a row read once for a group of instances; at most
+                           16 diagonals per stencil).  Tuning runs every candidate for
                            the first 64 iterations from the same start, keeps
                            the fastest per context (batch size, precision,
                            basis width, operator form, N) and reuses it, so
@@ -191,6 +195,13 @@ typedef struct {
                            before them is at most tau_dep of their restricted
                            norm are skipped (Alg. 2); the effective bound is
                            max(drop_rel, tau_dep); 1e-10                     */
+  int32_t poll_max;     /* chunks enqueued between two host polls, at most:
+                           convergence is decided on the device (blocks of a
+                           finished instance exit at once), and the host
+                           enqueues as many chunks as the slowest iterating
+                           instance is estimated to need (the decay of its
+                           residual since the last poll, halved), between 1
+                           and poll_max; 1 = poll after every chunk; 16    */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;
@@ -434,8 +445,8 @@ int adef2_active_set_batched(adef2_ctx *ctx, int32_t B, const double *y_d, const
                              int32_t *status);
 
 /* Iteration-kernel variant used by the last solve on ctx: rows per thread
- * (1 or 2) and w_mode (1, 2 or 3 as in adef2_opts), whether fixed by the
- * options or tuned.  ms (host f32[9], may be NULL) receives the trial times
+ * (1 or 2) and w_mode (1 .. 5 as in adef2_opts), whether fixed by the
+ * options or tuned.  ms (host f32[10], may be NULL) receives the trial times
  * of the tuned candidates, rows per thread outer, w_mode inner, restricted to
  * the candidates tried (0 when not tuned).  E_STATE before the first solve. */
 int adef2_variant(adef2_ctx *ctx, int32_t *rows_per_thread, int32_t *w_mode, float *ms);
@@ -446,9 +457,12 @@ typedef struct {
   int64_t launches[16];
   double total_ms[16];          /* HIP-event time summed over launches      */
   double alg_bytes[16];         /* algorithmic bytes summed over launches   */
+  int64_t polls;                /* host reads of the device convergence state
+                                   (counted in every mode, not only profile) */
 } adef2_stats;
 
-/* Per-kernel timings collected while opts.profile = 1. */
+/* Per-kernel timings collected while opts.profile = 1, and the number of
+ * host polls since the last reset. */
 int adef2_get_stats(adef2_ctx *ctx, adef2_stats *stats);
 int adef2_reset_stats(adef2_ctx *ctx);
 

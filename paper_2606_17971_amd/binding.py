@@ -49,6 +49,7 @@ class Opts(ctypes.Structure):
         ("ritz_keep", ctypes.c_int32),
         ("tau_safe", ctypes.c_double),
         ("tau_dep", ctypes.c_double),
+        ("poll_max", ctypes.c_int32),
     ]
 
 
@@ -59,6 +60,7 @@ class Stats(ctypes.Structure):
         ("launches", ctypes.c_int64 * 16),
         ("total_ms", ctypes.c_double * 16),
         ("alg_bytes", ctypes.c_double * 16),
+        ("polls", ctypes.c_int64),
     ]
 
 
@@ -131,6 +133,13 @@ def _dev(x, dtype) -> torch.Tensor:
     return t.contiguous()
 
 
+def _colmajor(Z) -> torch.Tensor:
+    """Column-major FP64 device copy of an N x k array (numpy or torch)."""
+    if isinstance(Z, torch.Tensor):
+        return Z.to(device="cuda", dtype=torch.float64).T.contiguous().reshape(-1)
+    return _dev(np.asfortranarray(Z, dtype=np.float64).ravel(order="F"), torch.float64)
+
+
 def _ptr(t) -> int | None:
     return None if t is None else t.data_ptr()
 
@@ -190,9 +199,7 @@ class Solver:
         ci = _dev(np.asarray(S.indices, dtype=np.int32), torch.int32)
         va = _dev(np.asarray(S.data, dtype=np.float64), torch.float64)
         k = 0 if Z is None else int(Z.shape[1])
-        Zt = None
-        if k > 0:
-            Zt = _dev(np.asfortranarray(Z, dtype=np.float64).ravel(order="F"), torch.float64)
+        Zt = _colmajor(Z) if k > 0 else None
         rc = _lib.adef2_set_reference(self._ctx, n, _ptr(rp), _ptr(ci), _ptr(va), int(S.nnz), k,
                                       _ptr(Zt))
         self._check(rc, allow=(OK,))
@@ -205,9 +212,7 @@ class Solver:
         ci = _dev(np.asarray(A.indices, dtype=np.int32), torch.int32)
         va = _dev(np.asarray(A.data, dtype=np.float64), torch.float64)
         k = 0 if Z is None else int(Z.shape[1])
-        Zt = None
-        if k > 0:
-            Zt = _dev(np.asfortranarray(Z, dtype=np.float64).ravel(order="F"), torch.float64)
+        Zt = _colmajor(Z) if k > 0 else None
         rc = _lib.adef2_set_reference_factored(self._ctx, n, _ptr(rp), _ptr(ci), _ptr(va),
                                                int(A.nnz), float(alpha), float(shift), k, _ptr(Zt))
         self._check(rc, allow=(OK,))
@@ -380,7 +385,7 @@ class Solver:
     def prolong_basis(self, Zc, dim: int, n: int, nc: int, tau_sv: float = 1e-10):
         """Coarse modes Zc (nc^dim x r) -> orthonormal fine-grid basis (n^dim x r')."""
         r = int(Zc.shape[1])
-        Zt = _dev(np.asfortranarray(Zc, dtype=np.float64).ravel(order="F"), torch.float64)
+        Zt = _colmajor(Zc)
         Nf = n ** dim
         out = torch.empty(Nf * r, dtype=torch.float64, device="cuda")
         ro = _i32(0)
@@ -404,7 +409,7 @@ class Solver:
     def variant(self):
         """(rows_per_thread, w_mode, trial ms) of the last solve."""
         r, wm = _i32(0), _i32(0)
-        ms = np.zeros(9, np.float32)
+        ms = np.zeros(10, np.float32)
         self._check(_lib.adef2_variant(self._ctx, ctypes.byref(r), ctypes.byref(wm), ms.ctypes.data),
                     allow=(OK,))
         return r.value, wm.value, ms
@@ -425,6 +430,12 @@ class Solver:
         self._check(_lib.adef2_get_stats(self._ctx, ctypes.byref(s)), allow=(OK,))
         return {s.name[i].decode(): dict(launches=s.launches[i], ms=s.total_ms[i],
                                          alg_bytes=s.alg_bytes[i]) for i in range(s.n_kernels)}
+
+    def polls(self) -> int:
+        """Host polls of the device convergence state since the last reset."""
+        s = Stats()
+        self._check(_lib.adef2_get_stats(self._ctx, ctypes.byref(s)), allow=(OK,))
+        return int(s.polls)
 
     def reset_stats(self):
         self._check(_lib.adef2_reset_stats(self._ctx), allow=(OK,))

@@ -167,7 +167,7 @@ struct adef2_ctx {
   int ub_ntiles = 0, ub_ntiles_pad = 0;    // tile-major boundary-form kernels (UB_ROWS-row tiles)
   RedGeom g_ub{};
   RedGeom g_bt{};
-  struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[9]; };
+  struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[10]; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
   int gram_blocks = 0;
@@ -180,6 +180,7 @@ struct adef2_ctx {
   int64_t st_launch[KI_COUNT] = {};
   double st_ms[KI_COUNT] = {};
   double st_bytes[KI_COUNT] = {};
+  int64_t st_polls = 0;          // host polls of the device state (all solves since reset)
   std::vector<long long> nI_host;
   std::vector<double> tol_h;     // per-instance tolerances of the current solve
 };
@@ -739,6 +740,7 @@ ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active
 }
 
 int poll(adef2_ctx* c, bool outer, bool* all_done) {
+  c->st_polls += 1;
   HIPCHK(c, hipMemcpyAsync(c->inst_h, c->inst, sizeof(Inst) * c->B, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   bool ad = true;
@@ -793,7 +795,7 @@ template <typename V, typename M>
 int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale, int rel_tol,
               double thresh_floor, int carry_dir, int max_chunks = 0) {
   // tile-major boundary-form kernels (w_mode 4): shared eigen-basis, FP64 vectors
-  const bool tm = c->wfree == 3 && c->KP > 0 && sizeof(V) == 8 && c->tm_ok;
+  const bool tm = (c->wfree == 3 || c->wfree == 4) && c->KP > 0 && sizeof(V) == 8 && c->tm_ok;
   const bool wfree = (c->wfree == 1 || c->wfree == 2) && c->KP > 0 && sizeof(V) == 8;
   // tile-major kernels (w_mode 2) need the basis shared by all instances
   const bool bt = wfree && c->wfree == 1 && c->zs == 0;
@@ -802,7 +804,7 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   const dim3 gut((unsigned)(c->ub_ntiles_pad * cdiv(c->B, UB_G)));
   const dim3 gfin((unsigned)cdiv(2 * c->KP + 2, FC), (unsigned)c->B);
   // tile-major stencil passes: coefficients of a row held in registers
-  const bool stm = tm && c->D <= SDR && (!c->factored || c->D1 <= SDR);
+  const bool stm = tm && c->wfree == 4 && c->D <= SDR && (!c->factored || c->D1 <= SDR);
   const dim3 gst((unsigned)(c->ub_ntiles_pad * cdiv(c->B, SG_G)));
   IterArgs<V, M> a = iter_args<V, M>(c);
   a.src = src;
@@ -896,6 +898,15 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
                                launch_chunk, &gexec);
     if (rc) return rc;
   }
+  // Convergence is decided on the device (finished instances' blocks exit at
+  // once); the host only has to notice that every instance is done.  Between
+  // polls it enqueues as many chunks as the slowest instance is estimated to
+  // still need: the decay of its squared residual since the last poll,
+  // extrapolated to its threshold, halved for safety (CG's residual is not
+  // monotone), at least one chunk, at most poll_max chunks.
+  const int pmax = std::max(1, c->o.poll_max);
+  std::vector<double> prev_rr(c->B, 0.0);
+  std::vector<int> prev_it(c->B, -1);
   int64_t launched = 0;
   for (;;) {
     bool ad = false;
@@ -905,18 +916,37 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
     // every instance stops at maxit on the device; this guards the host loop
     if (launched > (int64_t)c->o.maxit + 2 * chunk)
       return fail(c, ADEF2_E_HIP, "iteration kernels made no progress");
-    launched += chunk;
-    if (c->o.profile) bm = byte_model(c, (double)sizeof(V), (double)sizeof(M), true);
-    if (gexec) {
-      HIPCHK(c, hipEventRecord(c->gev_in, c->st));
-      HIPCHK(c, hipStreamWaitEvent(c->gst, c->gev_in, 0));
-      HIPCHK(c, hipGraphLaunch(gexec, c->gst));
-      HIPCHK(c, hipEventRecord(c->gev_out, c->gst));
-      HIPCHK(c, hipStreamWaitEvent(c->st, c->gev_out, 0));
-    } else {
-      launch_chunk(c->st);
+    double est = 0.0;
+    for (int m = 0; m < c->B; ++m) {
+      const Inst& s = c->inst_h[m];
+      if (s.done || s.outer_done) continue;
+      double rem = chunk;
+      if (prev_it[m] >= 0 && s.sweep_iters > prev_it[m] && s.rr > 0.0 && prev_rr[m] > s.rr &&
+          s.thresh2 > 0.0) {
+        const double rate = std::log(prev_rr[m] / s.rr) / (double)(s.sweep_iters - prev_it[m]);
+        rem = std::log(s.rr / s.thresh2) / rate;
+      }
+      rem = std::min(rem, (double)(c->o.maxit - s.iters));
+      est = std::max(est, rem);
+      prev_rr[m] = s.rr;
+      prev_it[m] = s.sweep_iters;
     }
-    HIPCHK(c, hipGetLastError());
+    int nrep = (int)std::min<double>((double)pmax, std::max(1.0, std::floor(0.5 * est / chunk)));
+    if (max_chunks > 0) nrep = std::min<int64_t>(nrep, std::max<int64_t>(1, max_chunks - launched / chunk));
+    for (int rep = 0; rep < nrep; ++rep) {
+      launched += chunk;
+      if (c->o.profile) bm = byte_model(c, (double)sizeof(V), (double)sizeof(M), true);
+      if (gexec) {
+        HIPCHK(c, hipEventRecord(c->gev_in, c->st));
+        HIPCHK(c, hipStreamWaitEvent(c->gst, c->gev_in, 0));
+        HIPCHK(c, hipGraphLaunch(gexec, c->gst));
+        HIPCHK(c, hipEventRecord(c->gev_out, c->gst));
+        HIPCHK(c, hipStreamWaitEvent(c->st, c->gev_out, 0));
+      } else {
+        launch_chunk(c->st);
+      }
+      HIPCHK(c, hipGetLastError());
+    }
     if (max_chunks > 0 && launched >= (int64_t)max_chunks * chunk) break;
   }
   return ADEF2_OK;
@@ -981,7 +1011,10 @@ int choose_variant(adef2_ctx* c, const double* b) {
   if (fw >= 2 && !vec64(c->prec))
     return fail(c, ADEF2_E_UNSUPPORTED, "W-free iterations need FP64 vectors (FP64 or MIXED_REFINE)");
   std::vector<int> rpts = (fr == 1 || fr == 2) ? std::vector<int>{fr} : std::vector<int>{1, 2};
-  if (fw == 4 && !c->tm_ok)
+  const bool stm_ok = c->D <= SDR && (!c->factored || c->D1 <= SDR);
+  if (fw == 5 && !stm_ok)
+    return fail(c, ADEF2_E_UNSUPPORTED, "tile-major stencil passes need at most 16 diagonals");
+  if ((fw == 4 || fw == 5) && !c->tm_ok)
     return fail(c, ADEF2_E_UNSUPPORTED,
                 "the tile-major boundary-form update needs FP32 panels with FP64 vectors (MIXED_REFINE), "
                 "reference modes shared by all instances that are eigenvectors of the reference operator, "
@@ -989,8 +1022,12 @@ int choose_variant(adef2_ctx* c, const double* b) {
   std::vector<int> wfs = (fw == 1 || c->KP == 0 || !vec64(c->prec)) ? std::vector<int>{0}
                          : (fw == 2 ? std::vector<int>{1}
                          : (fw == 3 ? std::vector<int>{2}
-                         : (fw == 4 ? std::vector<int>{3} : std::vector<int>{0, 1, 2})));
-  if (fw == 0 && c->tm_ok && c->KP > 0 && vec64(c->prec)) wfs.push_back(3);
+                         : (fw == 4 ? std::vector<int>{3}
+                         : (fw == 5 ? std::vector<int>{4} : std::vector<int>{0, 1, 2}))));
+  if (fw == 0 && c->tm_ok && c->KP > 0 && vec64(c->prec)) {
+    wfs.push_back(3);
+    if (stm_ok) wfs.push_back(4);
+  }
   if (rpts.size() * wfs.size() == 1) { set_variant(c, rpts[0], wfs[0]); return ADEF2_OK; }
   const int fact = c->factored ? 1 : 0;
   const int tmk = c->tm_ok ? 1 : 0;
@@ -1005,7 +1042,7 @@ int choose_variant(adef2_ctx* c, const double* b) {
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, tmk, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, tmk, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
   float best_ms = INFINITY;
   int rc = ADEF2_OK, ci = 0;
   for (int rpt : rpts) {
@@ -1134,9 +1171,9 @@ bool valid_opts(const adef2_opts* o) {
          (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
          o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0 &&
          (o->rows_per_thread == 0 || o->rows_per_thread == 1 || o->rows_per_thread == 2) &&
-         o->w_mode >= 0 && o->w_mode <= 4 && o->w_boundary >= 0 && o->w_boundary <= 2 &&
+         o->w_mode >= 0 && o->w_mode <= 5 && o->w_boundary >= 0 && o->w_boundary <= 2 &&
          (o->graph == 0 || o->graph == 1) && o->ritz_keep >= 0 && o->ritz_keep <= ADEF2_MAX_K &&
-         o->tau_safe >= 1.0 && o->tau_dep >= 0.0 && o->tau_dep < 1.0;
+         o->tau_safe >= 1.0 && o->tau_dep >= 0.0 && o->tau_dep < 1.0 && o->poll_max >= 1;
 }
 
 }  // namespace
@@ -1252,6 +1289,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->ritz_keep = 0;
   o->tau_safe = 1e4;
   o->tau_dep = 1e-10;
+  o->poll_max = 16;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
@@ -1876,11 +1914,11 @@ int adef2_variant(adef2_ctx* c, int32_t* rows_per_thread, int32_t* w_mode, float
   if (rows_per_thread) *rows_per_thread = c->rpt;
   if (w_mode) *w_mode = c->wfree + 1;
   if (ms) {
-    for (int i = 0; i < 9; ++i) ms[i] = 0.0f;
+    for (int i = 0; i < 10; ++i) ms[i] = 0.0f;
     const int fact = c->factored ? 1 : 0;
     for (const auto& t : c->tuned)
       if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N)
-        for (int i = 0; i < 9; ++i) ms[i] = t.ms[i];
+        for (int i = 0; i < 10; ++i) ms[i] = t.ms[i];
   }
   return ADEF2_OK;
 }
@@ -1917,6 +1955,7 @@ int adef2_get_stats(adef2_ctx* c, adef2_stats* s) {
     s->total_ms[i] = c->st_ms[i];
     s->alg_bytes[i] = c->st_bytes[i];
   }
+  s->polls = c->st_polls;
   return ADEF2_OK;
 }
 
@@ -1924,6 +1963,7 @@ int adef2_reset_stats(adef2_ctx* c) {
   if (!c) return ADEF2_E_ARG;
   ev_harvest(c);
   for (int i = 0; i < KI_COUNT; ++i) { c->st_launch[i] = 0; c->st_ms[i] = 0; c->st_bytes[i] = 0; }
+  c->st_polls = 0;
   return ADEF2_OK;
 }
 

@@ -1,6 +1,17 @@
-"""Parity at the benchmark's full size (511 x 511 upwind convection-diffusion,
-k = 32, tol 1e-10): sampled instances against x* from the oracle (banded
-Cholesky + double-double refinement of the factored operator)."""
+"""Parity at the benchmark's full size: the 511 x 511 upwind
+convection-diffusion workload, k = 32, the 16 benchmark instances in one
+batch, tol 1e-10, against x* of every instance (oracle route O9(i): sparse
+direct factorisation of the restricted factored operator plus double-double
+refinement, eq. (accuracy_rel_err)).
+
+Bars: e_rel <= 1e-8 for every instance in FP64 and in mixed precision; in
+mixed precision the FP64 true residual decides the stop, so its
+double-double value must also be at most 5e-10 on sampled instances (the
+FP64 rounding of x* itself has a relative residual of ~2e-10 on the
+largest inactive set, which is why status 3, "attainable accuracy
+reached", is accepted there)."""
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -18,42 +29,48 @@ def c2full():
 @pytest.fixture(scope="module")
 def xstars(c2full):
     op = c2full.op
-    out = {}
-    for m in (0, 15):
+
+    def one(m):
         inst = c2full.instances[m]
         I, _, _ = oracle.compact(inst.mask)
         F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
-        out[m] = (I, oracle.exact_solution(F, inst.b[I]), F)
-    return out
+        return I, oracle.exact_solution(F, inst.b[I]), F
+
+    with ThreadPoolExecutor(8) as ex:
+        return list(ex.map(one, range(len(c2full.instances))))
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_fullsize_batched_against_xstar(lib, c2full, xstars, prec):
-    print(f"[case] full-size 511^2 batched {prec} instances 0, 15", flush=True)
+    print(f"[case] full-size 511^2 batched {prec}, all 16 instances", flush=True)
     op = c2full.op
-    sel = [0, 15]
-    masks = np.stack([c2full.instances[m].mask for m in sel])
-    bs = np.stack([c2full.instances[m].b for m in sel])
+    B = len(c2full.instances)
+    masks = np.stack([i.mask for i in c2full.instances])
+    bs = np.stack([i.b for i in c2full.instances])
     p = lib.MIXED_REFINE if prec == "mixed" else lib.FP64
     s = lib.Solver(precision=p)
     s.set_reference_factored(op.A, op.alpha, op.shift, c2full.Z)
     out = s.solve_batched(masks, bs, 1e-10)
     print(f"   variant (rows/thread, w_mode, trial ms): {s.variant()}", flush=True)
     X = out["x"].cpu().numpy()
-    for j, m in enumerate(sel):
+    errs = []
+    for m in range(B):
         I, xs, F = xstars[m]
-        e = oracle.rel_err(X[j, I], xs)
-        # the FP64 rounding of x* itself has a relative residual of ~2e-10 on
-        # the largest inactive set, so that is the attainable floor
-        r_true = np.linalg.norm(oracle.dd_residual(F, X[j, I], c2full.instances[m].b[I])) / \
-            np.linalg.norm(c2full.instances[m].b[I])
-        print(f"   m={m} {prec}: e_rel={e:.3e} true relres={r_true:.3e} iters={out['iters'][j]} "
-              f"status={out['status'][j]}", flush=True)
+        e = oracle.rel_err(X[m, I], xs)
+        errs.append(e)
+        print(f"   m={m} n_I={len(I)} {prec}: e_rel={e:.3e} iters={out['iters'][m]} "
+              f"status={out['status'][m]} relres(FP64)={out['relres_true'][m]:.2e}", flush=True)
+        assert e <= 1e-8, (m, e)
         if prec == "mixed":
-            assert out["status"][j] in (0, 3)
-            assert r_true <= 5e-10
-            assert e <= 1e-8
+            assert out["status"][m] in (0, 3)
         else:
-            assert out["status"][j] == 0
-            assert e <= 1e-5
-    assert np.all(X[0, masks[0] == 1] == 0.0)
+            assert out["status"][m] == 0
+        assert np.all(X[m, masks[m] == 1] == 0.0)
+    print(f"   max e_rel {max(errs):.3e}", flush=True)
+    if prec == "mixed":
+        for m in (0, 15):
+            I, xs, F = xstars[m]
+            r_true = np.linalg.norm(oracle.dd_residual(F, X[m, I], c2full.instances[m].b[I])) / \
+                np.linalg.norm(c2full.instances[m].b[I])
+            print(f"   m={m} double-double true relres={r_true:.3e}", flush=True)
+            assert r_true <= 5e-10

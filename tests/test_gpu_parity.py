@@ -368,21 +368,22 @@ def test_kernel_variants_match_oracle(lib, rpt, w_mode, prec, form):
 
 
 @pytest.mark.parametrize("form", ["assembled", "factored"])
-@pytest.mark.parametrize("rpt", [1, 2])
+@pytest.mark.parametrize("rpt,w_mode", [(1, 4), (2, 4), (1, 5)])
 @pytest.mark.parametrize("B", [3, 11])
-def test_tile_major_boundary_update_matches_oracle(lib, form, rpt, B):
+def test_tile_major_boundary_update_matches_oracle(lib, form, rpt, w_mode, B):
     """Tile-major boundary-form iteration (w_mode 4: k_pupdate_tm /
-    k_update_tm, matrix-core products with the shared modes): B = 11 spans
+    k_update_tm / k_finish_tm, matrix-core products with the shared modes;
+    w_mode 5: also the tile-major stencil passes): B = 11 spans
     two update groups (8 + 3 instances) and one ragged p-update group; N =
     95^2 ends in a ragged tile."""
     w = gen.c2_workload(n=95, k=16, B=B)
     S = spec(w.op, form)
     masks = np.stack([i.mask for i in w.instances])
     bs = np.stack([i.b for i in w.instances])
-    case(f"tile-major boundary update rpt={rpt} {form} cd2d n=95 k=16 B={B}")
-    s = solver(lib, w.op, w.Z, form, precision=lib.MIXED_REFINE, rows_per_thread=rpt, w_mode=4)
+    case(f"tile-major boundary update rpt={rpt} w_mode={w_mode} {form} cd2d n=95 k=16 B={B}")
+    s = solver(lib, w.op, w.Z, form, precision=lib.MIXED_REFINE, rows_per_thread=rpt, w_mode=w_mode)
     out = s.solve_batched(masks, bs, 1e-10)
-    assert s.variant()[1] == 4
+    assert s.variant()[1] == w_mode
     X = out["x"].cpu().numpy()
     for m, inst in enumerate(w.instances):
         ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
@@ -462,3 +463,28 @@ def test_graph_replays_match_eager(lib, prec):
         np.testing.assert_array_equal(out["iters"], ref["iters"])
         np.testing.assert_array_equal(out["status"], ref["status"])
         np.testing.assert_array_equal(out["x"].cpu().numpy(), ref["x"].cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_adaptive_polling_matches_every_chunk_polling(lib, prec):
+    """Convergence is decided on the device: enqueuing several chunks between
+    host polls (poll_max 16) gives bitwise the result of polling after every
+    chunk (poll_max 1), with fewer polls."""
+    w = gen.c2_workload(n=95, k=16, B=4)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    p = lib.FP64 if prec == "fp64" else lib.MIXED_REFINE
+    case(f"adaptive polling {prec} cd2d n=95 B=4")
+    out, polls = [], []
+    for pm in (1, 16):
+        s = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=2, w_mode=1, poll_max=pm)
+        s.solve_batched(masks, bs, 1e-10)          # first solve: variant and graphs
+        s.reset_stats()
+        out.append(s.solve_batched(masks, bs, 1e-10))
+        polls.append(s.polls())
+    print(f"   polls every chunk {polls[0]}, adaptive {polls[1]}; iterations {out[0]['iters'].tolist()}",
+          flush=True)
+    np.testing.assert_array_equal(out[0]["iters"], out[1]["iters"])
+    np.testing.assert_array_equal(out[0]["status"], out[1]["status"])
+    np.testing.assert_array_equal(out[0]["x"].cpu().numpy(), out[1]["x"].cpu().numpy())
+    assert polls[1] < polls[0]
