@@ -55,8 +55,13 @@ def test_c3_full_batch_sampled(lib, c3full, prec):
     assert np.all(st == 0)
     rel = np.asarray(out["relres_true"])
     print(f"   true relative residual max {rel.max():.2e}", flush=True)
-    # mixed: the FP64 residual decides; FP64: the recurrence residual decides
-    # and the true one drifts (cond(S_II) up to ~1e9 here), e_rel is the bar
+    # mixed: the FP64 residual b - S x decides the stop, so it meets tol.
+    # FP64: as in the paper, the recurrence residual decides; rounding in the
+    # components of the largest eigenvalues makes the FP64 iterate's true
+    # residual drift above the recurrence one (cond(S_II) up to ~1e9 here)
+    # while e_rel, dominated by the smooth components, stays ~1e-11.  The
+    # oracle's own FP64 A-DEF2 drifts the same way: compared on the sampled
+    # instances below; e_rel against x* is the accuracy bar.
     assert np.all(rel <= (2e-8 if prec == "mixed" else 1e-5))
     nI = (masks == 0).sum(axis=1)
     np.testing.assert_array_equal(out["n_inactive"], nI)
@@ -74,8 +79,11 @@ def test_c3_full_batch_sampled(lib, c3full, prec):
         assert e <= 1e-8, (m, e)
         if prec == "fp64" and j in (0, 2):      # iteration parity on two of them (CPU time)
             ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-8)
-            print(f"      oracle iters {ref.iters}", flush=True)
+            print(f"      oracle iters {ref.iters}; true relres GPU {rel[m]:.2e} oracle {ref.relres_true:.2e}",
+                  flush=True)
             assert abs(int(out["iters"][m]) - ref.iters) <= max(2, ref.iters // 100)
+            # the same drift of the true residual as the oracle's FP64 loop
+            assert rel[m] <= 10 * ref.relres_true + 1e-9
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
