@@ -256,6 +256,22 @@ int adef2_set_operator_scale(adef2_ctx *ctx, double a, double c);
 int adef2_compact(adef2_ctx *ctx, const uint8_t *mask, int64_t n, int32_t *I,
                   int32_t *g2l, int64_t *n_inactive);
 
+/* adef2_compact without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same outputs as adef2_compact (I, g2l: device
+ * int32[n], may be NULL); the count goes to n_inactive_dev (device int64[1],
+ * may be NULL) and, when n_inactive (host) is not NULL, also to the host
+ * after one synchronisation of the context's stream (pass NULL to stay
+ * asynchronous, e.g. under capture).  Its chunk counts and offsets live in a
+ * static device array of the library (520 KiB per GPU, held until the
+ * process ends): n <= 2^28 (E_ARG beyond).  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (other streams or threads) race;
+ * calls ordered on one stream do not.  Nothing in it needs clearing: each
+ * call writes the counts and offsets before reading them.  E_STATE when the
+ * context's device is not current. */
+int adef2_compact_noalloc(adef2_ctx *ctx, const uint8_t *mask, int64_t n, int32_t *I,
+                          int32_t *g2l, int64_t *n_inactive_dev, int64_t *n_inactive);
+
 /* Restrict to the inactive set of mask (device uint8[n]) and build the coarse
  * space: restricted modes Z_I, their orthonormalisation (CholQR with column
  * dropping, folded into the k x k coarse matrix), W = S_II Z_I,

@@ -78,6 +78,7 @@ _sig = {
     "adef2_set_operator_scale": (ctypes.c_int, [_P, _f64, _f64]),
     "adef2_compact": (ctypes.c_int, [_P, _P, _i64, _P, _P, _Pi64]),
     "adef2_restrict": (ctypes.c_int, [_P, _P, _Pi64, _Pi32, _Pf64]),
+    "adef2_compact_noalloc": (ctypes.c_int, [_P, _P, _i64, _P, _P, _P, _Pi64]),
     "adef2_solve": (ctypes.c_int, [_P, _P, _P, _f64, _P, _Pi32, _Pf64, _Pf64]),
     "adef2_solve_batched": (ctypes.c_int, [_P, _i32, _P, _P, _P, _P, _P, _f64, _P, _P, _P, _P, _P, _P, _P,
                                            _P]),
@@ -238,6 +239,18 @@ class Solver:
         self._check(_lib.adef2_compact(self._ctx, _ptr(m), n, _ptr(I), _ptr(g2l), ctypes.byref(nI)),
                     allow=(OK,))
         return I[: nI.value], g2l, nI.value
+
+    def compact_noalloc(self, mask):
+        """adef2_compact_noalloc: (I, g2l, n_inactive, device count tensor)."""
+        m = _dev(mask, torch.uint8)
+        n = m.numel()
+        I = torch.empty(n, dtype=torch.int32, device="cuda")
+        g2l = torch.empty(n, dtype=torch.int32, device="cuda")
+        cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+        nI = _i64(0)
+        self._check(_lib.adef2_compact_noalloc(self._ctx, _ptr(m), n, _ptr(I), _ptr(g2l), _ptr(cnt),
+                                               ctypes.byref(nI)), allow=(OK,))
+        return I[: nI.value], g2l, nI.value, cnt
 
     def restrict(self, mask):
         m = _dev(mask, torch.uint8)

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,7 +16,35 @@
 
 using namespace adef2;
 
+// Scratch of the no-allocation compaction (adef2_compact_noalloc): chunk
+// counts, chunk offsets and the inactive count for masks of up to
+// NOALLOC_MAX_N entries (520 KiB).  Every GPU the library runs on holds one
+// copy until the process ends.  Host code never passes the symbol itself:
+// it uses the device address from hipGetSymbolAddress, taken once per device
+// with that device current (at adef2_create, or at the entry point's first
+// call on a device) and kept in g_scratch.
+constexpr int64_t NOALLOC_MAX_N = (int64_t)1 << 28;
+constexpr int64_t NOALLOC_CHUNKS = NOALLOC_MAX_N / adef2::CMP_CHUNK;
+constexpr size_t NOALLOC_BYTES = (size_t)NOALLOC_CHUNKS * 2 * sizeof(int) + 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
 namespace {
+
+constexpr int NOALLOC_MAX_DEV = 64;
+void* g_scratch[NOALLOC_MAX_DEV] = {};
+std::mutex g_scratch_mu;
+
+// device address of this device's scratch (dev must be current); null on failure
+void* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch[dev] = p;
+  }
+  return g_scratch[dev];
+}
 
 std::string g_create_error;
 
@@ -1305,6 +1334,7 @@ int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
   c->o = o;
   c->st = (hipStream_t)stream;
   c->dev = dev;
+  scratch_ptr(dev);          // the no-allocation entry point's scratch, once per device
   *out = c;
   return ADEF2_OK;
 }
@@ -1586,6 +1616,39 @@ int adef2_compact(adef2_ctx* c, const uint8_t* mask, int64_t n, int32_t* I, int3
   hipFree(tot);
   if (e != hipSuccess) return fail(c, ADEF2_E_HIP, hipGetErrorString(e));
   if (n_inactive) *n_inactive = t;
+  return ADEF2_OK;
+}
+
+int adef2_compact_noalloc(adef2_ctx* c, const uint8_t* mask, int64_t n, int32_t* I, int32_t* g2l,
+                          int64_t* n_inactive_dev, int64_t* n_inactive) {
+  if (!c || n < 0 || (n > 0 && !mask)) return ADEF2_E_ARG;
+  if (n > NOALLOC_MAX_N)
+    return fail(c, ADEF2_E_ARG, "compact_noalloc: n exceeds the 2^28 mask entries its static scratch holds");
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev != c->dev) return fail(c, ADEF2_E_STATE, "compact_noalloc: the context's device is not current");
+  void* base = scratch_ptr(dev);
+  if (!base) return fail(c, ADEF2_E_HIP, "compact_noalloc: hipGetSymbolAddress of the scratch failed");
+  const int nch = (int)cdiv(n, CMP_CHUNK);
+  int* cnt = (int*)base;
+  int* ofs = cnt + NOALLOC_CHUNKS;
+  long long* tot = (long long*)(ofs + NOALLOC_CHUNKS);
+  long long* tdst = n_inactive_dev ? (long long*)n_inactive_dev : tot;
+  if (n == 0) {
+    hipLaunchKernelGGL((k_fill<long long>), dim3(1), dim3(64), 0, c->st, tdst, (int64_t)1, 0LL);
+  } else {
+    // counts and offsets are written in full before they are read: nothing to clear
+    hipLaunchKernelGGL(k_compact_count, dim3(nch, 1), dim3(TPB), 0, c->st, n, mask, cnt, nch);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(TPB), 0, c->st, cnt, ofs, nch, tdst, (Inst*)nullptr);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nch, 1), dim3(TPB), 0, c->st, n, mask, ofs, nch, I, g2l);
+  }
+  HIPCHK(c, hipGetLastError());
+  if (n_inactive) {
+    long long t = 0;
+    HIPCHK(c, hipMemcpyAsync(&t, tdst, sizeof(long long), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    *n_inactive = t;
+  }
   return ADEF2_OK;
 }
 
