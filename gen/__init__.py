@@ -685,6 +685,24 @@ def mlp_params(seed: int = 0) -> np.ndarray:
     return np.concatenate(parts)
 
 
+def pod_snapshots(N: int, M: int, sigma, seed: int = 0):
+    """Snapshot columns with a prescribed centred spectrum:
+    X = mu 1^T + U diag(sigma) V^T with U (N x r) and V (M x r) orthonormal
+    and V^T 1 = 0, so the mean-centred matrix is exactly U diag(sigma) V^T
+    (its singular values are sigma, its left singular vectors U).
+    Returns X (N x M, column-major) and U."""
+    rng = np.random.default_rng(seed)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    r = len(sigma)
+    U = np.linalg.qr(rng.standard_normal((N, r)))[0]
+    G = rng.standard_normal((M, r))
+    G -= G.mean(axis=0, keepdims=True)
+    V = np.linalg.qr(G)[0]
+    mu = rng.standard_normal(N)
+    X = np.asfortranarray(mu[:, None] + (U * sigma) @ V.T)
+    return X, U
+
+
 def c3_operator(n: int = 255, seed: int = 300):
     h = 1.0 / (n + 1)
     G = gaussian_field_2d(n, seed)

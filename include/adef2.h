@@ -55,6 +55,8 @@ enum adef2_status {
   ADEF2_E_NOMEM = -4,       /* device allocation failed                      */
   ADEF2_E_NOT_SPD = -5,     /* non-positive diagonal or breakdown (p.Sp<=0)  */
   ADEF2_E_UNSUPPORTED = -6, /* operator has more than ADEF2_MAX_DIAGS diags  */
+  ADEF2_E_NOCONV = -7,      /* an iterative setup step (the eigensolver of
+                               adef2_pod for M > 256) did not converge       */
   ADEF2_W_FALLBACK = 1,     /* cond(E) > tau_cond or Cholesky of E failed:
                                solved as plain Jacobi-PCG (Alg. 3, Remark
                                tau_cond)                                     */
@@ -77,13 +79,21 @@ enum adef2_precision {
                                vectors (FP64 accumulation of dot products);
                                FP64 outer residual b - S x and FP64 x; the
                                k x k coarse algebra stays FP64               */
-  ADEF2_MIXED_REFINE = 2    /* as FP32_REFINE but with FP64 vectors: the
+  ADEF2_MIXED_REFINE = 2,   /* as FP32_REFINE but with FP64 vectors: the
                                operator values and the Z / W panels (most of
                                the bytes) are FP32, every vector and every
                                accumulation FP64.  Needed when cond(S) is
                                beyond 1 / FP32 roundoff: an FP32 vector's own
                                rounding noise is then amplified by
                                lambda_max / lambda of the modes it carries  */
+  ADEF2_FP64_REFINE = 3     /* FP64 segments (everything as in ADEF2_FP64),
+                               each run until its recurrence residual is
+                               below tol/2 (inner_rtol does not apply), then
+                               the FP64 residual b - S x replaces it; the stop
+                               is decided by the true residual.  For cond(S)
+                               so large that the FP64 recurrence residual
+                               drifts away from the true one (squared 3D
+                               operators with coefficient jumps)             */
 };
 
 enum adef2_precond {
@@ -104,13 +114,13 @@ typedef struct {
                            100000 (App. "CG stopping criterion")             */
   int32_t precision;    /* enum adef2_precision                              */
   int32_t precond;      /* enum adef2_precond                                */
-  double inner_rtol;    /* FP32_REFINE: an FP32 segment ends when its
+  double inner_rtol;    /* FP32_REFINE and MIXED_REFINE: a segment ends when its
                            recurrence residual fell to inner_rtol times the
                            FP64 residual it started from (or below tol/2
                            relative to ||b_I||); the FP64 residual b - S x
                            then replaces it and the search direction carries
                            on (residual replacement); 1e-2                   */
-  int32_t max_sweeps;   /* FP32_REFINE: cap on segments; 2000                */
+  int32_t max_sweeps;   /* refinement modes: cap on segments; 2000           */
   int32_t segment_maxit; /* refinement modes: a segment also ends after this
                            many iterations (periodic residual replacement);
                            < 0 = no cap, 0 = by precision (1000 with FP32
@@ -202,6 +212,15 @@ typedef struct {
                            instance is estimated to need (the decay of its
                            residual since the last poll, halved), between 1
                            and poll_max; 1 = poll after every chunk; 16    */
+  int32_t learned_objective; /* training objective of the learned enrichment,
+                           fixed when adef2_learned_prepare runs: 0 = energy
+                           capture (the fraction of the solution's energy
+                           the coarse correction with [Z_I, V_I] leaves);
+                           1 = deflated spectrum (log of the sum of the
+                           Ritz values of the Jacobi-preconditioned
+                           operator, deflated by Z_I, on span(V_I):
+                           small when V_I holds the slow modes that CG
+                           would otherwise have to resolve); 0             */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;
@@ -324,16 +343,27 @@ int adef2_solve_batched(adef2_ctx *ctx, int32_t B, const uint8_t *masks,
  * The enrichment vectors are V = Phi C^T, Phi = p POD modes of solution
  * snapshots (Sec. "Online POD enrichment": SVD of the mean-centred snapshot
  * matrix), C = MLP(theta) (8 x p; MLP 4 -> 128 -> 128 -> 8p, erf-GELU, BF16
- * weights, FP32 accumulation).  Training minimises the fraction of the
- * solution's energy norm that the A-DEF2 coarse correction with [Z_I, V_I]
- * leaves unresolved, L = 1 - (b_Z^T G_ZZ^-1 b_Z + s^T (C H C^T)^-1 s) / b^T x
- * (H, s defined from the Grams of [Z_I, Phi_I] under S_II).  Requires the
- * factored operator.  Parameter vector: 83200 FP32 values, packed
+ * weights, FP32 accumulation).  Training objective (opts.learned_objective):
+ *   0: the fraction of the solution's energy norm that the A-DEF2 coarse
+ *      correction with [Z_I, V_I] leaves unresolved,
+ *      L = 1 - (b_Z^T G_ZZ^-1 b_Z + s^T (C H C^T)^-1 s) / b^T x;
+ *   1: the deflated spectrum, L = log tr((C N C^T)^-1 C H C^T), the sum of
+ *      the Ritz values of D^-1 S_II (D = diag(S_II)) on span(V_I) after the
+ *      candidates are made S_II-orthogonal to Z_I;
+ * H = P~^T S_II P~, N = P~^T D P~, s = C (P~^T b) with P~ = Phi_I - Z_I
+ * G_ZZ^-1 G_ZP (Grams of [Z_I, Phi_I] under S_II).  Requires the factored
+ * operator.  Parameter vector: 83200 FP32 values, packed
  * W1[128][4], b1[128], W2[128][128], b2[128], W3[512][128], b3[512]. */
 
-/* POD modes of M snapshot columns X (device f64[n*M], column-major; 2 <= M
- * <= 256, 1 <= p < M, p <= 64), by the method of snapshots (Gram of the
- * centred snapshots, cyclic Jacobi eigensolver).  Keeps Phi in the context;
+/* POD modes of M snapshot columns X (device f64[n*M], column-major;
+ * 2 <= M <= 8192, 1 <= p < M, p <= 64) by the method of snapshots: the
+ * left singular vectors of the mean-centred snapshot matrix (Sec. "Online
+ * POD enrichment") from the eigenpairs of its M x M Gram.  M <= 256: cyclic
+ * Jacobi on the whole Gram.  M > 256: block subspace iteration with
+ * Rayleigh-Ritz on p + max(32, p/2) columns until every wanted pair has
+ * ||G v - theta v|| <= 1e-10 theta + 1e-13 theta_1 (E_NOCONV after 500
+ * iterations; the count is in adef2_stats.pod_iters).  Device memory:
+ * 8 (n M + 17 M^2) bytes at most while it runs.  Keeps Phi in the context;
  * Phi_out (device f64[n*p]) and sigma (host f64[p]) may be NULL. */
 int adef2_pod(adef2_ctx *ctx, int32_t M, const double *X, int32_t p, double *Phi_out,
               double *sigma);
@@ -361,9 +391,11 @@ int adef2_learned_set_params(adef2_ctx *ctx, const float *params, double tau_lea
 int adef2_learned_get_params(adef2_ctx *ctx, float *params);
 /* Training samples: masks (device u8[M*n]), right-hand sides b and solutions
  * xsol (device f64[M*n]), theta (device f32[M*4]), operator scales (host, or
- * NULL).  Computes per sample H (p x p), g (p), b_Z^T G_ZZ^-1 b_Z, b^T x.
- * E_ARG when a sample has b_I^T x_I <= 0 (x is not the solution, or b_I = 0);
- * E_UNSUPPORTED when k*k + k*(p+1) > 8192. */
+ * NULL).  Computes per sample H (p x p), g (p), b_Z^T G_ZZ^-1 b_Z, b^T x,
+ * and N (p x p) when opts.learned_objective = 1; the objective is fixed for
+ * these samples until the next call.  E_ARG when a sample has
+ * b_I^T x_I <= 0 (x is not the solution, or b_I = 0); E_UNSUPPORTED when
+ * k*k + k*(p+1) (+ k*p for objective 1) > 8192. */
 int adef2_learned_prepare(adef2_ctx *ctx, int32_t M, const uint8_t *masks, const double *b,
                           const double *xsol, const float *theta, const double *a,
                           const double *c);
@@ -475,6 +507,8 @@ typedef struct {
   double alg_bytes[16];         /* algorithmic bytes summed over launches   */
   int64_t polls;                /* host reads of the device convergence state
                                    (counted in every mode, not only profile) */
+  int64_t pod_iters;            /* subspace iterations of the last adef2_pod
+                                   (0: direct eigensolver, M <= 256)         */
 } adef2_stats;
 
 /* Per-kernel timings collected while opts.profile = 1, and the number of

@@ -19,6 +19,7 @@ import numpy as np
 
 __all__ = [
     "pod_modes", "LossData", "loss_data", "loss", "loss_grad", "coarse_energy_left",
+    "SpecData", "deflated_candidates", "spectral_data", "spectral_loss", "spectral_grad",
     "bf16_round", "gelu", "gelu_grad", "mlp_init", "mlp_forward", "mlp_backward",
     "adam_step", "DIMS",
 ]
@@ -88,6 +89,58 @@ def loss_grad(C: np.ndarray, d: LossData, eps: float = 0.0) -> np.ndarray:
     T = C @ d.H @ C.T + eps * np.eye(C.shape[0])
     u = np.linalg.solve(T, s)
     return -(2.0 * np.outer(u, d.g) - 2.0 * np.outer(u, u) @ C @ d.H) / d.bx
+
+
+# ---------------------------------------------------------------------------
+# deflated-spectrum loss of a learned enrichment (a reading of ours, like the
+# energy loss): CG's iteration count is governed by the spectrum of the
+# Jacobi-preconditioned operator left after deflation, so the enrichment
+# should hold its slowest modes.  With V = P~ C^T (P~: the candidates made
+# S_II-orthogonal to the reference modes), the sum of the Ritz values of
+# D^-1 S_II on span(V) is R(C) = tr((C N C^T)^-1 C H C^T),
+# H = P~^T S_II P~, N = P~^T D P~, D = diag(S_II); the loss is log R.
+# ---------------------------------------------------------------------------
+class SpecData:
+    """Per-sample H = P~^T S_II P~ and N = P~^T D P~ (p x p)."""
+
+    def __init__(self, H, N):
+        self.H, self.N = H, N
+
+
+def deflated_candidates(S_II, Z_I: np.ndarray, Phi_I: np.ndarray) -> np.ndarray:
+    """P~ = Phi_I - Z_I (Z_I^T S_II Z_I)^-1 Z_I^T S_II Phi_I: the candidates
+    with their S_II-projection onto span(Z_I) removed (A-DEF2's coarse space
+    is S_II-orthogonal to what the iteration sees)."""
+    SZ = np.asarray(S_II @ Z_I)
+    Gzz = Z_I.T @ SZ
+    Gzz = 0.5 * (Gzz + Gzz.T)
+    return Phi_I - Z_I @ np.linalg.solve(Gzz, SZ.T @ Phi_I)
+
+
+def spectral_data(S_II, Z_I: np.ndarray, Phi_I: np.ndarray) -> SpecData:
+    """H and N of the deflated-spectrum loss, from P~ written out."""
+    P = deflated_candidates(S_II, Z_I, Phi_I)
+    d = np.asarray(S_II.diagonal()).ravel()
+    H = P.T @ np.asarray(S_II @ P)
+    N = P.T @ (d[:, None] * P)
+    return SpecData(0.5 * (H + H.T), 0.5 * (N + N.T))
+
+
+def spectral_loss(C: np.ndarray, d: SpecData) -> float:
+    """L(C) = log tr((C N C^T)^-1 C H C^T)."""
+    T = C @ d.H @ C.T
+    U = C @ d.N @ C.T
+    return float(np.log(np.trace(np.linalg.solve(U, T))))
+
+
+def spectral_grad(C: np.ndarray, d: SpecData) -> np.ndarray:
+    """dL/dC = 2 (U^-1 C H - U^-1 T U^-1 C N) / R, T = C H C^T, U = C N C^T,
+    R = tr(U^-1 T)."""
+    T = C @ d.H @ C.T
+    U = C @ d.N @ C.T
+    X = np.linalg.inv(U)
+    R = float(np.trace(X @ T))
+    return 2.0 * (X @ C @ d.H - X @ T @ X @ C @ d.N) / R
 
 
 def coarse_energy_left(S_II, U: np.ndarray, b: np.ndarray, xstar: np.ndarray) -> float:

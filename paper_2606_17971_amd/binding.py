@@ -23,10 +23,11 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-OK, E_ARG, E_STATE, E_HIP, E_NOMEM, E_NOT_SPD, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+OK, E_ARG, E_STATE, E_HIP, E_NOMEM, E_NOT_SPD, E_UNSUPPORTED, E_NOCONV = 0, -1, -2, -3, -4, -5, -6, -7
 W_FALLBACK, W_MAXIT, W_STAGNATED = 1, 2, 3
-FP64, FP32_REFINE, MIXED_REFINE = 0, 1, 2
+FP64, FP32_REFINE, MIXED_REFINE, FP64_REFINE = 0, 1, 2, 3
 JACOBI, NONE = 0, 1
+ENERGY, SPECTRUM = 0, 1   # learned_objective
 MAX_K = 64
 
 
@@ -50,6 +51,7 @@ class Opts(ctypes.Structure):
         ("tau_safe", ctypes.c_double),
         ("tau_dep", ctypes.c_double),
         ("poll_max", ctypes.c_int32),
+        ("learned_objective", ctypes.c_int32),
     ]
 
 
@@ -61,6 +63,7 @@ class Stats(ctypes.Structure):
         ("total_ms", ctypes.c_double * 16),
         ("alg_bytes", ctypes.c_double * 16),
         ("polls", ctypes.c_int64),
+        ("pod_iters", ctypes.c_int64),
     ]
 
 
@@ -444,6 +447,12 @@ class Solver:
         return {s.name[i].decode(): dict(launches=s.launches[i], ms=s.total_ms[i],
                                          alg_bytes=s.alg_bytes[i]) for i in range(s.n_kernels)}
 
+    def pod_iters(self) -> int:
+        """Subspace iterations of the last pod() (0: direct eigensolver)."""
+        s = Stats()
+        self._check(_lib.adef2_get_stats(self._ctx, ctypes.byref(s)), allow=(OK,))
+        return int(s.pod_iters)
+
     def polls(self) -> int:
         """Host polls of the device convergence state since the last reset."""
         s = Stats()
@@ -456,7 +465,8 @@ class Solver:
 
 def status_name(code: int) -> str:
     return {OK: "ok", E_ARG: "e_arg", E_STATE: "e_state", E_HIP: "e_hip", E_NOMEM: "e_nomem",
-            E_NOT_SPD: "e_not_spd", E_UNSUPPORTED: "e_unsupported", W_FALLBACK: "w_fallback",
+            E_NOT_SPD: "e_not_spd", E_UNSUPPORTED: "e_unsupported", E_NOCONV: "e_noconv",
+            W_FALLBACK: "w_fallback",
             W_MAXIT: "w_maxit", W_STAGNATED: "w_stagnated"}.get(code, str(code))
 
 

@@ -122,6 +122,8 @@ struct adef2_ctx {
   int Mtr = 0;
   float* theta_tr = nullptr;
   double *Htr = nullptr, *gtr = nullptr, *e0tr = nullptr, *bxtr = nullptr;
+  double* Ntr = nullptr;          // [M][p][p] D-weighted Grams (deflated-spectrum objective)
+  int obj_tr = 0;                 // objective the training samples were prepared for
   float *act = nullptr, *mout = nullptr, *dout = nullptr, *dA1 = nullptr, *dA2 = nullptr;
   double* lossv = nullptr;
   int Mcap_mlp = 0;
@@ -142,7 +144,7 @@ struct adef2_ctx {
   // update): counts, offsets [B][ub_ntiles + 1], rows and W - Lambda Z rows
   bool tm_ok = false;            // the current restriction supports the tile-major update
   int* bcnt = nullptr;
-  double* ftot = nullptr;        // [B][2 KP + 2] totals of the tile-major finisher
+  double* ftot = nullptr;        // [B][slices][2 KP + 2] slice totals of the tile-major finisher
   unsigned* fctr = nullptr;      // [B] its arrival counters
   int* btoff = nullptr;
   int* btot = nullptr;
@@ -210,6 +212,7 @@ struct adef2_ctx {
   double st_ms[KI_COUNT] = {};
   double st_bytes[KI_COUNT] = {};
   int64_t st_polls = 0;          // host polls of the device state (all solves since reset)
+  int64_t pod_iters = 0;         // subspace iterations of the last POD (0: Jacobi on the whole Gram)
   std::vector<long long> nI_host;
   std::vector<double> tol_h;     // per-instance tolerances of the current solve
 };
@@ -302,7 +305,7 @@ void free_all(adef2_ctx* c) {
   F(c->t64); F(c->t32); F(c->Tm); F(c->dia1_64); F(c->dia1_32);
   F(c->part); F(c->ctr);
   F(c->Phi); F(c->mlp); F(c->mlp_bf); F(c->mlp_g); F(c->mlp_m); F(c->mlp_v); F(c->theta_tr);
-  F(c->Htr); F(c->gtr); F(c->e0tr); F(c->bxtr); F(c->act); F(c->mout); F(c->dout); F(c->dA1);
+  F(c->Htr); F(c->Ntr); F(c->gtr); F(c->e0tr); F(c->bxtr); F(c->act); F(c->mout); F(c->dout); F(c->dA1);
   F(c->dA2); F(c->lossv); F(c->Zb64); F(c->Zb32); F(c->mu64); F(c->eigf); F(c->bnd); F(c->hb); F(c->zero64);
   F(c->ZT32); F(c->bcnt); F(c->ftot); F(c->fctr); F(c->btoff); F(c->btot); F(c->bidx); F(c->bW32);
   if (c->inst_h) hipHostFree(c->inst_h);
@@ -347,7 +350,7 @@ void timed(adef2_ctx* c, int id, double bytes, F&& launch) {
 // precision modes: vectors FP64 unless FP32_REFINE; operator values and Z/W
 // panels FP64 only in FP64 mode
 inline bool vec64(int prec) { return prec != ADEF2_FP32_REFINE; }
-inline bool mat64(int prec) { return prec == ADEF2_FP64; }
+inline bool mat64(int prec) { return prec == ADEF2_FP64 || prec == ADEF2_FP64_REFINE; }
 
 template <typename V, typename M>
 KTab<V, M> pick(int KP, int rpt) {
@@ -499,7 +502,7 @@ int ensure_batch(adef2_ctx* c, int B, int prec) {
   if ((rc = dalloc(c, &c->Tm, c->factored ? BN * KP : 0))) return rc;
   if ((rc = dalloc(c, &c->bnd, BN)) || (rc = dalloc(c, &c->hb, BN)) || (rc = dalloc(c, &c->zero64, 64)))
     return rc;
-  if ((rc = dalloc(c, &c->ftot, (size_t)B * (2 * KP + 2))) || (rc = dalloc(c, &c->fctr, (size_t)B + 16)))
+  if ((rc = dalloc(c, &c->ftot, (size_t)B * FIN_MAX_SLICES * (2 * KP + 2))) || (rc = dalloc(c, &c->fctr, (size_t)B + 16)))
     return rc;
   HIPCHK(c, hipMemsetAsync(c->fctr, 0, ((size_t)B + 16) * sizeof(unsigned), c->st));
   if ((rc = dalloc(c, &c->bcnt, (size_t)B * c->ub_ntiles)) ||
@@ -831,7 +834,7 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   const dim3 gbt(c->bt_ntiles_pad);
   const dim3 gpt((unsigned)(c->ub_ntiles_pad * cdiv(c->B, PB_G)));
   const dim3 gut((unsigned)(c->ub_ntiles_pad * cdiv(c->B, UB_G)));
-  const dim3 gfin((unsigned)cdiv(2 * c->KP + 2, FC), (unsigned)c->B);
+  const dim3 gfin((unsigned)cdiv(2 * c->KP + 2, FC), (unsigned)fin_slices(c->ub_ntiles_pad), (unsigned)c->B);
   // tile-major stencil passes: coefficients of a row held in registers
   const bool stm = tm && c->wfree == 4 && c->D <= SDR && (!c->factored || c->D1 <= SDR);
   const dim3 gst((unsigned)(c->ub_ntiles_pad * cdiv(c->B, SG_G)));
@@ -1085,6 +1088,8 @@ int choose_variant(adef2_ctx* c, const double* b) {
       HIPCHK(c, hipEventRecord(e0, c->st));
       if (c->prec == ADEF2_FP64)
         rc = run_sweep<double, double>(c, b, nullptr, 1.0, 1, 0.0, 0, 2);
+      else if (mat64(c->prec))
+        rc = run_sweep<double, double>(c, c->r64, nullptr, 0.0, 0, 0.25, 0, 2);
       else if (vec64(c->prec))
         rc = run_sweep<double, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol, 0, 0.25, 0, 2);
       else
@@ -1144,20 +1149,26 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
       fill<double>(c, c->x64, (size_t)B * c->vs, 0.0);
     }
     if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, true))) return rc;
-    const double in2 = c->o.inner_rtol * c->o.inner_rtol;
-    const bool v64 = vec64(c->prec);
-    ByteModel bm = byte_model(c, v64 ? 8.0 : 4.0, 4.0, false);
+    const bool v64 = vec64(c->prec), m64 = mat64(c->prec);
+    // FP64 segments run until their recurrence residual is below tol/2: an
+    // FP64 recurrence stays close to the true residual over many orders of
+    // magnitude, and every restart costs CG's accumulated Krylov space
+    const double in2 = m64 ? 0.0 : c->o.inner_rtol * c->o.inner_rtol;
+    const double mb = m64 ? 8.0 : 4.0;
+    ByteModel bm = byte_model(c, v64 ? 8.0 : 4.0, mb, false);
     for (int sweep = 0;; ++sweep) {
       bool ad = false;
       if ((rc = poll(c, true, &ad))) return rc;
       if (ad) break;
       if (sweep > c->o.max_sweeps + 1) return fail(c, ADEF2_E_HIP, "refinement made no progress");
-      bm = byte_model(c, v64 ? 8.0 : 4.0, 4.0, false);
-      // FP32 segment on the correction equation S d = r64; it ends when its
-      // recurrence residual fell by inner_rtol (or below tol ||b|| / 2); the
-      // FP64 residual then replaces it and the search direction carries on
-      rc = v64 ? run_sweep<double, float>(c, c->r64, nullptr, in2, 0, 0.25, sweep > 0)
-               : run_sweep<float, float>(c, c->r64, nullptr, in2, 0, 0.25, sweep > 0);
+      bm = byte_model(c, v64 ? 8.0 : 4.0, mb, false);
+      // segment on the correction equation S d = r64 (FP32 operator and
+      // panels, or FP64 in FP64_REFINE); it ends when its recurrence
+      // residual fell by inner_rtol (or below tol ||b|| / 2); the FP64
+      // residual then replaces it and the search direction carries on
+      rc = m64 ? run_sweep<double, double>(c, c->r64, nullptr, in2, 0, 0.25, sweep > 0)
+               : v64 ? run_sweep<double, float>(c, c->r64, nullptr, in2, 0, 0.25, sweep > 0)
+                     : run_sweep<float, float>(c, c->r64, nullptr, in2, 0, 0.25, sweep > 0);
       if (rc) return rc;
       timed(c, KI_ACCUM, bm.accum, [&] {
         if (v64)
@@ -1196,13 +1207,14 @@ int worst_of(int a, int b) {
 bool valid_opts(const adef2_opts* o) {
   return o->maxit > 0 &&
          (o->precision == ADEF2_FP64 || o->precision == ADEF2_FP32_REFINE ||
-          o->precision == ADEF2_MIXED_REFINE) &&
+          o->precision == ADEF2_MIXED_REFINE || o->precision == ADEF2_FP64_REFINE) &&
          (o->precond == ADEF2_JACOBI || o->precond == ADEF2_NONE) && o->inner_rtol > 0.0 &&
          o->inner_rtol < 1.0 && o->max_sweeps > 0 && o->drop_rel >= 0.0 && o->tau_cond > 0.0 &&
          (o->rows_per_thread == 0 || o->rows_per_thread == 1 || o->rows_per_thread == 2) &&
          o->w_mode >= 0 && o->w_mode <= 5 && o->w_boundary >= 0 && o->w_boundary <= 2 &&
          (o->graph == 0 || o->graph == 1) && o->ritz_keep >= 0 && o->ritz_keep <= ADEF2_MAX_K &&
-         o->tau_safe >= 1.0 && o->tau_dep >= 0.0 && o->tau_dep < 1.0 && o->poll_max >= 1;
+         o->tau_safe >= 1.0 && o->tau_dep >= 0.0 && o->tau_dep < 1.0 && o->poll_max >= 1 &&
+         (o->learned_objective == 0 || o->learned_objective == 1);
 }
 
 }  // namespace
@@ -1238,8 +1250,12 @@ void mlp_forward_launch(adef2_ctx* c, int M, const float* theta) {
 // mean loss in c->mlp_g
 void mlp_grad_launch(adef2_ctx* c, int M) {
   mlp_forward_launch(c, M, c->theta_tr);
-  hipLaunchKernelGGL(k_loss_grad, dim3(M), dim3(512), 0, c->st, M, c->p, c->mout, c->Htr, c->gtr, c->e0tr,
-                     c->bxtr, 0.0, 1.0f / (float)M, c->dout, c->lossv);
+  if (c->obj_tr == 1)
+    hipLaunchKernelGGL(k_loss_grad_spec, dim3(M), dim3(512), 0, c->st, M, c->p, c->mout, c->Htr, c->Ntr,
+                       1.0f / (float)M, c->dout, c->lossv);
+  else
+    hipLaunchKernelGGL(k_loss_grad, dim3(M), dim3(512), 0, c->st, M, c->p, c->mout, c->Htr, c->gtr, c->e0tr,
+                       c->bxtr, 0.0, 1.0f / (float)M, c->dout, c->lossv);
   hipLaunchKernelGGL(k_mlp_bwd_act, dim3(M), dim3(128), 0, c->st, M, mlp_view(c), c->act, c->dout,
                      c->dA2, c->dA1);
   hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)cdiv(MD3 * MD2, 256)), dim3(256), 0, c->st, M, MD3, MD2,
@@ -1319,6 +1335,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->tau_safe = 1e4;
   o->tau_dep = 1e-10;
   o->poll_max = 16;
+  o->learned_objective = 0;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
@@ -2019,6 +2036,7 @@ int adef2_get_stats(adef2_ctx* c, adef2_stats* s) {
     s->alg_bytes[i] = c->st_bytes[i];
   }
   s->polls = c->st_polls;
+  s->pod_iters = c->pod_iters;
   return ADEF2_OK;
 }
 
@@ -2030,44 +2048,153 @@ int adef2_reset_stats(adef2_ctx* c) {
   return ADEF2_OK;
 }
 
+}  // extern "C"
+
+namespace {
+constexpr int POD_MAX_M = 8192;   // snapshots per POD call
+constexpr int POD_MAXIT = 500;    // subspace iterations (M > JMAX)
+
+// leading p eigenpairs of the symmetric M x M snapshot Gram G (device,
+// row-major) by block subspace iteration with Rayleigh-Ritz and SVQB
+// re-orthonormalisation.  V: device column-major M x p; th: host,
+// descending.  Converged when every wanted Ritz pair has
+// ||G v - theta v|| <= 1e-10 theta + 1e-13 theta_1.
+int gram_top_eigs(adef2_ctx* c, int M, const double* G, int p, double* V, std::vector<double>& th) {
+  const int L = std::min(M - 1, p + std::max(32, p / 2));
+  const size_t ML = (size_t)M * L, LL = (size_t)L * L;
+  double *Q = nullptr, *Y = nullptr, *QW = nullptr, *YW = nullptr, *C = nullptr, *U = nullptr, *d = nullptr,
+         *dsc = nullptr, *inv = nullptr, *ths = nullptr, *res = nullptr, *part = nullptr;
+  int* sel = nullptr;
+  auto cleanup = [&] {
+    for (void* q : {(void*)Q, (void*)Y, (void*)QW, (void*)YW, (void*)C, (void*)U, (void*)d, (void*)dsc,
+                    (void*)inv, (void*)ths, (void*)res, (void*)part, (void*)sel})
+      if (q) hipFree(q);
+  };
+  const int nt = (int)cdiv(L, GT);
+  int rc;
+  if ((rc = dalloc(c, &Q, ML)) || (rc = dalloc(c, &Y, ML)) || (rc = dalloc(c, &QW, ML)) ||
+      (rc = dalloc(c, &YW, ML)) || (rc = dalloc(c, &C, LL)) || (rc = dalloc(c, &U, LL)) ||
+      (rc = dalloc(c, &d, (size_t)L)) || (rc = dalloc(c, &dsc, (size_t)L)) || (rc = dalloc(c, &inv, (size_t)L)) ||
+      (rc = dalloc(c, &ths, (size_t)L)) || (rc = dalloc(c, &res, (size_t)L)) || (rc = dalloc(c, &part, LL)) ||
+      (rc = dalloc(c, &sel, (size_t)L))) { cleanup(); return rc; }
+  const dim3 gcol((unsigned)cdiv(M, 256), (unsigned)L);
+  // out = A^T B (L x L, row-major) over the M rows, one row block
+  auto gram = [&](const double* A, const double* Bm, double* out) {
+    hipLaunchKernelGGL(k_gram_ts, dim3(1, nt * nt, 1), dim3(TPB), 0, c->st, (int64_t)M, L, L, A, (int64_t)0, Bm,
+                       (int64_t)0, (const uint8_t*)nullptr, (int64_t)0, M, part);
+    hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)cdiv(LL, 256), 1), dim3(256), 0, c->st, 1, L, L, part, out);
+  };
+  // Qout = orthonormal basis of span(Z) (Qout != Z)
+  auto svqb = [&](const double* Z, double* Qout) {
+    gram(Z, Z, C);
+    hipLaunchKernelGGL(k_svqb_scale, dim3(1), dim3(1024), 0, c->st, L, C, dsc);
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(1024), 0, c->st, L, C, U, d);
+    hipLaunchKernelGGL(k_svqb_inv, dim3(1), dim3(256), 0, c->st, L, d, 1e-14, inv);
+    hipLaunchKernelGGL(k_comb_cols, gcol, dim3(256), 0, c->st, M, L, Z, dsc, U, (const int*)nullptr, inv, Qout);
+  };
+  hipLaunchKernelGGL(k_start_block, dim3((unsigned)cdiv(ML, 256)), dim3(256), 0, c->st, (int64_t)ML, Y);
+  svqb(Y, QW);
+  svqb(QW, Q);
+  std::vector<double> dh(L), thh(L), rh(L);
+  std::vector<int> idx(L);
+  for (int it = 0; it < POD_MAXIT; ++it) {
+    hipLaunchKernelGGL(k_symm_block, dim3((unsigned)cdiv(M, 256), (unsigned)cdiv(L, SYB)), dim3(256), 0, c->st,
+                       M, L, G, Q, Y);
+    gram(Q, Y, C);
+    hipLaunchKernelGGL(k_symmetrize, dim3(1), dim3(1024), 0, c->st, L, C);
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(1024), 0, c->st, L, C, U, d);
+    hipMemcpyAsync(dh.data(), d, sizeof(double) * L, hipMemcpyDeviceToHost, c->st);
+    if (hipStreamSynchronize(c->st) != hipSuccess) { cleanup(); return fail(c, ADEF2_E_HIP, "pod subspace sync"); }
+    for (int i = 0; i < L; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return dh[a] > dh[b]; });
+    for (int i = 0; i < L; ++i) thh[i] = dh[idx[i]];
+    hipMemcpyAsync(sel, idx.data(), sizeof(int) * L, hipMemcpyHostToDevice, c->st);
+    hipMemcpyAsync(ths, thh.data(), sizeof(double) * L, hipMemcpyHostToDevice, c->st);
+    hipLaunchKernelGGL(k_comb_cols, gcol, dim3(256), 0, c->st, M, L, Q, (const double*)nullptr, U, sel,
+                       (const double*)nullptr, QW);
+    hipLaunchKernelGGL(k_comb_cols, gcol, dim3(256), 0, c->st, M, L, Y, (const double*)nullptr, U, sel,
+                       (const double*)nullptr, YW);
+    hipLaunchKernelGGL(k_ritz_resid, dim3(L), dim3(256), 0, c->st, M, QW, YW, ths, res);
+    hipMemcpyAsync(rh.data(), res, sizeof(double) * L, hipMemcpyDeviceToHost, c->st);
+    if (hipStreamSynchronize(c->st) != hipSuccess) { cleanup(); return fail(c, ADEF2_E_HIP, "pod subspace sync"); }
+    bool done = true;
+    for (int j = 0; j < p; ++j)
+      if (!(rh[j] <= 1e-10 * std::fabs(thh[j]) + 1e-13 * std::fabs(thh[0]))) done = false;
+    if (done) {
+      hipMemcpyAsync(V, QW, sizeof(double) * (size_t)M * p, hipMemcpyDeviceToDevice, c->st);
+      const hipError_t e = hipStreamSynchronize(c->st);
+      cleanup();
+      if (e != hipSuccess) return fail(c, ADEF2_E_HIP, hipGetErrorString(e));
+      th.assign(thh.begin(), thh.begin() + p);
+      c->pod_iters = it + 1;
+      return ADEF2_OK;
+    }
+    // next block: the Ritz vectors multiplied by G, orthonormalised twice
+    svqb(YW, Y);
+    svqb(Y, Q);
+  }
+  cleanup();
+  return fail(c, ADEF2_E_NOCONV, "pod: the subspace iteration on the snapshot Gram did not converge");
+}
+}  // namespace
+
+extern "C" {
+
 int adef2_pod(adef2_ctx* c, int32_t M, const double* X, int32_t p, double* Phi_out, double* sigma) {
   if (!c) return ADEF2_E_ARG;
   if (!c->have_ref) return fail(c, ADEF2_E_STATE, "pod before set_reference");
-  if (M < 2 || M > JMAX || p < 1 || p > MLP_P || p >= M || !X)
-    return fail(c, ADEF2_E_ARG, "need 2 <= M <= 256 snapshots and 1 <= p < M, p <= 64");
+  if (M < 2 || M > POD_MAX_M || p < 1 || p > MLP_P || p >= M || !X)
+    return fail(c, ADEF2_E_ARG, "need 2 <= M <= 8192 snapshots and 1 <= p < M, p <= 64");
   const int64_t N = c->N;
+  const bool direct = M <= JMAX;
   double *Xc = nullptr, *part = nullptr, *G = nullptr, *V = nullptr, *ev = nullptr;
   int* sel = nullptr;
-  const int rpb = 4096;
+  // at most 16 row blocks of partial Grams (16 M^2 doubles)
+  const int rpb = (int)std::max<int64_t>(4096, cdiv(N, 16));
   const int nrb = (int)cdiv(N, rpb);
   const int nt = (int)cdiv(M, GT);
   auto cleanup = [&] { for (void* q : {(void*)Xc, (void*)part, (void*)G, (void*)V, (void*)ev, (void*)sel}) if (q) hipFree(q); };
   int rc;
   if ((rc = dalloc(c, &Xc, (size_t)N * M)) || (rc = dalloc(c, &part, (size_t)nrb * M * M)) ||
-      (rc = dalloc(c, &G, (size_t)M * M)) || (rc = dalloc(c, &V, (size_t)M * M)) ||
-      (rc = dalloc(c, &ev, (size_t)M)) || (rc = dalloc(c, &sel, (size_t)p))) { cleanup(); return rc; }
+      (rc = dalloc(c, &G, (size_t)M * M)) || (rc = dalloc(c, &V, direct ? (size_t)M * M : (size_t)M * p)) ||
+      (rc = dalloc(c, &ev, direct ? (size_t)M : (size_t)p)) || (rc = dalloc(c, &sel, (size_t)p))) { cleanup(); return rc; }
   hipLaunchKernelGGL(k_center, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, c->st, N, M, X, Xc);
   hipLaunchKernelGGL(k_gram_ts, dim3(nrb, nt * nt, 1), dim3(TPB), 0, c->st, N, M, M, Xc, (int64_t)0, Xc,
                      (int64_t)0, (const uint8_t*)nullptr, (int64_t)0, rpb, part);
-  hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)cdiv(M * M, 256), 1), dim3(256), 0, c->st, nrb, M, M,
+  hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)cdiv((int64_t)M * M, 256), 1), dim3(256), 0, c->st, nrb, M, M,
                      part, G);
-  hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(1024), 0, c->st, M, G, V, ev);
-  std::vector<double> evh(M);
-  hipMemcpyAsync(evh.data(), ev, sizeof(double) * M, hipMemcpyDeviceToHost, c->st);
-  if (hipStreamSynchronize(c->st) != hipSuccess) { cleanup(); return fail(c, ADEF2_E_HIP, "pod sync"); }
-  // order the eigenvalues (descending) on the host: p indices only
-  std::vector<int> idx(M);
-  for (int i = 0; i < M; ++i) idx[i] = i;
-  std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) { return evh[i] > evh[j]; });
-  hipMemcpyAsync(sel, idx.data(), sizeof(int) * p, hipMemcpyHostToDevice, c->st);
+  hipFree(part);
+  part = nullptr;
+  std::vector<double> th;
+  if (direct) {
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(1024), 0, c->st, M, G, V, ev);
+    std::vector<double> evh(M);
+    hipMemcpyAsync(evh.data(), ev, sizeof(double) * M, hipMemcpyDeviceToHost, c->st);
+    if (hipStreamSynchronize(c->st) != hipSuccess) { cleanup(); return fail(c, ADEF2_E_HIP, "pod sync"); }
+    // order the eigenvalues (descending) on the host: p indices only
+    std::vector<int> idx(M);
+    for (int i = 0; i < M; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) { return evh[i] > evh[j]; });
+    hipMemcpyAsync(sel, idx.data(), sizeof(int) * p, hipMemcpyHostToDevice, c->st);
+    for (int j = 0; j < p; ++j) th.push_back(evh[idx[j]]);
+    c->pod_iters = 0;
+  } else {
+    if ((rc = gram_top_eigs(c, M, G, p, V, th))) { cleanup(); return rc; }
+    hipMemcpyAsync(ev, th.data(), sizeof(double) * p, hipMemcpyHostToDevice, c->st);
+  }
   if ((rc = dalloc(c, &c->Phi, (size_t)N * p))) { cleanup(); return rc; }
-  hipLaunchKernelGGL(k_pod_modes, dim3((unsigned)cdiv(N, 256), p), dim3(256), 0, c->st, N, M, p, Xc, V, sel,
-                     ev, c->Phi);
+  // Phi[:, j] = Xc v_j / sqrt(theta_j)
+  if (direct)
+    hipLaunchKernelGGL(k_pod_modes, dim3((unsigned)cdiv(N, 256), p), dim3(256), 0, c->st, N, M, p, Xc, V,
+                       (int64_t)M, (int64_t)1, sel, ev, c->Phi);
+  else
+    hipLaunchKernelGGL(k_pod_modes, dim3((unsigned)cdiv(N, 256), p), dim3(256), 0, c->st, N, M, p, Xc, V,
+                       (int64_t)1, (int64_t)M, (const int*)nullptr, ev, c->Phi);
   if (Phi_out) hipMemcpyAsync(Phi_out, c->Phi, sizeof(double) * N * p, hipMemcpyDeviceToDevice, c->st);
   hipError_t e = hipStreamSynchronize(c->st);
   cleanup();
   if (e != hipSuccess) return fail(c, ADEF2_E_HIP, hipGetErrorString(e));
-  if (sigma) for (int j = 0; j < p; ++j) sigma[j] = evh[idx[j]] > 0 ? std::sqrt(evh[idx[j]]) : 0.0;
+  if (sigma) for (int j = 0; j < p; ++j) sigma[j] = th[j] > 0 ? std::sqrt(th[j]) : 0.0;
   c->p = p;
   return ADEF2_OK;
 }
@@ -2169,27 +2296,37 @@ int adef2_learned_prepare(adef2_ctx* c, int32_t M, const uint8_t* masks, const d
   if (M <= 0 || !masks || !b || !xsol || !theta) return fail(c, ADEF2_E_ARG, "invalid training arguments");
   const int64_t N = c->N;
   const int k = c->k, p = c->p, nb = k + p;
-  if (sizeof(double) * ((size_t)k * k + (size_t)k * (p + 1)) > 65536)
-    return fail(c, ADEF2_E_UNSUPPORTED, "learned_prepare: k*k + k*(p+1) must fit 8192 doubles");
+  const int obj = c->o.learned_objective;
+  const size_t lds = sizeof(double) * ((size_t)k * k + (size_t)k * (p + 1) + (obj == 1 ? (size_t)k * p : 0));
+  if (lds > 65536)
+    return fail(c, ADEF2_E_UNSUPPORTED, "learned_prepare: k*k + k*(p+1) (+ k*p for the deflated-spectrum "
+                                        "objective) must fit 8192 doubles");
   int rc;
+  c->Mtr = 0;
   if ((rc = dalloc(c, &c->theta_tr, (size_t)M * MD0)) || (rc = dalloc(c, &c->Htr, (size_t)M * p * p)) ||
       (rc = dalloc(c, &c->gtr, (size_t)M * p)) || (rc = dalloc(c, &c->e0tr, (size_t)M)) ||
-      (rc = dalloc(c, &c->bxtr, (size_t)M)))
+      (rc = dalloc(c, &c->bxtr, (size_t)M)) || (obj == 1 && (rc = dalloc(c, &c->Ntr, (size_t)M * p * p))))
     return rc;
   HIPCHK(c, hipMemcpyAsync(c->theta_tr, theta, sizeof(float) * M * MD0, hipMemcpyDeviceToDevice, c->st));
   double *VB = nullptr, *T = nullptr, *Wv = nullptr, *part = nullptr, *G = nullptr, *bz = nullptr, *bx1 = nullptr;
+  double *DV = nullptr, *Gd = nullptr;
   Inst* one = nullptr;
   const int rpb = 4096;
   const int nrb = (int)cdiv(N, rpb);
   const int nt = (int)cdiv(nb, GT);
   auto cleanup = [&] {
-    for (void* q : {(void*)VB, (void*)T, (void*)Wv, (void*)part, (void*)G, (void*)bz, (void*)bx1, (void*)one})
+    for (void* q : {(void*)VB, (void*)T, (void*)Wv, (void*)part, (void*)G, (void*)bz, (void*)bx1, (void*)one,
+                    (void*)DV, (void*)Gd})
       if (q) hipFree(q);
   };
   if ((rc = dalloc(c, &VB, (size_t)N * nb)) || (rc = dalloc(c, &T, (size_t)N * nb)) ||
       (rc = dalloc(c, &Wv, (size_t)N * nb)) || (rc = dalloc(c, &part, (size_t)nrb * nb * nb)) ||
       (rc = dalloc(c, &G, (size_t)nb * nb)) || (rc = dalloc(c, &bz, (size_t)nb)) ||
-      (rc = dalloc(c, &bx1, 1)) || (rc = dalloc(c, &one, 1))) { cleanup(); return rc; }
+      (rc = dalloc(c, &bx1, 1)) || (rc = dalloc(c, &one, 1)) ||
+      (obj == 1 && ((rc = dalloc(c, &DV, (size_t)N * nb)) || (rc = dalloc(c, &Gd, (size_t)nb * nb))))) {
+    cleanup();
+    return rc;
+  }
   // [Z | Phi] (k reference modes first)
   HIPCHK(c, hipMemcpyAsync(VB, c->Z64, sizeof(double) * N * k, hipMemcpyDeviceToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(VB + (size_t)N * k, c->Phi, sizeof(double) * N * p, hipMemcpyDeviceToDevice, c->st));
@@ -2218,10 +2355,18 @@ int adef2_learned_prepare(adef2_ctx* c, int32_t M, const uint8_t* masks, const d
     hipLaunchKernelGGL(k_gram_ts, dim3(nrb, 1, 1), dim3(TPB), 0, c->st, N, 1, 1, b + (size_t)m * N,
                        (int64_t)0, xsol + (size_t)m * N, (int64_t)0, mk, (int64_t)0, rpb, part);
     hipLaunchKernelGGL(k_gram_finish, dim3(1, 1), dim3(256), 0, c->st, nrb, 1, 1, part, c->bxtr + m);
-    const size_t lds = sizeof(double) * ((size_t)k * k + (size_t)k * (p + 1));
+    if (obj == 1) {   // D-weighted Gram of [Z | Phi] on the inactive rows, D = diag(S_II)
+      hipLaunchKernelGGL(k_dscale_cols, dim3((unsigned)cdiv(N, 256), nb), dim3(256), 0, c->st, N, VB, c->diag,
+                         mk, one, DV);
+      hipLaunchKernelGGL(k_gram_ts, dim3(nrb, nt * nt, 1), dim3(TPB), 0, c->st, N, nb, nb, VB, (int64_t)0,
+                         DV, (int64_t)0, mk, (int64_t)0, rpb, part);
+      hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)cdiv(nb * nb, 256), 1), dim3(256), 0, c->st, nrb, nb,
+                         nb, part, Gd);
+    }
     // the kernel indexes its one sample through blockIdx.x = 0; shift the outputs
     hipLaunchKernelGGL(k_loss_data, dim3(1), dim3(1024), lds, c->st, k, p, G, bz, c->Htr + (size_t)m * p * p,
-                       c->gtr + (size_t)m * p, c->e0tr + m, c->o.drop_rel);
+                       c->gtr + (size_t)m * p, c->e0tr + m, c->o.drop_rel, (const double*)Gd,
+                       obj == 1 ? c->Ntr + (size_t)m * p * p : (double*)nullptr);
   }
   hipError_t e = hipStreamSynchronize(c->st);
   cleanup();
@@ -2233,6 +2378,7 @@ int adef2_learned_prepare(adef2_ctx* c, int32_t M, const uint8_t* masks, const d
       return fail(c, ADEF2_E_ARG, "learned_prepare: sample " + std::to_string(m) +
                                       " has b_I^T x_I <= 0 (not a solution, or b_I = 0)");
   c->Mtr = M;
+  c->obj_tr = obj;
   return ADEF2_OK;
 }
 

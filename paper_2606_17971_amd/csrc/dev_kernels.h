@@ -129,7 +129,7 @@ struct IterArgs {
   const int32_t* btoff;    // [B][ub_ntiles + 1]
   const int32_t* bidx;
   const M* bW;
-  double* ftot;            // [B][2 KP + 2] totals of the tile-major finisher
+  double* ftot;            // [B][slices][2 KP + 2] slice totals of the tile-major finisher
   unsigned* fctr;          // [B] arrival counters of the tile-major finisher
 };
 

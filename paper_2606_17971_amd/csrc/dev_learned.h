@@ -165,17 +165,132 @@ __global__ void __launch_bounds__(1024) k_jacobi_eig(int n, double* A, double* V
   for (int i = tid; i < n; i += nt) evals[i] = A[i * n + i];
 }
 
-// Phi[:, j] = Xc V[:, sel[j]] / sigma_j  (sel: eigenvalue order, descending)
-__global__ void k_pod_modes(int64_t N, int M, int p, const double* Xc, const double* V, const int* sel,
-                            const double* evals, double* Phi) {
+// Phi[:, j] = Xc v_c / sqrt(lambda_c), c = sel[j] (eigenvalue order,
+// descending; identity when sel is null); entry m of eigenvector c at
+// V[m * vsm + c * vsc]
+__global__ void k_pod_modes(int64_t N, int M, int p, const double* Xc, const double* V, int64_t vsm,
+                            int64_t vsc, const int* sel, const double* evals, double* Phi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= N || j >= p) return;
-  const int c = sel[j];
+  const int c = sel ? sel[j] : j;
   double s = 0.0;
-  for (int m = 0; m < M; ++m) s += Xc[(size_t)m * N + i] * V[m * M + c];
+  for (int m = 0; m < M; ++m) s += Xc[(size_t)m * N + i] * V[(size_t)m * vsm + (size_t)c * vsc];
   const double lam = evals[c];
   Phi[(size_t)j * N + i] = lam > 0.0 ? s / sqrt(lam) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Subspace iteration for the leading eigenpairs of a large snapshot Gram
+// (M > JMAX): blocks of L orthonormal columns are multiplied by G, rotated
+// by the Rayleigh-Ritz eigenvectors of Q^T G Q and re-orthonormalised
+// (scaled Gram + eigen-decomposition, "SVQB"), until the residuals of the
+// wanted Ritz pairs are small.
+// ---------------------------------------------------------------------------
+constexpr int SYB = 8;   // columns per thread in k_symm_block
+
+// Y[:, j] = G Q[:, j], G symmetric M x M (row-major: row i is column i, so
+// the loads along m are coalesced across threads); Q, Y column-major M x L.
+__global__ void __launch_bounds__(256) k_symm_block(int M, int L, const double* G, const double* Q,
+                                                    double* Y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = blockIdx.y * SYB;
+  if (i >= M) return;
+  double s[SYB];
+#pragma unroll
+  for (int c = 0; c < SYB; ++c) s[c] = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const double g = G[(size_t)m * M + i];
+#pragma unroll
+    for (int c = 0; c < SYB; ++c)
+      if (j0 + c < L) s[c] += g * Q[(size_t)(j0 + c) * M + m];
+  }
+#pragma unroll
+  for (int c = 0; c < SYB; ++c)
+    if (j0 + c < L) Y[(size_t)(j0 + c) * M + i] = s[c];
+}
+
+// out[:, c] = scale[c] * sum_l A[:, l] pre[l] W[l][col(c)], col(c) = sel[c]
+// (or c); A, out column-major M x L, W row-major L x L (entry l of column j
+// at W[l * L + j]).  pre / scale / sel may be null (ones / identity).
+__global__ void k_comb_cols(int M, int L, const double* A, const double* pre, const double* W,
+                            const int* sel, const double* scale, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= M) return;
+  const int col = sel ? sel[c] : c;
+  double s = 0.0;
+  for (int l = 0; l < L; ++l) s += A[(size_t)l * M + i] * (pre ? pre[l] : 1.0) * W[(size_t)l * L + col];
+  out[(size_t)c * M + i] = scale ? s * scale[c] : s;
+}
+
+// SVQB pre-scaling: dsc[l] = C[l][l]^-1/2 (0 for a zero column) and
+// C <- D C D, symmetrised.  One workgroup.
+__global__ void k_svqb_scale(int L, double* C, double* dsc) {
+  for (int l = threadIdx.x; l < L; l += blockDim.x) {
+    const double d = C[(size_t)l * L + l];
+    dsc[l] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int a = e / L, b = e % L;
+    if (a > b) continue;
+    const double v = 0.5 * (C[(size_t)a * L + b] + C[(size_t)b * L + a]) * dsc[a] * dsc[b];
+    C[(size_t)a * L + b] = v;
+    C[(size_t)b * L + a] = v;
+  }
+}
+
+// SVQB post-scaling: inv[c] = d[c]^-1/2 for eigenvalues above drop * max(d),
+// else 0 (the direction is dropped: a zero column).  One workgroup.
+__global__ void k_svqb_inv(int L, const double* d, double drop, double* inv) {
+  __shared__ double mx;
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int l = 0; l < L; ++l) m = fmax(m, d[l]);
+    mx = m;
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < L; l += blockDim.x) inv[l] = d[l] > drop * mx ? 1.0 / sqrt(d[l]) : 0.0;
+}
+
+// H <- (H + H^T) / 2 (L x L).  One workgroup.
+__global__ void k_symmetrize(int L, double* H) {
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int a = e / L, b = e % L;
+    if (a >= b) continue;
+    const double v = 0.5 * (H[(size_t)a * L + b] + H[(size_t)b * L + a]);
+    H[(size_t)a * L + b] = v;
+    H[(size_t)b * L + a] = v;
+  }
+}
+
+// res[c] = || YW[:, c] - th[c] QW[:, c] ||_2 (one workgroup per column)
+__global__ void __launch_bounds__(256) k_ritz_resid(int M, const double* QW, const double* YW,
+                                                    const double* th, double* res) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const double r = YW[(size_t)c * M + i] - th[c] * QW[(size_t)c * M + i];
+    s += r * r;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) res[c] = sqrt(red[0] + red[1] + red[2] + red[3]);
+}
+
+// deterministic start block: entries uniform in [-1, 1) from a 64-bit mix
+// of the entry index (splitmix64 finaliser)
+__global__ void k_start_block(int64_t n, double* Q) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  uint64_t z = (uint64_t)e + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  Q[e] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -186,10 +301,12 @@ __global__ void k_pod_modes(int64_t N, int M, int p, const double* Xc, const dou
 // setup: dependent columns contribute nothing).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_loss_data(int k, int p, const double* G, const double* bzp,
-                                                    double* H, double* gv, double* e0v, double drop_rel) {
+                                                    double* H, double* gv, double* e0v, double drop_rel,
+                                                    const double* Gd, double* Nout) {
   extern __shared__ double sm[];
   double* L = sm;                 // k x k Cholesky (lower)
   double* A = L + k * k;          // k x (p+1): Gzz^-1 [Gzp | bZ]
+  double* GA = A + k * (p + 1);   // k x p: Dzz Gzz^-1 Gzp (with Gd only)
   __shared__ int s_keep[64];
   __shared__ double s_d;
   const int m = blockIdx.x;
@@ -256,6 +373,39 @@ __global__ void __launch_bounds__(1024) k_loss_data(int k, int p, const double* 
     for (int q = 0; q < k; ++q) s += bm[q] * A[q * (p + 1) + p];
     e0v[m] = s;
   }
+  if (!Gd) return;
+  // N = P~^T D P~ with P~ = P - Z Gzz^-1 Gzp (the candidates made
+  // S-orthogonal to Z) from the D-weighted Gram Gd of [Z | P]:
+  //   N = Dpp - Dpz A - A^T Dzp + A^T Dzz A,  A = Gzz^-1 Gzp
+  const double* Dm = Gd + (size_t)m * n * n;
+  for (int e = tid; e < k * p; e += nt) {
+    const int q = e / p, b = e % p;
+    double s = 0.0;
+    for (int r = 0; r < k; ++r) s += Dm[q * n + r] * A[r * (p + 1) + b];
+    GA[e] = s;
+  }
+  __syncthreads();
+  double* Nm = Nout + (size_t)m * p * p;
+  for (int e = tid; e < p * p; e += nt) {
+    const int a = e / p, b = e % p;
+    double s1 = Dm[(k + a) * n + k + b], s2 = Dm[(k + b) * n + k + a];
+    for (int q = 0; q < k; ++q) {
+      const double aqa = A[q * (p + 1) + a], aqb = A[q * (p + 1) + b];
+      s1 += aqa * GA[q * p + b] - Dm[(k + a) * n + q] * aqb - aqa * Dm[q * n + k + b];
+      s2 += aqb * GA[q * p + a] - Dm[(k + b) * n + q] * aqa - aqb * Dm[q * n + k + a];
+    }
+    Nm[e] = 0.5 * (s1 + s2);
+  }
+}
+
+// DV[q] = D V[q] on inactive rows (0 on active ones), D = diag(S_II) =
+// a diag + c of the instance (one->a, one->c)
+__global__ void k_dscale_cols(int64_t N, const double* Vb, const double* diag, const uint8_t* mask,
+                              const Inst* one, double* DV) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= N) return;
+  DV[(size_t)q * N + i] = mask[i] ? 0.0 : (one->a * diag[i] + one->c) * Vb[(size_t)q * N + i];
 }
 
 // ---------------------------------------------------------------------------
@@ -391,6 +541,109 @@ __global__ void __launch_bounds__(512) k_loss_grad(int B, int p, const float* ou
       double uCH = 0.0;
       for (int q = 0; q < MLP_NV; ++q) uCH += u[q] * CH[q * p + j];
       gr = -(2.0 * u[i] * gs[j] - 2.0 * u[i] * uCH) * ib;
+    }
+    dout[(size_t)smp * MD3 + e] = (float)(gr * wscale);
+  }
+}
+
+// Deflated-spectrum loss of one sample and its gradient.  C (NV x p) as in
+// k_loss_grad; H and N (p x p) are the S_II- and D-weighted Grams of the
+// candidates made S_II-orthogonal to the reference modes.  With
+// T = C H C^T and U = C N C^T, R = tr(U^-1 T) is the sum of the Ritz values
+// of the Jacobi-preconditioned deflated operator on the span of the NV
+// enrichment vectors:
+//   L = log R,  dL/dC = 2 (U^-1 C H - U^-1 T U^-1 C N) / R.
+// A sample whose U is not positive definite (rank-deficient C) gets a NaN
+// loss and zero gradient.
+__global__ void __launch_bounds__(512) k_loss_grad_spec(int B, int p, const float* out, const double* H,
+                                                        const double* Nv, float wscale, float* dout,
+                                                        double* lossv) {
+  __shared__ double buf[MLP_P * MLP_P];
+  __shared__ double C[MLP_NV * MLP_P], CH[MLP_NV * MLP_P], CN[MLP_NV * MLP_P];
+  __shared__ double T[MLP_NV * MLP_NV], U[MLP_NV * MLP_NV], X[MLP_NV * MLP_NV], P[MLP_NV * MLP_NV];
+  __shared__ double s_r;
+  const int smp = blockIdx.x, t = threadIdx.x;
+  if (smp >= B) return;
+  for (int e = t; e < MLP_NV * p; e += blockDim.x) C[e] = out[(size_t)smp * MD3 + (e / p) * MLP_P + e % p];
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* src = (pass == 0 ? H : Nv) + (size_t)smp * p * p;
+    double* dst = pass == 0 ? CH : CN;
+    __syncthreads();
+    for (int e = t; e < p * p; e += blockDim.x) buf[e] = src[e];
+    __syncthreads();
+    for (int e = t; e < MLP_NV * p; e += blockDim.x) {
+      const int i = e / p, j = e % p;
+      double s = 0.0;
+      for (int q = 0; q < p; ++q) s += C[i * p + q] * buf[q * p + j];
+      dst[e] = s;
+    }
+  }
+  __syncthreads();
+  if (t < 2 * MLP_NV * MLP_NV) {
+    const int w = t / (MLP_NV * MLP_NV), o = t % (MLP_NV * MLP_NV);
+    const int i = o / MLP_NV, j = o % MLP_NV;
+    const double* src = w == 0 ? CH : CN;
+    double s = 0.0;
+    for (int q = 0; q < p; ++q) s += src[i * p + q] * C[j * p + q];
+    (w == 0 ? T : U)[o] = s;
+  }
+  __syncthreads();
+  if (t == 0) {      // X = U^-1 by Cholesky (symmetrised U), R = tr(X T), P = X T X
+    double Lc[MLP_NV * MLP_NV];
+    bool ok = true;
+    for (int j = 0; j < MLP_NV && ok; ++j) {
+      double d = U[j * MLP_NV + j];
+      for (int q = 0; q < j; ++q) d -= Lc[j * MLP_NV + q] * Lc[j * MLP_NV + q];
+      if (!(d > 0.0)) { ok = false; break; }
+      Lc[j * MLP_NV + j] = sqrt(d);
+      for (int l = j + 1; l < MLP_NV; ++l) {
+        double v = 0.5 * (U[l * MLP_NV + j] + U[j * MLP_NV + l]);
+        for (int q = 0; q < j; ++q) v -= Lc[l * MLP_NV + q] * Lc[j * MLP_NV + q];
+        Lc[l * MLP_NV + j] = v / Lc[j * MLP_NV + j];
+      }
+    }
+    for (int c = 0; c < MLP_NV; ++c) {
+      double y[MLP_NV];
+      for (int i = 0; i < MLP_NV; ++i) {
+        double v = (i == c) ? 1.0 : 0.0;
+        for (int q = 0; q < i && ok; ++q) v -= Lc[i * MLP_NV + q] * y[q];
+        y[i] = ok ? v / Lc[i * MLP_NV + i] : 0.0;
+      }
+      for (int i = MLP_NV - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int q = i + 1; q < MLP_NV && ok; ++q) v -= Lc[q * MLP_NV + i] * X[q * MLP_NV + c];
+        X[i * MLP_NV + c] = ok ? v / Lc[i * MLP_NV + i] : 0.0;
+      }
+    }
+    double r = 0.0;
+    for (int i = 0; i < MLP_NV; ++i)
+      for (int j = 0; j < MLP_NV; ++j) r += X[i * MLP_NV + j] * 0.5 * (T[j * MLP_NV + i] + T[i * MLP_NV + j]);
+    double XT[MLP_NV * MLP_NV];
+    for (int i = 0; i < MLP_NV; ++i)
+      for (int j = 0; j < MLP_NV; ++j) {
+        double v = 0.0;
+        for (int q = 0; q < MLP_NV; ++q) v += X[i * MLP_NV + q] * 0.5 * (T[q * MLP_NV + j] + T[j * MLP_NV + q]);
+        XT[i * MLP_NV + j] = v;
+      }
+    for (int i = 0; i < MLP_NV; ++i)
+      for (int j = 0; j < MLP_NV; ++j) {
+        double v = 0.0;
+        for (int q = 0; q < MLP_NV; ++q) v += XT[i * MLP_NV + q] * X[q * MLP_NV + j];
+        P[i * MLP_NV + j] = v;
+      }
+    ok = ok && r > 0.0 && isfinite(r);
+    s_r = ok ? r : 0.0;
+    lossv[smp] = ok ? log(r) : __builtin_nan("");
+  }
+  __syncthreads();
+  const double r = s_r;
+  for (int e = t; e < MLP_NV * MLP_P; e += blockDim.x) {
+    const int i = e / MLP_P, j = e % MLP_P;
+    double gr = 0.0;
+    if (j < p && r > 0.0) {
+      double v = 0.0;
+      for (int q = 0; q < MLP_NV; ++q) v += X[i * MLP_NV + q] * CH[q * p + j] - P[i * MLP_NV + q] * CN[q * p + j];
+      gr = 2.0 * v / r;
     }
     dout[(size_t)smp * MD3 + e] = (float)(gr * wscale);
   }

@@ -373,15 +373,26 @@ __global__ void __launch_bounds__(UB_THREADS) k_update_tm(IterArgs<double, M> a)
 
 // ---------------------------------------------------------------------------
 // Finisher of the tile-major update: per instance the tile sums
-// part[m][tile][0 .. NV) are reduced in a fixed order, FC values per block
-// (thread (v, s) sums value v over tiles s, s + FS, ..., then the FS slices
-// are added in order); the block publishes its totals with agent-scope
-// stores, and the last of the instance's blocks (agent-scope counter) reads
-// all NV totals and ends the iteration (stopping tests, beta, coarse
-// coordinates) as k_update does.  Grid (ceil(NV / FC), B).
+// part[m][tile][0 .. NV) are reduced in a fixed order.  Block (ch, sc, m)
+// covers FC values of slice sc of the tiles (thread (v, s) sums value v over
+// the slice's tiles s, s + FS, ..., then the FS partial sums are added in
+// order) and publishes them with agent-scope stores to ftot[m][sc]; the last
+// of the instance's blocks (agent-scope counter) adds the slices in order
+// and ends the iteration (stopping tests, beta, coarse coordinates) as
+// k_update does.  Grid (ceil(NV / FC), slices, B); the slice count divides
+// ub_ntiles_pad (fin_slices).
 // ---------------------------------------------------------------------------
 constexpr int FC = 16;
 constexpr int FS = UB_THREADS / FC;
+constexpr int FIN_MAX_SLICES = 8;
+
+// slices of the finisher for a padded tile count (a multiple of 8): at
+// least 64 tiles each, at most FIN_MAX_SLICES
+inline int fin_slices(int ntiles_pad) {
+  int s = 1;
+  while (s < FIN_MAX_SLICES && ntiles_pad % (2 * s) == 0 && ntiles_pad / (2 * s) >= 64) s *= 2;
+  return s;
+}
 
 template <typename M, int KP>
 __global__ void __launch_bounds__(UB_THREADS) k_finish_tm(IterArgs<double, M> a) {
@@ -389,32 +400,39 @@ __global__ void __launch_bounds__(UB_THREADS) k_finish_tm(IterArgs<double, M> a)
   __shared__ double sl[UB_THREADS];
   __shared__ double tots[NV];
   __shared__ int s_last;
-  const int m = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const int m = blockIdx.z, ch = blockIdx.x, sc = blockIdx.y;
+  const int nsl = gridDim.y;
+  const unsigned nblk = gridDim.x * gridDim.y;
   Inst* S = a.inst + m;
   if (S->done) return;
   const int t = threadIdx.x;
   const int v = ch * FC + (t % FC), sidx = t / FC;
-  const double* pm = a.part + (size_t)m * a.ub_ntiles_pad * NV;
+  const int tps = a.ub_ntiles_pad / nsl;
+  const double* pm = a.part + ((size_t)m * a.ub_ntiles_pad + (size_t)sc * tps) * NV;
   double acc = 0.0;
   if (v < NV)
-    for (int tl = sidx; tl < a.ub_ntiles_pad; tl += FS) acc += pm[(size_t)tl * NV + v];
+    for (int tl = sidx; tl < tps; tl += FS) acc += pm[(size_t)tl * NV + v];
   sl[t] = acc;
   __syncthreads();
   if (t < FC && ch * FC + t < NV) {
     double tot = 0.0;
     for (int s2 = 0; s2 < FS; ++s2) tot += sl[s2 * FC + t];
-    st_coherent(&a.ftot[(size_t)m * NV + ch * FC + t], tot);
+    st_coherent(&a.ftot[((size_t)m * nsl + sc) * NV + ch * FC + t], tot);
   }
   wait_mem();
   __syncthreads();
   if (t == 0) {
     const unsigned old = __hip_atomic_fetch_add(&a.fctr[m], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (old == (unsigned)(nch - 1));
+    s_last = (old == nblk - 1);
     if (s_last) __hip_atomic_store(&a.fctr[m], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   if (!s_last) return;
-  for (int e = t; e < NV; e += UB_THREADS) tots[e] = ld_coherent(&a.ftot[(size_t)m * NV + e]);
+  for (int e = t; e < NV; e += UB_THREADS) {
+    double tot = 0.0;
+    for (int q = 0; q < nsl; ++q) tot += ld_coherent(&a.ftot[((size_t)m * nsl + q) * NV + e]);
+    tots[e] = tot;
+  }
   __syncthreads();
   update_finish<KP>(a.C + (size_t)m * KP * KP, tots, S, S->kk > 0, a.maxit, a.seg_maxit);
 }

@@ -106,6 +106,83 @@ def test_forward_loss_and_gradient_match_oracle(lib, setup):
         assert np.linalg.norm(gg - go) <= 2e-2 * np.linalg.norm(go) + 1e-12, k
 
 
+def _oracle_spectral_loss_grad(prm, w, op, Phi, thetas, insts):
+    """Mean deflated-spectrum loss and parameter gradients (FP64)."""
+    out, cache = OL.mlp_forward(prm, thetas)
+    M = len(insts)
+    losses = np.zeros(M)
+    dout = np.zeros_like(out)
+    for m, inst in enumerate(insts):
+        I, _, _ = oracle.compact(inst.mask)
+        F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
+        d = OL.spectral_data(F, w.Z[I, :], Phi[I, :])
+        C = out[m].reshape(8, 64)[:, :P]
+        losses[m] = OL.spectral_loss(C, d)
+        g = np.zeros((8, 64))
+        g[:, :P] = OL.spectral_grad(C, d) / M
+        dout[m] = g.ravel()
+    return losses, OL.mlp_backward(cache, dout)
+
+
+def test_spectral_loss_and_gradient_match_oracle(lib, setup):
+    """Deflated-spectrum objective: per-sample H and N from the GPU's Grams
+    (Schur-complement formulas) against the oracle's, which writes the
+    S-orthogonalised candidates out; losses to the MLP's FP32/BF16 accuracy,
+    gradients within 2e-2 relative Frobenius."""
+    w, op, thetas, insts, xs, X, Phi, sig = setup
+    case("deflated-spectrum loss / gradient parity")
+    prm, flat = _params(3)
+    s = lib.Solver(learned_objective=lib.SPECTRUM)
+    s.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    s.set_pod_modes(Phi)
+    s.learned_set_params(flat)
+    sel = list(range(12))
+    th = thetas[sel].astype(np.float32)
+    s.learned_prepare(np.stack([insts[m].mask for m in sel]), np.stack([insts[m].b for m in sel]), xs[sel], th)
+    loss_g, grad_g = s.learned_loss_grad()
+    loss_o, grads_o = _oracle_spectral_loss_grad(prm, w, op, Phi, th.astype(np.float64),
+                                                 [insts[m] for m in sel])
+    print(f"   losses GPU {np.round(loss_g[:4], 5).tolist()} oracle {np.round(loss_o[:4], 5).tolist()}", flush=True)
+    np.testing.assert_allclose(loss_g, loss_o, rtol=1e-3, atol=1e-3)
+    off = {"W1": 0, "b1": 512, "W2": 640, "b2": 17024, "W3": 17152, "b3": 82688}
+    for k, o in off.items():
+        go = grads_o[k].ravel()
+        gg = grad_g[o:o + go.size].astype(np.float64)
+        assert np.linalg.norm(gg - go) <= 2e-2 * np.linalg.norm(go) + 1e-12, k
+
+
+def test_spectral_objective_training_shortens_cg(lib, setup):
+    """Trained on the deflated-spectrum objective, the enrichment must lower
+    the iteration count of held-out instances in FP64 and keep them at the
+    x* bar."""
+    w, op, thetas, insts, xs, X, Phi, sig = setup
+    case("deflated-spectrum training, enriched solves on 12 held-out instances (fp64)")
+    prm, flat = _params(4)
+    s = lib.Solver(learned_objective=lib.SPECTRUM)
+    s.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    s.set_enrichment(Phi, flat)
+    th = thetas.astype(np.float32)
+    s.learned_prepare(np.stack([i.mask for i in insts[:MTR]]), np.stack([i.b for i in insts[:MTR]]),
+                      xs[:MTR], th[:MTR])
+    hist = s.learned_train(300, lr=3e-3)
+    print(f"   loss {hist[0]:.4f} -> {hist[-1]:.4f}", flush=True)
+    assert hist[-1] < hist[0]
+    test = list(range(MTR, MTR + 12))
+    masks = np.stack([insts[m].mask for m in test])
+    bs = np.stack([insts[m].b for m in test])
+    plain = s.solve_batched(masks, bs, 1e-10)
+    lrn = s.solve_batched(masks, bs, 1e-10, theta=th[test])
+    print(f"   iterations plain {plain['iters'].tolist()} learned {lrn['iters'].tolist()} "
+          f"learned-used {lrn['learned'].tolist()}", flush=True)
+    Xl = lrn["x"].cpu().numpy()
+    for j, m in enumerate(test):
+        I, _, _ = oracle.compact(insts[m].mask)
+        assert lrn["status"][j] == 0
+        assert oracle.rel_err(Xl[j, I], xs[m][I]) <= 1e-8
+    assert lrn["learned"].sum() > 0
+    assert lrn["iters"].mean() < plain["iters"].mean()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_training_enriched_solves_safeguard_and_gain(lib, setup, prec):
     """FP64: the paper's precision.  Mixed (FP32 operator and panels, FP64

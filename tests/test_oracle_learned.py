@@ -1,5 +1,6 @@
 """Pins of the learned-enrichment oracle (loss, gradient, POD, MLP, Adam)."""
 import numpy as np
+import scipy.sparse as sp
 import pytest
 import torch
 
@@ -32,6 +33,18 @@ def test_pod_matches_method_of_snapshots():
     np.testing.assert_allclose(s, np.sqrt(lam), rtol=1e-9)
     U2 = Xc @ V / np.sqrt(lam)
     np.testing.assert_allclose(np.abs(Phi.T @ U2), np.eye(6), atol=1e-8)
+
+
+def test_pod_recovers_a_prescribed_spectrum():
+    """Closed form: the centred snapshot matrix is U diag(sigma) V^T, so the
+    POD returns sigma and +-U (mean removal must be exact: V^T 1 = 0)."""
+    sigma = 5.0 * 0.9 ** np.arange(40)
+    X, U = gen.pod_snapshots(300, 120, sigma, seed=4)
+    Phi, s = L.pod_modes(X, 20)
+    np.testing.assert_allclose(s, sigma[:20], rtol=1e-10)
+    np.testing.assert_allclose(np.abs(np.sum(Phi * U[:, :20], axis=0)), np.ones(20), atol=1e-9)
+    # sign convention: the largest-magnitude entry of every mode is positive
+    assert np.all(Phi[np.argmax(np.abs(Phi), axis=0), np.arange(20)] > 0)
 
 
 def test_loss_equals_energy_left_by_the_coarse_correction(sample):
@@ -75,6 +88,82 @@ def test_loss_gradient_central_differences(sample, eps):
             Cm[i, j] -= h
             Gfd[i, j] = (L.loss(Cp, d, eps) - L.loss(Cm, d, eps)) / (2 * h)
     assert np.linalg.norm(G - Gfd) <= 1e-6 * np.linalg.norm(G)
+
+
+# ---------------------------------------------------------------------------
+# deflated-spectrum objective
+# ---------------------------------------------------------------------------
+def test_spectral_data_closed_form_on_sine_modes():
+    """Laplacian (diagonal 4) with exact sine eigenmodes: the candidates are
+    already S-orthogonal to the reference modes, so H = diag(lambda) of the
+    candidate modes and N = 4 I; the best 8-dimensional enrichment reaches
+    the 8 smallest of those eigenvalues over 4 (Ky Fan)."""
+    import scipy.linalg as sla
+    n, k, p = 15, 6, 14
+    S = gen.laplacian_2d(n)
+    Zall, _, lam = gen.sine_modes_2d(n, k + p)
+    Z, Phi = Zall[:, :k], Zall[:, k:]
+    d = L.spectral_data(S, Z, Phi)
+    np.testing.assert_allclose(d.H, np.diag(lam[k:]), atol=1e-12)
+    np.testing.assert_allclose(d.N, 4.0 * np.eye(p), atol=1e-12)
+    w, V = sla.eigh(d.H, d.N)
+    C = V[:, :8].T
+    np.testing.assert_allclose(np.exp(L.spectral_loss(C, d)), np.sort(lam[k:])[:8].sum() / 4.0, rtol=1e-12)
+
+
+def test_deflated_candidates_are_s_orthogonal_and_span_the_same_space():
+    rng = np.random.default_rng(5)
+    n = 120
+    T = gen._second_diff(n) + sp.diags(rng.uniform(0.1, 1.0, n))
+    Z = rng.standard_normal((n, 5))
+    Phi = rng.standard_normal((n, 7))
+    P = L.deflated_candidates(T, Z, Phi)
+    assert np.abs(Z.T @ (T @ P)).max() <= 1e-10 * np.abs(Z.T @ (T @ Phi)).max()
+    B1 = np.linalg.qr(np.column_stack([Z, P]))[0]
+    B2 = np.linalg.qr(np.column_stack([Z, Phi]))[0]
+    np.testing.assert_allclose(np.linalg.svd(B1.T @ B2, compute_uv=False), np.ones(12), atol=1e-10)
+    # H, N are the S- and D-weighted Grams of P~
+    d = L.spectral_data(T, Z, Phi)
+    np.testing.assert_allclose(d.H, P.T @ (T @ P), rtol=1e-12, atol=1e-12 * np.abs(d.H).max())
+    np.testing.assert_allclose(d.N, P.T @ (T.diagonal()[:, None] * P), rtol=1e-12,
+                               atol=1e-12 * np.abs(d.N).max())
+
+
+def _spec_sample(seed=6):
+    rng = np.random.default_rng(seed)
+    p = 12
+    A = rng.standard_normal((p, p))
+    H = A @ A.T + 0.1 * np.eye(p)
+    B = rng.standard_normal((p, p))
+    N = B @ B.T + 0.5 * np.eye(p)
+    return L.SpecData(H, N), rng.standard_normal((8, p))
+
+
+def test_spectral_loss_invariance_and_lower_bound():
+    import scipy.linalg as sla
+    d, C = _spec_sample()
+    A = np.random.default_rng(7).standard_normal((8, 8)) + 3.0 * np.eye(8)
+    # a change of basis of the 8 vectors leaves their span, hence R, unchanged
+    assert abs(L.spectral_loss(A @ C, d) - L.spectral_loss(C, d)) <= 1e-11
+    w, V = sla.eigh(d.H, d.N)
+    best = np.log(w[:8].sum())
+    assert abs(L.spectral_loss(V[:, :8].T, d) - best) <= 1e-12
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        assert L.spectral_loss(rng.standard_normal((8, 12)), d) >= best - 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-6])
+def test_spectral_grad_central_differences(eps):
+    d, C = _spec_sample(9)
+    G = L.spectral_grad(C, d)
+    num = np.zeros_like(C)
+    for i in range(C.shape[0]):
+        for j in range(C.shape[1]):
+            E = np.zeros_like(C)
+            E[i, j] = eps
+            num[i, j] = (L.spectral_loss(C + E, d) - L.spectral_loss(C - E, d)) / (2 * eps)
+    np.testing.assert_allclose(G, num, rtol=1e-6, atol=1e-8 * np.abs(G).max())
 
 
 def test_mlp_backward_central_differences():
