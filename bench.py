@@ -84,7 +84,6 @@ def parse():
     ap.add_argument("--cpu-reps", type=int, default=5, help="repetitions per CPU sample (median)")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time full C-oracle solves of instance 0 (all cores; minutes)")
-    ap.add_argument("--no-xstar", action="store_true", help="skip e_rel of the headline against x*")
     ap.add_argument("--no-pod-merge", action="store_true")
     ap.add_argument("--pod-merge-p", type=int, default=8)
     ap.add_argument("--tau-safe", type=float, default=1e4)
@@ -92,6 +91,17 @@ def parse():
     ap.add_argument("--c5-n", type=int, default=127)
     ap.add_argument("--c5-nc", type=int, default=31)
     ap.add_argument("--c5-plain", type=int, default=2, help="plain FP64 instances timed in the 3D arm")
+    ap.add_argument("--c5-precision", choices=["fp64_refine", "fp64", "mixed"], default="fp64_refine")
+    ap.add_argument("--c4", action="store_true",
+                    help="run the learned-enrichment arms on the 255^2 heterogeneous sweep (minutes)")
+    ap.add_argument("--c4-train", type=int, default=2000)
+    ap.add_argument("--c4-test", type=int, default=512)
+    ap.add_argument("--c4-pod", type=int, default=64)
+    ap.add_argument("--c4-batch", type=int, default=256)
+    ap.add_argument("--c4-steps", type=int, default=300)
+    ap.add_argument("--c4-lr", type=float, default=1e-3)
+    ap.add_argument("--c4-objective", choices=["spectrum", "energy"], default="energy")
+    ap.add_argument("--c4-precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-profile", action="store_true", help="skip the instrumented roofline pass")
     return ap.parse_args()
 
@@ -158,23 +168,6 @@ def cpu_baseline(w, spec, iters_ref: float, args):
             "all_cores": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in res["all_cores"].items()},
             "full_solve": full,
             "host": {"model": model, "cores_available": aff, "cpu_count": ncpu}}
-
-
-def xstar_errors(w, X):
-    """e_rel of each instance's solution against x* (oracle: sparse direct
-    factorisation with double-double refinement)."""
-    import oracle
-    op = w.op
-
-    def one(m):
-        inst = w.instances[m]
-        I, _, _ = oracle.compact(inst.mask)
-        F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
-        xs = oracle.exact_solution(F, inst.b[I])
-        return oracle.rel_err(X[m, I], xs)
-
-    with ThreadPoolExecutor(8) as ex:
-        return list(ex.map(one, range(len(w.instances))))
 
 
 def fit_enrichment(solver, args, op):
@@ -268,8 +261,9 @@ def pod_merge_arm(args, lib, op, Z, Phi, masks, bs, prec, tune, t_head, head_ite
 def c5_arm(args, lib, prec, tune):
     """127^3 x 16 two-material 3D workload (k = 64 modes prolonged from the
     coarse grid on the GPU, Alg. 4): batched (tuned, warmed up on a loose
-    tolerance) vs plain FP64 one instance at a time (a sample of instances
-    spanning the active fractions)."""
+    tolerance; FP64 segments stopped on the true residual by default) vs
+    plain FP64 one instance at a time (a sample of instances spanning the
+    active fractions)."""
     import torch
 
     import gen
@@ -279,7 +273,8 @@ def c5_arm(args, lib, prec, tune):
     op = w.op
     masks = torch.as_tensor(np.stack([i.mask for i in w.instances]), device="cuda")
     bs = torch.as_tensor(np.stack([i.b for i in w.instances]), device="cuda")
-    s = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
+    c5p = {"fp64_refine": lib.FP64_REFINE, "fp64": lib.FP64, "mixed": lib.MIXED_REFINE}[args.c5_precision]
+    s = lib.Solver(precision=c5p, inner_rtol=args.inner_rtol, **tune)
     Zg = s.prolong_basis(w.meta["Zc"], 3, args.c5_n, args.c5_nc)
     s.set_reference_factored(op.A, op.alpha, op.shift, Zg)
     s.solve_batched(masks, bs, 1e-3)                 # variant tuning and graphs
@@ -310,12 +305,140 @@ def c5_arm(args, lib, prec, tune):
     rate_p = len(sel) / t_p
     log(f"3D plain FP64 sample {sel}: {t_p:.2f}s ({rate_p:.3f} solves/s)")
     return {"workload": w.name, "grid": args.c5_n, "coarse_grid": args.c5_nc, "k": 64, "instances": 16, "tol": 1e-8,
+            "precision": args.c5_precision,
             "batched": {"solves_per_s": round(16 / t_b, 4), "seconds": round(t_b, 3), "iters_mean": float(it.mean()),
                         "iters_max": int(it.max()), "status": np.asarray(o["status"]).tolist(),
                         "relres_true_max": float(np.asarray(o["relres_true"]).max()),
                         "variant": {"rows_per_thread": v[0], "w_mode": v[1]}},
             "plain_fp64": {"solves_per_s": round(rate_p, 4), "instances_timed": sel, "iters": pit},
             "speedup_vs_plain": round((16 / t_b) / rate_p, 3)}
+
+
+def c4_arm(args, lib):
+    """Learned enrichment on the 255^2 heterogeneous-diffusion sweep.
+    Snapshots: args.c4_train family members (parameter seed 400) solved
+    batched to 1e-8 (mixed precision, stopped on the true residual); POD of
+    all of them (args.c4_pod modes); the MLP trained on the GPU with the
+    chosen objective.  Then args.c4_test held-out members (seed 500) in four
+    arms: reference modes only, learned, untrained MLP (same POD space,
+    initial parameters), and the paper's POD safe merge of the first 8 POD
+    modes (Alg. 2, tau_safe).  The enriched arms keep cond(E) <= 1e8 (FP64
+    panels) and fall back to the reference modes per instance otherwise.
+    Members are batched in order of their active fraction."""
+    import torch
+
+    import gen
+    n, k = 255, 32
+    t0 = time.perf_counter()
+    w = gen.c3_workload(n=n, k=k, B=1)
+    op, mf = w.op, w.meta["mask_field"]
+
+    def members(count, seed):
+        th = gen.c3_thetas(count, seed)
+        th = th[np.argsort(th[:, 3], kind="stable")]
+        return th, [gen.c3_instance(n, t, mf, op.shift) for t in th]
+
+    th_tr, tr = members(args.c4_train, 400)
+    th_te, te = members(args.c4_test, 500)
+    log(f"C4 inputs ({len(tr)} training, {len(te)} test members) in {time.perf_counter() - t0:.1f}s")
+
+    def batch(ins, th):
+        m = torch.as_tensor(np.stack([i.mask for i in ins]), device="cuda")
+        b = torch.as_tensor(np.stack([i.b for i in ins]), device="cuda")
+        a = np.array([i.a for i in ins])
+        c = np.array([i.c for i in ins]) - a * op.shift
+        return m, b, a, c, torch.as_tensor(th.astype(np.float32), device="cuda")
+
+    Bt = args.c4_batch
+    snap = lib.Solver(precision=lib.MIXED_REFINE)
+    snap.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    X = torch.empty((len(tr), op.N), dtype=torch.float64, device="cuda")
+    snap_it = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for j in range(0, len(tr), Bt):
+        m, b, a, c, _ = batch(tr[j:j + Bt], th_tr[j:j + Bt])
+        o = snap.solve_batched(m, b, 1e-8, a=a, c=c)
+        X[j:j + Bt] = o["x"]
+        snap_it += list(o["iters"])
+        if np.any(np.asarray(o["status"]) < 0):
+            raise RuntimeError("snapshot solve failed")
+    torch.cuda.synchronize()
+    t_snap = time.perf_counter() - t1
+    Phi, sig = snap.pod(X.T, args.c4_pod)
+    pod_iters = snap.pod_iters()
+    torch.cuda.synchronize()
+    t_pod = time.perf_counter() - t1 - t_snap
+    snap.close()
+    log(f"C4 snapshots {t_snap:.1f}s (iterations mean {np.mean(snap_it):.0f}), POD {t_pod:.2f}s "
+        f"({pod_iters} subspace iterations, sigma_p/sigma_1 {sig[-1] / sig[0]:.2e})")
+    prec = lib.FP64 if args.c4_precision == "fp64" else lib.MIXED_REFINE
+    obj = lib.SPECTRUM if args.c4_objective == "spectrum" else lib.ENERGY
+    ref_x = []
+
+    def run_arm(name, solver, use_theta):
+        m, b, a, c, th = batch(te[:Bt], th_te[:Bt])
+        solver.solve_batched(m, b, 1e-3, a=a, c=c, theta=th if use_theta else None)   # tuning, graphs
+        its, lu, rel, st, dx = [], 0, [], [], []
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for q, j in enumerate(range(0, len(te), Bt)):
+            m, b, a, c, th = batch(te[j:j + Bt], th_te[j:j + Bt])
+            o = solver.solve_batched(m, b, 1e-8, a=a, c=c, theta=th if use_theta else None)
+            its += list(o["iters"])
+            lu += int(np.sum(o["learned"]))
+            rel += list(o["relres_true"])
+            st += list(o["status"])
+            if name == "plain":
+                ref_x.append(o["x"])
+            else:
+                dx.append(float((torch.linalg.norm(o["x"] - ref_x[q], dim=1) /
+                                 torch.linalg.norm(ref_x[q], dim=1)).max()))
+        torch.cuda.synchronize()
+        t = time.perf_counter() - ta
+        r = {"seconds": round(t, 3), "solves_per_s": round(len(te) / t, 3), "iters_mean": float(np.mean(its)),
+             "iters_max": int(np.max(its)), "learned_used": lu, "relres_true_max": float(np.max(rel)),
+             "status_counts": {str(int(v)): int(cn) for v, cn in zip(*np.unique(st, return_counts=True))}}
+        if dx:
+            r["vs_plain_rel_diff_max"] = max(dx)
+        log(f"C4 arm {name}: {t:.1f}s, iterations mean {r['iters_mean']:.1f}, learned basis used {lu}/{len(te)}")
+        return r
+
+    arms = {}
+    sp = lib.Solver(precision=prec)
+    sp.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    arms["plain"] = run_arm("plain", sp, False)
+    sp.close()
+    su = lib.Solver(precision=prec, learned_objective=obj)
+    su.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    su.set_enrichment(Phi, gen.mlp_params(1))
+    arms["untrained"] = run_arm("untrained", su, True)
+    mt, bt, at, ct, tht = batch(tr, th_tr)
+    t2 = time.perf_counter()
+    su.learned_prepare(mt, bt, X, tht, a=at, c=ct)
+    hist = su.learned_train(args.c4_steps, lr=args.c4_lr)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t2
+    del mt, bt, X
+    log(f"C4 training ({args.c4_objective}): {t_fit:.1f}s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    arms["learned"] = run_arm("learned", su, True)
+    su.close()
+    sm = lib.Solver(precision=prec)
+    sm.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    sm.set_pod_modes(Phi[:, :8])
+    sm.pod_enrich(8, args.tau_safe)
+    arms["pod_merge"] = run_arm("pod_merge", sm, False)
+    sm.close()
+    return {"workload": f"hetdiff2d_{n}x{n}_k{k}", "train_members": len(tr), "test_members": len(te),
+            "batch": Bt, "pod_modes": args.c4_pod, "objective": args.c4_objective,
+            "precision": args.c4_precision, "tol": 1e-8, "tau_learned": 1e8, "tau_safe": args.tau_safe,
+            "snapshots": {"seconds": round(t_snap, 2), "iters_mean": float(np.mean(snap_it)),
+                          "precision": "mixed"},
+            "pod": {"seconds": round(t_pod, 3), "subspace_iterations": pod_iters,
+                    "sigma_ratio_last": float(sig[-1] / sig[0])},
+            "training": {"steps": args.c4_steps, "lr": args.c4_lr, "seconds": round(t_fit, 2),
+                         "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
+            "arms": arms}
 
 
 def measured_traffic(kernel: str):
@@ -426,15 +549,6 @@ def main():
                        "vs_headline_e_rel_max": float((num / den).max())}
         log(f"batched + learned (forced): {t_l:.2f}s ({B / t_l:.3f} solves/s)")
 
-    xerr = None
-    if not args.no_xstar:
-        t1 = time.perf_counter()
-        e = xstar_errors(w, X_head.cpu().numpy())
-        xerr = {"e_rel_max": float(max(e)), "e_rel_per_instance": [float(v) for v in e],
-                "route": "sparse LU of the restricted factored operator + double-double refinement",
-                "seconds": round(time.perf_counter() - t1, 1)}
-        log(f"headline e_rel against x*: max {max(e):.2e}")
-
     pod_arm = None
     if Phi is not None and not args.no_pod_merge:
         try:
@@ -468,6 +582,13 @@ def main():
         ps.close()
         del X_plain
         log(f"plain step done ({t_plain:.2f}s)")
+
+    c4 = None
+    if args.c4:
+        try:
+            c4 = c4_arm(args, lib)
+        except Exception as ex:            # reported, never fatal for the headline
+            c4 = {"error": str(ex)}
 
     c5 = None
     if not args.no_c5:
@@ -543,12 +664,12 @@ def main():
         "cond_E": {"min": float(np.min(out["cond_E"])), "max": float(np.max(out["cond_E"]))},
         "iters_per_instance": head_iters.tolist(),
         "relres_true_max": float(head_rel.max()),
-        "xstar": xerr,
         "plain": plain,
         "speedup_vs_plain": (round(value / plain["solves_per_s"], 3) if plain else None),
         "learned_fit": learned,
         "learned_arm": learned_arm,
         "pod_merge": pod_arm,
+        "c4": c4,
         "c5": c5,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -395,7 +395,8 @@ int adef2_learned_get_params(adef2_ctx *ctx, float *params);
  * and N (p x p) when opts.learned_objective = 1; the objective is fixed for
  * these samples until the next call.  E_ARG when a sample has
  * b_I^T x_I <= 0 (x is not the solution, or b_I = 0); E_UNSUPPORTED when
- * k*k + k*(p+1) (+ k*p for objective 1) > 8192. */
+ * k*k + k*(p+1) (+ k*p for objective 1) > 20352 (159 KiB of LDS; k = 64
+ * with p = 64 fits both objectives). */
 int adef2_learned_prepare(adef2_ctx *ctx, int32_t M, const uint8_t *masks, const double *b,
                           const double *xsol, const float *theta, const double *a,
                           const double *c);
@@ -499,12 +500,13 @@ int adef2_active_set_batched(adef2_ctx *ctx, int32_t B, const double *y_d, const
  * the candidates tried (0 when not tuned).  E_STATE before the first solve. */
 int adef2_variant(adef2_ctx *ctx, int32_t *rows_per_thread, int32_t *w_mode, float *ms);
 
+#define ADEF2_STATS_KERNELS 24
 typedef struct {
   int32_t n_kernels;            /* entries filled                           */
-  const char *name[16];
-  int64_t launches[16];
-  double total_ms[16];          /* HIP-event time summed over launches      */
-  double alg_bytes[16];         /* algorithmic bytes summed over launches   */
+  const char *name[ADEF2_STATS_KERNELS];
+  int64_t launches[ADEF2_STATS_KERNELS];
+  double total_ms[ADEF2_STATS_KERNELS];  /* HIP-event time summed over launches */
+  double alg_bytes[ADEF2_STATS_KERNELS]; /* algorithmic bytes summed over launches */
   int64_t polls;                /* host reads of the device convergence state
                                    (counted in every mode, not only profile) */
   int64_t pod_iters;            /* subspace iterations of the last adef2_pod

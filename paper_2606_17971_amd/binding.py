@@ -58,10 +58,10 @@ class Opts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [
         ("n_kernels", ctypes.c_int32),
-        ("name", ctypes.c_char_p * 16),
-        ("launches", ctypes.c_int64 * 16),
-        ("total_ms", ctypes.c_double * 16),
-        ("alg_bytes", ctypes.c_double * 16),
+        ("name", ctypes.c_char_p * 24),
+        ("launches", ctypes.c_int64 * 24),
+        ("total_ms", ctypes.c_double * 24),
+        ("alg_bytes", ctypes.c_double * 24),
         ("polls", ctypes.c_int64),
         ("pod_iters", ctypes.c_int64),
     ]

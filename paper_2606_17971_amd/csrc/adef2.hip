@@ -60,10 +60,12 @@ constexpr double FP32_COND = 1e-3 / 5.96e-8;   // learned cond(E) bound with FP3
 
 enum KernelId { KI_INIT = 0, KI_INIT2, KI_PUPDATE, KI_SPMV, KI_UPDATE, KI_RESID, KI_ACCUM,
                 KI_GRAM, KI_COARSE, KI_COMPACT, KI_UPDATE_NW, KI_ZPROJ, KI_PUPDATE_BT, KI_ZPROJ_BT,
-                KI_PUPDATE_TM, KI_UPDATE_TM, KI_COUNT };
+                KI_PUPDATE_TM, KI_UPDATE_TM, KI_FINISH_TM, KI_STENCIL, KI_COUNT };
+static_assert(KI_COUNT <= ADEF2_STATS_KERNELS, "adef2_stats holds ADEF2_STATS_KERNELS entries");
 const char* kKernelNames[KI_COUNT] = {"init", "init2", "pupdate", "spmv", "update", "resid64",
                                       "accumulate", "spmm_gram", "coarse", "compact", "update_nw",
-                                      "zproj", "pupdate_bt", "zproj_bt", "pupdate_tm", "update_tm"};
+                                      "zproj", "pupdate_bt", "zproj_bt", "pupdate_tm", "update_tm",
+                                      "finish_tm", "stencil1"};
 
 }  // namespace
 
@@ -724,7 +726,8 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
 
 // algorithmic bytes per launch (per instance: inactive rows only); wv / wm =
 // bytes per vector entry / per operator or panel entry
-struct ByteModel { double init, init2, pupdate, spmv, update, resid, accum, update_nw, zproj, update_tm; };
+struct ByteModel { double init, init2, pupdate, stencil, spmv, update, resid, accum, update_nw, zproj, update_tm,
+                   finish_tm; };
 // Algorithmic bytes per launch.  Per-instance data (vectors, W, the mask) is
 // counted for every instance still iterating at the last poll (a finished
 // instance's blocks exit at their first instruction); operands shared by
@@ -754,12 +757,16 @@ ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active
   b.pupdate = nI * 3 * wv + zsh + Nall;                        // z, p -> p; Z c
   const double outer = nI * 3 * wv + U * D * wm + Nall;        // t (or p), p -> w; A^T or S
   const double inner = c->factored ? (Nall * 2 * wv + N1 * D1 * wm) : 0.0;   // t = A v
-  b.spmv = inner + outer;
+  b.stencil = inner;
+  b.spmv = outer;
   b.update = nI * (k * wm + 8 * wv) + zsh + Nall;              // W, Z; x p r w dinv -> x r z
   b.update_nw = nI * 8 * wv + Nall;                            // x p r w dinv -> x r z
   // x p r w -> x r z; the Jacobi scaling from the shared diagonal (N rows once);
   // Z once (row-major copy); the boundary rows' list entries
   b.update_tm = nI * 7 * wv + Nall + N1 * 8.0 + zsh + (double)c->nbnd * (4.0 + k * wm);
+  // tile partial sums of the iterating instances, the slice totals written and read back
+  const double nv = 2.0 * (double)c->KP + 2.0;
+  b.finish_tm = (double)nact * nv * 8.0 * ((double)c->ub_ntiles_pad + 2.0 * fin_slices(c->ub_ntiles_pad));
   // (t = A z), z, r; Z^T u, Z^T r with the FP64 operator and modes
   const double inner64 = c->factored ? (Nall * 2 * wv + N1 * D1 * 8.0) : 0.0;
   b.zproj = inner64 + nI * 3 * wv + U * D * 8.0 + zsh * (8.0 / wm) + Nall;
@@ -884,26 +891,30 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
       }
       if (!tm && !bt)
         timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, s, a); });
+      if (c->factored)
+        timed(c, KI_STENCIL, bm.stencil, [&] {
+          if constexpr (sizeof(V) == 8)
+            if (stm) hipLaunchKernelGGL(btt.stencil1_tm, gst, dim3(UB_THREADS), 0, s, a);
+          if (!stm)
+            hipLaunchKernelGGL(st1, grid, blk, 0, s, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
+        });
       timed(c, KI_SPMV, bm.spmv, [&] {
         if constexpr (sizeof(V) == 8) {
           if (stm) {
-            if (c->factored) hipLaunchKernelGGL(btt.stencil1_tm, gst, dim3(UB_THREADS), 0, s, a);
             hipLaunchKernelGGL(btt.spmv_tm, gst, dim3(UB_THREADS), 0, s, a);
             hipLaunchKernelGGL(btt.alpha_tm, dim3((unsigned)c->B), dim3(UB_THREADS), 0, s, a);
           }
         }
-        if (!stm) {
-          if (c->factored)
-            hipLaunchKernelGGL(st1, grid, blk, 0, s, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
-          hipLaunchKernelGGL(kt.spmv, grid, blk, 0, s, a);
-        }
+        if (!stm) hipLaunchKernelGGL(kt.spmv, grid, blk, 0, s, a);
       });
       if (tm) {
         if constexpr (sizeof(V) == 8)
-          timed(c, KI_UPDATE_TM, bm.update_tm, [&] {
-            hipLaunchKernelGGL(btt.update_tm, gut, dim3(UB_THREADS), 0, s, a);
-            hipLaunchKernelGGL(btt.finish_tm, gfin, dim3(UB_THREADS), 0, s, a);
-          });
+        {
+          timed(c, KI_UPDATE_TM, bm.update_tm,
+                [&] { hipLaunchKernelGGL(btt.update_tm, gut, dim3(UB_THREADS), 0, s, a); });
+          timed(c, KI_FINISH_TM, bm.finish_tm,
+                [&] { hipLaunchKernelGGL(btt.finish_tm, gfin, dim3(UB_THREADS), 0, s, a); });
+        }
       } else if (!wfree) {
         timed(c, KI_UPDATE, bm.update, [&] {
           hipLaunchKernelGGL((c->ne > 0 ? kt.update_spec : kt.update), grid, blk, 0, s, a);
@@ -2051,6 +2062,7 @@ int adef2_reset_stats(adef2_ctx* c) {
 }  // extern "C"
 
 namespace {
+constexpr size_t LOSS_LDS_MAX = 159 * 1024;   // dynamic LDS of k_loss_data (160 KiB less its static part)
 constexpr int POD_MAX_M = 8192;   // snapshots per POD call
 constexpr int POD_MAXIT = 500;    // subspace iterations (M > JMAX)
 
@@ -2298,9 +2310,14 @@ int adef2_learned_prepare(adef2_ctx* c, int32_t M, const uint8_t* masks, const d
   const int k = c->k, p = c->p, nb = k + p;
   const int obj = c->o.learned_objective;
   const size_t lds = sizeof(double) * ((size_t)k * k + (size_t)k * (p + 1) + (obj == 1 ? (size_t)k * p : 0));
-  if (lds > 65536)
+  // k_loss_data keeps the k x k Cholesky factor and its solves in LDS: up to
+  // 159 KiB of gfx950's 160 KiB per workgroup (k = 64, p = 64 fits either
+  // objective)
+  if (lds > LOSS_LDS_MAX)
     return fail(c, ADEF2_E_UNSUPPORTED, "learned_prepare: k*k + k*(p+1) (+ k*p for the deflated-spectrum "
-                                        "objective) must fit 8192 doubles");
+                                        "objective) must fit 20352 doubles (159 KiB of LDS)");
+  if (lds > 65536)
+    HIPCHK(c, hipFuncSetAttribute((const void*)k_loss_data, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   int rc;
   c->Mtr = 0;
   if ((rc = dalloc(c, &c->theta_tr, (size_t)M * MD0)) || (rc = dalloc(c, &c->Htr, (size_t)M * p * p)) ||

@@ -151,6 +151,49 @@ def test_spectral_loss_and_gradient_match_oracle(lib, setup):
         assert np.linalg.norm(gg - go) <= 2e-2 * np.linalg.norm(go) + 1e-12, k
 
 
+@pytest.mark.parametrize("objective", ["energy", "spectrum"])
+def test_loss_data_with_64_reference_modes_and_64_pod_modes(lib, objective):
+    """k = 64 reference modes with p = 64 POD modes: the per-sample Schur
+    complement data no longer fit 64 KiB of LDS (66 KiB with the energy
+    objective, 99 KiB with the deflated-spectrum objective); losses against
+    the oracle on 6 samples."""
+    case(f"loss data with k=64, p=64 ({objective})")
+    w = gen.c2_workload(n=N_GRID, k=64, B=1)
+    op = w.op
+    thetas = gen.c2_thetas(72, 901)
+    insts = [gen.c2_family_instance(N_GRID, th) for th in thetas]
+    xs = []
+    for inst in insts:
+        I, _, _ = oracle.compact(inst.mask)
+        F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
+        x = np.zeros(op.N)
+        x[I] = oracle.exact_solution(F, inst.b[I])
+        xs.append(x)
+    xs = np.array(xs)
+    Phi, _ = OL.pod_modes(xs.T, 64)
+    prm, flat = _params(5)
+    s = lib.Solver(learned_objective=lib.SPECTRUM if objective == "spectrum" else lib.ENERGY)
+    s.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    s.set_pod_modes(Phi)
+    s.learned_set_params(flat)
+    sel = list(range(6))
+    th = thetas[sel].astype(np.float32)
+    s.learned_prepare(np.stack([insts[m].mask for m in sel]), np.stack([insts[m].b for m in sel]), xs[sel], th)
+    loss_g, _ = s.learned_loss_grad()
+    out_o, _ = OL.mlp_forward(prm, th.astype(np.float64))
+    for j, m in enumerate(sel):
+        inst = insts[m]
+        I, _, _ = oracle.compact(inst.mask)
+        F, _ = oracle.restrict_factored(op.A, op.alpha, op.shift, I)
+        C = out_o[j].reshape(8, 64)
+        if objective == "spectrum":
+            lo = OL.spectral_loss(C, OL.spectral_data(F, w.Z[I, :], Phi[I, :]))
+        else:
+            lo = OL.loss(C, OL.loss_data(F, w.Z[I, :], Phi[I, :], inst.b[I], xs[m][I]))
+        print(f"   m={m} loss GPU {loss_g[j]:.6f} oracle {lo:.6f}", flush=True)
+        assert abs(loss_g[j] - lo) <= 1e-3 * max(1.0, abs(lo))
+
+
 def test_spectral_objective_training_shortens_cg(lib, setup):
     """Trained on the deflated-spectrum objective, the enrichment must lower
     the iteration count of held-out instances in FP64 and keep them at the
