@@ -56,11 +56,11 @@ __device__ __forceinline__ void tile_group(int ntiles_pad, int ngroups, int& til
 // ---------------------------------------------------------------------------
 template <typename M, int KP>
 __global__ void __launch_bounds__(UB_THREADS) k_pupdate_tm(IterArgs<double, M> a) {
-  constexpr int KS = KP / 4;                        // matrix-core k steps (KP % 8 == 0)
+  constexpr int KS = KP / 4;
   constexpr int K1 = KP > 0 ? KP : 1;
   __shared__ double cf[PB_G][K1 + 1];
   __shared__ double s_beta[PB_G];
-  __shared__ int s_k[PB_G];                        // 0 skip, 1 no coarse space, 2 deflated
+  __shared__ int s_k[PB_G];
   __shared__ int s_keep[PB_G];
   int tile, grp;
   tile_group(a.ub_ntiles_pad, a.pb_ngroups, tile, grp);
@@ -71,27 +71,6 @@ __global__ void __launch_bounds__(UB_THREADS) k_pupdate_tm(IterArgs<double, M> a
   const int64_t N = a.op.N;
   const int64_t base = (int64_t)tile * UB_ROWS;
   const int cn = lane & 15, kk = lane >> 4;
-  // loads that need no instance state first: masks and the rows of Z
-  // (B operand: B[k = kk][row = cn] = Z[4 s + kk][row])
-  uint8_t mk[4][4];
-#pragma unroll
-  for (int sl = 0; sl < 4; ++sl) {
-    const int64_t i = base + 64 * wid + 16 * sl + cn;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int j = 4 * e + kk;
-      mk[sl][e] = (j < G && i < N) ? a.mask[(size_t)(g0 + j) * N + i] : (uint8_t)1;
-    }
-  }
-  double bv[4][KS > 0 ? KS : 1];
-  if constexpr (KP > 0) {
-#pragma unroll
-    for (int sl = 0; sl < 4; ++sl) {
-      const int64_t ib = base + 64 * wid + 16 * sl + cn;
-#pragma unroll
-      for (int s = 0; s < KS; ++s) bv[sl][s] = ib < N ? (double)a.Z[(size_t)(4 * s + kk) * N + ib] : 0.0;
-    }
-  }
   if (t < PB_G) {
     int k = 0, keep = 0;
     double b = 0.0;
@@ -101,9 +80,7 @@ __global__ void __launch_bounds__(UB_THREADS) k_pupdate_tm(IterArgs<double, M> a
       keep = !S->fresh;
       b = S->fresh ? 0.0 : S->beta;
     }
-    s_k[t] = k;
-    s_keep[t] = keep;
-    s_beta[t] = b;
+    s_k[t] = k; s_keep[t] = keep; s_beta[t] = b;
   }
   for (int e = t; e < PB_G * KP; e += UB_THREADS) {
     const int j = e / K1, q = e - j * K1;
@@ -118,50 +95,61 @@ __global__ void __launch_bounds__(UB_THREADS) k_pupdate_tm(IterArgs<double, M> a
   bool any = false;
   for (int j = 0; j < PB_G; ++j) any |= s_k[j] != 0;
   if (!any) return;
-  // this lane's outputs: instance j = 4 e + kk of row base + 64 wid + 16 sl + cn
-  double zv[4][4], pv[4][4];
+  // A operand: the coarse coordinates, A[j = cn][k = kk]; B operand: rows
+  // of Z, B[k = kk][row = cn] = Z[row][4 s + kk]
+  double av[KS > 0 ? KS : 1];
 #pragma unroll
-  for (int sl = 0; sl < 4; ++sl)
+  for (int s = 0; s < KS; ++s) av[s] = cf[cn][4 * s + kk];
+  // one 16-row slice at a time (low register use: 4 waves per SIMD)
+#pragma unroll 1
+  for (int s0 = 0; s0 < 4; ++s0) {
+    constexpr int SPP = 1;
+    uint8_t mk[SPP][4];
+    double bv[SPP][KS > 0 ? KS : 1], zv[SPP][4], pv[SPP][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (!s_k[4 * e + kk]) mk[sl][e] = 1;
+    for (int u = 0; u < SPP; ++u) {
+      const int64_t i = base + 64 * wid + 16 * (s0 + u) + cn;
 #pragma unroll
-  for (int sl = 0; sl < 4; ++sl) {
-    const int64_t i = base + 64 * wid + 16 * sl + cn;
+      for (int s = 0; s < KS; ++s) bv[u][s] = i < N ? (double)a.Z[(size_t)(4 * s + kk) * N + i] : 0.0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int j = 4 * e + kk;
-      zv[sl][e] = 0.0;
-      pv[sl][e] = 0.0;
-      if (!mk[sl][e]) {
-        const int64_t o = (int64_t)(g0 + j) * a.vs + i;
-        zv[sl][e] = a.z[o];
-        if (s_keep[j]) pv[sl][e] = a.p[o];
+      for (int e = 0; e < 4; ++e) {
+        const int j = 4 * e + kk;
+        mk[u][e] = (j < G && i < N && s_k[j]) ? a.mask[(size_t)(g0 + j) * N + i] : (uint8_t)1;
       }
     }
-  }
-  tm_d4 d[4];
 #pragma unroll
-  for (int sl = 0; sl < 4; ++sl) d[sl] = tm_d4{0.0, 0.0, 0.0, 0.0};
-  if constexpr (KP > 0) {
-    double av[KS];
+    for (int u = 0; u < SPP; ++u) {
+      const int64_t i = base + 64 * wid + 16 * (s0 + u) + cn;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) av[s] = cf[cn][4 * s + kk];    // A[j = cn][k = kk]
+      for (int e = 0; e < 4; ++e) {
+        const int j = 4 * e + kk;
+        zv[u][e] = 0.0;
+        pv[u][e] = 0.0;
+        if (!mk[u][e]) {
+          const int64_t o = (int64_t)(g0 + j) * a.vs + i;
+          zv[u][e] = a.z[o];
+          if (s_keep[j]) pv[u][e] = a.p[o];
+        }
+      }
+    }
+    tm_d4 d[SPP];
 #pragma unroll
-    for (int sl = 0; sl < 4; ++sl)
+    for (int u = 0; u < SPP; ++u) {
+      d[u] = tm_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int s = 0; s < KS; ++s) d[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[sl][s], d[sl], 0, 0, 0);
-  }
+      for (int s = 0; s < KS; ++s) d[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[u][s], d[u], 0, 0, 0);
+    }
 #pragma unroll
-  for (int sl = 0; sl < 4; ++sl) {
-    const int64_t i = base + 64 * wid + 16 * sl + cn;
+    for (int u = 0; u < SPP; ++u) {
+      const int64_t i = base + 64 * wid + 16 * (s0 + u) + cn;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (mk[sl][e]) continue;
-      const int j = 4 * e + kk;
-      double p = zv[sl][e] - d[sl][e];
-      if (s_keep[j]) p += s_beta[j] * pv[sl][e];
-      a.p[(int64_t)(g0 + j) * a.vs + i] = p;
+      for (int e = 0; e < 4; ++e) {
+        if (mk[u][e]) continue;
+        const int j = 4 * e + kk;
+        double pn = zv[u][e] - d[u][e];
+        if (s_keep[j]) pn += s_beta[j] * pv[u][e];
+        a.p[(int64_t)(g0 + j) * a.vs + i] = pn;
+      }
     }
   }
 }
@@ -171,8 +159,13 @@ __global__ void __launch_bounds__(UB_THREADS) k_pupdate_tm(IterArgs<double, M> a
 // block sums [W^T z_j | Z^T r_j | r_j.z_j | r_j.r_j] of the tile, stored to
 // part[m][tile][0 .. 2 KP + 2) for k_finish_tm
 // ---------------------------------------------------------------------------
+// Up to 32 modes: at least 4 waves per SIMD, the register budget (<= 128)
+// that lets four 256-thread blocks share a CU; the default allocation (3
+// waves) left the vector loads' latency exposed (71 vs 81 us at 511^2 x 16).
+// Wider bases would spill under that budget and keep the default.
 template <typename M, int KP>
-__global__ void __launch_bounds__(UB_THREADS) k_update_tm(IterArgs<double, M> a) {
+__global__ void __launch_bounds__(UB_THREADS) __attribute__((amdgpu_waves_per_eu(KP <= 32 ? 4 : 1, 8)))
+k_update_tm(IterArgs<double, M> a) {
   constexpr int KQ = (KP + 15) / 16 * 16;          // columns padded to the matrix-core tile
   constexpr int NQT = KQ / 16;
   constexpr int NV = 2 * KP + 2;

@@ -288,6 +288,36 @@ def test_batched_operator_scales(lib, form):
         assert abs(int(out["iters"][m]) - ref.iters) <= 2
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp64_refine"])
+def test_per_instance_tolerances(lib, prec):
+    """solve_batched with one tolerance per instance (App. "CG stopping
+    criterion" applied per instance): each instance stops on its own
+    tolerance.  FP64: iteration counts within 2 of the oracle's FP64 loop at
+    that tolerance; refinement modes: the FP64 true residual meets it."""
+    w = gen.c2_workload(n=95, k=16, B=4)
+    S = spec(w.op, "factored")
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    tols = np.array([1e-4, 1e-6, 1e-8, 1e-10])
+    case(f"per-instance tolerances {tols.tolist()} cd2d n=95 {prec}")
+    p = {"fp64": lib.FP64, "mixed": lib.MIXED_REFINE, "fp64_refine": lib.FP64_REFINE}[prec]
+    s = solver(lib, w.op, w.Z, "factored", precision=p)
+    out = s.solve_batched(masks, bs, tols)
+    X = out["x"].cpu().numpy()
+    print(f"   iterations {out['iters'].tolist()} relres {np.asarray(out['relres_true']).tolist()}", flush=True)
+    for m, inst in enumerate(w.instances):
+        ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, tols[m])
+        I, xs = _xstar(S, inst.mask, inst.b)
+        assert out["status"][m] == 0
+        if prec == "fp64":
+            assert abs(int(out["iters"][m]) - ref.iters) <= 2, (m, out["iters"][m], ref.iters)
+        else:
+            assert out["relres_true"][m] <= tols[m]
+        # the error at each tolerance is the oracle's at that tolerance
+        e, e_or = oracle.rel_err(X[m, I], xs), oracle.rel_err(ref.x[I], xs)
+        assert e <= max(1e-8, 10 * e_or), (m, e, e_or)
+
+
 # ---------------------------------------------------------------------------
 # status paths
 # ---------------------------------------------------------------------------
