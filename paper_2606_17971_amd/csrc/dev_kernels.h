@@ -303,6 +303,7 @@ __device__ __forceinline__ double adef2_direction(const double* Cm, const double
     __syncthreads();
     for (int q = threadIdx.x; q < KP; q += blockDim.x) {
       double s = 0.0;
+#pragma unroll 4
       for (int l = 0; l < KP; ++l) s += Cm[q * KP + l] * gl[l];
       cl[q] = s;
       S->coef[q] = s;
@@ -312,6 +313,7 @@ __device__ __forceinline__ double adef2_direction(const double* Cm, const double
   if (threadIdx.x == 0) {
     double corr = 0.0;
     if (defl)
+#pragma unroll 4
       for (int q = 0; q < KP; ++q) corr += tot[KP + q] * cl[q];
     s_rho = tot[2 * KP] - corr;
   }
@@ -913,7 +915,7 @@ typedef double bt_d4 __attribute__((ext_vector_type(4)));
 constexpr int BT_TPB = 4;
 
 template <typename M, int KP>
-__global__ void __launch_bounds__(BT_THREADS) k_zproj_bt(IterArgs<double, M> a) {
+__global__ void __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) k_zproj_bt(IterArgs<double, M> a) {
   constexpr int KQ = (KP + 15) / 16 * 16;          // Z columns padded to the MFMA tile
   constexpr int NC = 2 * BT_G;                     // V columns
   constexpr int NV = 2 * KP + 2;
@@ -998,15 +1000,18 @@ __global__ void __launch_bounds__(BT_THREADS) k_zproj_bt(IterArgs<double, M> a) 
           const int qt = ot / (NC / 16), ct = ot % (NC / 16);
           const int cb = ct * 16 + (lane & 15), kr = lane >> 4;
           const int qa = qt * 16 + (lane & 15);
-          double av[KS];
+          // A operands in chunks of 8 k steps (fewer live registers)
+          for (int k0 = 0; k0 < KS; k0 += 8) {
+            double av[8];
 #pragma unroll
-          for (int k = 0; k < KS; ++k) {
-            const int64_t gi = base + 4 * k + kr;
-            av[k] = (qa < KP && tile < a.bt_ntiles && gi < N) ? a.Z64[(size_t)qa * N + gi] : 0.0;
+            for (int k = 0; k < 8; ++k) {
+              const int64_t gi = base + 4 * (k0 + k) + kr;
+              av[k] = (qa < KP && tile < a.bt_ntiles && gi < N) ? a.Z64[(size_t)qa * N + gi] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+              acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], vs[4 * (k0 + k) + kr][cb], acc[s], 0, 0, 0);
           }
-#pragma unroll
-          for (int k = 0; k < KS; ++k)
-            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], vs[4 * k + kr][cb], acc[s], 0, 0, 0);
         }
       }
       __syncthreads();
