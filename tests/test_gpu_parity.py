@@ -426,6 +426,31 @@ def test_tile_major_boundary_update_matches_oracle(lib, form, rpt, w_mode, B):
     assert np.all(X[masks == 1] == 0.0)
 
 
+@pytest.mark.parametrize("w_mode", [4, 5])
+def test_tile_major_boundary_update_wide_basis(lib, w_mode):
+    """The tile-major kernels with 48 shared modes (3 matrix-core column
+    tiles; above 32 modes the update keeps the compiler's register
+    allocation instead of the 4-waves-per-SIMD budget)."""
+    w = gen.c2_workload(n=95, k=48, B=11)
+    S = spec(w.op, "factored")
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case(f"tile-major boundary update w_mode={w_mode} factored cd2d n=95 k=48 B=11")
+    s = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE, rows_per_thread=1, w_mode=w_mode)
+    out = s.solve_batched(masks, bs, 1e-10)
+    assert s.variant()[1] == w_mode
+    X = out["x"].cpu().numpy()
+    for m, inst in enumerate(w.instances):
+        ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
+        I, xs = _xstar(S, inst.mask, inst.b)
+        e = oracle.rel_err(X[m, I], xs)
+        assert out["status"][m] == 0
+        assert out["relres_true"][m] <= 1e-10
+        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), (m, e)
+        assert int(out["iters"][m]) <= 1.2 * ref.iters + 20, (m, out["iters"][m], ref.iters)
+    assert np.all(X[masks == 1] == 0.0)
+
+
 def test_tile_major_needs_eigen_basis(lib):
     """w_mode 4 is refused (E_UNSUPPORTED) with FP64 panels, where the
     boundary form of W is not used."""
