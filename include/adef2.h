@@ -221,6 +221,25 @@ typedef struct {
                            operator, deflated by Z_I, on span(V_I):
                            small when V_I holds the slow modes that CG
                            would otherwise have to resolve); 0             */
+  int32_t op_fused;     /* operator pass of the factored form S = alpha A^T A
+                           + shift I inside the iteration: 1 = fused, one
+                           kernel per iteration forms t = A p for a tile of
+                           rows and the stencil reach around it in LDS and
+                           applies A^T to it there (t never reaches HBM);
+                           -1 = two passes (t = A p written to HBM, then
+                           A^T t); 0 (default) = tuned on the first solve
+                           of each configuration, after the tile height and
+                           w_mode, whenever the fused pass applies, at
+                           tile heights of 2, 4 and 8 times the stencil
+                           reach (the fastest is kept; 1 takes 4 times, or
+                           the nearest that fits).  It applies to the
+                           factored form when a tile of twice the stencil
+                           reach plus that reach on both sides fits 64 KiB
+                           of LDS (2D grids up to about 2000 points wide;
+                           not 3D grids, whose reach is a whole plane); 1
+                           is E_UNSUPPORTED otherwise.  Same arithmetic per
+                           row as the two passes; only the summation tree
+                           of p.S p differs                                 */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;
@@ -499,6 +518,15 @@ int adef2_active_set_batched(adef2_ctx *ctx, int32_t B, const double *y_d, const
  * of the tuned candidates, rows per thread outer, w_mode inner, restricted to
  * the candidates tried (0 when not tuned).  E_STATE before the first solve. */
 int adef2_variant(adef2_ctx *ctx, int32_t *rows_per_thread, int32_t *w_mode, float *ms);
+
+/* Operator form used by the last solve on ctx (see opts.op_fused): fused
+ * (1) or two passes (0), the fused pass's tile height in rows (0 when not
+ * fused), and in ms (host f32[4], may be NULL) the tuning trial times with
+ * the chosen rows per thread and w_mode: ms[0] two passes, ms[1..3] the
+ * fused pass at tile heights of 2, 4 and 8 times the stencil reach (rounded
+ * up to 256 rows; 0 where a height does not fit or nothing was tuned).
+ * E_STATE before the first solve. */
+int adef2_operator_variant(adef2_ctx *ctx, int32_t *fused, int32_t *tile_rows, float *ms);
 
 #define ADEF2_STATS_KERNELS 24
 typedef struct {

@@ -60,12 +60,12 @@ constexpr double FP32_COND = 1e-3 / 5.96e-8;   // learned cond(E) bound with FP3
 
 enum KernelId { KI_INIT = 0, KI_INIT2, KI_PUPDATE, KI_SPMV, KI_UPDATE, KI_RESID, KI_ACCUM,
                 KI_GRAM, KI_COARSE, KI_COMPACT, KI_UPDATE_NW, KI_ZPROJ, KI_PUPDATE_BT, KI_ZPROJ_BT,
-                KI_PUPDATE_TM, KI_UPDATE_TM, KI_FINISH_TM, KI_STENCIL, KI_COUNT };
+                KI_PUPDATE_TM, KI_UPDATE_TM, KI_FINISH_TM, KI_STENCIL, KI_OPFUSED, KI_COUNT };
 static_assert(KI_COUNT <= ADEF2_STATS_KERNELS, "adef2_stats holds ADEF2_STATS_KERNELS entries");
 const char* kKernelNames[KI_COUNT] = {"init", "init2", "pupdate", "spmv", "update", "resid64",
                                       "accumulate", "spmm_gram", "coarse", "compact", "update_nw",
                                       "zproj", "pupdate_bt", "zproj_bt", "pupdate_tm", "update_tm",
-                                      "finish_tm", "stencil1"};
+                                      "finish_tm", "stencil1", "opfused"};
 
 }  // namespace
 
@@ -200,7 +200,15 @@ struct adef2_ctx {
   int ub_ntiles = 0, ub_ntiles_pad = 0;    // tile-major boundary-form kernels (UB_ROWS-row tiles)
   RedGeom g_ub{};
   RedGeom g_bt{};
-  struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[10]; };
+  // fused operator pass of the factored form (k_opfused), 0 = two passes
+  int opf = 0;
+  int of_rows = 0, of_halo = 0, of_ntiles = 0, of_ntiles_pad = 0;
+  RedGeom g_of{};
+  // opo: the op_fused option the entry was tuned under; opf: rows of the
+  // fused operator pass (0 = two passes); ms_op: trial times of the two
+  // passes and of the fused pass at each candidate tile height, with the
+  // chosen rpt / wfree
+  struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[10]; int opo, opf; float ms_op[4]; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
   int gram_blocks = 0;
@@ -434,9 +442,44 @@ void launch_coarse(adef2_ctx* c) {
 // -------------------------------------------------------- buffer management
 // Tile geometry of the streaming kernels for rpt rows per thread (the
 // reduction scratch is sized for rpt = 1, the largest tile count).
-void set_variant(adef2_ctx* c, int rpt, int wfree) {
+// Tile heights of the fused operator pass: 2, 4 and 8 times the reach Ho of
+// the outer stencil, rounded up to 256 rows (the LDS halo adds Ho / R on
+// each side of inner-stencil work), kept while the tile and its halo fit
+// 64 KiB of LDS.  None for an assembled operator; none for a 3D grid, whose
+// reach is a whole plane.  The default (op_fused = 1 with nothing tuned) is
+// the middle candidate that applies.
+int opf_halo(const adef2_ctx* c) {
+  int ho = 0;
+  for (int o : c->offs) ho = std::max(ho, std::abs(o));
+  return ho;
+}
+
+std::vector<int> opf_candidates(const adef2_ctx* c) {
+  std::vector<int> r;
+  if (!c->factored || c->D1 == 0) return r;
+  const int64_t ho = opf_halo(c);
+  for (int64_t f : {2, 4, 8}) {
+    const int64_t R = std::max<int64_t>(256, cdiv(f * ho, (int64_t)256) * 256);
+    if ((R + 2 * ho) * 8 <= 64 * 1024 && (r.empty() || r.back() != R)) r.push_back((int)R);
+  }
+  return r;
+}
+
+int opf_default_rows(const adef2_ctx* c) {
+  const std::vector<int> r = opf_candidates(c);
+  return r.empty() ? 0 : r[r.size() / 2];
+}
+
+// opf: rows of the fused operator pass's tiles (0 = two passes)
+void set_variant(adef2_ctx* c, int rpt, int wfree, int opf = 0) {
   c->rpt = rpt;
   c->wfree = wfree;
+  c->of_rows = opf;
+  c->opf = c->of_rows > 0;
+  c->of_halo = c->opf ? opf_halo(c) : 0;
+  c->of_ntiles = c->opf ? (int)cdiv(c->N, (int64_t)c->of_rows) : 0;
+  c->of_ntiles_pad = (int)cdiv(c->of_ntiles, 8) * 8;
+  c->g_of = make_geom(std::max(c->of_ntiles_pad, 8));
   c->ntiles = (int)cdiv(c->N, (int64_t)IPB * rpt);
   c->ntiles_pad = (int)cdiv(c->ntiles, 8) * 8;
   c->g_iter = make_geom(c->ntiles_pad);
@@ -688,6 +731,11 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.bidx = c->bidx;
   a.ftot = c->ftot;
   a.fctr = c->fctr;
+  a.of_rows = c->of_rows;
+  a.of_halo = c->of_halo;
+  a.of_ntiles = c->of_ntiles;
+  a.of_ntiles_pad = c->of_ntiles_pad;
+  a.gof = c->g_of;
   if constexpr (sizeof(M) == 8) {
     a.ZT = nullptr;
     a.bW = nullptr;
@@ -727,7 +775,7 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
 // algorithmic bytes per launch (per instance: inactive rows only); wv / wm =
 // bytes per vector entry / per operator or panel entry
 struct ByteModel { double init, init2, pupdate, stencil, spmv, update, resid, accum, update_nw, zproj, update_tm,
-                   finish_tm; };
+                   finish_tm, opfused; };
 // Algorithmic bytes per launch.  Per-instance data (vectors, W, the mask) is
 // counted for every instance still iterating at the last poll (a finished
 // instance's blocks exit at their first instruction); operands shared by
@@ -759,6 +807,9 @@ ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active
   const double inner = c->factored ? (Nall * 2 * wv + N1 * D1 * wm) : 0.0;   // t = A v
   b.stencil = inner;
   b.spmv = outer;
+  // fused pass: p on all rows (the inner stencil's source), the mask, w on
+  // the inactive rows, both stencils' coefficients once; t stays in LDS
+  b.opfused = Nall * wv + nI * wv + Nall + N1 * D1 * wm + U * D * wm;
   b.update = nI * (k * wm + 8 * wv) + zsh + Nall;              // W, Z; x p r w dinv -> x r z
   b.update_nw = nI * 8 * wv + Nall;                            // x p r w dinv -> x r z
   // x p r w -> x r z; the Jacobi scaling from the shared diagonal (N rows once);
@@ -845,6 +896,11 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   // tile-major stencil passes: coefficients of a row held in registers
   const bool stm = tm && c->wfree == 4 && c->D <= SDR && (!c->factored || c->D1 <= SDR);
   const dim3 gst((unsigned)(c->ub_ntiles_pad * cdiv(c->B, SG_G)));
+  // fused operator pass: one block per (fused tile, instance), A p in LDS
+  const dim3 gof((unsigned)(c->of_ntiles_pad * c->B));
+  const size_t of_lds = (size_t)(c->of_rows + 2 * c->of_halo) * sizeof(double);
+  // five-point stencils (2D grids) with the diagonal count known at compile time
+  auto opk = (c->D == 5 && c->D1 == 5) ? k_opfused<V, M, 5> : k_opfused<V, M, 0>;
   IterArgs<V, M> a = iter_args<V, M>(c);
   a.src = src;
   a.x0 = x0pad;
@@ -891,14 +947,17 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
       }
       if (!tm && !bt)
         timed(c, KI_PUPDATE, bm.pupdate, [&] { hipLaunchKernelGGL(kt.pupdate, grid, blk, 0, s, a); });
-      if (c->factored)
+      if (c->opf)
+        timed(c, KI_OPFUSED, bm.opfused,
+              [&] { hipLaunchKernelGGL(opk, gof, blk, of_lds, s, a); });
+      if (c->factored && !c->opf)
         timed(c, KI_STENCIL, bm.stencil, [&] {
           if constexpr (sizeof(V) == 8)
             if (stm) hipLaunchKernelGGL(btt.stencil1_tm, gst, dim3(UB_THREADS), 0, s, a);
           if (!stm)
             hipLaunchKernelGGL(st1, grid, blk, 0, s, og, a.dia1, (const V*)a.p, a.t, c->vs, c->inst, 1);
         });
-      timed(c, KI_SPMV, bm.spmv, [&] {
+      if (!c->opf) timed(c, KI_SPMV, bm.spmv, [&] {
         if constexpr (sizeof(V) == 8) {
           if (stm) {
             hipLaunchKernelGGL(btt.spmv_tm, gst, dim3(UB_THREADS), 0, s, a);
@@ -937,7 +996,8 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   };
   hipGraphExec_t gexec = nullptr;
   if (c->o.graph && !c->o.profile) {
-    int rc = chunk_graph<V, M>(c, a, chunk, (int)tm * 8 + (int)bt * 4 + (int)wfree * 2 + (c->ne > 0 ? 1 : 0),
+    int rc = chunk_graph<V, M>(c, a, chunk,
+                               (int)c->opf * 16 + (int)tm * 8 + (int)bt * 4 + (int)wfree * 2 + (c->ne > 0 ? 1 : 0),
                                launch_chunk, &gexec);
     if (rc) return rc;
   }
@@ -1050,7 +1110,7 @@ int reset_solve_state(adef2_ctx* c) {
 // same start and the fastest is kept for this context, so repeated solves of
 // one configuration use the same kernels (and give identical results).
 int choose_variant(adef2_ctx* c, const double* b) {
-  const int fr = c->o.rows_per_thread, fw = c->o.w_mode;
+  const int fr = c->o.rows_per_thread, fw = c->o.w_mode, fo = c->o.op_fused;
   if (fw >= 2 && !vec64(c->prec))
     return fail(c, ADEF2_E_UNSUPPORTED, "W-free iterations need FP64 vectors (FP64 or MIXED_REFINE)");
   std::vector<int> rpts = (fr == 1 || fr == 2) ? std::vector<int>{fr} : std::vector<int>{1, 2};
@@ -1062,6 +1122,12 @@ int choose_variant(adef2_ctx* c, const double* b) {
                 "the tile-major boundary-form update needs FP32 panels with FP64 vectors (MIXED_REFINE), "
                 "reference modes shared by all instances that are eigenvectors of the reference operator, "
                 "and w_boundary enabled");
+  const std::vector<int> ofc = opf_candidates(c);
+  const bool opf_ok = !ofc.empty();
+  if (fo == 1 && !opf_ok)
+    return fail(c, ADEF2_E_UNSUPPORTED,
+                "the fused operator pass needs the factored operator with a stencil reach whose tile and "
+                "halo fit 64 KiB of LDS (2D grids up to about 2000 points wide)");
   std::vector<int> wfs = (fw == 1 || c->KP == 0 || !vec64(c->prec)) ? std::vector<int>{0}
                          : (fw == 2 ? std::vector<int>{1}
                          : (fw == 3 ? std::vector<int>{2}
@@ -1071,13 +1137,17 @@ int choose_variant(adef2_ctx* c, const double* b) {
     wfs.push_back(3);
     if (stm_ok) wfs.push_back(4);
   }
-  if (rpts.size() * wfs.size() == 1) { set_variant(c, rpts[0], wfs[0]); return ADEF2_OK; }
+  // operator form: fused (1) or two passes (0); tuned only when it applies
+  // and the option leaves it open
+  const bool tune_op = fo == 0 && opf_ok;
+  const int op0 = fo == 1 ? opf_default_rows(c) : 0;
+  if (rpts.size() * wfs.size() == 1 && !tune_op) { set_variant(c, rpts[0], wfs[0], op0); return ADEF2_OK; }
   const int fact = c->factored ? 1 : 0;
   const int tmk = c->tm_ok ? 1 : 0;
   for (const auto& t : c->tuned)
     if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.tm == tmk &&
-        t.N == c->N) {
-      set_variant(c, t.rpt, t.wfree);
+        t.N == c->N && t.opo == fo) {
+      set_variant(c, t.rpt, t.wfree, t.opf);
       return ADEF2_OK;
     }
   const int prof = c->o.profile;
@@ -1085,42 +1155,62 @@ int choose_variant(adef2_ctx* c, const double* b) {
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, tmk, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, tmk, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+                        fo, op0, {0, 0, 0, 0}};
+  // one trial: the solve's first two chunks of iterations from the same start
+  auto trial = [&](int rpt, int wf, int opf, float* ms) -> int {
+    set_variant(c, rpt, wf, opf);
+    int rc = reset_solve_state(c);
+    if (rc) return rc;
+    if (c->prec != ADEF2_FP64) {
+      fill<double>(c, c->x64, (size_t)c->B * c->vs, 0.0);
+      if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, true))) return rc;
+    }
+    HIPCHK(c, hipEventRecord(e0, c->st));
+    if (c->prec == ADEF2_FP64)
+      rc = run_sweep<double, double>(c, b, nullptr, 1.0, 1, 0.0, 0, 2);
+    else if (mat64(c->prec))
+      rc = run_sweep<double, double>(c, c->r64, nullptr, 0.0, 0, 0.25, 0, 2);
+    else if (vec64(c->prec))
+      rc = run_sweep<double, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol, 0, 0.25, 0, 2);
+    else
+      rc = run_sweep<float, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol, 0, 0.25, 0, 2);
+    if (rc) return rc;
+    HIPCHK(c, hipEventRecord(e1, c->st));
+    HIPCHK(c, hipEventSynchronize(e1));
+    HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
+    return ADEF2_OK;
+  };
   float best_ms = INFINITY;
   int rc = ADEF2_OK, ci = 0;
+  // stage 1: tile height and W mode, with the operator form the option fixes
+  // (two passes while the form is tuned)
   for (int rpt : rpts) {
     for (int wf : wfs) {
-      set_variant(c, rpt, wf);
-      if ((rc = reset_solve_state(c))) break;
-      if (c->prec != ADEF2_FP64) {
-        fill<double>(c, c->x64, (size_t)c->B * c->vs, 0.0);
-        if ((rc = resid64(c, b, interior(c, c->x64), 1, 1, true))) break;
-      }
-      HIPCHK(c, hipEventRecord(e0, c->st));
-      if (c->prec == ADEF2_FP64)
-        rc = run_sweep<double, double>(c, b, nullptr, 1.0, 1, 0.0, 0, 2);
-      else if (mat64(c->prec))
-        rc = run_sweep<double, double>(c, c->r64, nullptr, 0.0, 0, 0.25, 0, 2);
-      else if (vec64(c->prec))
-        rc = run_sweep<double, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol, 0, 0.25, 0, 2);
-      else
-        rc = run_sweep<float, float>(c, c->r64, nullptr, c->o.inner_rtol * c->o.inner_rtol, 0, 0.25, 0, 2);
-      if (rc) break;
-      HIPCHK(c, hipEventRecord(e1, c->st));
-      HIPCHK(c, hipEventSynchronize(e1));
       float ms = 0.0f;
-      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      if ((rc = trial(rpt, wf, op0, &ms))) break;
       best.ms[ci++] = ms;
       if (ms < best_ms) { best_ms = ms; best.rpt = rpt; best.wfree = wf; }
     }
     if (rc) break;
+  }
+  // stage 2: the fused operator pass at each candidate tile height, with
+  // the winner of stage 1
+  if (!rc && tune_op) {
+    best.ms_op[0] = best_ms;
+    for (size_t q = 0; q < ofc.size() && !rc; ++q) {
+      float ms = 0.0f;
+      rc = trial(best.rpt, best.wfree, ofc[q], &ms);
+      best.ms_op[1 + q] = ms;
+      if (!rc && ms < best_ms) { best_ms = ms; best.opf = ofc[q]; }
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->o.profile = prof;
   if (rc) return rc;
   c->tuned.push_back(best);
-  set_variant(c, best.rpt, best.wfree);
+  set_variant(c, best.rpt, best.wfree, best.opf);
   return ADEF2_OK;
 }
 
@@ -1225,7 +1315,8 @@ bool valid_opts(const adef2_opts* o) {
          o->w_mode >= 0 && o->w_mode <= 5 && o->w_boundary >= 0 && o->w_boundary <= 2 &&
          (o->graph == 0 || o->graph == 1) && o->ritz_keep >= 0 && o->ritz_keep <= ADEF2_MAX_K &&
          o->tau_safe >= 1.0 && o->tau_dep >= 0.0 && o->tau_dep < 1.0 && o->poll_max >= 1 &&
-         (o->learned_objective == 0 || o->learned_objective == 1);
+         (o->learned_objective == 0 || o->learned_objective == 1) &&
+         (o->op_fused >= -1 && o->op_fused <= 1);
 }
 
 }  // namespace
@@ -1347,6 +1438,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->tau_dep = 1e-10;
   o->poll_max = 16;
   o->learned_objective = 0;
+  o->op_fused = 0;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
@@ -2010,6 +2102,22 @@ int adef2_variant(adef2_ctx* c, int32_t* rows_per_thread, int32_t* w_mode, float
     for (const auto& t : c->tuned)
       if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N)
         for (int i = 0; i < 10; ++i) ms[i] = t.ms[i];
+  }
+  return ADEF2_OK;
+}
+
+int adef2_operator_variant(adef2_ctx* c, int32_t* fused, int32_t* tile_rows, float* ms) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->solved) return fail(c, ADEF2_E_STATE, "operator_variant before the first solve");
+  if (fused) *fused = c->opf;
+  if (tile_rows) *tile_rows = c->of_rows;
+  if (ms) {
+    for (int q = 0; q < 4; ++q) ms[q] = 0.0f;
+    const int fact = c->factored ? 1 : 0;
+    for (const auto& t : c->tuned)
+      if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N &&
+          t.opo == c->o.op_fused)
+        for (int q = 0; q < 4; ++q) ms[q] = t.ms_op[q];
   }
   return ADEF2_OK;
 }

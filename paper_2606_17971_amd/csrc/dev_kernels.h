@@ -131,6 +131,11 @@ struct IterArgs {
   const M* bW;
   double* ftot;            // [B][slices][2 KP + 2] slice totals of the tile-major finisher
   unsigned* fctr;          // [B] arrival counters of the tile-major finisher
+  // fused operator pass of the factored form (k_opfused): of_rows-row tiles,
+  // inner product A p staged in LDS over of_halo extra rows on each side
+  int32_t of_rows, of_halo;
+  int32_t of_ntiles, of_ntiles_pad;
+  RedGeom gof;             // reduction tree over the fused tiles
 };
 
 template <int RPT> struct Rows { static constexpr int PB = IPB * RPT; };

@@ -113,6 +113,172 @@ __global__ void __launch_bounds__(IPB) k_stencil1(OpGeom op, const VM* dia1, con
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused operator pass of the factored form: w = a A^T (A p) + c p on the
+// inactive rows of one tile, p.w, and alpha = rho / p.w.  One block per
+// (tile, instance), tile = of_rows consecutive rows [i0, i0 + R).  The inner
+// product t = A p is formed for rows [i0 - Ho, i0 + R + Ho) (Ho = the reach of
+// the outer stencil A^T) into LDS and never written to HBM; rows outside
+// [0, N) hold 0, as the zero halo of the padded t does.  The arithmetic of
+// each row (difference form for FP32 coefficients, t rounded to the vector
+// type) is that of k_stencil1 followed by k_spmv; only the p.w reduction tree
+// differs (one leaf per fused tile).  The rows of the halo are recomputed by
+// the neighbouring tiles' blocks (2 Ho / R more inner stencil work, from L2).
+// Dynamic LDS: (R + 2 Ho) doubles.
+// ---------------------------------------------------------------------------
+// One row of a stencil from its coefficients cw[] and source values vw[]
+// (DC diagonals, already loaded): the arithmetic and order of stencil_row
+// (difference form with FP32 coefficients when the stencil has an offset-0
+// slot d0).
+template <typename M, int DC>
+__device__ __forceinline__ double stencil_combine(const double (&cw)[DC], const double (&vw)[DC], int d0) {
+  double acc = 0.0;
+  if constexpr (sizeof(M) == 4) {
+    if (d0 >= 0) {
+      double vi = 0.0, dg = 0.0;
+#pragma unroll
+      for (int d = 0; d < DC; ++d)
+        if (d == d0) { vi = vw[d]; dg = cw[d]; }
+      acc = dg * vi;
+#pragma unroll
+      for (int d = 0; d < DC; ++d)
+        if (d != d0) acc += cw[d] * (vw[d] - vi);
+      return acc;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < DC; ++d) acc += cw[d] * vw[d];
+  return acc;
+}
+
+// DC: diagonals of both stencils known at compile time (0 = any: one row at
+// a time through stencil_row).  With DC > 0 each thread loads the
+// coefficients and sources of OU rows before it combines any of them, so
+// their loads are in flight together (row indices are clamped into range so
+// that no load is conditional; rows out of range are discarded).
+template <typename V, typename M, int DC>
+__global__ void __launch_bounds__(IPB) k_opfused(IterArgs<V, M> a) {
+  constexpr int OU = DC > 0 ? 4 : 1;
+  constexpr int DX = DC > 0 ? DC : 1;
+  extern __shared__ double ts[];
+  __shared__ double red[NIWAVE];
+  __shared__ double bv[1];
+  __shared__ double tot[1];
+  int tile, m;
+  tile_inst(a.of_ntiles_pad, tile, m);
+  Inst* S = a.inst + m;
+  if (S->done) return;
+  const int64_t N = a.op.N;
+  const int R = a.of_rows, Ho = a.of_halo;
+  const int64_t i0 = (int64_t)tile * R;
+  const V* p = a.p + m * a.vs;
+  const uint8_t* mk = a.mask + (size_t)m * N;
+  V* w = a.w + m * a.vs;
+  const double sa = S->a, sc = S->c;
+  double v[1] = {0.0};
+  const bool live = tile < a.of_ntiles;
+  if (live) {
+    const int L = R + 2 * Ho;
+    for (int e0 = threadIdx.x; e0 < L; e0 += OU * IPB) {
+      double tv[OU];
+      if constexpr (DC > 0) {
+        double cw[OU][DX], vw[OU][DX];
+#pragma unroll
+        for (int u = 0; u < OU; ++u) {
+          const int64_t j = i0 - Ho + e0 + u * IPB;
+          const int64_t jc = j < 0 ? 0 : (j >= N ? N - 1 : j);
+#pragma unroll
+          for (int d = 0; d < DC; ++d) {
+            cw[u][d] = (double)a.dia1[(size_t)d * N + jc];
+            vw[u][d] = (double)p[jc + a.op.offs1[d]];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < OU; ++u) {
+          const int64_t j = i0 - Ho + e0 + u * IPB;
+          tv[u] = (j < 0 || j >= N) ? 0.0 : (double)(V)stencil_combine<M, DX>(cw[u], vw[u], a.op.d01);
+        }
+      } else {
+        const int64_t j = i0 - Ho + e0;
+        tv[0] = (j >= 0 && j < N) ? (double)(V)stencil_row(a.dia1, a.op.offs1, a.op.D1, a.op.d01, N, j, p) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < OU; ++u)
+        if (e0 + u * IPB < L) ts[e0 + u * IPB] = tv[u];
+    }
+  }
+  __syncthreads();
+  if (live) {
+    for (int e0 = threadIdx.x; e0 < R; e0 += OU * IPB) {
+      double wv[OU], pv[OU];
+      bool ok[OU];
+      if constexpr (DC > 0) {
+        double cw[OU][DX], vw[OU][DX];
+        uint8_t mv[OU];
+        int ec[OU];
+#pragma unroll
+        for (int u = 0; u < OU; ++u) {
+          const int e = e0 + u * IPB;
+          const int64_t i = i0 + (e < R ? e : R - 1);
+          const int64_t ic = i < N ? i : N - 1;      // i0 <= ic < min(i0 + R, N)
+          ec[u] = (int)(ic - i0) + Ho;
+          mv[u] = mk[ic];
+          pv[u] = (double)p[ic];
+#pragma unroll
+          for (int d = 0; d < DC; ++d) cw[u][d] = (double)a.dia[(size_t)d * N + ic];
+          ok[u] = (e < R) & (i < N);
+        }
+#pragma unroll
+        for (int u = 0; u < OU; ++u) {
+#pragma unroll
+          for (int d = 0; d < DC; ++d) vw[u][d] = ts[ec[u] + a.op.offs[d]];
+          ok[u] = ok[u] & (mv[u] == 0);
+          wv[u] = sa * stencil_combine<M, DX>(cw[u], vw[u], a.op.d0) + sc * pv[u];
+        }
+      } else {
+        const int64_t i = i0 + e0;
+        ok[0] = i < N && mk[i] == 0;
+        pv[0] = wv[0] = 0.0;
+        if (ok[0]) {
+          double acc = 0.0;
+          const int d0 = a.op.d0, li = e0 + Ho;
+          if (sizeof(M) == 4 && d0 >= 0) {
+            const double ti = ts[li];
+            acc = (double)a.dia[(size_t)d0 * N + i] * ti;
+            for (int d = 0; d < a.op.D; ++d)
+              if (d != d0) acc += (double)a.dia[(size_t)d * N + i] * (ts[li + a.op.offs[d]] - ti);
+          } else {
+            for (int d = 0; d < a.op.D; ++d) acc += (double)a.dia[(size_t)d * N + i] * ts[li + a.op.offs[d]];
+          }
+          pv[0] = (double)p[i];
+          wv[0] = sa * acc + sc * pv[0];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < OU; ++u) {
+        if (!ok[u]) continue;
+        w[i0 + e0 + u * IPB] = (V)wv[u];
+        v[0] += pv[u] * (double)(V)wv[u];
+      }
+    }
+  }
+  block_sum<1, NIWAVE>(v, red, bv);
+  double* part = a.part + (size_t)m * a.gof.ptotal;
+  unsigned* ctr = a.ctr + (size_t)m * a.gof.ctotal;
+  if (!tree_reduce(a.gof, tile, 1, part, ctr, bv, tot)) return;
+  if (threadIdx.x == 0) {
+    const double pw = tot[0];
+    S->pw = pw;
+    if (!(pw > 0.0) || !(pw < INFINITY)) {
+      S->done = 1;
+      S->outer_done = 1;
+      S->status = -5;
+    } else {
+      S->alpha = S->rho / pw;
+    }
+  }
+}
+
 // x64 += d (FP32 correction of the last sweep)
 template <typename V, int RPT>
 __global__ void __launch_bounds__(IPB) k_accumulate(OpGeom op, const uint8_t* mask, const V* d,

@@ -543,3 +543,85 @@ def test_adaptive_polling_matches_every_chunk_polling(lib, prec):
     np.testing.assert_array_equal(out[0]["status"], out[1]["status"])
     np.testing.assert_array_equal(out[0]["x"].cpu().numpy(), out[1]["x"].cpu().numpy())
     assert polls[1] < polls[0]
+
+
+# ---------------------------------------------------------------------------
+# fused operator pass of the factored form (t = A p kept in LDS)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,w_mode", [("fp64", 1), ("mixed", 1), ("mixed", 4), ("fp32", 1)])
+@pytest.mark.parametrize("B", [3, 11])
+def test_fused_operator_matches_oracle(lib, prec, w_mode, B):
+    """op_fused = 1: one kernel forms A p over a tile and its stencil reach in
+    LDS and applies A^T there.  n = 95 takes 512-row tiles (4 times the
+    95-row reach, rounded up; 18 per instance, the last one 321 rows)."""
+    w = gen.c2_workload(n=95, k=16, B=B)
+    S = spec(w.op, "factored")
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    p = {"fp64": lib.FP64, "mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE}[prec]
+    case(f"fused operator {prec} w_mode={w_mode} factored cd2d n=95 k=16 B={B}")
+    s = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=1, w_mode=w_mode, op_fused=1)
+    out = s.solve_batched(masks, bs, 1e-10)
+    fused, rows, _ = s.op_variant()
+    assert fused == 1 and rows == 512
+    X = out["x"].cpu().numpy()
+    for m, inst in enumerate(w.instances):
+        ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
+        I, xs = _xstar(S, inst.mask, inst.b)
+        e = oracle.rel_err(X[m, I], xs)
+        if prec == "fp32":
+            assert out["status"][m] in (0, 3), (m, out["status"][m])
+            assert e <= 1e-6, (m, e)
+            continue
+        assert out["status"][m] == 0
+        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), (m, e)
+        if prec == "fp64":
+            assert abs(int(out["iters"][m]) - ref.iters) <= 2, (m, out["iters"][m], ref.iters)
+        else:
+            assert out["relres_true"][m] <= 1e-10
+            assert int(out["iters"][m]) <= 1.2 * ref.iters + 20, (m, out["iters"][m], ref.iters)
+    assert np.all(X[masks == 1] == 0.0)
+
+
+def test_fused_operator_large_tiles(lib):
+    """255^2 x 16 (mixed, tile-major update): 1024-row fused tiles with a
+    255-row halo on each side, 64 tiles per instance, the last one ragged
+    (513 rows).  Sampled instances against x*, every instance against the
+    two-pass operator's iteration count and solution."""
+    w = gen.c2_workload(n=255, k=32, B=16)
+    S = spec(w.op, "factored")
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case("fused operator vs two passes, mixed w_mode=4 factored cd2d n=255 k=32 B=16")
+    outs = {}
+    for fo in (1, -1):
+        s = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE, rows_per_thread=1, w_mode=4,
+                   op_fused=fo)
+        outs[fo] = s.solve_batched(masks, bs, 1e-10)
+        f, rows, _ = s.op_variant()
+        assert f == (1 if fo == 1 else 0)
+        if fo == 1:
+            assert rows == 1024
+        s.close()
+    Xf, Xt = outs[1]["x"].cpu().numpy(), outs[-1]["x"].cpu().numpy()
+    assert np.all(outs[1]["status"] == 0) and np.all(outs[1]["relres_true"] <= 1e-10)
+    for m in range(16):
+        it_f, it_t = int(outs[1]["iters"][m]), int(outs[-1]["iters"][m])
+        assert abs(it_f - it_t) <= 0.05 * it_t + 20, (m, it_f, it_t)
+        assert oracle.rel_err(Xf[m], Xt[m]) <= 1e-8, m
+    for m in (0, 7, 15):
+        inst = w.instances[m]
+        I, xs = _xstar(S, inst.mask, inst.b)
+        assert oracle.rel_err(Xf[m, I], xs) <= 1e-8, m
+    assert np.all(Xf[masks == 1] == 0.0)
+
+
+def test_fused_operator_refused_for_assembled(lib):
+    w = gen.c2_workload(n=63, k=8, B=2)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case("fused operator refused for the assembled form")
+    s = solver(lib, w.op, w.Z, "assembled", precision=lib.FP64, op_fused=1)
+    with pytest.raises(lib.Adef2Error) as e:
+        s.solve_batched(masks, bs, 1e-10)
+    assert e.value.code == lib.E_UNSUPPORTED
