@@ -846,7 +846,7 @@ int poll(adef2_ctx* c, bool outer, bool* all_done) {
 // chunks of iterations until every instance's sweep is done
 // Instantiated graph of one chunk of iterations for these kernel arguments:
 // captured on the private stream the first time, then reused while the
-// arguments (buffers, geometry, variant) are unchanged.  A handful of
+// arguments (buffers, geometry, variant) are unchanged.  Up to 24
 // configurations are kept per context.
 template <typename V, typename M, typename F>
 int chunk_graph(adef2_ctx* c, const IterArgs<V, M>& a, int chunk, int variant, F&& launch_chunk,
@@ -871,7 +871,7 @@ int chunk_graph(adef2_ctx* c, const IterArgs<V, M>& a, int chunk, int variant, F
   const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   hipGraphDestroy(graph);
   if (ie != hipSuccess) return fail(c, ADEF2_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
-  if (c->graphs.size() >= 8) {
+  if (c->graphs.size() >= 24) {
     hipGraphExecDestroy(c->graphs.front().exec);
     c->graphs.erase(c->graphs.begin());
   }
@@ -996,8 +996,12 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   };
   hipGraphExec_t gexec = nullptr;
   if (c->o.graph && !c->o.profile) {
+    // the key names every choice that changes the launches: the W mode code
+    // itself (w_mode 4 and 5 differ only in the stencil kernels), the
+    // operator form and the boundary form
     int rc = chunk_graph<V, M>(c, a, chunk,
-                               (int)c->opf * 16 + (int)tm * 8 + (int)bt * 4 + (int)wfree * 2 + (c->ne > 0 ? 1 : 0),
+                               ((int)c->opf << 8) | (c->wfree << 4) | ((int)tm << 3) | ((int)bt << 2) |
+                                   ((int)wfree << 1) | (c->ne > 0 ? 1 : 0),
                                launch_chunk, &gexec);
     if (rc) return rc;
   }

@@ -11,10 +11,14 @@
 //
 //   k_pupdate_tm: p_j = z_j - Z c_j + beta_j p_j for PB_G = 16 instances.
 //     For each 16-row slice, D[j][row] = sum_q c_j[q] Z[row][q] is one 16 x 16
-//     output tile (A = the coarse coordinates, B = 16 rows of Z).
+//     output tile (A = the coarse coordinates, B = 16 rows of Z); the masks
+//     of a wave's four slices are loaded first, and two slices are in
+//     flight at a time.
 //   k_update_tm: x_j += alpha_j p_j, r_j -= alpha_j w_j, z_j = K r_j for
 //     UB_G = 8 instances, then [Z^T z_j | Z^T r_j] for all of them as
-//     Z_tile^T [z_1 r_1 ... z_8 r_8] (KQ x 16 outputs), and W^T z from the
+//     Z_tile^T [z_1 r_1 ... z_8 r_8] (KQ x 16 outputs), r_j.z_j and r_j.r_j
+//     from the Gram of the same 16 columns (one more matrix-core product per
+//     k step instead of wave-wide shuffle reductions), and W^T z from the
 //     boundary form of W = S_II Z_I: every reference mode q is an eigenvector
 //     of the reference operator B (S = a B + c I, B z_q = mu_q z_q), so
 //     W = Lambda Z_I + (W - Lambda Z_I) with Lambda_q = a mu_q + c, and the
@@ -57,6 +61,7 @@ __device__ __forceinline__ void tile_group(int ntiles_pad, int ngroups, int& til
 template <typename M, int KP>
 __global__ void __launch_bounds__(UB_THREADS) k_pupdate_tm(IterArgs<double, M> a) {
   constexpr int KS = KP / 4;
+  constexpr int KS1 = KS > 0 ? KS : 1;
   constexpr int K1 = KP > 0 ? KP : 1;
   __shared__ double cf[PB_G][K1 + 1];
   __shared__ double s_beta[PB_G];
@@ -91,67 +96,85 @@ __global__ void __launch_bounds__(UB_THREADS) k_pupdate_tm(IterArgs<double, M> a
     }
     cf[j][q] = v;
   }
+  // masks of the wave's four 16-row slices: they do not depend on the
+  // instance state, so they are loaded (unconditionally, indices clamped)
+  // before the barrier and kept only for iterating instances after it
+  uint8_t mk[4][4];
+#pragma unroll
+  for (int s0 = 0; s0 < 4; ++s0) {
+    const int64_t i = base + 64 * wid + 16 * s0 + cn;
+    const int64_t ic = i < N ? i : N - 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = 4 * e + kk;
+      mk[s0][e] = a.mask[(size_t)(g0 + (j < G ? j : 0)) * N + ic];
+    }
+  }
   __syncthreads();
   bool any = false;
   for (int j = 0; j < PB_G; ++j) any |= s_k[j] != 0;
   if (!any) return;
-  // A operand: the coarse coordinates, A[j = cn][k = kk]; B operand: rows
-  // of Z, B[k = kk][row = cn] = Z[row][4 s + kk]
-  double av[KS > 0 ? KS : 1];
 #pragma unroll
-  for (int s = 0; s < KS; ++s) av[s] = cf[cn][4 * s + kk];
-  // one 16-row slice at a time (low register use: 4 waves per SIMD)
-#pragma unroll 1
   for (int s0 = 0; s0 < 4; ++s0) {
-    constexpr int SPP = 1;
-    uint8_t mk[SPP][4];
-    double bv[SPP][KS > 0 ? KS : 1], zv[SPP][4], pv[SPP][4];
+    const int64_t i = base + 64 * wid + 16 * s0 + cn;
 #pragma unroll
-    for (int u = 0; u < SPP; ++u) {
-      const int64_t i = base + 64 * wid + 16 * (s0 + u) + cn;
-#pragma unroll
-      for (int s = 0; s < KS; ++s) bv[u][s] = i < N ? (double)a.Z[(size_t)(4 * s + kk) * N + i] : 0.0;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int j = 4 * e + kk;
-        mk[u][e] = (j < G && i < N && s_k[j]) ? a.mask[(size_t)(g0 + j) * N + i] : (uint8_t)1;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < SPP; ++u) {
-      const int64_t i = base + 64 * wid + 16 * (s0 + u) + cn;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int j = 4 * e + kk;
-        zv[u][e] = 0.0;
-        pv[u][e] = 0.0;
-        if (!mk[u][e]) {
-          const int64_t o = (int64_t)(g0 + j) * a.vs + i;
-          zv[u][e] = a.z[o];
-          if (s_keep[j]) pv[u][e] = a.p[o];
-        }
-      }
-    }
-    tm_d4 d[SPP];
-#pragma unroll
-    for (int u = 0; u < SPP; ++u) {
-      d[u] = tm_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < KS; ++s) d[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[u][s], d[u], 0, 0, 0);
-    }
-#pragma unroll
-    for (int u = 0; u < SPP; ++u) {
-      const int64_t i = base + 64 * wid + 16 * (s0 + u) + cn;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (mk[u][e]) continue;
-        const int j = 4 * e + kk;
-        double pn = zv[u][e] - d[u][e];
-        if (s_keep[j]) pn += s_beta[j] * pv[u][e];
-        a.p[(int64_t)(g0 + j) * a.vs + i] = pn;
-      }
+    for (int e = 0; e < 4; ++e) {
+      const int j = 4 * e + kk;
+      if (!(j < G && i < N && s_k[j])) mk[s0][e] = 1;
     }
   }
+  // A operand: the coarse coordinates, A[j = cn][k = kk]; B operand: rows
+  // of Z, B[k = kk][row = cn] = Z[row][4 s + kk]
+  double av[KS1];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) av[s] = cf[cn][4 * s + kk];
+  // loads of one 16-row slice: the rows of Z first, then the vectors (a
+  // wave's loads complete in order, so the products wait for Z only)
+  auto load_slice = [&](int s0, M (&bv)[KS1], double (&zv)[4], double (&pv)[4]) {
+    const int64_t i = base + 64 * wid + 16 * s0 + cn;
+    const int64_t ic = i < N ? i : N - 1;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) bv[s] = a.Z[(size_t)(4 * s + kk) * N + ic];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = 4 * e + kk;
+      zv[e] = 0.0;
+      pv[e] = 0.0;
+      if (!mk[s0][e]) {
+        const int64_t o = (int64_t)(g0 + j) * a.vs + i;
+        zv[e] = a.z[o];
+        if (s_keep[j]) pv[e] = a.p[o];
+      }
+    }
+  };
+  // D[j][row] = sum_q c_j[q] Z[row][q] on the matrix cores, then the stores
+  auto finish_slice = [&](int s0, const M (&bv)[KS1], const double (&zv)[4], const double (&pv)[4]) {
+    const int64_t i = base + 64 * wid + 16 * s0 + cn;
+    tm_d4 d = tm_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], i < N ? (double)bv[s] : 0.0, d, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (mk[s0][e]) continue;
+      const int j = 4 * e + kk;
+      double pn = zv[e] - d[e];
+      if (s_keep[j]) pn += s_beta[j] * pv[e];
+      a.p[(int64_t)(g0 + j) * a.vs + i] = pn;
+    }
+  };
+  // two slices in flight: the next slice's loads are issued before this
+  // slice's products and stores
+  M bv0[KS1], bv1[KS1];
+  double zv0[4], pv0[4], zv1[4], pv1[4];
+  load_slice(0, bv0, zv0, pv0);
+  load_slice(1, bv1, zv1, pv1);
+  finish_slice(0, bv0, zv0, pv0);
+  load_slice(2, bv0, zv0, pv0);
+  finish_slice(1, bv1, zv1, pv1);
+  load_slice(3, bv1, zv1, pv1);
+  finish_slice(2, bv0, zv0, pv0);
+  finish_slice(3, bv1, zv1, pv1);
 }
 
 // ---------------------------------------------------------------------------
@@ -172,14 +195,14 @@ k_update_tm(IterArgs<double, M> a) {
   constexpr int NC = 2 * UB_G;                     // z_j, r_j columns
   constexpr int NWV = UB_THREADS / 64;
   constexpr int ZR = UB_ROWS * NC;                 // [row][NC] tile of z and r
-  constexpr int PW = NWV * (NQT > 0 ? NQT : 1) * 256;   // wave partials of the products
+  constexpr int NQG = (NQT > 0 ? NQT : 1) + 1;     // product tiles + the Gram of [z r]
+  constexpr int PW = NWV * NQG * 256;              // wave partials of the products
   constexpr int SH = ZR > PW ? ZR : PW;
   constexpr int LPE = KP <= 32 ? 2 : 1;            // boundary entries per wave step
   constexpr int BU = 4;                            // boundary steps loaded ahead
   constexpr int KB = KQ > 0 ? KQ : 1;
   __shared__ double sh[SH];
   __shared__ double bsum[UB_G][KB];
-  __shared__ double red[NWV][NC];
   __shared__ double s_alpha[UB_G], s_a[UB_G], s_c[UB_G];
   __shared__ int s_k[UB_G];
   int tile, grp;
@@ -277,12 +300,6 @@ k_update_tm(IterArgs<double, M> a) {
       a.r[o] = rq;
       a.z[o] = zq;
     }
-    const double s1 = wave_sum(rq * zq);
-    const double s2 = wave_sum(rq * rq);
-    if (lane == 0) {
-      red[wid][2 * j] = s1;
-      red[wid][2 * j + 1] = s2;
-    }
     sh[t * NC + 2 * j] = zq;
     sh[t * NC + 2 * j + 1] = rq;
   }
@@ -290,10 +307,13 @@ k_update_tm(IterArgs<double, M> a) {
 
   // [Z^T z_j | Z^T r_j] on the matrix cores: wave w sums rows 64 w .. 64 w + 63;
   // in k step s lane group kk takes row 64 w + 4 s + kk, so A (row-major Z)
-  // reads 4 rows x 16 consecutive columns per instruction
-  tm_d4 acc[NQT > 0 ? NQT : 1];
+  // reads 4 rows x 16 consecutive columns per instruction.  The same B
+  // operand as A gives the Gram [z r]^T [z r] of the wave's rows (acc[NQG - 1]),
+  // whose entries (2j, 2j + 1) and (2j + 1, 2j + 1) are r_j.z_j and r_j.r_j:
+  // one matrix-core product instead of 16 wave-wide shuffle reductions
+  tm_d4 acc[NQG];
 #pragma unroll
-  for (int qt = 0; qt < (NQT > 0 ? NQT : 1); ++qt) acc[qt] = tm_d4{0.0, 0.0, 0.0, 0.0};
+  for (int qt = 0; qt < NQG; ++qt) acc[qt] = tm_d4{0.0, 0.0, 0.0, 0.0};
   if constexpr (KP > 0) {
     const int cn = lane & 15, kk = lane >> 4;
     M zraw[16][NQT];
@@ -312,6 +332,14 @@ k_update_tm(IterArgs<double, M> a) {
 #pragma unroll
       for (int qt = 0; qt < NQT; ++qt)
         acc[qt] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)zraw[s][qt], bval, acc[qt], 0, 0, 0);
+      acc[NQG - 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bval, bval, acc[NQG - 1], 0, 0, 0);
+    }
+  } else {
+    const int cn = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const double bval = sh[(64 * wid + 4 * s + kk) * NC + cn];
+      acc[NQG - 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bval, bval, acc[NQG - 1], 0, 0, 0);
     }
   }
   // boundary rows: (W - Lambda Z)^T z_j over the tile's listed rows, lanes
@@ -335,15 +363,14 @@ k_update_tm(IterArgs<double, M> a) {
     if (bsub == 0 && bq < KB) bsum[j][bq] = ab;
   }
   __syncthreads();                                  // sh no longer holds [z r]
-  if constexpr (KP > 0) {
 #pragma unroll
-    for (int qt = 0; qt < NQT; ++qt)
+  for (int qt = 0; qt < NQG; ++qt)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) sh[((wid * NQT + qt) * 4 + e) * 64 + lane] = acc[qt][e];
-  }
+    for (int e = 0; e < 4; ++e) sh[((wid * NQG + qt) * 4 + e) * 64 + lane] = acc[qt][e];
   __syncthreads();
   // block sums per instance: D[q][c] sits in wave partial (qt = q / 16,
-  // e = (q % 16) / 4) at lane 16 (q % 4) + c; stored for the finisher
+  // e = (q % 16) / 4) at lane 16 (q % 4) + c (the Gram in partial NQG - 1);
+  // stored for the finisher
   for (int o = t; o < UB_G * NV; o += UB_THREADS) {
     const int j = o / NV, v = o - j * NV;
     if (!((act >> j) & 1u)) continue;
@@ -354,11 +381,13 @@ k_update_tm(IterArgs<double, M> a) {
       const int c = 2 * j + (zpart ? 0 : 1);
       const int qt = q >> 4, e = (q & 15) >> 2, ln = (q & 3) * 16 + c;
       double dsum = 0.0;
-      for (int w = 0; w < NWV; ++w) dsum += sh[((w * (NQT > 0 ? NQT : 1) + qt) * 4 + e) * 64 + ln];
+      for (int w = 0; w < NWV; ++w) dsum += sh[((w * NQG + qt) * 4 + e) * 64 + ln];
       val = zpart ? (s_a[j] * a.mu[q] + s_c[j]) * dsum + bsum[j][q] : dsum;
     } else {
-      const int which = v - 2 * KP;
-      for (int w = 0; w < NWV; ++w) val += red[w][2 * j + which];
+      // r_j.z_j = G[2j][2j + 1], r_j.r_j = G[2j + 1][2j + 1]
+      const int gr = v == 2 * KP ? 2 * j : 2 * j + 1, gc = 2 * j + 1;
+      const int e = (gr & 15) >> 2, ln = (gr & 3) * 16 + gc;
+      for (int w = 0; w < NWV; ++w) val += sh[((w * NQG + NQG - 1) * 4 + e) * 64 + ln];
     }
     a.part[((size_t)(g0 + j) * a.ub_ntiles_pad + tile) * NV + v] = val;
   }

@@ -476,6 +476,27 @@ def test_autotuned_variant_is_reused(lib):
     np.testing.assert_array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
 
 
+def test_graphs_keyed_by_variant(lib):
+    """A context that switches w_mode (4 -> 5: the same update kernels, other
+    stencil kernels) or the operator form replays graphs of the new variant:
+    its solves equal those of a fresh context with that variant, bitwise."""
+    w = gen.c2_workload(n=95, k=16, B=2)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case("graph cache keyed by w_mode and operator form")
+    s = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE, rows_per_thread=1, w_mode=4,
+               op_fused=-1)
+    s.solve_batched(masks, bs, 1e-10)
+    for opts in (dict(w_mode=5, op_fused=-1), dict(w_mode=5, op_fused=1), dict(w_mode=4, op_fused=1)):
+        s.set_opts(**opts)
+        got = s.solve_batched(masks, bs, 1e-10)
+        f = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE, rows_per_thread=1, **opts)
+        ref = f.solve_batched(masks, bs, 1e-10)
+        f.close()
+        np.testing.assert_array_equal(got["iters"], ref["iters"])
+        np.testing.assert_array_equal(got["x"].cpu().numpy(), ref["x"].cpu().numpy())
+
+
 @pytest.mark.parametrize("form", ["assembled", "factored"])
 @pytest.mark.parametrize("w_boundary", [0, 1])
 def test_boundary_form_of_w(lib, form, w_boundary):
