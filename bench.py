@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--w-mode", type=int, default=0, choices=[0, 1, 2, 3, 4, 5],
                     help="1 = read W, 2 = W-free tile-major, 3 = W-free per instance, "
                          "4 = tile-major boundary form, 5 = 4 with tile-major stencils, 0 = tuned")
+    ap.add_argument("--op-fused", type=int, default=0, choices=[-1, 0, 1],
+                    help="operator pass of the factored form: 1 = fused (A p kept in LDS), "
+                         "-1 = two passes, 0 = tuned")
     ap.add_argument("--w-boundary", type=int, default=2, choices=[0, 1, 2],
                     help="boundary form of W for eigen reference modes: 0 off, 1 on, "
                          "2 when every reference mode is an eigenvector")
@@ -486,7 +489,8 @@ def main():
     bs = torch.as_tensor(np.stack([i.b for i in w.instances]), device="cuda")
     B = args.batch
     prec = {"mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE, "fp64": lib.FP64}[args.precision]
-    tune = dict(rows_per_thread=args.rpt, w_mode=args.w_mode, w_boundary=args.w_boundary)
+    tune = dict(rows_per_thread=args.rpt, w_mode=args.w_mode, w_boundary=args.w_boundary,
+                op_fused=args.op_fused)
     head = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
     head.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     thetas = torch.as_tensor(np.stack([i.theta for i in w.instances]).astype(np.float32), device="cuda")
@@ -510,7 +514,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"counter_run": True, "iters": np.asarray(out["iters"]).tolist(),
-                          "variant": list(head.variant()[:2]), "copy_bytes_each_way": src.numel() * 8}))
+                          "variant": list(head.variant()[:2]), "op_variant": list(head.op_variant()[:2]),
+                          "copy_bytes_each_way": src.numel() * 8}))
         return
 
     for _ in range(args.warmup):
@@ -526,6 +531,7 @@ def main():
     polls = head.polls() / args.steps
     head_iters = np.asarray(out["iters"])
     v_rpt, v_wm, v_ms = head.variant()
+    o_f, o_rows, o_ms = head.op_variant()
     head_rel = np.asarray(out["relres_true"])
     X_head = out["x"].clone()
     value = B / t_head
@@ -601,7 +607,8 @@ def main():
     if not args.no_profile:
         # one instrumented headline step: HIP events on the solver stream around every launch
         prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1,
-                          rows_per_thread=v_rpt, w_mode=v_wm, w_boundary=args.w_boundary)
+                          rows_per_thread=v_rpt, w_mode=v_wm, w_boundary=args.w_boundary,
+                          op_fused=1 if o_f else -1)
         prof.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
         if apply_learned:
             prof.set_pod_modes(Phi)
@@ -620,6 +627,8 @@ def main():
                   lib.FP64: ("double", "double")}[prec]
         if dom in ("update_tm", "pupdate_tm"):
             inst = f"k_{dom}<{mt}, {kp}>"
+        elif dom == "opfused":
+            inst = f"k_opfused<{vt}, {mt}, 5>"
         elif dom == "update":
             inst = f"k_{dom}<{vt}, {mt}, {kp}, {v_rpt}, {'true' if args.w_boundary else 'false'}>"
         else:
@@ -660,7 +669,9 @@ def main():
                   "max": int(head_iters.max())},
         "polls_per_step": polls,
         "variant": {"rows_per_thread": v_rpt, "w_mode": v_wm, "tuned": args.rpt == 0 or args.w_mode == 0,
-                    "trial_ms": [round(float(tt), 3) for tt in v_ms]},
+                    "trial_ms": [round(float(tt), 3) for tt in v_ms],
+                    "op_fused": int(o_f), "op_tile_rows": int(o_rows),
+                    "op_trial_ms": [round(float(tt), 3) for tt in o_ms]},
         "cond_E": {"min": float(np.min(out["cond_E"])), "max": float(np.max(out["cond_E"]))},
         "iters_per_instance": head_iters.tolist(),
         "relres_true_max": float(head_rel.max()),

@@ -129,12 +129,19 @@ __global__ void __launch_bounds__(UB_THREADS) k_pupdate_tm(IterArgs<double, M> a
 #pragma unroll
   for (int s = 0; s < KS; ++s) av[s] = cf[cn][4 * s + kk];
   // loads of one 16-row slice: the rows of Z first, then the vectors (a
-  // wave's loads complete in order, so the products wait for Z only)
+  // wave's loads complete in order, so the products wait for Z only).  With
+  // FP32 panels Z is read from its row-major copy: the KP values of a row are
+  // one contiguous run that this slice's loads consume whole (in the
+  // column-major layout each load takes half of a 128-byte line per column
+  // and the other half is left to another slice)
   auto load_slice = [&](int s0, M (&bv)[KS1], double (&zv)[4], double (&pv)[4]) {
     const int64_t i = base + 64 * wid + 16 * s0 + cn;
     const int64_t ic = i < N ? i : N - 1;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) bv[s] = a.Z[(size_t)(4 * s + kk) * N + ic];
+    for (int s = 0; s < KS; ++s) {
+      if constexpr (sizeof(M) == 4) bv[s] = a.ZT[(size_t)ic * KP + 4 * s + kk];
+      else bv[s] = a.Z[(size_t)(4 * s + kk) * N + ic];
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int j = 4 * e + kk;
