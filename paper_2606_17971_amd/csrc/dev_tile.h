@@ -17,8 +17,7 @@
 //   k_update_tm: x_j += alpha_j p_j, r_j -= alpha_j w_j, z_j = K r_j for
 //     UB_G = 8 instances, then [Z^T z_j | Z^T r_j] for all of them as
 //     Z_tile^T [z_1 r_1 ... z_8 r_8] (KQ x 16 outputs), r_j.z_j and r_j.r_j
-//     from the Gram of the same 16 columns (one more matrix-core product per
-//     k step instead of wave-wide shuffle reductions), and W^T z from the
+//     from the same staged tile (32 threads per instance), and W^T z from the
 //     boundary form of W = S_II Z_I: every reference mode q is an eigenvector
 //     of the reference operator B (S = a B + c I, B z_q = mu_q z_q), so
 //     W = Lambda Z_I + (W - Lambda Z_I) with Lambda_q = a mu_q + c, and the
@@ -41,6 +40,7 @@ constexpr int UB_ROWS = 256;      // rows per tile
 constexpr int UB_THREADS = 256;   // one row per thread, 4 waves
 constexpr int UB_G = 8;           // instances per update block: 2 UB_G = 16 matrix-core columns
 constexpr int PB_G = 16;          // instances per p-update block: 16 matrix-core rows
+static_assert(UB_THREADS == 32 * UB_G, "the update's dot products take 32 threads per instance");
 
 typedef double tm_d4 __attribute__((ext_vector_type(4)));
 
@@ -202,7 +202,7 @@ k_update_tm(IterArgs<double, M> a) {
   constexpr int NC = 2 * UB_G;                     // z_j, r_j columns
   constexpr int NWV = UB_THREADS / 64;
   constexpr int ZR = UB_ROWS * NC;                 // [row][NC] tile of z and r
-  constexpr int NQG = (NQT > 0 ? NQT : 1) + 1;     // product tiles + the Gram of [z r]
+  constexpr int NQG = NQT > 0 ? NQT : 1;           // product tiles
   constexpr int PW = NWV * NQG * 256;              // wave partials of the products
   constexpr int SH = ZR > PW ? ZR : PW;
   constexpr int LPE = KP <= 32 ? 2 : 1;            // boundary entries per wave step
@@ -210,6 +210,7 @@ k_update_tm(IterArgs<double, M> a) {
   constexpr int KB = KQ > 0 ? KQ : 1;
   __shared__ double sh[SH];
   __shared__ double bsum[UB_G][KB];
+  __shared__ double dots[UB_G][2];                 // r_j.z_j, r_j.r_j of the tile
   __shared__ double s_alpha[UB_G], s_a[UB_G], s_c[UB_G];
   __shared__ int s_k[UB_G];
   int tile, grp;
@@ -314,10 +315,7 @@ k_update_tm(IterArgs<double, M> a) {
 
   // [Z^T z_j | Z^T r_j] on the matrix cores: wave w sums rows 64 w .. 64 w + 63;
   // in k step s lane group kk takes row 64 w + 4 s + kk, so A (row-major Z)
-  // reads 4 rows x 16 consecutive columns per instruction.  The same B
-  // operand as A gives the Gram [z r]^T [z r] of the wave's rows (acc[NQG - 1]),
-  // whose entries (2j, 2j + 1) and (2j + 1, 2j + 1) are r_j.z_j and r_j.r_j:
-  // one matrix-core product instead of 16 wave-wide shuffle reductions
+  // reads 4 rows x 16 consecutive columns per instruction
   tm_d4 acc[NQG];
 #pragma unroll
   for (int qt = 0; qt < NQG; ++qt) acc[qt] = tm_d4{0.0, 0.0, 0.0, 0.0};
@@ -339,14 +337,30 @@ k_update_tm(IterArgs<double, M> a) {
 #pragma unroll
       for (int qt = 0; qt < NQT; ++qt)
         acc[qt] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)zraw[s][qt], bval, acc[qt], 0, 0, 0);
-      acc[NQG - 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bval, bval, acc[NQG - 1], 0, 0, 0);
     }
-  } else {
-    const int cn = lane & 15, kk = lane >> 4;
+  }
+  // r_j.z_j and r_j.r_j from the staged tile: thread t sums 8 rows of
+  // instance j = t / 32, then 5 shuffle steps within its 32 lanes (instead of
+  // 16 wave-wide reductions, or a Gram on the matrix cores, whose FP64 rate
+  // is the vector rate on this chip)
+  {
+    const int j = t >> 5, l = t & 31;
+    double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const double bval = sh[(64 * wid + 4 * s + kk) * NC + cn];
-      acc[NQG - 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bval, bval, acc[NQG - 1], 0, 0, 0);
+    for (int u = 0; u < UB_ROWS / 32; ++u) {
+      const int rw = l + 32 * u;
+      const double zz = sh[rw * NC + 2 * j], rr = sh[rw * NC + 2 * j + 1];
+      s1 += rr * zz;
+      s2 += rr * rr;
+    }
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+      s1 += __shfl_xor(s1, off, 64);
+      s2 += __shfl_xor(s2, off, 64);
+    }
+    if (l == 0) {
+      dots[j][0] = s1;
+      dots[j][1] = s2;
     }
   }
   // boundary rows: (W - Lambda Z)^T z_j over the tile's listed rows, lanes
@@ -376,8 +390,7 @@ k_update_tm(IterArgs<double, M> a) {
     for (int e = 0; e < 4; ++e) sh[((wid * NQG + qt) * 4 + e) * 64 + lane] = acc[qt][e];
   __syncthreads();
   // block sums per instance: D[q][c] sits in wave partial (qt = q / 16,
-  // e = (q % 16) / 4) at lane 16 (q % 4) + c (the Gram in partial NQG - 1);
-  // stored for the finisher
+  // e = (q % 16) / 4) at lane 16 (q % 4) + c; stored for the finisher
   for (int o = t; o < UB_G * NV; o += UB_THREADS) {
     const int j = o / NV, v = o - j * NV;
     if (!((act >> j) & 1u)) continue;
@@ -391,10 +404,7 @@ k_update_tm(IterArgs<double, M> a) {
       for (int w = 0; w < NWV; ++w) dsum += sh[((w * NQG + qt) * 4 + e) * 64 + ln];
       val = zpart ? (s_a[j] * a.mu[q] + s_c[j]) * dsum + bsum[j][q] : dsum;
     } else {
-      // r_j.z_j = G[2j][2j + 1], r_j.r_j = G[2j + 1][2j + 1]
-      const int gr = v == 2 * KP ? 2 * j : 2 * j + 1, gc = 2 * j + 1;
-      const int e = (gr & 15) >> 2, ln = (gr & 3) * 16 + gc;
-      for (int w = 0; w < NWV; ++w) val += sh[((w * NQG + NQG - 1) * 4 + e) * 64 + ln];
+      val = dots[j][v - 2 * KP];
     }
     a.part[((size_t)(g0 + j) * a.ub_ntiles_pad + tile) * NV + v] = val;
   }
