@@ -531,9 +531,9 @@ def test_graph_replays_match_eager(lib, prec):
     bs = np.stack([i.b for i in w.instances])
     p = lib.FP64 if prec == "fp64" else lib.MIXED_REFINE
     case(f"graph replays vs eager {prec} cd2d n=95 B=4")
-    eager = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=2, w_mode=1, graph=0)
+    eager = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=2, w_mode=1, op_fused=1, graph=0)
     ref = eager.solve_batched(masks, bs, 1e-10)
-    g = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=2, w_mode=1, graph=1)
+    g = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=2, w_mode=1, op_fused=1, graph=1)
     for rep in range(3):
         out = g.solve_batched(masks, bs, 1e-10)
         np.testing.assert_array_equal(out["iters"], ref["iters"])
@@ -553,7 +553,8 @@ def test_adaptive_polling_matches_every_chunk_polling(lib, prec):
     case(f"adaptive polling {prec} cd2d n=95 B=4")
     out, polls = [], []
     for pm in (1, 16):
-        s = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=2, w_mode=1, poll_max=pm)
+        s = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=2, w_mode=1, op_fused=1,
+                   poll_max=pm)
         s.solve_batched(masks, bs, 1e-10)          # first solve: variant and graphs
         s.reset_stats()
         out.append(s.solve_batched(masks, bs, 1e-10))

@@ -86,7 +86,7 @@ def test_pod_enrich_zero_restores_reference_modes(lib, podcase):
     case("pod_enrich(0) after an enrichment gives the plain reference-mode results")
     outs = []
     for enrich in (False, True):
-        s = lib.Solver(precision=lib.FP64, rows_per_thread=1, w_mode=1)
+        s = lib.Solver(precision=lib.FP64, rows_per_thread=1, w_mode=1, op_fused=-1)
         s.set_reference_factored(w.op.A, w.op.alpha, w.op.shift, Z)
         if enrich:
             s.set_pod_modes(Phi)

@@ -68,7 +68,7 @@ def test_ritz_keep_at_pool_size_is_default_path(lib, ritz_case):
     case("ritz_keep >= pool reproduces the default path bitwise")
     outs = []
     for keep in (0, POOL):
-        s = lib.Solver(precision=lib.FP64, ritz_keep=keep, rows_per_thread=1, w_mode=1)
+        s = lib.Solver(precision=lib.FP64, ritz_keep=keep, rows_per_thread=1, w_mode=1, op_fused=-1)
         s.set_reference_factored(w.op.A, w.op.alpha, w.op.shift, Z)
         outs.append(s.solve_batched(masks, bs, TOL))
         s.close()
