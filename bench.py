@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--op-fused", type=int, default=0, choices=[-1, 0, 1],
                     help="operator pass of the factored form: 1 = fused (A p kept in LDS), "
                          "-1 = two passes, 0 = tuned")
+    ap.add_argument("--op-rows", type=int, default=0, help="tile height of the fused pass (0 = tuned)")
+    ap.add_argument("--op-group", type=int, default=0, choices=[0, 1, 4],
+                    help="instances per block of the fused pass (0 = tuned)")
     ap.add_argument("--w-boundary", type=int, default=2, choices=[0, 1, 2],
                     help="boundary form of W for eigen reference modes: 0 off, 1 on, "
                          "2 when every reference mode is an eigenvector")
@@ -490,7 +493,7 @@ def main():
     B = args.batch
     prec = {"mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE, "fp64": lib.FP64}[args.precision]
     tune = dict(rows_per_thread=args.rpt, w_mode=args.w_mode, w_boundary=args.w_boundary,
-                op_fused=args.op_fused)
+                op_fused=args.op_fused, op_rows=args.op_rows, op_group=args.op_group)
     head = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
     head.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     thetas = torch.as_tensor(np.stack([i.theta for i in w.instances]).astype(np.float32), device="cuda")
@@ -514,7 +517,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"counter_run": True, "iters": np.asarray(out["iters"]).tolist(),
-                          "variant": list(head.variant()[:2]), "op_variant": list(head.op_variant()[:2]),
+                          "variant": list(head.variant()[:2]), "op_variant": [head.op_variant()[q] for q in (0, 1, 3)],
                           "copy_bytes_each_way": src.numel() * 8}))
         return
 
@@ -531,7 +534,7 @@ def main():
     polls = head.polls() / args.steps
     head_iters = np.asarray(out["iters"])
     v_rpt, v_wm, v_ms = head.variant()
-    o_f, o_rows, o_ms = head.op_variant()
+    o_f, o_rows, o_ms, o_grp = head.op_variant()
     head_rel = np.asarray(out["relres_true"])
     X_head = out["x"].clone()
     value = B / t_head
@@ -608,7 +611,7 @@ def main():
         # one instrumented headline step: HIP events on the solver stream around every launch
         prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1,
                           rows_per_thread=v_rpt, w_mode=v_wm, w_boundary=args.w_boundary,
-                          op_fused=1 if o_f else -1)
+                          op_fused=1 if o_f else -1, op_rows=o_rows, op_group=o_grp)
         prof.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
         if apply_learned:
             prof.set_pod_modes(Phi)
@@ -670,7 +673,7 @@ def main():
         "polls_per_step": polls,
         "variant": {"rows_per_thread": v_rpt, "w_mode": v_wm, "tuned": args.rpt == 0 or args.w_mode == 0,
                     "trial_ms": [round(float(tt), 3) for tt in v_ms],
-                    "op_fused": int(o_f), "op_tile_rows": int(o_rows),
+                    "op_fused": int(o_f), "op_tile_rows": int(o_rows), "op_group": int(o_grp),
                     "op_trial_ms": [round(float(tt), 3) for tt in o_ms]},
         "cond_E": {"min": float(np.min(out["cond_E"])), "max": float(np.max(out["cond_E"]))},
         "iters_per_instance": head_iters.tolist(),

@@ -231,8 +231,12 @@ typedef struct {
                            of each configuration, after the tile height and
                            w_mode, whenever the fused pass applies, at
                            tile heights of 2, 4 and 8 times the stencil
-                           reach (the fastest is kept; 1 takes 4 times, or
-                           the nearest that fits).  It applies to the
+                           reach, with one instance per block or (five-
+                           point stencils, four LDS copies within 64 KiB)
+                           four instances sharing each row's coefficients
+                           (the fastest is kept; 1 takes 4 times the reach,
+                           or the nearest that fits, one instance per
+                           block).  It applies to the
                            factored form when a tile of twice the stencil
                            reach plus that reach on both sides fits 64 KiB
                            of LDS (2D grids up to about 2000 points wide;
@@ -240,6 +244,16 @@ typedef struct {
                            is E_UNSUPPORTED otherwise.  Same arithmetic per
                            row as the two passes; only the summation tree
                            of p.S p differs                                 */
+  int32_t op_rows;      /* tile height of the fused operator pass in rows (a
+                           multiple of 256): 0 = the candidates above (tuned)
+                           or 4 times the reach (op_fused = 1); a tile and
+                           its halo that do not fit give E_UNSUPPORTED; 0   */
+  int32_t op_group;     /* instances per block of the fused pass: 1, or 4
+                           (five-point stencils: the coefficients of a row
+                           are loaded once for four instances, each with its
+                           own LDS copy of A p, so four copies must fit 64
+                           KiB); 0 = tuned (op_fused = 0) or 1 (op_fused =
+                           1); 0                                            */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;
@@ -520,13 +534,15 @@ int adef2_active_set_batched(adef2_ctx *ctx, int32_t B, const double *y_d, const
 int adef2_variant(adef2_ctx *ctx, int32_t *rows_per_thread, int32_t *w_mode, float *ms);
 
 /* Operator form used by the last solve on ctx (see opts.op_fused): fused
- * (1) or two passes (0), the fused pass's tile height in rows (0 when not
- * fused), and in ms (host f32[4], may be NULL) the tuning trial times with
- * the chosen rows per thread and w_mode: ms[0] two passes, ms[1..3] the
- * fused pass at tile heights of 2, 4 and 8 times the stencil reach (rounded
- * up to 256 rows; 0 where a height does not fit or nothing was tuned).
- * E_STATE before the first solve. */
-int adef2_operator_variant(adef2_ctx *ctx, int32_t *fused, int32_t *tile_rows, float *ms);
+ * (1) or two passes (0), the fused pass's tile height in rows and its
+ * instances per block (1, or 4 when the coefficients of a row are shared by
+ * a group of instances; both 0 when not fused), and in ms (host f32[7], may
+ * be NULL) the tuning trial times with the chosen rows per thread and
+ * w_mode: ms[0] two passes, ms[1..3] the fused pass at tile heights of 2, 4
+ * and 8 times the stencil reach (rounded up to 256 rows), ms[4..6] the same
+ * with 4 instances per block (0 where a height does not fit or nothing was
+ * tuned).  E_STATE before the first solve. */
+int adef2_operator_variant(adef2_ctx *ctx, int32_t *fused, int32_t *tile_rows, int32_t *group, float *ms);
 
 #define ADEF2_STATS_KERNELS 24
 typedef struct {

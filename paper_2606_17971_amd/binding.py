@@ -53,6 +53,8 @@ class Opts(ctypes.Structure):
         ("poll_max", ctypes.c_int32),
         ("learned_objective", ctypes.c_int32),
         ("op_fused", ctypes.c_int32),
+        ("op_rows", ctypes.c_int32),
+        ("op_group", ctypes.c_int32),
     ]
 
 
@@ -97,7 +99,7 @@ _sig = {
     "adef2_apply_restricted": (ctypes.c_int, [_P, _P, _P]),
     "adef2_coarse_info": (ctypes.c_int, [_P, _P, _P, _Pi32, _Pf64]),
     "adef2_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _P]),
-    "adef2_operator_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _P]),
+    "adef2_operator_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _Pi32, _P]),
     "adef2_active_set_batched": (ctypes.c_int, [_P, _i32, _P, _P, _f64, _f64, _i32, _P, _P, _P, _P, _P]),
     "adef2_pod_enrich": (ctypes.c_int, [_P, _i32, _f64]),
     "adef2_set_enrichment": (ctypes.c_int, [_P, _i32, _P, _P, _i32, _f64]),
@@ -434,12 +436,13 @@ class Solver:
 
     def op_variant(self):
         """(fused, tile rows, trial ms [two passes, fused at 2 / 4 / 8 x the
-        stencil reach]) of the last solve."""
-        f, rows = _i32(0), _i32(0)
-        ms = np.zeros(4, np.float32)
+        stencil reach with one instance per block, the same with four],
+        instances per block) of the last solve."""
+        f, rows, grp = _i32(0), _i32(0), _i32(0)
+        ms = np.zeros(7, np.float32)
         self._check(_lib.adef2_operator_variant(self._ctx, ctypes.byref(f), ctypes.byref(rows),
-                                                ms.ctypes.data), allow=(OK,))
-        return f.value, rows.value, ms
+                                                ctypes.byref(grp), ms.ctypes.data), allow=(OK,))
+        return f.value, rows.value, ms, grp.value
 
     def coarse_info(self):
         k = max(self.k, 1)

@@ -202,13 +202,15 @@ struct adef2_ctx {
   RedGeom g_bt{};
   // fused operator pass of the factored form (k_opfused), 0 = two passes
   int opf = 0;
+  int opg = 1;                   // instances per block of the fused pass (1, or 4: k_opfused_g)
   int of_rows = 0, of_halo = 0, of_ntiles = 0, of_ntiles_pad = 0;
   RedGeom g_of{};
   // opo: the op_fused option the entry was tuned under; opf: rows of the
-  // fused operator pass (0 = two passes); ms_op: trial times of the two
-  // passes and of the fused pass at each candidate tile height, with the
-  // chosen rpt / wfree
-  struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[10]; int opo, opf; float ms_op[4]; };
+  // fused operator pass (0 = two passes), opg its instances per block;
+  // ms_op: trial times of the two passes and of the fused pass at each
+  // candidate tile height, one instance per block [1..3] and four [4..6],
+  // with the chosen rpt / wfree
+  struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[10]; int opo, opf, opg; float ms_op[7]; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
   int gram_blocks = 0;
@@ -470,12 +472,14 @@ int opf_default_rows(const adef2_ctx* c) {
   return r.empty() ? 0 : r[r.size() / 2];
 }
 
-// opf: rows of the fused operator pass's tiles (0 = two passes)
-void set_variant(adef2_ctx* c, int rpt, int wfree, int opf = 0) {
+// opf: rows of the fused operator pass's tiles (0 = two passes); opg: its
+// instances per block
+void set_variant(adef2_ctx* c, int rpt, int wfree, int opf = 0, int opg = 1) {
   c->rpt = rpt;
   c->wfree = wfree;
   c->of_rows = opf;
   c->opf = c->of_rows > 0;
+  c->opg = c->opf ? opg : 1;
   c->of_halo = c->opf ? opf_halo(c) : 0;
   c->of_ntiles = c->opf ? (int)cdiv(c->N, (int64_t)c->of_rows) : 0;
   c->of_ntiles_pad = (int)cdiv(c->of_ntiles, 8) * 8;
@@ -735,6 +739,7 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.of_halo = c->of_halo;
   a.of_ntiles = c->of_ntiles;
   a.of_ntiles_pad = c->of_ntiles_pad;
+  a.of_ngroups = (int)cdiv(c->B, c->opg);
   a.gof = c->g_of;
   if constexpr (sizeof(M) == 8) {
     a.ZT = nullptr;
@@ -896,11 +901,16 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   // tile-major stencil passes: coefficients of a row held in registers
   const bool stm = tm && c->wfree == 4 && c->D <= SDR && (!c->factored || c->D1 <= SDR);
   const dim3 gst((unsigned)(c->ub_ntiles_pad * cdiv(c->B, SG_G)));
-  // fused operator pass: one block per (fused tile, instance), A p in LDS
-  const dim3 gof((unsigned)(c->of_ntiles_pad * c->B));
-  const size_t of_lds = (size_t)(c->of_rows + 2 * c->of_halo) * sizeof(double);
+  // fused operator pass: one block per (fused tile, instance), or per
+  // (fused tile, group of 4 instances), A p in LDS
+  const dim3 gof((unsigned)(c->of_ntiles_pad * cdiv(c->B, c->opg)));
+  const size_t of_lds = (size_t)c->opg * (c->of_rows + 2 * c->of_halo) * sizeof(double);
   // five-point stencils (2D grids) with the diagonal count known at compile time
-  auto opk = (c->D == 5 && c->D1 == 5) ? k_opfused<V, M, 5> : k_opfused<V, M, 0>;
+  auto opk = (c->D == 5 && c->D1 == 5) ? (c->opg == 4 ? k_opfused_g<V, M, 5, 4> : k_opfused<V, M, 5>)
+                                       : k_opfused<V, M, 0>;
+  // four LDS copies of up to 64 KiB together, plus the kernel's static LDS:
+  // above the default per-launch bound
+  if (c->opf) HIPCHK(c, hipFuncSetAttribute((const void*)opk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)of_lds));
   IterArgs<V, M> a = iter_args<V, M>(c);
   a.src = src;
   a.x0 = x0pad;
@@ -1000,7 +1010,7 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
     // itself (w_mode 4 and 5 differ only in the stencil kernels), the
     // operator form and the boundary form
     int rc = chunk_graph<V, M>(c, a, chunk,
-                               ((int)c->opf << 8) | (c->wfree << 4) | ((int)tm << 3) | ((int)bt << 2) |
+                               (c->opg << 9) | ((int)c->opf << 8) | (c->wfree << 4) | ((int)tm << 3) | ((int)bt << 2) |
                                    ((int)wfree << 1) | (c->ne > 0 ? 1 : 0),
                                launch_chunk, &gexec);
     if (rc) return rc;
@@ -1126,12 +1136,33 @@ int choose_variant(adef2_ctx* c, const double* b) {
                 "the tile-major boundary-form update needs FP32 panels with FP64 vectors (MIXED_REFINE), "
                 "reference modes shared by all instances that are eigenvectors of the reference operator, "
                 "and w_boundary enabled");
-  const std::vector<int> ofc = opf_candidates(c);
-  const bool opf_ok = !ofc.empty();
-  if (fo == 1 && !opf_ok)
+  // fused operator pass: the (tile height, instances per block) candidates
+  // the options allow; slot: where a candidate's trial time is reported
+  const int64_t ho = opf_halo(c);
+  const bool five = c->D == 5 && c->D1 == 5;
+  auto fits = [&](int R, int G) {
+    return c->factored && c->D1 > 0 && R >= 256 && R % 256 == 0 && (G == 1 || (G == 4 && five)) &&
+           (int64_t)G * (R + 2 * ho) * 8 <= 64 * 1024;
+  };
+  struct OpC { int R, G, slot; };
+  std::vector<OpC> opc;
+  {
+    const std::vector<int> Rs = c->o.op_rows > 0 ? std::vector<int>{c->o.op_rows} : opf_candidates(c);
+    const std::vector<int> Gs = c->o.op_group > 0 ? std::vector<int>{c->o.op_group} : std::vector<int>{1, 4};
+    for (size_t q = 0; q < Rs.size(); ++q)
+      for (int G : Gs)
+        if (fits(Rs[q], G) && (G == 1 || c->B > 1))
+          opc.push_back({Rs[q], G, 1 + (G == 4 ? 3 : 0) + (int)std::min<size_t>(q, 2)});
+  }
+  // op_fused = 1: the given tile height and group, else 4 times the reach
+  // (or the nearest candidate that fits) with one instance per block
+  const int R1 = c->o.op_rows > 0 ? c->o.op_rows : opf_default_rows(c);
+  const int G1 = c->o.op_group > 0 ? c->o.op_group : 1;
+  if (fo == 1 && !fits(R1, G1))
     return fail(c, ADEF2_E_UNSUPPORTED,
                 "the fused operator pass needs the factored operator with a stencil reach whose tile and "
-                "halo fit 64 KiB of LDS (2D grids up to about 2000 points wide)");
+                "halo fit 64 KiB of LDS (2D grids up to about 2000 points wide; 4 instances per block: "
+                "five-point stencils and four such copies)");
   std::vector<int> wfs = (fw == 1 || c->KP == 0 || !vec64(c->prec)) ? std::vector<int>{0}
                          : (fw == 2 ? std::vector<int>{1}
                          : (fw == 3 ? std::vector<int>{2}
@@ -1143,15 +1174,19 @@ int choose_variant(adef2_ctx* c, const double* b) {
   }
   // operator form: fused (1) or two passes (0); tuned only when it applies
   // and the option leaves it open
-  const bool tune_op = fo == 0 && opf_ok;
-  const int op0 = fo == 1 ? opf_default_rows(c) : 0;
-  if (rpts.size() * wfs.size() == 1 && !tune_op) { set_variant(c, rpts[0], wfs[0], op0); return ADEF2_OK; }
+  const bool tune_op = fo == 0 && !opc.empty();
+  const int op0 = fo == 1 ? R1 : 0, og0 = fo == 1 ? G1 : 1;
+  if (rpts.size() * wfs.size() == 1 && !tune_op) {
+    set_variant(c, rpts[0], wfs[0], op0, og0);
+    return ADEF2_OK;
+  }
   const int fact = c->factored ? 1 : 0;
   const int tmk = c->tm_ok ? 1 : 0;
+  const int opo = fo + 4 * c->o.op_group + 32 * c->o.op_rows;   // the operator options tuned under
   for (const auto& t : c->tuned)
     if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.tm == tmk &&
-        t.N == c->N && t.opo == fo) {
-      set_variant(c, t.rpt, t.wfree, t.opf);
+        t.N == c->N && t.opo == opo) {
+      set_variant(c, t.rpt, t.wfree, t.opf, t.opg);
       return ADEF2_OK;
     }
   const int prof = c->o.profile;
@@ -1160,10 +1195,10 @@ int choose_variant(adef2_ctx* c, const double* b) {
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, tmk, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
-                        fo, op0, {0, 0, 0, 0}};
+                        opo, op0, og0, {0, 0, 0, 0, 0, 0, 0}};
   // one trial: the solve's first two chunks of iterations from the same start
-  auto trial = [&](int rpt, int wf, int opf, float* ms) -> int {
-    set_variant(c, rpt, wf, opf);
+  auto trial = [&](int rpt, int wf, int opf, int opg, float* ms) -> int {
+    set_variant(c, rpt, wf, opf, opg);
     int rc = reset_solve_state(c);
     if (rc) return rc;
     if (c->prec != ADEF2_FP64) {
@@ -1192,7 +1227,7 @@ int choose_variant(adef2_ctx* c, const double* b) {
   for (int rpt : rpts) {
     for (int wf : wfs) {
       float ms = 0.0f;
-      if ((rc = trial(rpt, wf, op0, &ms))) break;
+      if ((rc = trial(rpt, wf, op0, og0, &ms))) break;
       best.ms[ci++] = ms;
       if (ms < best_ms) { best_ms = ms; best.rpt = rpt; best.wfree = wf; }
     }
@@ -1202,11 +1237,11 @@ int choose_variant(adef2_ctx* c, const double* b) {
   // the winner of stage 1
   if (!rc && tune_op) {
     best.ms_op[0] = best_ms;
-    for (size_t q = 0; q < ofc.size() && !rc; ++q) {
+    for (size_t q = 0; q < opc.size() && !rc; ++q) {
       float ms = 0.0f;
-      rc = trial(best.rpt, best.wfree, ofc[q], &ms);
-      best.ms_op[1 + q] = ms;
-      if (!rc && ms < best_ms) { best_ms = ms; best.opf = ofc[q]; }
+      rc = trial(best.rpt, best.wfree, opc[q].R, opc[q].G, &ms);
+      best.ms_op[opc[q].slot] = ms;
+      if (!rc && ms < best_ms) { best_ms = ms; best.opf = opc[q].R; best.opg = opc[q].G; }
     }
   }
   hipEventDestroy(e0);
@@ -1214,7 +1249,7 @@ int choose_variant(adef2_ctx* c, const double* b) {
   c->o.profile = prof;
   if (rc) return rc;
   c->tuned.push_back(best);
-  set_variant(c, best.rpt, best.wfree, best.opf);
+  set_variant(c, best.rpt, best.wfree, best.opf, best.opg);
   return ADEF2_OK;
 }
 
@@ -1320,7 +1355,8 @@ bool valid_opts(const adef2_opts* o) {
          (o->graph == 0 || o->graph == 1) && o->ritz_keep >= 0 && o->ritz_keep <= ADEF2_MAX_K &&
          o->tau_safe >= 1.0 && o->tau_dep >= 0.0 && o->tau_dep < 1.0 && o->poll_max >= 1 &&
          (o->learned_objective == 0 || o->learned_objective == 1) &&
-         (o->op_fused >= -1 && o->op_fused <= 1);
+         (o->op_fused >= -1 && o->op_fused <= 1) && o->op_rows >= 0 && o->op_rows % 256 == 0 &&
+         o->op_rows <= (1 << 16) && (o->op_group == 0 || o->op_group == 1 || o->op_group == 4);
 }
 
 }  // namespace
@@ -1443,6 +1479,8 @@ void adef2_default_opts(adef2_opts* o) {
   o->poll_max = 16;
   o->learned_objective = 0;
   o->op_fused = 0;
+  o->op_rows = 0;
+  o->op_group = 0;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
@@ -2110,18 +2148,19 @@ int adef2_variant(adef2_ctx* c, int32_t* rows_per_thread, int32_t* w_mode, float
   return ADEF2_OK;
 }
 
-int adef2_operator_variant(adef2_ctx* c, int32_t* fused, int32_t* tile_rows, float* ms) {
+int adef2_operator_variant(adef2_ctx* c, int32_t* fused, int32_t* tile_rows, int32_t* group, float* ms) {
   if (!c) return ADEF2_E_ARG;
   if (!c->solved) return fail(c, ADEF2_E_STATE, "operator_variant before the first solve");
   if (fused) *fused = c->opf;
   if (tile_rows) *tile_rows = c->of_rows;
+  if (group) *group = c->opf ? c->opg : 0;
   if (ms) {
-    for (int q = 0; q < 4; ++q) ms[q] = 0.0f;
+    for (int q = 0; q < 7; ++q) ms[q] = 0.0f;
     const int fact = c->factored ? 1 : 0;
     for (const auto& t : c->tuned)
       if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N &&
-          t.opo == c->o.op_fused)
-        for (int q = 0; q < 4; ++q) ms[q] = t.ms_op[q];
+          t.opo == c->o.op_fused + 4 * c->o.op_group + 32 * c->o.op_rows)
+        for (int q = 0; q < 7; ++q) ms[q] = t.ms_op[q];
   }
   return ADEF2_OK;
 }

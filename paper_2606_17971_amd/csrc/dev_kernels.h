@@ -135,6 +135,7 @@ struct IterArgs {
   // inner product A p staged in LDS over of_halo extra rows on each side
   int32_t of_rows, of_halo;
   int32_t of_ntiles, of_ntiles_pad;
+  int32_t of_ngroups;      // instance groups of the grouped pass (k_opfused_g)
   RedGeom gof;             // reduction tree over the fused tiles
 };
 

@@ -4,7 +4,7 @@
 // restricted matvec test hook and the Jacobi preconditioner.  Used by the
 // host runtime only (one translation unit).
 #pragma once
-#include "dev_kernels.h"
+#include "dev_tile.h"
 
 namespace adef2 {
 
@@ -268,6 +268,142 @@ __global__ void __launch_bounds__(IPB) k_opfused(IterArgs<V, M> a) {
   if (!tree_reduce(a.gof, tile, 1, part, ctr, bv, tot)) return;
   if (threadIdx.x == 0) {
     const double pw = tot[0];
+    S->pw = pw;
+    if (!(pw > 0.0) || !(pw < INFINITY)) {
+      S->done = 1;
+      S->outer_done = 1;
+      S->status = -5;
+    } else {
+      S->alpha = S->rho / pw;
+    }
+  }
+}
+
+// Grouped form of the fused operator pass: one block per tile and group of
+// G instances, so the coefficients of a row (shared by every instance) are
+// loaded once for the group instead of once per instance; each instance has
+// its own LDS copy of t (dynamic LDS: G (R + 2 Ho) doubles).  Same per-row
+// arithmetic as k_opfused; the p.w trees of the group's instances advance
+// together (tree_reduce_multi).  DC > 0 only; OU rows per thread and step.
+template <typename V, typename M, int DC, int G>
+__global__ void __launch_bounds__(IPB) k_opfused_g(IterArgs<V, M> a) {
+  static_assert(DC > 0 && G >= 2 && G <= 8, "grouped fused pass: compile-time stencil, 2..8 instances");
+  constexpr int OU = 2;
+  extern __shared__ double ts[];
+  __shared__ double red[NIWAVE * G];
+  __shared__ double bvv[G];
+  __shared__ double tot[G];
+  int tile, grp;
+  tile_group(a.of_ntiles_pad, a.of_ngroups, tile, grp);
+  const int g0 = grp * G;
+  const int Gn = min(G, a.B - g0);
+  unsigned act = 0u;
+  double sa[G], sc[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    sa[j] = sc[j] = 0.0;
+    if (j < Gn) {
+      const Inst* S = a.inst + g0 + j;
+      if (!S->done) {
+        act |= 1u << j;
+        sa[j] = S->a;
+        sc[j] = S->c;
+      }
+    }
+  }
+  if (!act) return;
+  const int64_t N = a.op.N;
+  const int R = a.of_rows, Ho = a.of_halo;
+  const int L = R + 2 * Ho;
+  const int64_t i0 = (int64_t)tile * R;
+  double v[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) v[j] = 0.0;
+  const bool live = tile < a.of_ntiles;
+  if (live) {
+    for (int e0 = threadIdx.x; e0 < L; e0 += OU * IPB) {
+      double cw[OU][DC];
+      int64_t jc[OU];
+#pragma unroll
+      for (int u = 0; u < OU; ++u) {
+        const int64_t j = i0 - Ho + e0 + u * IPB;
+        jc[u] = j < 0 ? 0 : (j >= N ? N - 1 : j);
+#pragma unroll
+        for (int d = 0; d < DC; ++d) cw[u][d] = (double)a.dia1[(size_t)d * N + jc[u]];
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (!((act >> g) & 1u)) continue;
+        const V* p = a.p + (g0 + g) * a.vs;
+        double vw[OU][DC];
+#pragma unroll
+        for (int u = 0; u < OU; ++u)
+#pragma unroll
+          for (int d = 0; d < DC; ++d) vw[u][d] = (double)p[jc[u] + a.op.offs1[d]];
+#pragma unroll
+        for (int u = 0; u < OU; ++u) {
+          const int e = e0 + u * IPB;
+          const int64_t j = i0 - Ho + e;
+          const double tv = (j < 0 || j >= N) ? 0.0 : (double)(V)stencil_combine<M, DC>(cw[u], vw[u], a.op.d01);
+          if (e < L) ts[g * L + e] = tv;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (live) {
+    for (int e0 = threadIdx.x; e0 < R; e0 += OU * IPB) {
+      double cw[OU][DC];
+      int64_t ic[OU];
+      int ec[OU];
+      bool ok[OU];
+#pragma unroll
+      for (int u = 0; u < OU; ++u) {
+        const int e = e0 + u * IPB;
+        const int64_t i = i0 + (e < R ? e : R - 1);
+        ic[u] = i < N ? i : N - 1;      // i0 <= ic < min(i0 + R, N)
+        ec[u] = (int)(ic[u] - i0) + Ho;
+        ok[u] = (e < R) & (i < N);
+#pragma unroll
+        for (int d = 0; d < DC; ++d) cw[u][d] = (double)a.dia[(size_t)d * N + ic[u]];
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (!((act >> g) & 1u)) continue;
+        const int m = g0 + g;
+        const V* p = a.p + m * a.vs;
+        const uint8_t* mk = a.mask + (size_t)m * N;
+        V* w = a.w + m * a.vs;
+        uint8_t mv[OU];
+        double pv[OU], wv[OU];
+#pragma unroll
+        for (int u = 0; u < OU; ++u) {
+          mv[u] = mk[ic[u]];
+          pv[u] = (double)p[ic[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < OU; ++u) {
+          double vw[DC];
+#pragma unroll
+          for (int d = 0; d < DC; ++d) vw[d] = ts[g * L + ec[u] + a.op.offs[d]];
+          wv[u] = sa[g] * stencil_combine<M, DC>(cw[u], vw, a.op.d0) + sc[g] * pv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < OU; ++u) {
+          if (!(ok[u] && mv[u] == 0)) continue;
+          w[i0 + e0 + u * IPB] = (V)wv[u];
+          v[g] += pv[u] * (double)(V)wv[u];
+        }
+      }
+    }
+  }
+  block_sum<G, NIWAVE>(v, red, bvv);
+  const unsigned fin = tree_reduce_multi(a.gof, tile, 1, act, G, a.part + (size_t)g0 * a.gof.ptotal,
+                                         (size_t)a.gof.ptotal, a.ctr + (size_t)g0 * a.gof.ctotal,
+                                         (size_t)a.gof.ctotal, bvv, tot);
+  if (threadIdx.x < G && ((fin >> threadIdx.x) & 1u)) {
+    Inst* S = a.inst + g0 + threadIdx.x;
+    const double pw = tot[threadIdx.x];
     S->pw = pw;
     if (!(pw > 0.0) || !(pw < INFINITY)) {
       S->done = 1;

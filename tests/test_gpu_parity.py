@@ -572,20 +572,24 @@ def test_adaptive_polling_matches_every_chunk_polling(lib, prec):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec,w_mode", [("fp64", 1), ("mixed", 1), ("mixed", 4), ("fp32", 1)])
 @pytest.mark.parametrize("B", [3, 11])
-def test_fused_operator_matches_oracle(lib, prec, w_mode, B):
+@pytest.mark.parametrize("group", [1, 4])
+def test_fused_operator_matches_oracle(lib, prec, w_mode, B, group):
     """op_fused = 1: one kernel forms A p over a tile and its stencil reach in
     LDS and applies A^T there.  n = 95 takes 512-row tiles (4 times the
-    95-row reach, rounded up; 18 per instance, the last one 321 rows)."""
+    95-row reach, rounded up; 18 per instance, the last one 321 rows);
+    group 4 shares each row's coefficients among 4 instances (B = 3: one
+    partial group; B = 11: groups of 4, 4 and 3)."""
     w = gen.c2_workload(n=95, k=16, B=B)
     S = spec(w.op, "factored")
     masks = np.stack([i.mask for i in w.instances])
     bs = np.stack([i.b for i in w.instances])
     p = {"fp64": lib.FP64, "mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE}[prec]
-    case(f"fused operator {prec} w_mode={w_mode} factored cd2d n=95 k=16 B={B}")
-    s = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=1, w_mode=w_mode, op_fused=1)
+    case(f"fused operator group={group} {prec} w_mode={w_mode} factored cd2d n=95 k=16 B={B}")
+    s = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=1, w_mode=w_mode, op_fused=1,
+               op_group=group)
     out = s.solve_batched(masks, bs, 1e-10)
-    fused, rows, _ = s.op_variant()
-    assert fused == 1 and rows == 512
+    fused, rows, _, grp = s.op_variant()
+    assert fused == 1 and rows == 512 and grp == group
     X = out["x"].cpu().numpy()
     for m, inst in enumerate(w.instances):
         ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
@@ -605,25 +609,27 @@ def test_fused_operator_matches_oracle(lib, prec, w_mode, B):
     assert np.all(X[masks == 1] == 0.0)
 
 
-def test_fused_operator_large_tiles(lib):
+@pytest.mark.parametrize("group", [1, 4])
+def test_fused_operator_large_tiles(lib, group):
     """255^2 x 16 (mixed, tile-major update): 1024-row fused tiles with a
     255-row halo on each side, 64 tiles per instance, the last one ragged
-    (513 rows).  Sampled instances against x*, every instance against the
-    two-pass operator's iteration count and solution."""
+    (513 rows), one or four instances per block.  Sampled instances against
+    x*, every instance against the two-pass operator's iteration count and
+    solution."""
     w = gen.c2_workload(n=255, k=32, B=16)
     S = spec(w.op, "factored")
     masks = np.stack([i.mask for i in w.instances])
     bs = np.stack([i.b for i in w.instances])
-    case("fused operator vs two passes, mixed w_mode=4 factored cd2d n=255 k=32 B=16")
+    case(f"fused operator (group {group}) vs two passes, mixed w_mode=4 factored cd2d n=255 k=32 B=16")
     outs = {}
     for fo in (1, -1):
         s = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE, rows_per_thread=1, w_mode=4,
-                   op_fused=fo)
+                   op_fused=fo, op_group=group if fo == 1 else 0)
         outs[fo] = s.solve_batched(masks, bs, 1e-10)
-        f, rows, _ = s.op_variant()
+        f, rows, _, grp = s.op_variant()
         assert f == (1 if fo == 1 else 0)
         if fo == 1:
-            assert rows == 1024
+            assert rows == 1024 and grp == group
         s.close()
     Xf, Xt = outs[1]["x"].cpu().numpy(), outs[-1]["x"].cpu().numpy()
     assert np.all(outs[1]["status"] == 0) and np.all(outs[1]["relres_true"] <= 1e-10)
@@ -636,6 +642,24 @@ def test_fused_operator_large_tiles(lib):
         I, xs = _xstar(S, inst.mask, inst.b)
         assert oracle.rel_err(Xf[m, I], xs) <= 1e-8, m
     assert np.all(Xf[masks == 1] == 0.0)
+
+
+def test_fused_operator_options_checked(lib):
+    """op_group 4 whose four LDS copies do not fit, and an op_rows below
+    twice the reach that still fits, as the header states."""
+    w = gen.c2_workload(n=255, k=8, B=4)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case("fused operator options: group 4 with 4096-row tiles refused, 256-row tiles accepted")
+    s = solver(lib, w.op, w.Z, "factored", precision=lib.FP64, op_fused=1, op_rows=4096, op_group=4)
+    with pytest.raises(lib.Adef2Error) as e:
+        s.solve_batched(masks, bs, 1e-8)
+    assert e.value.code == lib.E_UNSUPPORTED
+    s = solver(lib, w.op, w.Z, "factored", precision=lib.FP64, rows_per_thread=1, w_mode=1, op_fused=1,
+               op_rows=256, op_group=4)
+    out = s.solve_batched(masks, bs, 1e-8)
+    assert s.op_variant()[1] == 256 and s.op_variant()[3] == 4
+    assert np.all(out["status"] == 0)
 
 
 def test_fused_operator_refused_for_assembled(lib):
