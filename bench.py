@@ -98,6 +98,10 @@ def parse():
     ap.add_argument("--c5-nc", type=int, default=31)
     ap.add_argument("--c5-plain", type=int, default=2, help="plain FP64 instances timed in the 3D arm")
     ap.add_argument("--c5-precision", choices=["fp64_refine", "fp64", "mixed"], default="fp64_refine")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 255^2 x 256 sweep arm")
+    ap.add_argument("--c3-n", type=int, default=255)
+    ap.add_argument("--c3-batch", type=int, default=256)
+    ap.add_argument("--c3-plain", type=int, default=4, help="plain FP64 instances timed in the sweep arm")
     ap.add_argument("--c4", action="store_true",
                     help="run the learned-enrichment arms on the 255^2 heterogeneous sweep (minutes)")
     ap.add_argument("--c4-train", type=int, default=2000)
@@ -318,6 +322,65 @@ def c5_arm(args, lib, prec, tune):
                         "variant": {"rows_per_thread": v[0], "w_mode": v[1]}},
             "plain_fp64": {"solves_per_s": round(rate_p, 4), "instances_timed": sel, "iters": pit},
             "speedup_vs_plain": round((16 / t_b) / rate_p, 3)}
+
+
+def c3_arm(args, lib, prec, tune):
+    """The batched parameter sweep: args.c3_batch instances of the 255^2
+    heterogeneous-diffusion family (per-instance operator scale, inactive sets
+    of 40-95 % of N, k = 32 shared eigenvectors of the reference operator,
+    tol 1e-8) in one batched solve, vs the FP64 solver one instance at a time
+    on a sample of args.c3_plain instances spanning the inactive-set sizes."""
+    import torch
+
+    import gen
+    t0 = time.perf_counter()
+    w = gen.c3_workload(n=args.c3_n, k=32, B=args.c3_batch)
+    log(f"sweep workload {w.name} generated in {time.perf_counter() - t0:.1f}s")
+    op = w.op
+    B = len(w.instances)
+    masks = torch.as_tensor(np.stack([i.mask for i in w.instances]), device="cuda")
+    bs = torch.as_tensor(np.stack([i.b for i in w.instances]), device="cuda")
+    a = np.array([i.a for i in w.instances])
+    c = np.array([i.c for i in w.instances]) - a * op.shift
+    s = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
+    s.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    s.solve_batched(masks, bs, 1e-3, a=a, c=c)       # variant tuning and graphs
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    o = s.solve_batched(masks, bs, 1e-8, a=a, c=c)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t1
+    it = np.asarray(o["iters"])
+    v, ov = s.variant(), s.op_variant()
+    s.close()
+    log(f"sweep batched: {t_b:.2f}s ({B / t_b:.2f} solves/s), iterations mean {it.mean():.0f} max {it.max()}")
+    nI = (masks == 0).sum(dim=1).cpu().numpy()
+    order = np.argsort(nI)
+    sel = [int(order[j]) for j in np.linspace(0, B - 1, max(1, args.c3_plain)).round().astype(int)]
+    ps = lib.Solver(precision=lib.FP64)
+    ps.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
+    ps.solve_batched(masks[sel[0]:sel[0] + 1], bs[sel[0]:sel[0] + 1], 1e-3, a=a[sel[0]:sel[0] + 1],
+                     c=c[sel[0]:sel[0] + 1])         # warm-up: variant and graphs
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pit = []
+    for m in sel:
+        po = ps.solve_batched(masks[m:m + 1], bs[m:m + 1], 1e-8, a=a[m:m + 1], c=c[m:m + 1])
+        pit.append(int(po["iters"][0]))
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t2
+    ps.close()
+    rate_p = len(sel) / t_p
+    log(f"sweep plain FP64 sample of {len(sel)}: {t_p:.2f}s ({rate_p:.3f} solves/s)")
+    return {"workload": w.name, "grid": args.c3_n, "k": 32, "instances": B, "tol": 1e-8,
+            "precision": args.precision,
+            "batched": {"solves_per_s": round(B / t_b, 3), "seconds": round(t_b, 3), "iters_mean": float(it.mean()),
+                        "iters_max": int(it.max()), "status": np.unique(np.asarray(o["status"])).tolist(),
+                        "relres_true_max": float(np.asarray(o["relres_true"]).max()),
+                        "variant": {"rows_per_thread": v[0], "w_mode": v[1], "op_fused": ov[0],
+                                    "op_tile_rows": ov[1], "op_group": ov[3]}},
+            "plain_fp64": {"solves_per_s": round(rate_p, 4), "instances_timed": sel, "iters": pit},
+            "speedup_vs_plain": round((B / t_b) / rate_p, 3)}
 
 
 def c4_arm(args, lib):
@@ -599,6 +662,13 @@ def main():
         except Exception as ex:            # reported, never fatal for the headline
             c4 = {"error": str(ex)}
 
+    c3 = None
+    if not args.no_c3:
+        try:
+            c3 = c3_arm(args, lib, prec, tune)
+        except Exception as ex:            # reported, never fatal for the headline
+            c3 = {"error": str(ex)}
+
     c5 = None
     if not args.no_c5:
         try:
@@ -683,6 +753,7 @@ def main():
         "learned_fit": learned,
         "learned_arm": learned_arm,
         "pod_merge": pod_arm,
+        "c3": c3,
         "c4": c4,
         "c5": c5,
         "roofline": roofline,
