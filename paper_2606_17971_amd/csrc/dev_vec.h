@@ -1,8 +1,8 @@
-// Per-instance vector kernels around the iteration: the FP64 outer residual
-// of the refinement modes, the inner stencil of the factored operator, the
-// accumulation of FP32 corrections, scatter / copy / fill helpers, the
-// restricted matvec test hook and the Jacobi preconditioner.  Used by the
-// host runtime only (one translation unit).
+// Kernels of the host runtime's translation unit: the FP64 outer residual of
+// the refinement modes, the inner stencil of the factored operator, the fused
+// operator pass of the factored form (one instance or a group of four per
+// block), the accumulation of FP32 corrections, scatter / copy / fill
+// helpers, the restricted matvec test hook and the Jacobi preconditioner.
 #pragma once
 #include "dev_tile.h"
 
