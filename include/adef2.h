@@ -254,6 +254,16 @@ typedef struct {
                            own LDS copy of A p, so four copies must fit 64
                            KiB); 0 = tuned (op_fused = 0) or 1 (op_fused =
                            1); 0                                            */
+  int32_t sweep_async;  /* refinement modes: 1 (default) = an instance whose
+                           segment ends starts its next one at the end of the
+                           same chunk of iterations (correction, FP64
+                           residual, outer test and the next segment's set-up
+                           run inside the chunk, for the instances concerned
+                           only), so no instance waits for the others'
+                           segments; 0 = every instance's segment must end
+                           before the host starts the next segment for all.
+                           The arithmetic of every instance is the same
+                           either way (same iterations, same x)             */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;

@@ -55,6 +55,7 @@ class Opts(ctypes.Structure):
         ("op_fused", ctypes.c_int32),
         ("op_rows", ctypes.c_int32),
         ("op_group", ctypes.c_int32),
+        ("sweep_async", ctypes.c_int32),
     ]
 
 

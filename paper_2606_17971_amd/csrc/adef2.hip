@@ -847,6 +847,44 @@ int poll(adef2_ctx* c, bool outer, bool* all_done) {
   return ADEF2_OK;
 }
 
+// FP64 outer residual r64 = b - S_II x (stored when store), its norm and the
+// outer stopping rule (decide); trans_mode: only instances whose sweep has
+// ended (sweep transitions inside a chunk)
+ResidArgs resid_args(const adef2_ctx* c, const double* b, const double* xpad, int first, int decide, bool store,
+                     int trans_mode) {
+  ResidArgs ra{};
+  ra.op = op_geom(c);
+  ra.dia = c->dia64;
+  ra.mask = c->masks;
+  ra.b = b;
+  ra.x = xpad;
+  ra.sv = xpad;
+  ra.vs = c->vs;
+  ra.r64 = store ? c->r64 : nullptr;
+  ra.inst = c->inst;
+  ra.part = c->part;
+  ra.ctr = c->ctr;
+  ra.g = c->g_iter;
+  ra.first = first;
+  ra.decide = decide;
+  ra.maxit = c->o.maxit;
+  ra.max_sweeps = c->o.max_sweeps;
+  ra.stall_steps = 4;
+  ra.trans_mode = trans_mode;
+  return ra;
+}
+
+// the residual kernel (after t = A x for the factored operator, stencil skip
+// mode as in k_stencil1) on stream s
+void launch_resid(adef2_ctx* c, ResidArgs ra, const double* xpad, hipStream_t s, int skip) {
+  if (c->factored) {
+    hipLaunchKernelGGL((stencil1_fn<double, double, double>(c->rpt)), dim3(c->ntiles_pad * c->B), dim3(IPB), 0, s,
+                       ra.op, c->dia1_64, xpad, interior(c, c->t64), c->vs, c->inst, skip);
+    ra.sv = interior(c, c->t64);
+  }
+  hipLaunchKernelGGL(resid_fn(c->rpt), dim3(c->ntiles_pad * c->B), dim3(IPB), 0, s, ra);
+}
+
 // run one A-DEF2 sweep in precision V for all instances: init, init2, then
 // chunks of iterations until every instance's sweep is done
 // Instantiated graph of one chunk of iterations for these kernel arguments:
@@ -854,12 +892,13 @@ int poll(adef2_ctx* c, bool outer, bool* all_done) {
 // arguments (buffers, geometry, variant) are unchanged.  Up to 24
 // configurations are kept per context.
 template <typename V, typename M, typename F>
-int chunk_graph(adef2_ctx* c, const IterArgs<V, M>& a, int chunk, int variant, F&& launch_chunk,
+int chunk_graph(adef2_ctx* c, const IterArgs<V, M>& a, int chunk, int variant, const void* tag, F&& launch_chunk,
                 hipGraphExec_t* out) {
-  std::vector<char> key(sizeof(a) + 4 * sizeof(int));
+  std::vector<char> key(sizeof(a) + 4 * sizeof(int) + sizeof(tag));
   std::memcpy(key.data(), &a, sizeof(a));
   const int extra[4] = {(int)sizeof(V), (int)sizeof(M), chunk, variant * 16 + c->rpt};
   std::memcpy(key.data() + sizeof(a), extra, sizeof(extra));
+  std::memcpy(key.data() + sizeof(a) + sizeof(extra), &tag, sizeof(tag));
   for (auto& g : c->graphs)
     if (g.key == key) { *out = g.exec; return ADEF2_OK; }
   if (!c->gst) {
@@ -887,8 +926,12 @@ int chunk_graph(adef2_ctx* c, const IterArgs<V, M>& a, int chunk, int variant, F
 
 // max_chunks > 0 stops after that many chunks (tuning trials).
 template <typename V, typename M>
+// b_outer != null: refinement with sweep transitions inside the chunks (each
+// instance starts its next sweep at the end of the chunk in which its sweep
+// ended; x64 accumulates the corrections; the run ends when every instance
+// meets the outer test), b_outer being the right-hand side of the solve
 int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thresh_scale, int rel_tol,
-              double thresh_floor, int carry_dir, int max_chunks = 0) {
+              double thresh_floor, int carry_dir, int max_chunks = 0, const double* b_outer = nullptr) {
   // tile-major boundary-form kernels (w_mode 4): shared eigen-basis, FP64 vectors
   const bool tm = (c->wfree == 3 || c->wfree == 4) && c->KP > 0 && sizeof(V) == 8 && c->tm_ok;
   const bool wfree = (c->wfree == 1 || c->wfree == 2) && c->KP > 0 && sizeof(V) == 8;
@@ -942,6 +985,13 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   timed(c, KI_INIT, bm.init, [&] { hipLaunchKernelGGL(kt.init, grid, blk, 0, c->st, a); });
   timed(c, KI_INIT2, bm.init2, [&] { hipLaunchKernelGGL(kt.init2, grid, blk, 0, c->st, a); });
   HIPCHK(c, hipGetLastError());
+  // sweep transitions: the next sweep's init and init2 carry the direction
+  // over and touch only the instances whose sweep has ended
+  IterArgs<V, M> at = a;
+  at.carry_dir = 1;
+  at.trans_mode = 1;
+  const ResidArgs ra_t = resid_args(c, b_outer, interior(c, c->x64), 0, 1, true, 1);
+  const ByteModel bm64 = byte_model(c, 8.0, 8.0, false);
   const int chunk = std::max(1, c->o.check_every);
   // one chunk of iterations on stream s (kernel arguments are the same for
   // every iteration: all per-iteration state lives in device memory)
@@ -1003,6 +1053,18 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
         });
       }
     }
+    if (b_outer) {
+      // instances whose sweep ended in this chunk: the correction into x64,
+      // the FP64 residual and the outer test, then the next sweep's set-up
+      timed(c, KI_ACCUM, bm.accum, [&] {
+        hipLaunchKernelGGL(accum_fn<V>(c->rpt), grid, blk, 0, s, og, c->masks, (const V*)a.x,
+                           interior(c, c->x64), c->vs, c->inst);
+      });
+      timed(c, KI_RESID, bm64.resid, [&] { launch_resid(c, ra_t, interior(c, c->x64), s, 3); });
+      timed(c, KI_INIT, bm.init, [&] { hipLaunchKernelGGL(kt.init, grid, blk, 0, s, at); });
+      timed(c, KI_INIT2, bm.init2, [&] { hipLaunchKernelGGL(kt.init2, grid, blk, 0, s, at); });
+      hipLaunchKernelGGL(k_trans_clear, dim3((unsigned)cdiv(c->B, 64)), dim3(64), 0, s, c->inst, c->B);
+    }
   };
   hipGraphExec_t gexec = nullptr;
   if (c->o.graph && !c->o.profile) {
@@ -1010,9 +1072,9 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
     // itself (w_mode 4 and 5 differ only in the stencil kernels), the
     // operator form and the boundary form
     int rc = chunk_graph<V, M>(c, a, chunk,
-                               (c->opg << 9) | ((int)c->opf << 8) | (c->wfree << 4) | ((int)tm << 3) | ((int)bt << 2) |
-                                   ((int)wfree << 1) | (c->ne > 0 ? 1 : 0),
-                               launch_chunk, &gexec);
+                               ((b_outer ? 1 : 0) << 12) | (c->opg << 9) | ((int)c->opf << 8) | (c->wfree << 4) |
+                                   ((int)tm << 3) | ((int)bt << 2) | ((int)wfree << 1) | (c->ne > 0 ? 1 : 0),
+                               b_outer, launch_chunk, &gexec);
     if (rc) return rc;
   }
   // Convergence is decided on the device (finished instances' blocks exit at
@@ -1027,11 +1089,11 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   int64_t launched = 0;
   for (;;) {
     bool ad = false;
-    int rc = poll(c, false, &ad);
+    int rc = poll(c, b_outer != nullptr, &ad);
     if (rc) return rc;
     if (ad) break;
     // every instance stops at maxit on the device; this guards the host loop
-    if (launched > (int64_t)c->o.maxit + 2 * chunk)
+    if (launched > (int64_t)c->o.maxit + (int64_t)(pmax + 2) * chunk)
       return fail(c, ADEF2_E_HIP, "iteration kernels made no progress");
     double est = 0.0;
     for (int m = 0; m < c->B; ++m) {
@@ -1048,7 +1110,9 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
       prev_rr[m] = s.rr;
       prev_it[m] = s.sweep_iters;
     }
-    int nrep = (int)std::min<double>((double)pmax, std::max(1.0, std::floor(0.5 * est / chunk)));
+    // with sweep transitions the horizon is the outer test, which the sweep
+    // residuals do not predict: poll_max chunks between polls
+    int nrep = b_outer ? pmax : (int)std::min<double>((double)pmax, std::max(1.0, std::floor(0.5 * est / chunk)));
     if (max_chunks > 0) nrep = std::min<int64_t>(nrep, std::max<int64_t>(1, max_chunks - launched / chunk));
     for (int rep = 0; rep < nrep; ++rep) {
       launched += chunk;
@@ -1070,34 +1134,9 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
 }
 
 int resid64(adef2_ctx* c, const double* b, const double* xpad, int first, int decide, bool store) {
-  ResidArgs ra{};
-  ra.op = op_geom(c);
-  ra.dia = c->dia64;
-  ra.mask = c->masks;
-  ra.b = b;
-  ra.x = xpad;
-  ra.sv = xpad;
-  ra.vs = c->vs;
-  ra.r64 = store ? c->r64 : nullptr;
-  ra.inst = c->inst;
-  ra.part = c->part;
-  ra.ctr = c->ctr;
-  ra.g = c->g_iter;
-  ra.first = first;
-  ra.decide = decide;
-  ra.maxit = c->o.maxit;
-  ra.max_sweeps = c->o.max_sweeps;
-  ra.stall_steps = 4;
+  const ResidArgs ra = resid_args(c, b, xpad, first, decide, store, 0);
   const ByteModel bm = byte_model(c, 8.0, 8.0, false);
-  timed(c, KI_RESID, bm.resid, [&] {
-    if (c->factored) {
-      hipLaunchKernelGGL((stencil1_fn<double, double, double>(c->rpt)), dim3(c->ntiles_pad * c->B),
-                         dim3(IPB), 0, c->st, ra.op, c->dia1_64, xpad, interior(c, c->t64), c->vs,
-                         c->inst, decide ? 2 : 0);
-      ra.sv = interior(c, c->t64);
-    }
-    hipLaunchKernelGGL(resid_fn(c->rpt), dim3(c->ntiles_pad * c->B), dim3(IPB), 0, c->st, ra);
-  });
+  timed(c, KI_RESID, bm.resid, [&] { launch_resid(c, ra, xpad, c->st, decide ? 2 : 0); });
   HIPCHK(c, hipGetLastError());
   return ADEF2_OK;
 }
@@ -1108,7 +1147,7 @@ int reset_solve_state(adef2_ctx* c) {
     Inst& s = c->inst_h[m];
     s.iters = 0; s.sweep_iters = 0; s.done = 0; s.outer_done = 0; s.status = 0; s.sweeps = 0;
     s.has_dir = 0; s.rho_end = 0.0; s.stall = 0; s.rr64_best = INFINITY; s.drift = 0;
-    s.capped = 0;
+    s.capped = 0; s.trans = 0;
     s.rr = 0; s.rr64 = 0; s.bb64 = 0;
     const double t = m < (int)c->tol_h.size() ? c->tol_h[m] : 1e-8;
     s.tol2 = t * t;
@@ -1296,7 +1335,15 @@ int solve_batch(adef2_ctx* c, const double* b, const double* x0, double tol, dou
     const double in2 = m64 ? 0.0 : c->o.inner_rtol * c->o.inner_rtol;
     const double mb = m64 ? 8.0 : 4.0;
     ByteModel bm = byte_model(c, v64 ? 8.0 : 4.0, mb, false);
-    for (int sweep = 0;; ++sweep) {
+    if (c->o.sweep_async) {
+      // every instance moves to its next segment at the end of the chunk in
+      // which its segment ended
+      rc = m64 ? run_sweep<double, double>(c, c->r64, nullptr, in2, 0, 0.25, 0, 0, b)
+               : v64 ? run_sweep<double, float>(c, c->r64, nullptr, in2, 0, 0.25, 0, 0, b)
+                     : run_sweep<float, float>(c, c->r64, nullptr, in2, 0, 0.25, 0, 0, b);
+      if (rc) return rc;
+    }
+    for (int sweep = 0; !c->o.sweep_async; ++sweep) {
       bool ad = false;
       if ((rc = poll(c, true, &ad))) return rc;
       if (ad) break;
@@ -1356,7 +1403,8 @@ bool valid_opts(const adef2_opts* o) {
          o->tau_safe >= 1.0 && o->tau_dep >= 0.0 && o->tau_dep < 1.0 && o->poll_max >= 1 &&
          (o->learned_objective == 0 || o->learned_objective == 1) &&
          (o->op_fused >= -1 && o->op_fused <= 1) && o->op_rows >= 0 && o->op_rows % 256 == 0 &&
-         o->op_rows <= (1 << 16) && (o->op_group == 0 || o->op_group == 1 || o->op_group == 4);
+         o->op_rows <= (1 << 16) && (o->op_group == 0 || o->op_group == 1 || o->op_group == 4) &&
+         (o->sweep_async == 0 || o->sweep_async == 1);
 }
 
 }  // namespace
@@ -1481,6 +1529,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->op_fused = 0;
   o->op_rows = 0;
   o->op_group = 0;
+  o->sweep_async = 1;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {

@@ -48,6 +48,7 @@ struct Inst {
   int32_t has_dir;      // a search direction from the previous sweep exists
   int32_t stall;        // outer steps since the best residual last halved
   int32_t learned;      // the learned enrichment vectors are in the coarse space
+  int32_t trans;        // a new sweep was set up in this chunk's transition (init2 pending)
   double coef[KMAX];    // coarse coefficients of the next x / p update
 };
 

@@ -105,6 +105,8 @@ struct IterArgs {
   double thresh_floor;     //               thresh_floor * tol2 * ||b_I||^2), tol2 per instance
   int32_t thresh_rel_tol;  // multiply thresh_scale by the instance's tol2
   int32_t carry_dir;       // keep the previous sweep's search direction
+  int32_t trans_mode;      // init / init2 of a sweep transition: only instances whose
+                           // sweep ended (init) or that init set up (init2)
   int32_t seg_maxit;       // a sweep ends after this many iterations (0 = none)
   // W-free projection: FP64 operator and modes (see k_zproj)
   const double* dia64;     // [D][N]
@@ -222,7 +224,7 @@ __global__ void __launch_bounds__(IPB) k_init(IterArgs<V, M> a) {
   int tile, m;
   tile_inst(a.op.ntiles_pad, tile, m);
   Inst* S = a.inst + m;
-  if (S->outer_done) return;
+  if (S->outer_done || (a.trans_mode && !S->done)) return;
   const int64_t N = a.op.N;
   const int64_t base = (int64_t)tile * R;
   const uint8_t* mk = a.mask + (size_t)m * N;
@@ -279,6 +281,7 @@ __global__ void __launch_bounds__(IPB) k_init(IterArgs<V, M> a) {
     S->done = 0;
     S->sweep_iters = 0;
     S->fresh = 1;
+    if (a.trans_mode) S->trans = 1;
     if (!(b2 < INFINITY)) { S->done = 1; S->outer_done = 1; S->status = -1; }
     else if (b2 == 0.0) { S->done = 1; }
   }
@@ -472,7 +475,7 @@ __global__ void __launch_bounds__(IPB) k_init2(IterArgs<V, M> a) {
   int tile, m;
   tile_inst(a.op.ntiles_pad, tile, m);
   Inst* S = a.inst + m;
-  if (S->outer_done) return;
+  if (S->outer_done || (a.trans_mode && !S->trans)) return;
   const int64_t N = a.op.N;
   const int64_t base = (int64_t)tile * R;
   const uint8_t* mk = a.mask + (size_t)m * N;

@@ -27,6 +27,7 @@ struct ResidArgs {
   int32_t decide;          // apply the outer stopping rule
   int32_t maxit, max_sweeps;
   int32_t stall_steps;     // outer steps without halving before W_STAGNATED
+  int32_t trans_mode;      // only instances whose sweep has ended (sweep transition)
 };
 
 template <int RPT>
@@ -38,6 +39,7 @@ __global__ void __launch_bounds__(IPB) k_resid64(ResidArgs a) {
   tile_inst(a.op.ntiles_pad, tile, m);
   Inst* S = a.inst + m;
   if (S->outer_done && a.decide) return;
+  if (a.trans_mode && !S->done) return;
   const int64_t N = a.op.N;
   const uint8_t* mk = a.mask + (size_t)m * N;
   const double* b = a.b + (size_t)m * N;
@@ -92,14 +94,16 @@ __global__ void __launch_bounds__(IPB) k_resid64(ResidArgs a) {
 
 // Inner stencil of the factored operator on all rows: t = A v (v is zero on
 // the active set, so t = A[:, I] v_I).  skip: 1 = skip instances whose sweep is
-// done, 2 = skip finished solves, 0 = none.
+// done, 2 = skip finished solves, 3 = only instances whose sweep has ended
+// (sweep transition), 0 = none.
 template <typename VM, typename VI, typename VO, int RPT>
 __global__ void __launch_bounds__(IPB) k_stencil1(OpGeom op, const VM* dia1, const VI* v, VO* t,
                                                   int64_t vs, const Inst* inst, int skip) {
   int tile, m;
   tile_inst(op.ntiles_pad, tile, m);
   const Inst* S = inst + m;
-  if ((skip == 1 && S->done) || (skip == 2 && S->outer_done)) return;
+  if ((skip == 1 && S->done) || (skip == 2 && S->outer_done) || (skip == 3 && (S->outer_done || !S->done)))
+    return;
   if (tile >= op.ntiles) return;
   const int64_t N = op.N;
   const VI* vm = v + m * vs;
@@ -415,14 +419,15 @@ __global__ void __launch_bounds__(IPB) k_opfused_g(IterArgs<V, M> a) {
   }
 }
 
-// x64 += d (FP32 correction of the last sweep)
+// x64 += d (correction of the sweep that has just ended; instances still in
+// their sweep are skipped)
 template <typename V, int RPT>
 __global__ void __launch_bounds__(IPB) k_accumulate(OpGeom op, const uint8_t* mask, const V* d,
                                                     double* x64, int64_t vs, Inst* inst) {
   int tile, m;
   tile_inst(op.ntiles_pad, tile, m);
   Inst* S = inst + m;
-  if (S->outer_done) return;
+  if (S->outer_done || !S->done) return;
   if (tile >= op.ntiles) return;
   const int64_t N = op.N;
   const uint8_t* mk = mask + (size_t)m * N;
@@ -432,6 +437,12 @@ __global__ void __launch_bounds__(IPB) k_accumulate(OpGeom op, const uint8_t* ma
     if (i < N && mk[i] == 0) x64[m * vs + i] += (double)d[m * vs + i];
   }
   if (tile == 0 && threadIdx.x == 0) S->sweeps += 1;
+}
+
+// end of a chunk's sweep transitions: no instance has a pending init2
+__global__ void k_trans_clear(Inst* inst, int B) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < B) inst[m].trans = 0;
 }
 
 // out[i] = x[i] on inactive rows, 0 on active rows (instance-major, unpadded)

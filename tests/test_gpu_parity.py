@@ -671,3 +671,39 @@ def test_fused_operator_refused_for_assembled(lib):
     with pytest.raises(lib.Adef2Error) as e:
         s.solve_batched(masks, bs, 1e-10)
     assert e.value.code == lib.E_UNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# refinement segments: transitions inside the chunks vs synchronised segments
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,w_mode", [("mixed", 4), ("mixed", 1), ("fp32", 1), ("fp64_refine", 1)])
+def test_async_segments_match_synchronised(lib, prec, w_mode):
+    """sweep_async = 1 moves an instance to its next segment at the end of the
+    chunk in which its segment ended; sweep_async = 0 waits for every
+    instance's segment.  Every instance's arithmetic is the same, so the
+    iteration counts, statuses and solutions agree bitwise.  The batch mixes
+    per-instance tolerances (segments of very different lengths) and a zero
+    right-hand side."""
+    w = gen.c2_workload(n=95, k=16, B=6)
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    bs[4] = 0.0
+    tols = np.array([1e-10, 1e-6, 1e-9, 1e-4, 1e-10, 1e-8])
+    p = {"mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE, "fp64_refine": lib.FP64_REFINE}[prec]
+    case(f"async vs synchronised segments {prec} w_mode={w_mode} cd2d n=95 k=16 B=6")
+    outs = []
+    for sa in (0, 1):
+        s = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=1, w_mode=w_mode, op_fused=1,
+                   sweep_async=sa)
+        outs.append(s.solve_batched(masks, bs, tols))
+        s.close()
+    print(f"   iterations {outs[1]['iters'].tolist()} statuses {outs[1]['status'].tolist()}", flush=True)
+    np.testing.assert_array_equal(outs[0]["iters"], outs[1]["iters"])
+    np.testing.assert_array_equal(outs[0]["status"], outs[1]["status"])
+    np.testing.assert_array_equal(outs[0]["x"].cpu().numpy(), outs[1]["x"].cpu().numpy())
+    assert np.all(outs[1]["x"][4].cpu().numpy() == 0.0)
+    S = spec(w.op, "factored")
+    for m in (0, 3, 5):
+        I, xs = _xstar(S, w.instances[m].mask, bs[m])
+        e = oracle.rel_err(outs[1]["x"].cpu().numpy()[m, I], xs)
+        assert e <= max(1e-6, 10 * tols[m]), (m, e)
