@@ -571,7 +571,9 @@ def main():
         return head.solve_batched(masks, bs, args.tol, theta=use_theta)
 
     if args.counter_run:
-        head.set_opts(maxit=args.counter_maxit)
+        # synchronised segments: the host stops enqueuing at the cap, so every
+        # counted dispatch of the iteration kernels has all instances iterating
+        head.set_opts(maxit=args.counter_maxit, sweep_async=0)
         out = head_step()
         torch.cuda.synchronize()
         src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").uniform_()
