@@ -86,14 +86,17 @@ def test_c3_full_batch_sampled(lib, c3full, prec):
             assert rel[m] <= 10 * ref.relres_true + 1e-9
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_3d_two_material(lib, prec):
+@pytest.mark.parametrize("prec,op_fused", [("mixed", 0), ("fp64", 0), ("fp64", 1), ("mixed", 1)])
+def test_3d_two_material(lib, prec, op_fused):
+    """3D 7-point operator at 23^3.  op_fused = 1 forces the fused operator
+    pass with the run-time diagonal loop (7 diagonals; the 529-row reach of a
+    grid plane still fits in LDS at this size)."""
     w = gen.c5_workload(n=23, k=16, B=3)
     op = w.op
-    case(f"3d n=23 k=16 B=3 {prec}")
+    case(f"3d n=23 k=16 B=3 {prec} op_fused={op_fused}")
     masks = np.stack([i.mask for i in w.instances])
     bs = np.stack([i.b for i in w.instances])
-    s = lib.Solver(precision=lib.MIXED_REFINE if prec == "mixed" else lib.FP64)
+    s = lib.Solver(precision=lib.MIXED_REFINE if prec == "mixed" else lib.FP64, op_fused=op_fused)
     s.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     out = s.solve_batched(masks, bs, 1e-10)
     X = out["x"].cpu().numpy()
@@ -107,6 +110,8 @@ def test_3d_two_material(lib, prec):
         assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), (m, e)
         if prec == "fp64":
             assert abs(int(out["iters"][m]) - ref.iters) <= 2
+    if op_fused == 1:
+        assert s.op_variant()[0] == 1 and s.op_variant()[3] == 1
 
 
 @pytest.mark.parametrize("form", ["assembled", "factored"])
