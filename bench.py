@@ -351,7 +351,7 @@ def c3_arm(args, lib, prec, tune):
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t1
     it = np.asarray(o["iters"])
-    v, ov = s.variant(), s.op_variant()
+    v, ov, uv = s.variant(), s.op_variant(), s.update_variant()
     s.close()
     log(f"sweep batched: {t_b:.2f}s ({B / t_b:.2f} solves/s), iterations mean {it.mean():.0f} max {it.max()}")
     nI = (masks == 0).sum(dim=1).cpu().numpy()
@@ -378,7 +378,7 @@ def c3_arm(args, lib, prec, tune):
                         "iters_max": int(it.max()), "status": np.unique(np.asarray(o["status"])).tolist(),
                         "relres_true_max": float(np.asarray(o["relres_true"]).max()),
                         "variant": {"rows_per_thread": v[0], "w_mode": v[1], "op_fused": ov[0],
-                                    "op_tile_rows": ov[1], "op_group": ov[3]}},
+                                    "op_tile_rows": ov[1], "op_group": ov[3], "update_ws": uv[0]}},
             "plain_fp64": {"solves_per_s": round(rate_p, 4), "instances_timed": sel, "iters": pit},
             "speedup_vs_plain": round((B / t_b) / rate_p, 3)}
 
@@ -600,6 +600,7 @@ def main():
     head_iters = np.asarray(out["iters"])
     v_rpt, v_wm, v_ms = head.variant()
     o_f, o_rows, o_ms, o_grp = head.op_variant()
+    u_ws, u_tpb, u_ms = head.update_variant()
     head_rel = np.asarray(out["relres_true"])
     X_head = out["x"].clone()
     value = B / t_head
@@ -683,7 +684,8 @@ def main():
         # one instrumented headline step: HIP events on the solver stream around every launch
         prof = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, profile=1,
                           rows_per_thread=v_rpt, w_mode=v_wm, w_boundary=args.w_boundary,
-                          op_fused=1 if o_f else -1, op_rows=o_rows, op_group=o_grp)
+                          op_fused=1 if o_f else -1, op_rows=o_rows, op_group=o_grp,
+                          update_ws=1 if u_ws else -1)
         prof.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
         if apply_learned:
             prof.set_pod_modes(Phi)
@@ -746,6 +748,7 @@ def main():
         "variant": {"rows_per_thread": v_rpt, "w_mode": v_wm, "tuned": args.rpt == 0 or args.w_mode == 0,
                     "trial_ms": [round(float(tt), 3) for tt in v_ms],
                     "op_fused": int(o_f), "op_tile_rows": int(o_rows), "op_group": int(o_grp),
+                    "update_ws": int(u_ws), "update_trial_ms": [round(float(tt), 3) for tt in u_ms],
                     "op_trial_ms": [round(float(tt), 3) for tt in o_ms]},
         "cond_E": {"min": float(np.min(out["cond_E"])), "max": float(np.max(out["cond_E"]))},
         "iters_per_instance": head_iters.tolist(),

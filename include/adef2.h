@@ -264,6 +264,17 @@ typedef struct {
                            before the host starts the next segment for all.
                            The arithmetic of every instance is the same
                            either way (same iterations, same x)             */
+  int32_t update_ws;    /* update kernel of the tile-major boundary-form path
+                           (w_mode 4 and 5, at most 32 modes): 1 = warp-
+                           specialised, each block of 8 waves owns a run of
+                           tiles, 4 waves update x, r, z of one tile while
+                           the other 4 form the previous tile's projections
+                           on the matrix cores (the products overlap the
+                           loads; one partial sum per run and instance);
+                           -1 = one block per tile; 0 (default) = tuned on
+                           the first solve after the operator form.  1 is
+                           E_UNSUPPORTED where the tile-major path does not
+                           apply or above 32 modes                          */
 } adef2_opts;
 
 typedef struct adef2_ctx adef2_ctx;
@@ -553,6 +564,13 @@ int adef2_variant(adef2_ctx *ctx, int32_t *rows_per_thread, int32_t *w_mode, flo
  * with 4 instances per block (0 where a height does not fit or nothing was
  * tuned).  E_STATE before the first solve. */
 int adef2_operator_variant(adef2_ctx *ctx, int32_t *fused, int32_t *tile_rows, int32_t *group, float *ms);
+
+/* Update kernel used by the last solve on ctx (see opts.update_ws):
+ * warp-specialised (1) or one block per tile (0), the tiles per block (0
+ * when the tile-major path is not in use), and in ms (host f32[2], may be
+ * NULL) the tuning trial times of the two forms (0 when not tuned).
+ * E_STATE before the first solve. */
+int adef2_update_variant(adef2_ctx *ctx, int32_t *warp_specialised, int32_t *tiles_per_block, float *ms);
 
 #define ADEF2_STATS_KERNELS 24
 typedef struct {

@@ -56,6 +56,7 @@ class Opts(ctypes.Structure):
         ("op_rows", ctypes.c_int32),
         ("op_group", ctypes.c_int32),
         ("sweep_async", ctypes.c_int32),
+        ("update_ws", ctypes.c_int32),
     ]
 
 
@@ -101,6 +102,7 @@ _sig = {
     "adef2_coarse_info": (ctypes.c_int, [_P, _P, _P, _Pi32, _Pf64]),
     "adef2_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _P]),
     "adef2_operator_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _Pi32, _P]),
+    "adef2_update_variant": (ctypes.c_int, [_P, _Pi32, _Pi32, _P]),
     "adef2_active_set_batched": (ctypes.c_int, [_P, _i32, _P, _P, _f64, _f64, _i32, _P, _P, _P, _P, _P]),
     "adef2_pod_enrich": (ctypes.c_int, [_P, _i32, _f64]),
     "adef2_set_enrichment": (ctypes.c_int, [_P, _i32, _P, _P, _i32, _f64]),
@@ -434,6 +436,15 @@ class Solver:
         self._check(_lib.adef2_variant(self._ctx, ctypes.byref(r), ctypes.byref(wm), ms.ctypes.data),
                     allow=(OK,))
         return r.value, wm.value, ms
+
+    def update_variant(self):
+        """(warp-specialised, tiles per block, trial ms [per tile, warp-
+        specialised]) of the last solve's update kernel."""
+        ws, tpb = _i32(0), _i32(0)
+        ms = np.zeros(2, np.float32)
+        self._check(_lib.adef2_update_variant(self._ctx, ctypes.byref(ws), ctypes.byref(tpb), ms.ctypes.data),
+                    allow=(OK,))
+        return ws.value, tpb.value, ms
 
     def op_variant(self):
         """(fused, tile rows, trial ms [two passes, fused at 2 / 4 / 8 x the

@@ -203,6 +203,8 @@ struct adef2_ctx {
   // fused operator pass of the factored form (k_opfused), 0 = two passes
   int opf = 0;
   int opg = 1;                   // instances per block of the fused pass (1, or 4: k_opfused_g)
+  int uws = 0;                   // warp-specialised update (k_update_ws) instead of k_update_tm
+  int ws_T = 1, ws_cpx = 0;      // its tiles per block and runs per XCD
   int of_rows = 0, of_halo = 0, of_ntiles = 0, of_ntiles_pad = 0;
   RedGeom g_of{};
   // opo: the op_fused option the entry was tuned under; opf: rows of the
@@ -210,7 +212,10 @@ struct adef2_ctx {
   // ms_op: trial times of the two passes and of the fused pass at each
   // candidate tile height, one instance per block [1..3] and four [4..6],
   // with the chosen rpt / wfree
-  struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[10]; int opo, opf, opg; float ms_op[7]; };
+  // uwo: the update_ws option tuned under; uws: the update form kept; ms_uw:
+  // trial times of the per-tile and warp-specialised updates
+  struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[10]; int opo, opf, opg; float ms_op[7];
+                 int uwo, uws; float ms_uw[2]; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
   int gram_blocks = 0;
@@ -474,7 +479,7 @@ int opf_default_rows(const adef2_ctx* c) {
 
 // opf: rows of the fused operator pass's tiles (0 = two passes); opg: its
 // instances per block
-void set_variant(adef2_ctx* c, int rpt, int wfree, int opf = 0, int opg = 1) {
+void set_variant(adef2_ctx* c, int rpt, int wfree, int opf = 0, int opg = 1, int uws = 0) {
   c->rpt = rpt;
   c->wfree = wfree;
   c->of_rows = opf;
@@ -494,7 +499,17 @@ void set_variant(adef2_ctx* c, int rpt, int wfree, int opf = 0, int opg = 1) {
   c->ub_ntiles = (int)cdiv(c->N, (int64_t)UB_ROWS);
   c->ub_ntiles_pad = (int)cdiv(c->ub_ntiles, 8) * 8;
   c->g_ub = make_geom(c->ub_ntiles_pad);
+  // warp-specialised update: runs of ws_T tiles, the smallest power of two
+  // that keeps the grid within two 512-thread blocks per CU
+  c->uws = uws;
+  const int per = c->ub_ntiles_pad / 8, ng = (int)cdiv(std::max(c->B, 1), UB_G);
+  c->ws_T = 1;
+  while (c->ws_T < per && 8 * ng * cdiv(per, c->ws_T) > 512) c->ws_T *= 2;
+  c->ws_cpx = (int)cdiv(per, c->ws_T);
 }
+
+// partial sums per instance that k_finish_tm adds
+int fin_leaves(const adef2_ctx* c) { return c->uws ? 8 * c->ws_cpx : c->ub_ntiles_pad; }
 
 template <typename V>
 void fill(adef2_ctx* c, V* p, size_t n, V v);
@@ -735,6 +750,9 @@ IterArgs<V, M> iter_args(adef2_ctx* c) {
   a.bidx = c->bidx;
   a.ftot = c->ftot;
   a.fctr = c->fctr;
+  a.fin_leaves = fin_leaves(c);
+  a.ws_T = c->ws_T;
+  a.ws_cpx = c->ws_cpx;
   a.of_rows = c->of_rows;
   a.of_halo = c->of_halo;
   a.of_ntiles = c->of_ntiles;
@@ -822,7 +840,7 @@ ByteModel byte_model(const adef2_ctx* c, double wv, double wm, bool sweep_active
   b.update_tm = nI * 7 * wv + Nall + N1 * 8.0 + zsh + (double)c->nbnd * (4.0 + k * wm);
   // tile partial sums of the iterating instances, the slice totals written and read back
   const double nv = 2.0 * (double)c->KP + 2.0;
-  b.finish_tm = (double)nact * nv * 8.0 * ((double)c->ub_ntiles_pad + 2.0 * fin_slices(c->ub_ntiles_pad));
+  b.finish_tm = (double)nact * nv * 8.0 * ((double)fin_leaves(c) + 2.0 * fin_slices(fin_leaves(c)));
   // (t = A z), z, r; Z^T u, Z^T r with the FP64 operator and modes
   const double inner64 = c->factored ? (Nall * 2 * wv + N1 * D1 * 8.0) : 0.0;
   b.zproj = inner64 + nI * 3 * wv + U * D * 8.0 + zsh * (8.0 / wm) + Nall;
@@ -940,7 +958,8 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
   const dim3 gbt(c->bt_ntiles_pad);
   const dim3 gpt((unsigned)(c->ub_ntiles_pad * cdiv(c->B, PB_G)));
   const dim3 gut((unsigned)(c->ub_ntiles_pad * cdiv(c->B, UB_G)));
-  const dim3 gfin((unsigned)cdiv(2 * c->KP + 2, FC), (unsigned)fin_slices(c->ub_ntiles_pad), (unsigned)c->B);
+  const dim3 gfin((unsigned)cdiv(2 * c->KP + 2, FC), (unsigned)fin_slices(fin_leaves(c)), (unsigned)c->B);
+  const dim3 gws((unsigned)(8 * cdiv(c->B, UB_G) * c->ws_cpx));
   // tile-major stencil passes: coefficients of a row held in registers
   const bool stm = tm && c->wfree == 4 && c->D <= SDR && (!c->factored || c->D1 <= SDR);
   const dim3 gst((unsigned)(c->ub_ntiles_pad * cdiv(c->B, SG_G)));
@@ -1029,8 +1048,10 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
       if (tm) {
         if constexpr (sizeof(V) == 8)
         {
-          timed(c, KI_UPDATE_TM, bm.update_tm,
-                [&] { hipLaunchKernelGGL(btt.update_tm, gut, dim3(UB_THREADS), 0, s, a); });
+          timed(c, KI_UPDATE_TM, bm.update_tm, [&] {
+            if (c->uws) hipLaunchKernelGGL(btt.update_ws, gws, dim3(WS_THREADS), 0, s, a);
+            else hipLaunchKernelGGL(btt.update_tm, gut, dim3(UB_THREADS), 0, s, a);
+          });
           timed(c, KI_FINISH_TM, bm.finish_tm,
                 [&] { hipLaunchKernelGGL(btt.finish_tm, gfin, dim3(UB_THREADS), 0, s, a); });
         }
@@ -1072,7 +1093,7 @@ int run_sweep(adef2_ctx* c, const double* src, const double* x0pad, double thres
     // itself (w_mode 4 and 5 differ only in the stencil kernels), the
     // operator form and the boundary form
     int rc = chunk_graph<V, M>(c, a, chunk,
-                               ((b_outer ? 1 : 0) << 12) | (c->opg << 9) | ((int)c->opf << 8) | (c->wfree << 4) |
+                               (c->uws << 13) | ((b_outer ? 1 : 0) << 12) | (c->opg << 9) | ((int)c->opf << 8) | (c->wfree << 4) |
                                    ((int)tm << 3) | ((int)bt << 2) | ((int)wfree << 1) | (c->ne > 0 ? 1 : 0),
                                b_outer, launch_chunk, &gexec);
     if (rc) return rc;
@@ -1215,8 +1236,17 @@ int choose_variant(adef2_ctx* c, const double* b) {
   // and the option leaves it open
   const bool tune_op = fo == 0 && !opc.empty();
   const int op0 = fo == 1 ? R1 : 0, og0 = fo == 1 ? G1 : 1;
-  if (rpts.size() * wfs.size() == 1 && !tune_op) {
-    set_variant(c, rpts[0], wfs[0], op0, og0);
+  // update form of the tile-major path: per tile (k_update_tm) or
+  // warp-specialised runs of tiles (k_update_ws, up to 32 modes)
+  const int fu = c->o.update_ws;
+  const bool ws_ok = c->tm_ok && c->KP > 0 && c->KP <= 32 && vec64(c->prec);
+  if (fu == 1 && !ws_ok)
+    return fail(c, ADEF2_E_UNSUPPORTED,
+                "the warp-specialised update needs the tile-major boundary-form path with at most 32 modes");
+  const bool tune_uw = fu == 0 && ws_ok;
+  const int uw0 = fu == 1 ? 1 : 0;
+  if (rpts.size() * wfs.size() == 1 && !tune_op && !tune_uw) {
+    set_variant(c, rpts[0], wfs[0], op0, og0, uw0);
     return ADEF2_OK;
   }
   const int fact = c->factored ? 1 : 0;
@@ -1224,8 +1254,8 @@ int choose_variant(adef2_ctx* c, const double* b) {
   const int opo = fo + 4 * c->o.op_group + 32 * c->o.op_rows;   // the operator options tuned under
   for (const auto& t : c->tuned)
     if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.tm == tmk &&
-        t.N == c->N && t.opo == opo) {
-      set_variant(c, t.rpt, t.wfree, t.opf, t.opg);
+        t.N == c->N && t.opo == opo && t.uwo == fu) {
+      set_variant(c, t.rpt, t.wfree, t.opf, t.opg, t.uws);
       return ADEF2_OK;
     }
   const int prof = c->o.profile;
@@ -1234,10 +1264,10 @@ int choose_variant(adef2_ctx* c, const double* b) {
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, tmk, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
-                        opo, op0, og0, {0, 0, 0, 0, 0, 0, 0}};
+                        opo, op0, og0, {0, 0, 0, 0, 0, 0, 0}, fu, uw0, {0, 0}};
   // one trial: the solve's first two chunks of iterations from the same start
-  auto trial = [&](int rpt, int wf, int opf, int opg, float* ms) -> int {
-    set_variant(c, rpt, wf, opf, opg);
+  auto trial = [&](int rpt, int wf, int opf, int opg, int uws, float* ms) -> int {
+    set_variant(c, rpt, wf, opf, opg, uws);
     int rc = reset_solve_state(c);
     if (rc) return rc;
     if (c->prec != ADEF2_FP64) {
@@ -1266,7 +1296,7 @@ int choose_variant(adef2_ctx* c, const double* b) {
   for (int rpt : rpts) {
     for (int wf : wfs) {
       float ms = 0.0f;
-      if ((rc = trial(rpt, wf, op0, og0, &ms))) break;
+      if ((rc = trial(rpt, wf, op0, og0, uw0, &ms))) break;
       best.ms[ci++] = ms;
       if (ms < best_ms) { best_ms = ms; best.rpt = rpt; best.wfree = wf; }
     }
@@ -1278,17 +1308,25 @@ int choose_variant(adef2_ctx* c, const double* b) {
     best.ms_op[0] = best_ms;
     for (size_t q = 0; q < opc.size() && !rc; ++q) {
       float ms = 0.0f;
-      rc = trial(best.rpt, best.wfree, opc[q].R, opc[q].G, &ms);
+      rc = trial(best.rpt, best.wfree, opc[q].R, opc[q].G, uw0, &ms);
       best.ms_op[opc[q].slot] = ms;
       if (!rc && ms < best_ms) { best_ms = ms; best.opf = opc[q].R; best.opg = opc[q].G; }
     }
+  }
+  // stage 3: the warp-specialised update, when the tile-major path won
+  if (!rc && tune_uw && (best.wfree == 3 || best.wfree == 4)) {
+    float ms = 0.0f;
+    rc = trial(best.rpt, best.wfree, best.opf, best.opg, 1, &ms);
+    best.ms_uw[0] = best_ms;
+    best.ms_uw[1] = ms;
+    if (!rc && ms < best_ms) { best_ms = ms; best.uws = 1; }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->o.profile = prof;
   if (rc) return rc;
   c->tuned.push_back(best);
-  set_variant(c, best.rpt, best.wfree, best.opf, best.opg);
+  set_variant(c, best.rpt, best.wfree, best.opf, best.opg, best.uws);
   return ADEF2_OK;
 }
 
@@ -1404,7 +1442,7 @@ bool valid_opts(const adef2_opts* o) {
          (o->learned_objective == 0 || o->learned_objective == 1) &&
          (o->op_fused >= -1 && o->op_fused <= 1) && o->op_rows >= 0 && o->op_rows % 256 == 0 &&
          o->op_rows <= (1 << 16) && (o->op_group == 0 || o->op_group == 1 || o->op_group == 4) &&
-         (o->sweep_async == 0 || o->sweep_async == 1);
+         (o->sweep_async == 0 || o->sweep_async == 1) && o->update_ws >= -1 && o->update_ws <= 1;
 }
 
 }  // namespace
@@ -1530,6 +1568,7 @@ void adef2_default_opts(adef2_opts* o) {
   o->op_rows = 0;
   o->op_group = 0;
   o->sweep_async = 1;
+  o->update_ws = 0;
 }
 
 int adef2_create(adef2_ctx** out, const adef2_opts* opts, void* stream) {
@@ -2210,6 +2249,25 @@ int adef2_operator_variant(adef2_ctx* c, int32_t* fused, int32_t* tile_rows, int
       if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N &&
           t.opo == c->o.op_fused + 4 * c->o.op_group + 32 * c->o.op_rows)
         for (int q = 0; q < 7; ++q) ms[q] = t.ms_op[q];
+  }
+  return ADEF2_OK;
+}
+
+int adef2_update_variant(adef2_ctx* c, int32_t* warp_specialised, int32_t* tiles_per_block, float* ms) {
+  if (!c) return ADEF2_E_ARG;
+  if (!c->solved) return fail(c, ADEF2_E_STATE, "update_variant before the first solve");
+  const bool tm = (c->wfree == 3 || c->wfree == 4) && c->tm_ok;
+  if (warp_specialised) *warp_specialised = tm && c->uws;
+  if (tiles_per_block) *tiles_per_block = tm && c->uws ? c->ws_T : (tm ? 1 : 0);
+  if (ms) {
+    ms[0] = ms[1] = 0.0f;
+    const int fact = c->factored ? 1 : 0;
+    for (const auto& t : c->tuned)
+      if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.N == c->N &&
+          t.uwo == c->o.update_ws) {
+        ms[0] = t.ms_uw[0];
+        ms[1] = t.ms_uw[1];
+      }
   }
   return ADEF2_OK;
 }

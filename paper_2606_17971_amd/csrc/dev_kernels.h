@@ -133,6 +133,9 @@ struct IterArgs {
   const M* bW;
   double* ftot;            // [B][slices][2 KP + 2] slice totals of the tile-major finisher
   unsigned* fctr;          // [B] arrival counters of the tile-major finisher
+  int32_t fin_leaves;      // partial sums per instance that the finisher adds (tiles,
+                           // or runs of ws_T tiles for the warp-specialised update)
+  int32_t ws_T, ws_cpx;    // warp-specialised update: tiles per block, runs per XCD
   // fused operator pass of the factored form (k_opfused): of_rows-row tiles,
   // inner product A p staged in LDS over of_halo extra rows on each side
   int32_t of_rows, of_halo;

@@ -411,6 +411,222 @@ k_update_tm(IterArgs<double, M> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Warp-specialised form of the update (up to 32 modes): one block of 8 waves
+// owns an instance group and a run of T consecutive tiles.  Waves 0-3 do
+// the vector work of tile q (x, r, z for the group's 8 instances) and stage
+// [z r] into zr[q & 1], while waves 4-7 form the projections of tile q - 1
+// from zr[(q - 1) & 1]: the matrix-core products with the shared modes, the
+// boundary rows, r.z and r.r.  One barrier per step; the two halves work on
+// different tiles, so the products overlap the next tile's loads (within one
+// wave they could not: a wave's vector-memory counter completes in order).
+// The products, boundary sums and dot products accumulate over the run in
+// registers, and each block stores one partial per instance (the run's
+// leaf) for k_finish_tm.  Same per-row arithmetic as k_update_tm; the sums
+// are added tile by tile within a run.
+// ---------------------------------------------------------------------------
+constexpr int WS_THREADS = 512;
+
+template <typename M, int KP>
+__global__ void __launch_bounds__(WS_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_update_ws(IterArgs<double, M> a) {
+  static_assert(KP > 0 && KP <= 32, "warp-specialised update: 1..32 modes");
+  constexpr int KQ = (KP + 15) / 16 * 16;
+  constexpr int NQT = KQ / 16;
+  constexpr int NV = 2 * KP + 2;
+  constexpr int NC = 2 * UB_G;
+  constexpr int ZR = UB_ROWS * NC;
+  constexpr int LPE = 2;
+  constexpr int BU = 4;
+  __shared__ double zr[2][ZR];
+  __shared__ double s_alpha[UB_G], s_a[UB_G], s_c[UB_G];
+  __shared__ int s_k[UB_G];
+  const int per = a.ub_ntiles_pad >> 3;
+  const int xcd = blockIdx.x & 7, jb = blockIdx.x >> 3;
+  const int grp = jb % a.ub_ngroups, run = jb / a.ub_ngroups;
+  const int T = a.ws_T;
+  const int tb = xcd * per + run * T;
+  const int te = min(tb + T, (xcd + 1) * per);
+  const int leaf = xcd * a.ws_cpx + run;
+  const int g0 = grp * UB_G;
+  const int G = min(UB_G, a.B - g0);
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const bool memw = wid < 4;
+  const int tt = t & 255;
+  const int64_t N = a.op.N;
+  if (t < UB_G) {
+    int k = 0;
+    double al = 0.0, sa = 0.0, sc = 0.0;
+    if (t < G) {
+      const Inst* S = a.inst + g0 + t;
+      k = S->done ? 0 : (S->kk > 0 ? 2 : 1);
+      al = S->alpha;
+      sa = S->a;
+      sc = S->c;
+    }
+    s_k[t] = k;
+    s_alpha[t] = al;
+    s_a[t] = sa;
+    s_c[t] = sc;
+  }
+  __syncthreads();
+  unsigned act = 0u;
+  for (int j = 0; j < UB_G; ++j)
+    if (s_k[j]) act |= 1u << j;
+  if (!act) return;
+  // product waves: running sums over the run's tiles
+  const int cw = wid - 4;
+  const int cn = lane & 15, kk = lane >> 4;
+  const int bq = lane & 31, bsub = lane >> 5;
+  tm_d4 acc[NQT];
+#pragma unroll
+  for (int qt = 0; qt < NQT; ++qt) acc[qt] = tm_d4{0.0, 0.0, 0.0, 0.0};
+  double ab[2] = {0.0, 0.0};
+  double d1 = 0.0, d2 = 0.0;
+  for (int q = 0; q <= te - tb; ++q) {
+    if (memw) {
+      if (tb + q < te) {
+        const int tile = tb + q;
+        const int64_t i = (int64_t)tile * UB_ROWS + tt;
+        const bool row = tile < a.ub_ntiles && i < N;
+        const int64_t ic = row ? i : 0;
+        uint8_t mk[UB_G];
+#pragma unroll
+        for (int j = 0; j < UB_G; ++j) {
+          const uint8_t mv = a.mask[(size_t)(g0 + (j < G ? j : 0)) * N + ic];
+          mk[j] = (j < G && row && s_k[j]) ? mv : (uint8_t)1;
+        }
+        const double dg = a.diag[ic];
+        double xv[UB_G], pv[UB_G], rv[UB_G], wv[UB_G];
+#pragma unroll
+        for (int j = 0; j < UB_G; ++j) {
+          xv[j] = pv[j] = rv[j] = wv[j] = 0.0;
+          if (!mk[j]) {
+            const int64_t o = (int64_t)(g0 + j) * a.vs + i;
+            xv[j] = a.x[o];
+            pv[j] = a.p[o];
+            rv[j] = a.r[o];
+            wv[j] = a.w[o];
+          }
+        }
+        double* zb = zr[q & 1];
+#pragma unroll
+        for (int j = 0; j < UB_G; ++j) {
+          double zq = 0.0, rq = 0.0;
+          if (!mk[j]) {
+            const int64_t o = (int64_t)(g0 + j) * a.vs + i;
+            const double al = s_alpha[j];
+            const double xn = xv[j] + al * pv[j];
+            rq = rv[j] - al * wv[j];
+            const double dinv = a.precond_none ? 1.0 : 1.0 / (s_a[j] * dg + s_c[j]);
+            zq = dinv * rq;
+            a.x[o] = xn;
+            a.r[o] = rq;
+            a.z[o] = zq;
+          }
+          zb[tt * NC + 2 * j] = zq;
+          zb[tt * NC + 2 * j + 1] = rq;
+        }
+      }
+    } else if (q >= 1) {
+      const int tile = tb + q - 1;
+      const int64_t base = (int64_t)tile * UB_ROWS;
+      const bool in_tile = tile < a.ub_ntiles;
+      const double* zb = zr[(q - 1) & 1];
+      // boundary lists of this wave's instances j = cw + 4 h
+      int e0[2] = {0, 0}, e1[2] = {0, 0};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = cw + 4 * h;
+        if (in_tile && j < G && s_k[j] == 2) {
+          const int32_t* to = a.btoff + (size_t)(g0 + j) * (a.ub_ntiles + 1) + tile;
+          e0[h] = to[0];
+          e1[h] = to[1];
+        }
+      }
+      M zraw[16][NQT];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int64_t gi = base + 64 * cw + 4 * s + kk;
+#pragma unroll
+        for (int qt = 0; qt < NQT; ++qt) {
+          const int qq = qt * 16 + cn;
+          zraw[s][qt] = (qq < KP && in_tile && gi < N) ? a.ZT[(size_t)gi * KP + qq] : (M)0;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const double bval = zb[(64 * cw + 4 * s + kk) * NC + cn];
+#pragma unroll
+        for (int qt = 0; qt < NQT; ++qt)
+          acc[qt] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)zraw[s][qt], bval, acc[qt], 0, 0, 0);
+      }
+      {
+        const int ct = t - 256, j = ct >> 5, l = ct & 31;
+#pragma unroll
+        for (int u = 0; u < UB_ROWS / 32; ++u) {
+          const int rw = l + 32 * u;
+          const double zz = zb[rw * NC + 2 * j], rr = zb[rw * NC + 2 * j + 1];
+          d1 += rr * zz;
+          d2 += rr * rr;
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = cw + 4 * h;
+        for (int e = e0[h] + bsub; e < e1[h]; e += LPE) {
+          const double wq = bq < KP ? (double)a.bW[(size_t)e * KP + bq] : 0.0;
+          ab[h] += wq * zb[(int)(a.bidx[e] - base) * NC + 2 * j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // run totals: the product waves' partials into zr[0], the boundary sums and
+  // dot products into zr[1]; then one partial per instance for the finisher
+  double* pw = zr[0];
+  double* bs = zr[1];                              // [UB_G][32] boundary sums, then [UB_G][2] dots
+  if (!memw) {
+#pragma unroll
+    for (int qt = 0; qt < NQT; ++qt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pw[((cw * NQT + qt) * 4 + e) * 64 + lane] = acc[qt][e];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double v = ab[h] + __shfl_down(ab[h], 32, 64);
+      if (bsub == 0) bs[(cw + 4 * h) * 32 + bq] = v;
+    }
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+      d1 += __shfl_xor(d1, off, 64);
+      d2 += __shfl_xor(d2, off, 64);
+    }
+    const int ct = t - 256;
+    if ((ct & 31) == 0) {
+      bs[UB_G * 32 + 2 * (ct >> 5)] = d1;
+      bs[UB_G * 32 + 2 * (ct >> 5) + 1] = d2;
+    }
+  }
+  __syncthreads();
+  for (int o = t; o < UB_G * NV; o += WS_THREADS) {
+    const int j = o / NV, v = o - j * NV;
+    if (!((act >> j) & 1u)) continue;
+    double val = 0.0;
+    if (v < 2 * KP) {
+      const bool zpart = v < KP;
+      const int q = zpart ? v : v - KP;
+      const int c = 2 * j + (zpart ? 0 : 1);
+      const int qt = q >> 4, e = (q & 15) >> 2, ln = (q & 3) * 16 + c;
+      double dsum = 0.0;
+      for (int w = 0; w < 4; ++w) dsum += pw[((w * NQT + qt) * 4 + e) * 64 + ln];
+      val = zpart ? (s_a[j] * a.mu[q] + s_c[j]) * dsum + bs[j * 32 + q] : dsum;
+    } else {
+      val = bs[UB_G * 32 + 2 * j + (v - 2 * KP)];
+    }
+    a.part[((size_t)(g0 + j) * a.fin_leaves + leaf) * NV + v] = val;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Finisher of the tile-major update: per instance the tile sums
 // part[m][tile][0 .. NV) are reduced in a fixed order.  Block (ch, sc, m)
 // covers FC values of slice sc of the tiles (thread (v, s) sums value v over
@@ -446,8 +662,8 @@ __global__ void __launch_bounds__(UB_THREADS) k_finish_tm(IterArgs<double, M> a)
   if (S->done) return;
   const int t = threadIdx.x;
   const int v = ch * FC + (t % FC), sidx = t / FC;
-  const int tps = a.ub_ntiles_pad / nsl;
-  const double* pm = a.part + ((size_t)m * a.ub_ntiles_pad + (size_t)sc * tps) * NV;
+  const int tps = a.fin_leaves / nsl;
+  const double* pm = a.part + ((size_t)m * a.fin_leaves + (size_t)sc * tps) * NV;
   double acc = 0.0;
   if (v < NV)
     for (int tl = sidx; tl < tps; tl += FS) acc += pm[(size_t)tl * NV + v];

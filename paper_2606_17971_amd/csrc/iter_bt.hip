@@ -6,8 +6,12 @@ namespace adef2 {
 
 template <typename M, int KP>
 static BtTab<M> make_bt() {
-  return {k_pupdate_bt<double, M, KP>, k_zproj_bt<M, KP>, k_pupdate_tm<M, KP>, k_update_tm<M, KP>,
-          k_finish_tm<M, KP>, k_stencil1_tm<M>, k_spmv_tm<M>, k_alpha_tm<M>};
+  if constexpr (KP <= 32)
+    return {k_pupdate_bt<double, M, KP>, k_zproj_bt<M, KP>, k_pupdate_tm<M, KP>, k_update_tm<M, KP>,
+            k_finish_tm<M, KP>, k_stencil1_tm<M>, k_spmv_tm<M>, k_alpha_tm<M>, k_update_ws<M, KP>};
+  else
+    return {k_pupdate_bt<double, M, KP>, k_zproj_bt<M, KP>, k_pupdate_tm<M, KP>, k_update_tm<M, KP>,
+            k_finish_tm<M, KP>, k_stencil1_tm<M>, k_spmv_tm<M>, k_alpha_tm<M>, nullptr};
 }
 
 template <typename M>

@@ -38,6 +38,7 @@ struct BtTab {
   void (*stencil1_tm)(IterArgs<double, M>);
   void (*spmv_tm)(IterArgs<double, M>);
   void (*alpha_tm)(IterArgs<double, M>);
+  void (*update_ws)(IterArgs<double, M>);   // warp-specialised update (KP <= 32; null above)
 };
 
 // defined in iter_bt.hip for M in {double, float}

@@ -707,3 +707,64 @@ def test_async_segments_match_synchronised(lib, prec, w_mode):
         I, xs = _xstar(S, w.instances[m].mask, bs[m])
         e = oracle.rel_err(outs[1]["x"].cpu().numpy()[m, I], xs)
         assert e <= max(1e-6, 10 * tols[m]), (m, e)
+
+
+# ---------------------------------------------------------------------------
+# warp-specialised update (runs of tiles, products overlapping the loads)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("B", [3, 11])
+def test_warp_specialised_update_matches_oracle(lib, B):
+    """update_ws = 1 at n = 95 (runs of one tile; B = 11: groups of 8 and 3)
+    against the oracle, as the per-tile update is tested."""
+    w = gen.c2_workload(n=95, k=16, B=B)
+    S = spec(w.op, "factored")
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case(f"warp-specialised update factored cd2d n=95 k=16 B={B}")
+    s = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE, rows_per_thread=1, w_mode=4,
+               update_ws=1)
+    out = s.solve_batched(masks, bs, 1e-10)
+    assert s.update_variant()[0] == 1
+    X = out["x"].cpu().numpy()
+    for m, inst in enumerate(w.instances):
+        ref = oracle.solve_instance(S, w.Z, inst.mask, inst.b, 1e-10)
+        I, xs = _xstar(S, inst.mask, inst.b)
+        e = oracle.rel_err(X[m, I], xs)
+        assert out["status"][m] == 0
+        assert out["relres_true"][m] <= 1e-10
+        assert e <= max(1e-8, 2 * oracle.rel_err(ref.x[I], xs)), (m, e)
+        assert int(out["iters"][m]) <= 1.2 * ref.iters + 20, (m, out["iters"][m], ref.iters)
+    assert np.all(X[masks == 1] == 0.0)
+
+
+def test_warp_specialised_update_runs_of_tiles(lib):
+    """255^2 x 37 instances: runs of 4 tiles per block (5 groups, the last of 5
+    instances), against the per-tile update on every instance and x* on
+    samples."""
+    w = gen.c2_workload(n=255, k=32, B=37)
+    S = spec(w.op, "factored")
+    masks = np.stack([i.mask for i in w.instances])
+    bs = np.stack([i.b for i in w.instances])
+    case("warp-specialised update vs per tile, mixed w_mode=4 cd2d n=255 k=32 B=37")
+    outs = {}
+    for uw in (1, -1):
+        s = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE, rows_per_thread=1, w_mode=4,
+                   op_fused=1, update_ws=uw)
+        outs[uw] = s.solve_batched(masks, bs, 1e-10)
+        ws, tpb, _ = s.update_variant()
+        assert ws == (1 if uw == 1 else 0)
+        if uw == 1:
+            assert tpb == 4
+        s.close()
+    Xw, Xt = outs[1]["x"].cpu().numpy(), outs[-1]["x"].cpu().numpy()
+    assert np.all(outs[1]["status"] == outs[-1]["status"])
+    assert np.all(outs[1]["relres_true"] <= 1e-10) or np.all(np.isin(outs[1]["status"], (0, 3)))
+    for m in range(37):
+        it_w, it_t = int(outs[1]["iters"][m]), int(outs[-1]["iters"][m])
+        assert abs(it_w - it_t) <= 0.05 * it_t + 20, (m, it_w, it_t)
+        assert oracle.rel_err(Xw[m], Xt[m]) <= 1e-8, m
+    for m in (0, 18, 36):
+        inst = w.instances[m]
+        I, xs = _xstar(S, inst.mask, inst.b)
+        assert oracle.rel_err(Xw[m, I], xs) <= 1e-8, m
+    assert np.all(Xw[masks == 1] == 0.0)
