@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--op-rows", type=int, default=0, help="tile height of the fused pass (0 = tuned)")
     ap.add_argument("--op-group", type=int, default=0, choices=[0, 1, 4],
                     help="instances per block of the fused pass (0 = tuned)")
+    ap.add_argument("--update-ws", type=int, default=0, choices=[-1, 0, 1],
+                    help="tile-major update: 1 = warp-specialised, -1 = per tile, 0 = tuned")
     ap.add_argument("--w-boundary", type=int, default=2, choices=[0, 1, 2],
                     help="boundary form of W for eigen reference modes: 0 off, 1 on, "
                          "2 when every reference mode is an eigenvector")
@@ -556,7 +558,8 @@ def main():
     B = args.batch
     prec = {"mixed": lib.MIXED_REFINE, "fp32": lib.FP32_REFINE, "fp64": lib.FP64}[args.precision]
     tune = dict(rows_per_thread=args.rpt, w_mode=args.w_mode, w_boundary=args.w_boundary,
-                op_fused=args.op_fused, op_rows=args.op_rows, op_group=args.op_group)
+                op_fused=args.op_fused, op_rows=args.op_rows, op_group=args.op_group,
+                update_ws=args.update_ws)
     head = lib.Solver(precision=prec, inner_rtol=args.inner_rtol, **tune)
     head.set_reference_factored(op.A, op.alpha, op.shift, w.Z)
     thetas = torch.as_tensor(np.stack([i.theta for i in w.instances]).astype(np.float32), device="cuda")
