@@ -215,7 +215,7 @@ struct adef2_ctx {
   // uwo: the update_ws option tuned under; uws: the update form kept; ms_uw:
   // trial times of the per-tile and warp-specialised updates
   struct Tuned { int B, prec, KP, fact, tm; int64_t N; int rpt, wfree; float ms[10]; int opo, opf, opg; float ms_op[7];
-                 int uwo, uws; float ms_uw[2]; };
+                 int uwo, uws; float ms_uw[2]; int fro, fwo; };
   std::vector<Tuned> tuned;      // autotuned variants per configuration
   RedGeom g_iter{};
   int gram_blocks = 0;
@@ -1254,7 +1254,7 @@ int choose_variant(adef2_ctx* c, const double* b) {
   const int opo = fo + 4 * c->o.op_group + 32 * c->o.op_rows;   // the operator options tuned under
   for (const auto& t : c->tuned)
     if (t.B == c->B && t.prec == c->prec && t.KP == c->KP && t.fact == fact && t.tm == tmk &&
-        t.N == c->N && t.opo == opo && t.uwo == fu) {
+        t.N == c->N && t.opo == opo && t.uwo == fu && t.fro == fr && t.fwo == fw) {
       set_variant(c, t.rpt, t.wfree, t.opf, t.opg, t.uws);
       return ADEF2_OK;
     }
@@ -1264,7 +1264,7 @@ int choose_variant(adef2_ctx* c, const double* b) {
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   adef2_ctx::Tuned best{c->B, c->prec, c->KP, fact, tmk, c->N, rpts[0], wfs[0], {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
-                        opo, op0, og0, {0, 0, 0, 0, 0, 0, 0}, fu, uw0, {0, 0}};
+                        opo, op0, og0, {0, 0, 0, 0, 0, 0, 0}, fu, uw0, {0, 0}, fr, fw};
   // one trial: the solve's first two chunks of iterations from the same start
   auto trial = [&](int rpt, int wf, int opf, int opg, int uws, float* ms) -> int {
     set_variant(c, rpt, wf, opf, opg, uws);

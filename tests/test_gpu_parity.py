@@ -485,9 +485,10 @@ def test_graphs_keyed_by_variant(lib):
     bs = np.stack([i.b for i in w.instances])
     case("graph cache keyed by w_mode and operator form")
     s = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE, rows_per_thread=1, w_mode=4,
-               op_fused=-1)
+               op_fused=-1, update_ws=-1)
     s.solve_batched(masks, bs, 1e-10)
-    for opts in (dict(w_mode=5, op_fused=-1), dict(w_mode=5, op_fused=1), dict(w_mode=4, op_fused=1)):
+    for opts in (dict(w_mode=5, op_fused=-1, update_ws=-1), dict(w_mode=5, op_fused=1, update_ws=-1),
+                 dict(w_mode=4, op_fused=1, update_ws=-1), dict(w_mode=4, op_fused=1, update_ws=1)):
         s.set_opts(**opts)
         got = s.solve_batched(masks, bs, 1e-10)
         f = solver(lib, w.op, w.Z, "factored", precision=lib.MIXED_REFINE, rows_per_thread=1, **opts)
@@ -694,7 +695,7 @@ def test_async_segments_match_synchronised(lib, prec, w_mode):
     outs = []
     for sa in (0, 1):
         s = solver(lib, w.op, w.Z, "factored", precision=p, rows_per_thread=1, w_mode=w_mode, op_fused=1,
-                   sweep_async=sa)
+                   update_ws=-1, sweep_async=sa)
         outs.append(s.solve_batched(masks, bs, tols))
         s.close()
     print(f"   iterations {outs[1]['iters'].tolist()} statuses {outs[1]['status'].tolist()}", flush=True)
